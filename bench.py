@@ -1,0 +1,319 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the MI355X Tensorized Pauli Decomposition.
+
+Default workload (the largest single-GPU configuration): one dense Hermitian
+2^16 x 2^16 matrix, A = (G + G^H)/2 with complex N(0,1) G (seed 5),
+complex128, decomposed out of place into its 4^16 canonical Pauli
+coefficients.  A step is one full decomposition (bitmap clear + two HBM
+sweeps, pruning on).  Inputs are generated on the GPU and resident in HBM
+before the timed region.  Prints ONE JSON line.
+
+Extras in the same line: the complex64 run of the same matrix, the same
+matrix in place (matrix layout), the n = 14 structured Hamiltonian with
+zero-block pruning, the 4096-matrix batched workload (graph replay vs
+per-matrix launches), and the CPU oracle timed on the host.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--extras ...]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+METRIC = "Pauli coeffs/sec + HBM GB/s (% peak) at n=14/16, FP64 vs FP32; batched mats/s"
+KERNEL_SOURCES = ["paper_2310_13421_amd/csrc/tpd_kernels.hip", "paper_2310_13421_amd/csrc/tpd_core.h",
+                  "paper_2310_13421_amd/csrc/tpd_internal.h"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(key):
+    """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE and
+    WRITE_SIZE scaled by a plain-copy calibration), if taken on the current
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return t.get("kernels", {}).get(key)
+
+
+def timed_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1000.0 / steps
+
+
+def kernel_avgs(plan):
+    ms, cnt = plan.timing(reset=True)
+    return [m / c if c else 0.0 for m, c in zip(ms, cnt)], cnt
+
+
+def single_matrix_run(tpd, torch, A, n, dtype_code, steps, warmup, esize, in_place=False, layout="canonical"):
+    out = A.view(-1) if in_place else torch.empty(4 ** n, dtype=A.dtype, device=A.device)
+    plan = tpd.Plan(n, dtype_code, timing=True, in_place=in_place, layout=layout)
+    ms = timed_steps(lambda: plan.execute(A, out), steps, warmup, torch)
+    avgs, cnt = kernel_avgs(plan)
+    plan.timing(reset=True)
+    desc = plan.describe()
+    plan.close()
+    sweep_bytes = 2 * 4 ** n * esize
+    res = {
+        "ms_per_step": ms,
+        "coeffs_per_s": 4 ** n / (ms / 1e3),
+        "algorithmic_GBps": sweep_bytes / (ms / 1e3) / 1e9,
+        "kernel_ms": avgs,
+        "kernel_launches": cnt,
+        "sweep_GBps": [sweep_bytes / (a / 1e3) / 1e9 if a else None for a in avgs],
+        "sweeps": len(desc["sweeps"]),
+    }
+    res["pct_peak_algorithmic"] = 100.0 * res["algorithmic_GBps"] / PEAK_HBM_GBPS
+    return res, out
+
+
+def cpu_baseline(n_sample=13, min_seconds=10.0):
+    """The oracle's Algorithm 1 (plain single-threaded C, binary64) on a
+    Hermitian matrix of the workload's distribution at n = n_sample."""
+    import numpy as np
+
+    from oracle import oracle as O
+    import workloads as W
+
+    A = W.gaussian(n_sample, seed=5, hermitian=True)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        O.tpd_recursive(A)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds:
+            break
+    rate = reps * 4 ** n_sample / el
+    del A, np
+    return {
+        "value": rate,
+        "unit": "coeffs/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle Algorithm 1 recursion (single-threaded C, binary64) on a dense Hermitian "
+                   f"n={n_sample} matrix of the workload's distribution, {reps} run(s), {el:.1f} s; its cost per "
+                   f"coefficient grows with n, so the n=16 rate is about {n_sample}/16 of this"),
+        "seconds": el,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=16)
+    ap.add_argument("--extras", default="fp32,inplace,n14,batched",
+                    help="comma list of fp32,inplace,n14,batched, or 'none'")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2310_13421_amd import tpd
+    import workloads as W
+
+    extras = set() if args.extras == "none" else set(args.extras.split(","))
+    torch.cuda.set_device(0)
+    n = args.n
+    log(f"generating n={n} Hermitian complex128 input on the GPU")
+    A = W.gaussian_device(n, seed=5, hermitian=True)
+    torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        nbytes = 1 << 32
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {nbytes} bytes")
+        del src, dst
+        torch.cuda.empty_cache()
+
+    log(f"main: n={n} complex128 out of place, {args.warmup} warmup + {args.steps} timed steps")
+    main_res, out = single_matrix_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16)
+    log(f"main: {main_res['ms_per_step']:.3f} ms/step, {main_res['coeffs_per_s']:.3e} coeffs/s, "
+        f"kernels {main_res['kernel_ms']}")
+    del out
+    torch.cuda.empty_cache()
+
+    avgs = main_res["kernel_ms"]
+    k = max(range(len(avgs)), key=lambda i: avgs[i])
+    unit_bytes = 2 * 16  # one complex128 read + one write per coefficient
+    achieved = unit_bytes * 4 ** n / (avgs[k] / 1e3) / 1e9
+    tr = load_traffic(f"sweep{k + 1}_n{n}_c128")
+    roofline = {
+        "bound": "hbm",
+        "kernel": f"k_sweep (sweep {k + 1} of 2)",
+        "achieved": achieved,
+        "peak": PEAK_HBM_GBPS,
+        "unit": "GB/s",
+        "frac": achieved / PEAK_HBM_GBPS,
+        "traffic": tr,
+    }
+
+    result = {
+        "metric": METRIC,
+        "value": main_res["coeffs_per_s"],
+        "unit": "coeffs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"dense Hermitian {2 ** n}x{2 ** n} complex128 (n={n}), A=(G+G^H)/2, G complex N(0,1) "
+                        f"seed 5; out of place, canonical order, pruning on",
+            "n": n,
+            "precision": "complex128",
+            "layout": "canonical",
+            "placement": "out-of-place",
+        },
+        "hbm_GBps_algorithmic": main_res["algorithmic_GBps"],
+        "pct_peak_algorithmic": main_res["pct_peak_algorithmic"],
+        "sweeps": main_res["sweeps"],
+        "kernel_ms": main_res["kernel_ms"],
+        "sweep_GBps": main_res["sweep_GBps"],
+        "roofline": roofline,
+    }
+
+    steps_x = max(3, min(args.steps, 10))
+    if "inplace" in extras:
+        log("extra: in place, matrix layout, complex128")
+        B = A.clone()
+        r, _ = single_matrix_run(tpd, torch, B, n, tpd.TPD_C128, steps_x, 1, 16, in_place=True, layout="matrix")
+        result["inplace_c128"] = r
+        del B
+        torch.cuda.empty_cache()
+    if "fp32" in extras:
+        log("extra: complex64")
+        A32 = A.to(torch.complex64)
+        del A
+        A = None
+        torch.cuda.empty_cache()
+        r, o32 = single_matrix_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8)
+        r["speedup_vs_c128"] = main_res["ms_per_step"] / r["ms_per_step"]
+        result["fp32"] = r
+        del o32, A32
+        torch.cuda.empty_cache()
+    if A is not None:
+        del A
+        torch.cuda.empty_cache()
+
+    if "n14" in extras:
+        log("extra: n=14 Heisenberg chain + 200 4-local strings, pruning")
+        n14 = 14
+        H = W.dense_from_terms_device(W.heisenberg_terms(n14, seed=3, n_local=200), n14)
+        r, o = single_matrix_run(tpd, torch, H, n14, tpd.TPD_C128, args.steps, args.warmup, 16)
+        plan = tpd.Plan(n14)
+        plan.execute(H, o)
+        st = plan.prune_stats()
+        plan.close()
+        r["live_tile_fraction"] = st["live_tiles"] / st["total_tiles"]
+        r["live_prefixes_level"] = st["prefix_level"]
+        r["live_prefixes"] = st["live_prefixes"]
+        rn, o2 = single_matrix_run(tpd, torch, H, n14, tpd.TPD_C128, steps_x, 1, 16)
+        result["n14_structured"] = r
+        del H, o, o2
+        torch.cuda.empty_cache()
+
+    if "batched" in extras:
+        log("extra: batched 4096 matrices, n in 2..9")
+        ns = [int(v) for v in W.batched_qubits(4096, seed=4)]
+        bres = {"count": len(ns), "elements": int(sum(4 ** v for v in ns))}
+        for name, dt, code, es in (("c128", torch.complex128, tpd.TPD_C128, 16),
+                                   ("c64", torch.complex64, tpd.TPD_C64, 8)):
+            mats = W.batched_matrices_device(ns, seed=4, dtype=dt)
+            outs = [torch.empty(4 ** v, dtype=dt, device="cuda") for v in ns]
+            plan = tpd.BatchedPlan(ns, code, timing=True)
+            dp = tpd.BatchedPlan.pointer_table(mats)
+            do = tpd.BatchedPlan.pointer_table(outs)
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                plan.execute(dp, do)
+            torch.cuda.current_stream().wait_stream(s)
+            torch.cuda.synchronize()
+            plan.timing(reset=True)
+            ms_eager = timed_steps(lambda: plan.execute(dp, do), args.steps, args.warmup, torch)
+            kavg, _ = kernel_avgs(plan)
+            plan_g = tpd.BatchedPlan(ns, code)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                plan_g.execute(dp, do)
+            ms_graph = timed_steps(lambda: g.replay(), args.steps, args.warmup, torch)
+
+            def loop():
+                for m, o in zip(mats, outs):
+                    tpd.decompose(m, o)
+
+            ms_loop = timed_steps(loop, max(2, steps_x // 3), 1, torch)
+            bytes_ = 2 * bres["elements"] * es
+            bres[name] = {
+                "graph_ms": ms_graph,
+                "mats_per_s": len(ns) / (ms_graph / 1e3),
+                "eager_ms": ms_eager,
+                "kernel_ms": kavg[0],
+                "kernel_GBps": bytes_ / (kavg[0] / 1e3) / 1e9,
+                "per_matrix_launch_loop_ms": ms_loop,
+                "per_matrix_mats_per_s": len(ns) / (ms_loop / 1e3),
+                "speedup_vs_per_matrix": ms_loop / ms_graph,
+                "algorithmic_GBps": bytes_ / (ms_graph / 1e3) / 1e9,
+            }
+            plan.close()
+            plan_g.close()
+            del mats, outs, g
+            torch.cuda.empty_cache()
+        result["batched"] = bres
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on the host")
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

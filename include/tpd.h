@@ -1,0 +1,191 @@
+/*
+ * tpd.h -- C ABI of libtpd, the MI355X (gfx950) implementation of the
+ * Tensorized Pauli Decomposition (TPD) of Hantzko, Binkowski and Gupta,
+ * "Tensorized Pauli decomposition algorithm", arXiv:2310.13421.
+ *
+ * The decomposition (section "Problem formulation", eq. (PauliDecomposition))
+ * writes a complex 2^n x 2^n matrix A as
+ *     A = sum_t w_t sigma^t,    w_t = 2^-n tr(sigma^t A),
+ * over the 4^n Pauli strings sigma^t = sigma^{t_1} (x) ... (x) sigma^{t_n}
+ * (eq. (PauliString)), letters I=0, X=1, Y=2, Z=3.  It is computed by n
+ * slicing levels (section "Methods", eq. (CumulativeWeightsDefinition)):
+ * the quadrants A11, A12, A21, A22 become the cumulative matrix weights
+ * (A11+A22)/2, (A12+A21)/2, i(A12-A21)/2, (A11-A22)/2; zero blocks are
+ * pruned (eq. (CumulativeWeightsFormula) and the remark after it).
+ *
+ * Data formats
+ *   - Complex numbers are interleaved (re, im): TPD_C128 = two IEEE binary64
+ *     (16 bytes), TPD_C64 = two IEEE binary32 (8 bytes).
+ *   - A is row-major with leading dimension 2^n.
+ *   - Coefficients, canonical layout (default): 4^n complex values, the
+ *     weight of string t_1..t_n at index q = sum_k t_k 4^(n-k), t_1 being the
+ *     first (outermost) tensor factor.
+ *   - Coefficients, matrix layout (TPD_FLAG_LAYOUT_MATRIX): the weight of t
+ *     at row h, column l of a 2^n x 2^n array, where bit (n-k) of h is 1 iff
+ *     t_k is Y or Z and bit (n-k) of l is 1 iff t_k is X or Z.  q and (h, l)
+ *     are related by q = interleave(h, l) with the bits of h in the odd
+ *     positions.
+ *
+ * Memory, ownership, aliasing
+ *   - All matrix and coefficient pointers are DEVICE pointers owned by the
+ *     caller, on the current HIP device.  Alignment: 16 bytes (C128) or 8
+ *     bytes (C64); otherwise TPD_ERROR_INVALID_VALUE.
+ *   - Out of place (coeffs != A, no overlap): A is read and not modified.
+ *   - In place (coeffs == A): supported with TPD_FLAG_LAYOUT_MATRIX for every
+ *     n, and in the canonical layout only for n <= 6.  Partial overlap is
+ *     rejected with TPD_ERROR_INVALID_VALUE.
+ *   - The library owns its workspace (pruning bitmaps, work tables); it is
+ *     allocated on first use per (device, stream) and by plan creation, and
+ *     released by tpd_release_workspace / tpd_plan_destroy.
+ *
+ * Execution and errors
+ *   - Calls validate their arguments on the host, synchronously, before
+ *     enqueueing anything; then they enqueue kernels on `stream` (a
+ *     hipStream_t, NULL = the default stream) and return without waiting.
+ *     Device-side faults surface at the caller's next synchronisation.
+ *   - No C++ exception crosses this ABI.  Nothing is printed unless the
+ *     environment variable TPD_LOG=1 is set.
+ *   - Concurrent calls on different streams use different workspaces and do
+ *     not interfere; calls on one stream are ordered by the stream.
+ */
+#ifndef TPD_H_
+#define TPD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* tpd_stream_t; /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+  TPD_C128 = 0, /* interleaved binary64 pairs */
+  TPD_C64 = 1   /* interleaved binary32 pairs */
+} tpd_dtype_t;
+
+typedef enum {
+  TPD_SUCCESS = 0,
+  TPD_ERROR_INVALID_VALUE = 1, /* NULL/misaligned pointer, bad flags, overlap */
+  TPD_ERROR_UNSUPPORTED = 2,   /* n out of range, unsupported layout/aliasing */
+  TPD_ERROR_OUT_OF_MEMORY = 3, /* workspace allocation failed */
+  TPD_ERROR_LAUNCH = 4,        /* a kernel launch or HIP call failed */
+  TPD_ERROR_INTERNAL = 5,
+  TPD_ERROR_NO_DEVICE = 6      /* no usable gfx950 device */
+} tpd_status_t;
+
+/* flags (bitwise OR) */
+#define TPD_FLAG_NO_PRUNE 0x1u      /* disable the zero-block bitmap (it is on by default) */
+#define TPD_FLAG_LAYOUT_MATRIX 0x2u /* coefficients in the matrix layout (see above) */
+#define TPD_FLAG_TIMING 0x4u        /* plans only: record per-kernel HIP events */
+#define TPD_FLAG_ORDER_BOTTOM 0x8u  /* register phases bottom level first (tuning) */
+#define TPD_FLAGS_ALL 0xFu
+
+/* Largest supported n: 16 for both dtypes (the two-sweep tile schedule and
+ * 288 GB of HBM for an out-of-place n = 16 C128 pair). */
+int tpd_max_qubits(tpd_dtype_t dtype);
+
+/* Decompose one matrix, complex128, canonical layout, pruning on.
+ * Section "Methods"; Fig. 1, Algorithms 1 and 2.
+ *   A      [in]  device, 2^n x 2^n complex128, row-major
+ *   n      [in]  0 <= n <= tpd_max_qubits(TPD_C128)
+ *   coeffs [out] device, 4^n complex128; may equal A only if n <= 6
+ *   stream [in]  hipStream_t or NULL                                     */
+tpd_status_t tpd_decompose(const void* A, int n, void* coeffs, tpd_stream_t stream);
+
+/* Same, with the dtype and flags (TPD_FLAG_NO_PRUNE, TPD_FLAG_LAYOUT_MATRIX,
+ * TPD_FLAG_ORDER_BOTTOM) chosen by the caller. */
+tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
+                              tpd_stream_t stream);
+
+/* Decompose `count` independent matrices of mixed sizes in one persistent
+ * kernel launch (the paper's motivation: many time steps of a
+ * time-dependent Hamiltonian, section "Introduction").
+ *   ptrs     [in] HOST array[count] of device pointers to the matrices
+ *   ns       [in] HOST array[count], 0 <= ns[i] <= 9
+ *   count    [in] >= 0 (0 is a no-op)
+ *   out_ptrs [in] HOST array[count] of device pointers to 4^ns[i]
+ *                 coefficients each, or NULL for in place (in place needs
+ *                 TPD_FLAG_LAYOUT_MATRIX when any ns[i] > 6)
+ * The pointer tables are copied to the device before the call returns.  */
+tpd_status_t tpd_decompose_batched(const void* const* ptrs, const int* ns, int count, void* const* out_ptrs,
+                                   tpd_dtype_t dtype, unsigned flags, tpd_stream_t stream);
+
+/* ---- plans: all allocation at creation, execution is graph-capturable ---- */
+typedef struct tpd_plan_s* tpd_plan_t;
+
+/* Plan for one n-qubit matrix (flags as tpd_decompose_ex plus
+ * TPD_FLAG_TIMING).  `in_place` selects the in-place schedule.           */
+tpd_status_t tpd_plan_create(int n, tpd_dtype_t dtype, unsigned flags, int in_place, tpd_plan_t* plan);
+
+/* Plan for a batch of matrices with qubit counts ns[0..count) (HOST array,
+ * copied).  The work table is sorted largest-first and uploaded now.     */
+tpd_status_t tpd_plan_create_batched(const int* ns, int count, tpd_dtype_t dtype, unsigned flags,
+                                     int in_place, tpd_plan_t* plan);
+
+/* Execute a single-matrix plan.  A / coeffs as in tpd_decompose_ex.
+ * Allocates nothing and synchronises nothing: safe inside hipGraph capture. */
+tpd_status_t tpd_plan_execute(tpd_plan_t plan, const void* A, void* coeffs, tpd_stream_t stream);
+
+/* Execute a batched plan.  d_ptrs / d_out_ptrs are DEVICE arrays[count] of
+ * device pointers (d_out_ptrs may be NULL for a plan created in place).
+ * Allocates nothing: safe inside hipGraph capture.                        */
+tpd_status_t tpd_plan_execute_batched(tpd_plan_t plan, const void* const* d_ptrs, void* const* d_out_ptrs,
+                                      tpd_stream_t stream);
+
+tpd_status_t tpd_plan_destroy(tpd_plan_t plan);
+
+/* Kernels per execution of the plan and their names (for profiling). */
+int tpd_plan_num_kernels(tpd_plan_t plan);
+
+/* With TPD_FLAG_TIMING: accumulated milliseconds and launch counts of each
+ * kernel of the plan since creation or the last reset.  Synchronises the
+ * recorded events (call after the stream is idle).  ms/counts: arrays of
+ * at least tpd_plan_num_kernels(plan) entries.                          */
+tpd_status_t tpd_plan_timing(tpd_plan_t plan, double* ms, uint64_t* counts, int reset);
+
+/* Zero-block statistics of the last execution of a single-matrix plan with
+ * pruning on: second-sweep tiles that were live, the total, and the number
+ * of live cumulative matrix weights after the first sweep (the paper's
+ * frontier |S^{n1+1}|, Fig. 1, Algorithm 2).  Synchronises `stream`.     */
+tpd_status_t tpd_plan_prune_stats(tpd_plan_t plan, uint64_t* live_tiles, uint64_t* total_tiles,
+                                  uint64_t* live_prefixes, int* prefix_level, tpd_stream_t stream);
+
+/* JSON text describing the plan (sweeps, tile shapes, layouts, bytes). */
+tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len);
+
+/* Release the per-(device, stream) workspaces held for tpd_decompose*. */
+tpd_status_t tpd_release_workspace(void);
+
+/* ---- host helpers (no device access) ---- */
+const char* tpd_status_string(tpd_status_t status);
+
+/* "XYZI..." (first letter = first tensor factor) -> canonical q; UINT64_MAX
+ * for an empty string, more than 32 letters or a letter outside IXYZ.    */
+uint64_t tpd_index_from_string(const char* s);
+
+/* canonical q -> n-letter string in buf (needs n+1 bytes); 0 on success. */
+int tpd_string_from_index(uint64_t q, int n, char* buf, size_t len);
+
+/* Describe the sweep schedule chosen for (n, dtype, flags, in_place) as
+ * JSON without touching a device (used by host-side tests).             */
+tpd_status_t tpd_schedule_describe(int n, tpd_dtype_t dtype, unsigned flags, int in_place, char* buf,
+                                   size_t len);
+
+/* Host replay of the exact device schedule (same tile maps, thread roles,
+ * LDS exchanges and arithmetic, executed sequentially on the CPU) for
+ * small n.  A debugging aid for the index algebra; the library never uses
+ * it to produce results.  A / coeffs are HOST pointers.                  */
+tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
+                               int in_place);
+
+/* Host replay of the batched schedule for one batch (HOST pointer arrays). */
+tpd_status_t tpd_debug_emulate_batched(const void* const* ptrs, const int* ns, int count, void* const* out_ptrs,
+                                       tpd_dtype_t dtype, unsigned flags);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPD_H_ */

@@ -1,0 +1,808 @@
+// tpd_api.cpp -- C ABI of libtpd: argument validation, sweep scheduling,
+// workspaces, plans (graph-capturable execution), timing, and a host replay
+// of the device schedule for CPU-side testing of the index algebra.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/tpd.h"
+#include "tpd_internal.h"
+
+using namespace tpd;
+
+namespace {
+
+constexpr int kMaxQubits = 16;
+constexpr int kMaxBatchQubits = 9;
+
+bool log_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("TPD_LOG");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+void logf(const char* fmt, ...) {
+  if (!log_on()) return;
+  va_list ap;
+  va_start(ap, fmt);
+  std::fprintf(stderr, "[tpd] ");
+  std::vfprintf(stderr, fmt, ap);
+  std::fprintf(stderr, "\n");
+  va_end(ap);
+}
+
+size_t elem_bytes(Dtype dt) { return dt == DT_C128 ? 16 : 8; }
+
+// ---------------------------------------------------------------------------
+// schedule
+// ---------------------------------------------------------------------------
+struct Schedule {
+  int n = 0;
+  Dtype dt = DT_C128;
+  bool matrix_layout = false;
+  bool in_place = false;
+  bool prune = false;
+  int nsweep = 0;
+  SweepDesc sw[2];
+  int n1 = 0, n2 = 0;
+  uint64_t bitmap_words = 0;
+};
+
+int single_db(int n) {
+  static const int t[9] = {0, 1, 2, 3, 4, 5, 6, 5, 4};
+  return t[n];
+}
+
+tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Schedule* s) {
+  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  *s = Schedule{};
+  s->n = n;
+  s->dt = dt;
+  s->matrix_layout = (flags & TPD_FLAG_LAYOUT_MATRIX) != 0;
+  s->in_place = in_place;
+  if (n == 0) return TPD_SUCCESS;
+  const int out_l = s->matrix_layout ? L_MAT : L_CAN;
+  if (n <= 8) {
+    if (in_place && !s->matrix_layout && n > 6) return TPD_ERROR_UNSUPPORTED;
+    s->nsweep = 1;
+    SweepDesc& w = s->sw[0];
+    w.xlo = 0;
+    w.xb = n;
+    w.db = single_db(n);
+    w.in_layout = L_MAT;
+    w.out_layout = out_l;
+    w.bitmap_mode = 0;
+    w.order = 0;
+    w.ntiles = (uint64_t)1 << (n - w.db);
+    return TPD_SUCCESS;
+  }
+  if (in_place && !s->matrix_layout) return TPD_ERROR_UNSUPPORTED;
+  s->nsweep = 2;
+  s->n1 = (n + 1) / 2;
+  s->n2 = n / 2;
+  const int db = (dt == DT_C64 && s->n2 >= 5) ? 5 : 4;
+  s->prune = (flags & TPD_FLAG_NO_PRUNE) == 0;
+  SweepDesc& a = s->sw[0];
+  a.xlo = s->n2;
+  a.xb = s->n1;
+  a.db = db;
+  a.in_layout = L_MAT;
+  a.out_layout = s->matrix_layout ? L_MAT : L_MID;
+  a.bitmap_mode = s->prune ? 1 : 0;
+  a.order = 0;
+  a.ntiles = ((uint64_t)1 << s->n2) << (n - db);
+  SweepDesc& b = s->sw[1];
+  b.xlo = 0;
+  b.xb = s->n2;
+  b.db = db;
+  b.in_layout = s->matrix_layout ? L_MAT : L_MID;
+  b.out_layout = out_l;
+  b.bitmap_mode = s->prune ? 2 : 0;
+  b.order = (flags & TPD_FLAG_ORDER_BOTTOM) ? 1 : 0;
+  b.ntiles = ((uint64_t)1 << s->n1) << (n - db);
+  const uint64_t bits = ((uint64_t)1 << s->n1) << (n - db);
+  s->bitmap_words = (bits + 31) / 32;
+  for (int i = 0; i < 2; ++i)
+    if (!sweep_supported(dt, s->sw[i])) return TPD_ERROR_INTERNAL;
+  return TPD_SUCCESS;
+}
+
+const char* layout_name(int l) { return l == L_MAT ? "MAT" : (l == L_CAN ? "CAN" : "MID"); }
+
+std::string describe(const Schedule& s) {
+  char buf[512];
+  const size_t eb = elem_bytes(s.dt);
+  const uint64_t count = (uint64_t)1 << (2 * s.n);
+  std::string j;
+  std::snprintf(buf, sizeof buf,
+                "{\"n\":%d,\"dtype\":\"%s\",\"layout\":\"%s\",\"in_place\":%s,\"prune\":%s,"
+                "\"elements\":%llu,\"algorithmic_bytes\":%llu,\"bitmap_words\":%llu,\"sweeps\":[",
+                s.n, s.dt == DT_C128 ? "c128" : "c64", s.matrix_layout ? "matrix" : "canonical",
+                s.in_place ? "true" : "false", s.prune ? "true" : "false", (unsigned long long)count,
+                (unsigned long long)(2 * count * eb), (unsigned long long)s.bitmap_words);
+  j += buf;
+  for (int i = 0; i < s.nsweep; ++i) {
+    const SweepDesc& w = s.sw[i];
+    const int B = w.xb + w.db;
+    const int R = B < 4 ? B : 4;
+    std::snprintf(buf, sizeof buf,
+                  "%s{\"xlo\":%d,\"xb\":%d,\"db\":%d,\"in\":\"%s\",\"out\":\"%s\",\"bitmap\":\"%s\","
+                  "\"order\":%d,\"tiles\":%llu,\"tile_elems\":%d,\"threads\":%d}",
+                  i ? "," : "", w.xlo, w.xb, w.db, layout_name(w.in_layout), layout_name(w.out_layout),
+                  w.bitmap_mode == 1 ? "set" : (w.bitmap_mode == 2 ? "check" : "none"), w.order,
+                  (unsigned long long)w.ntiles, 1 << B, 1 << (B - R));
+    j += buf;
+  }
+  j += "]}";
+  return j;
+}
+
+tpd_status_t copy_out(const std::string& s, char* buf, size_t len) {
+  if (!buf || len == 0) return TPD_ERROR_INVALID_VALUE;
+  if (s.size() + 1 > len) return TPD_ERROR_INVALID_VALUE;
+  std::memcpy(buf, s.c_str(), s.size() + 1);
+  return TPD_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------
+// validation helpers
+// ---------------------------------------------------------------------------
+tpd_status_t check_dtype_flags(int dtype, unsigned flags) {
+  if (dtype != TPD_C128 && dtype != TPD_C64) return TPD_ERROR_INVALID_VALUE;
+  if (flags & ~TPD_FLAGS_ALL) return TPD_ERROR_INVALID_VALUE;
+  return TPD_SUCCESS;
+}
+
+tpd_status_t check_buffers(const void* A, void* C, int n, Dtype dt) {
+  if (!A || !C) return TPD_ERROR_INVALID_VALUE;
+  const size_t eb = elem_bytes(dt);
+  if (((uintptr_t)A % eb) || ((uintptr_t)C % eb)) return TPD_ERROR_INVALID_VALUE;
+  if (A != C) {
+    const uint64_t bytes = ((uint64_t)1 << (2 * n)) * eb;
+    const uintptr_t a0 = (uintptr_t)A, c0 = (uintptr_t)C;
+    if (a0 < c0 + bytes && c0 < a0 + bytes) return TPD_ERROR_INVALID_VALUE;
+  }
+  return TPD_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------
+// device checks and workspaces
+// ---------------------------------------------------------------------------
+std::mutex g_mu;
+std::map<int, int> g_dev_ok;  // device -> 1 gfx950, 0 not
+
+tpd_status_t current_device(int* dev) {
+  int d = -1;
+  if (hipGetDevice(&d) != hipSuccess || d < 0) return TPD_ERROR_NO_DEVICE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_dev_ok.find(d);
+  if (it == g_dev_ok.end()) {
+    hipDeviceProp_t p;
+    int ok = 0;
+    if (hipGetDeviceProperties(&p, d) == hipSuccess) ok = std::strncmp(p.gcnArchName, "gfx950", 6) == 0;
+    it = g_dev_ok.emplace(d, ok).first;
+    logf("device %d arch ok=%d", d, ok);
+  }
+  if (!it->second) return TPD_ERROR_NO_DEVICE;
+  *dev = d;
+  return TPD_SUCCESS;
+}
+
+bool fail_alloc_hook() {
+  const char* e = std::getenv("TPD_TEST_FAIL_ALLOC");
+  return e && e[0] == '1';
+}
+
+tpd_status_t dev_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return TPD_SUCCESS;
+  if (fail_alloc_hook()) return TPD_ERROR_OUT_OF_MEMORY;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return TPD_ERROR_OUT_OF_MEMORY;
+  }
+  return TPD_SUCCESS;
+}
+
+struct Workspace {
+  uint32_t* bitmap = nullptr;
+  uint64_t bitmap_words = 0;
+  unsigned long long* counter = nullptr;
+  void* table = nullptr;  // batched tables (perm, items, pointer arrays)
+  size_t table_bytes = 0;
+  void* host_table = nullptr;  // pinned staging copy of the table
+  size_t host_bytes = 0;
+  hipEvent_t staged = nullptr;  // recorded after the last staging copy
+};
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+tpd_status_t ensure_bitmap(Workspace& w, uint64_t words) {
+  if (w.bitmap_words >= words) return TPD_SUCCESS;
+  if (w.bitmap) (void)hipFree(w.bitmap);
+  w.bitmap = nullptr;
+  w.bitmap_words = 0;
+  void* p;
+  tpd_status_t st = dev_alloc(&p, words * 4);
+  if (st) return st;
+  w.bitmap = (uint32_t*)p;
+  w.bitmap_words = words;
+  return TPD_SUCCESS;
+}
+
+// device table plus a pinned host staging buffer; the staging buffer is
+// only rewritten after the previous copy out of it has completed.
+tpd_status_t ensure_table(Workspace& w, size_t bytes) {
+  if (!w.staged && hipEventCreateWithFlags(&w.staged, hipEventDisableTiming) != hipSuccess) {
+    w.staged = nullptr;
+    return TPD_ERROR_OUT_OF_MEMORY;
+  }
+  if (w.host_table && hipEventSynchronize(w.staged) != hipSuccess) return TPD_ERROR_LAUNCH;
+  if (w.table_bytes < bytes) {
+    if (w.table) (void)hipFree(w.table);
+    w.table = nullptr;
+    w.table_bytes = 0;
+    tpd_status_t st = dev_alloc(&w.table, bytes);
+    if (st) return st;
+    w.table_bytes = bytes;
+  }
+  if (w.host_bytes < bytes) {
+    if (w.host_table) (void)hipHostFree(w.host_table);
+    w.host_table = nullptr;
+    w.host_bytes = 0;
+    if (fail_alloc_hook() || hipHostMalloc(&w.host_table, bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      w.host_table = nullptr;
+      return TPD_ERROR_OUT_OF_MEMORY;
+    }
+    w.host_bytes = bytes;
+  }
+  return TPD_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------
+// timing (plans with TPD_FLAG_TIMING)
+// ---------------------------------------------------------------------------
+constexpr int kMaxKernels = 3;
+constexpr int kEventPool = 256;
+struct Timing {
+  bool on = false;
+  int nk = 0;
+  std::vector<hipEvent_t> ev;  // [k][slot][2]
+  int used[kMaxKernels] = {0, 0, 0};
+  double ms[kMaxKernels] = {0, 0, 0};
+  uint64_t cnt[kMaxKernels] = {0, 0, 0};
+  hipEvent_t& at(int k, int slot, int which) { return ev[((size_t)k * kEventPool + slot) * 2 + which]; }
+  tpd_status_t create(int nkern) {
+    nk = nkern;
+    ev.assign((size_t)kMaxKernels * kEventPool * 2, nullptr);
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) return TPD_ERROR_OUT_OF_MEMORY;
+    on = true;
+    return TPD_SUCCESS;
+  }
+  void destroy() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    ev.clear();
+  }
+  void drain(int k) {
+    for (int s = 0; s < used[k]; ++s) {
+      float t = 0;
+      if (hipEventSynchronize(at(k, s, 1)) == hipSuccess && hipEventElapsedTime(&t, at(k, s, 0), at(k, s, 1)) == hipSuccess) {
+        ms[k] += t;
+        cnt[k] += 1;
+      }
+    }
+    used[k] = 0;
+  }
+  int begin(int k, hipStream_t st) {
+    if (!on) return -1;
+    if (used[k] == kEventPool) drain(k);
+    const int s = used[k]++;
+    (void)hipEventRecord(at(k, s, 0), st);
+    return s;
+  }
+  void end(int k, int s, hipStream_t st) {
+    if (s >= 0) (void)hipEventRecord(at(k, s, 1), st);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// single-matrix execution
+// ---------------------------------------------------------------------------
+tpd_status_t run_schedule(const Schedule& s, const void* A, void* C, uint32_t* bitmap, hipStream_t st,
+                          Timing* tm) {
+  const size_t eb = elem_bytes(s.dt);
+  if (s.n == 0) {
+    if (A != C && hipMemcpyAsync(C, A, eb, hipMemcpyDeviceToDevice, st) != hipSuccess) return TPD_ERROR_LAUNCH;
+    return TPD_SUCCESS;
+  }
+  if (s.prune && s.nsweep == 2) {
+    if (launch_fill_u32(bitmap, s.bitmap_words, 0u, st) != hipSuccess) return TPD_ERROR_LAUNCH;
+  }
+  for (int i = 0; i < s.nsweep; ++i) {
+    const SweepDesc& w = s.sw[i];
+    SweepArgs a{};
+    a.in = (i == 0) ? A : C;
+    a.out = C;
+    a.n = s.n;
+    a.xlo = w.xlo;
+    a.db = w.db;
+    a.nfix_d = s.n - w.db;
+    a.bitmap = bitmap;
+    a.bitmap_mode = w.bitmap_mode;
+    a.bm_xbits = s.n1;
+    a.ntiles = w.ntiles;
+    const int slot = tm ? tm->begin(i, st) : -1;
+    const hipError_t e = launch_sweep(s.dt, w, a, st);
+    if (tm) tm->end(i, slot, st);
+    if (e != hipSuccess) {
+      logf("sweep %d launch failed: %s", i, hipGetErrorString(e));
+      return TPD_ERROR_LAUNCH;
+    }
+  }
+  return TPD_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------
+// batched work tables
+// ---------------------------------------------------------------------------
+struct BatchTables {
+  std::vector<uint32_t> perm;  // position -> caller's matrix index
+  std::vector<BatchItem> items;
+};
+
+tpd_status_t build_batch(const int* ns, int count, bool in_place, unsigned flags, BatchTables* bt) {
+  const bool matrix_layout = (flags & TPD_FLAG_LAYOUT_MATRIX) != 0;
+  for (int i = 0; i < count; ++i) {
+    if (ns[i] < 0 || ns[i] > kMaxBatchQubits) return TPD_ERROR_UNSUPPORTED;
+    if (in_place && !matrix_layout && ns[i] > 6) return TPD_ERROR_UNSUPPORTED;
+  }
+  bt->perm.resize(count);
+  for (int i = 0; i < count; ++i) bt->perm[i] = (uint32_t)i;
+  // largest first, stable within a size
+  std::stable_sort(bt->perm.begin(), bt->perm.end(), [&](uint32_t a, uint32_t b) { return ns[a] > ns[b]; });
+  bt->items.clear();
+  int pos = 0;
+  while (pos < count) {
+    const int n = ns[bt->perm[pos]];
+    int end = pos;
+    while (end < count && ns[bt->perm[end]] == n) ++end;
+    const BatchGeom g = batch_geom(n);
+    if (g.mb > 0) {
+      const int per = 1 << g.mb;
+      for (int m = pos; m < end; m += per) {
+        BatchItem it{};
+        it.mat0 = (uint32_t)m;
+        it.n = (uint16_t)n;
+        it.nmat = (uint16_t)std::min(per, end - m);
+        it.tile = 0;
+        bt->items.push_back(it);
+      }
+    } else {
+      const uint32_t tiles = 1u << (n - g.db);
+      for (int m = pos; m < end; ++m)
+        for (uint32_t t = 0; t < tiles; ++t) {
+          BatchItem it{};
+          it.mat0 = (uint32_t)m;
+          it.n = (uint16_t)n;
+          it.nmat = 1;
+          it.tile = t;
+          bt->items.push_back(it);
+        }
+    }
+    pos = end;
+  }
+  return TPD_SUCCESS;
+}
+
+int batched_grid(Dtype dt, uint32_t nitems) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+  }
+  const int per_cu = dt == DT_C128 ? 2 : 4;  // LDS-limited residency of the 256-thread item loop
+  const int g = cus * per_cu;
+  return (uint32_t)g > nitems ? (int)nitems : g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+struct tpd_plan_s {
+  bool batched = false;
+  int device = 0;
+  Dtype dt = DT_C128;
+  unsigned flags = 0;
+  bool in_place = false;
+  Schedule sched;
+  uint32_t* bitmap = nullptr;
+  unsigned long long* counter = nullptr;
+  // batched
+  int count = 0;
+  uint32_t nitems = 0;
+  int grid = 0;
+  uint32_t* d_perm = nullptr;
+  BatchItem* d_items = nullptr;
+  Timing timing;
+};
+
+extern "C" {
+
+int tpd_max_qubits(tpd_dtype_t dtype) {
+  if (dtype != TPD_C128 && dtype != TPD_C64) return -1;
+  return kMaxQubits;
+}
+
+const char* tpd_status_string(tpd_status_t s) {
+  switch (s) {
+    case TPD_SUCCESS: return "TPD_SUCCESS";
+    case TPD_ERROR_INVALID_VALUE: return "TPD_ERROR_INVALID_VALUE";
+    case TPD_ERROR_UNSUPPORTED: return "TPD_ERROR_UNSUPPORTED";
+    case TPD_ERROR_OUT_OF_MEMORY: return "TPD_ERROR_OUT_OF_MEMORY";
+    case TPD_ERROR_LAUNCH: return "TPD_ERROR_LAUNCH";
+    case TPD_ERROR_INTERNAL: return "TPD_ERROR_INTERNAL";
+    case TPD_ERROR_NO_DEVICE: return "TPD_ERROR_NO_DEVICE";
+  }
+  return "TPD_ERROR_UNKNOWN";
+}
+
+uint64_t tpd_index_from_string(const char* s) {
+  if (!s || !s[0]) return UINT64_MAX;
+  uint64_t q = 0;
+  int len = 0;
+  for (const char* p = s; *p; ++p) {
+    int t;
+    switch (*p) {
+      case 'I': t = 0; break;
+      case 'X': t = 1; break;
+      case 'Y': t = 2; break;
+      case 'Z': t = 3; break;
+      default: return UINT64_MAX;
+    }
+    if (++len > 32) return UINT64_MAX;
+    q = q * 4 + (uint64_t)t;
+  }
+  return q;
+}
+
+int tpd_string_from_index(uint64_t q, int n, char* buf, size_t len) {
+  if (!buf || n < 0 || n > 32 || len < (size_t)n + 1) return 1;
+  if (n < 32 && (q >> (2 * n)) != 0) return 1;
+  for (int k = 1; k <= n; ++k) buf[k - 1] = "IXYZ"[(q >> (2 * (n - k))) & 3u];
+  buf[n] = 0;
+  return 0;
+}
+
+tpd_status_t tpd_schedule_describe(int n, tpd_dtype_t dtype, unsigned flags, int in_place, char* buf, size_t len) {
+  tpd_status_t st = check_dtype_flags(dtype, flags);
+  if (st) return st;
+  Schedule s;
+  st = make_schedule(n, (Dtype)dtype, flags, in_place != 0, &s);
+  if (st) return st;
+  return copy_out(describe(s), buf, len);
+}
+
+tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
+                              tpd_stream_t stream) {
+  tpd_status_t st = check_dtype_flags(dtype, flags);
+  if (st) return st;
+  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  const Dtype dt = (Dtype)dtype;
+  st = check_buffers(A, coeffs, n, dt);
+  if (st) return st;
+  Schedule s;
+  st = make_schedule(n, dt, flags, A == coeffs, &s);
+  if (st) return st;
+  int dev;
+  st = current_device(&dev);
+  if (st) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  uint32_t* bm = nullptr;
+  if (s.prune && s.nsweep == 2) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace& w = g_ws[{dev, hs}];
+    st = ensure_bitmap(w, s.bitmap_words);
+    if (st) return st;
+    bm = w.bitmap;
+  }
+  logf("decompose n=%d %s", n, describe(s).c_str());
+  return run_schedule(s, A, coeffs, bm, hs, nullptr);
+}
+
+tpd_status_t tpd_decompose(const void* A, int n, void* coeffs, tpd_stream_t stream) {
+  return tpd_decompose_ex(A, n, coeffs, TPD_C128, 0u, stream);
+}
+
+tpd_status_t tpd_release_workspace(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_ws) {
+    Workspace& w = kv.second;
+    if (w.staged) (void)hipEventSynchronize(w.staged);
+    if (w.bitmap) (void)hipFree(w.bitmap);
+    if (w.counter) (void)hipFree(w.counter);
+    if (w.table) (void)hipFree(w.table);
+    if (w.host_table) (void)hipHostFree(w.host_table);
+    if (w.staged) (void)hipEventDestroy(w.staged);
+  }
+  g_ws.clear();
+  return TPD_SUCCESS;
+}
+
+tpd_status_t tpd_plan_create(int n, tpd_dtype_t dtype, unsigned flags, int in_place, tpd_plan_t* plan) {
+  if (!plan) return TPD_ERROR_INVALID_VALUE;
+  *plan = nullptr;
+  tpd_status_t st = check_dtype_flags(dtype, flags);
+  if (st) return st;
+  Schedule s;
+  st = make_schedule(n, (Dtype)dtype, flags, in_place != 0, &s);
+  if (st) return st;
+  int dev;
+  st = current_device(&dev);
+  if (st) return st;
+  tpd_plan_s* p = new (std::nothrow) tpd_plan_s();
+  if (!p) return TPD_ERROR_OUT_OF_MEMORY;
+  p->device = dev;
+  p->dt = (Dtype)dtype;
+  p->flags = flags;
+  p->in_place = in_place != 0;
+  p->sched = s;
+  void* mem = nullptr;
+  st = dev_alloc(&mem, (size_t)s.bitmap_words * 4);
+  if (!st) {
+    p->bitmap = (uint32_t*)mem;
+    st = dev_alloc(&mem, sizeof(unsigned long long) * 2);
+    p->counter = (unsigned long long*)mem;
+  }
+  if (!st && (flags & TPD_FLAG_TIMING)) st = p->timing.create(kMaxKernels);
+  if (st) {
+    tpd_plan_destroy(p);
+    return st;
+  }
+  *plan = p;
+  return TPD_SUCCESS;
+}
+
+tpd_status_t tpd_plan_create_batched(const int* ns, int count, tpd_dtype_t dtype, unsigned flags, int in_place,
+                                     tpd_plan_t* plan) {
+  if (!plan) return TPD_ERROR_INVALID_VALUE;
+  *plan = nullptr;
+  tpd_status_t st = check_dtype_flags(dtype, flags);
+  if (st) return st;
+  if (count < 0 || (count > 0 && !ns)) return TPD_ERROR_INVALID_VALUE;
+  BatchTables bt;
+  st = build_batch(ns, count, in_place != 0, flags, &bt);
+  if (st) return st;
+  int dev;
+  st = current_device(&dev);
+  if (st) return st;
+  tpd_plan_s* p = new (std::nothrow) tpd_plan_s();
+  if (!p) return TPD_ERROR_OUT_OF_MEMORY;
+  p->batched = true;
+  p->device = dev;
+  p->dt = (Dtype)dtype;
+  p->flags = flags;
+  p->in_place = in_place != 0;
+  p->count = count;
+  p->nitems = (uint32_t)bt.items.size();
+  p->grid = batched_grid(p->dt, p->nitems);
+  void* mem = nullptr;
+  st = dev_alloc(&mem, sizeof(uint32_t) * (size_t)count);
+  if (!st) {
+    p->d_perm = (uint32_t*)mem;
+    st = dev_alloc(&mem, sizeof(BatchItem) * bt.items.size());
+    p->d_items = (BatchItem*)mem;
+  }
+  if (!st && count > 0 &&
+      hipMemcpy(p->d_perm, bt.perm.data(), sizeof(uint32_t) * (size_t)count, hipMemcpyHostToDevice) != hipSuccess)
+    st = TPD_ERROR_LAUNCH;
+  if (!st && !bt.items.empty() &&
+      hipMemcpy(p->d_items, bt.items.data(), sizeof(BatchItem) * bt.items.size(), hipMemcpyHostToDevice) !=
+          hipSuccess)
+    st = TPD_ERROR_LAUNCH;
+  if (!st && (flags & TPD_FLAG_TIMING)) st = p->timing.create(kMaxKernels);
+  if (st) {
+    tpd_plan_destroy(p);
+    return st;
+  }
+  *plan = p;
+  return TPD_SUCCESS;
+}
+
+tpd_status_t tpd_plan_execute(tpd_plan_t plan, const void* A, void* coeffs, tpd_stream_t stream) {
+  if (!plan || plan->batched) return TPD_ERROR_INVALID_VALUE;
+  tpd_status_t st = check_buffers(A, coeffs, plan->sched.n, plan->dt);
+  if (st) return st;
+  if ((A == coeffs) != plan->in_place) return TPD_ERROR_INVALID_VALUE;
+  return run_schedule(plan->sched, A, coeffs, plan->bitmap, (hipStream_t)stream,
+                      plan->timing.on ? &plan->timing : nullptr);
+}
+
+tpd_status_t tpd_plan_execute_batched(tpd_plan_t plan, const void* const* d_ptrs, void* const* d_out_ptrs,
+                                      tpd_stream_t stream) {
+  if (!plan || !plan->batched) return TPD_ERROR_INVALID_VALUE;
+  if (plan->count == 0) return TPD_SUCCESS;
+  if (!d_ptrs) return TPD_ERROR_INVALID_VALUE;
+  if (!d_out_ptrs && !plan->in_place) return TPD_ERROR_INVALID_VALUE;
+  hipStream_t hs = (hipStream_t)stream;
+  const int slot = plan->timing.on ? plan->timing.begin(0, hs) : -1;
+  const hipError_t e =
+      launch_batched_perm(plan->dt, d_ptrs, d_out_ptrs ? d_out_ptrs : (void* const*)d_ptrs, plan->d_perm,
+                          plan->d_items, plan->nitems,
+                          (plan->flags & TPD_FLAG_LAYOUT_MATRIX) ? L_MAT : L_CAN, plan->grid, hs);
+  if (plan->timing.on) plan->timing.end(0, slot, hs);
+  return e == hipSuccess ? TPD_SUCCESS : TPD_ERROR_LAUNCH;
+}
+
+tpd_status_t tpd_plan_destroy(tpd_plan_t plan) {
+  if (!plan) return TPD_ERROR_INVALID_VALUE;
+  if (plan->bitmap) (void)hipFree(plan->bitmap);
+  if (plan->counter) (void)hipFree(plan->counter);
+  if (plan->d_perm) (void)hipFree(plan->d_perm);
+  if (plan->d_items) (void)hipFree(plan->d_items);
+  plan->timing.destroy();
+  delete plan;
+  return TPD_SUCCESS;
+}
+
+int tpd_plan_num_kernels(tpd_plan_t plan) {
+  if (!plan) return -1;
+  return plan->batched ? 1 : plan->sched.nsweep;
+}
+
+tpd_status_t tpd_plan_timing(tpd_plan_t plan, double* ms, uint64_t* counts, int reset) {
+  if (!plan || !ms || !counts) return TPD_ERROR_INVALID_VALUE;
+  if (!plan->timing.on) return TPD_ERROR_UNSUPPORTED;
+  const int nk = tpd_plan_num_kernels(plan);
+  for (int k = 0; k < nk; ++k) {
+    plan->timing.drain(k);
+    ms[k] = plan->timing.ms[k];
+    counts[k] = plan->timing.cnt[k];
+    if (reset) {
+      plan->timing.ms[k] = 0;
+      plan->timing.cnt[k] = 0;
+    }
+  }
+  return TPD_SUCCESS;
+}
+
+tpd_status_t tpd_plan_prune_stats(tpd_plan_t plan, uint64_t* live_tiles, uint64_t* total_tiles,
+                                  uint64_t* live_prefixes, int* prefix_level, tpd_stream_t stream) {
+  if (!plan || plan->batched || !live_tiles || !total_tiles || !live_prefixes || !prefix_level)
+    return TPD_ERROR_INVALID_VALUE;
+  const Schedule& s = plan->sched;
+  if (!s.prune || s.nsweep != 2) return TPD_ERROR_UNSUPPORTED;
+  hipStream_t hs = (hipStream_t)stream;
+  if (hipMemsetAsync(plan->counter, 0, sizeof(unsigned long long), hs) != hipSuccess) return TPD_ERROR_LAUNCH;
+  if (launch_popcount(plan->bitmap, s.bitmap_words, plan->counter, hs) != hipSuccess) return TPD_ERROR_LAUNCH;
+  unsigned long long c = 0;
+  if (hipMemcpyAsync(&c, plan->counter, sizeof c, hipMemcpyDeviceToHost, hs) != hipSuccess) return TPD_ERROR_LAUNCH;
+  std::vector<uint32_t> words(s.bitmap_words);
+  if (hipMemcpyAsync(words.data(), plan->bitmap, 4 * s.bitmap_words, hipMemcpyDeviceToHost, hs) != hipSuccess)
+    return TPD_ERROR_LAUNCH;
+  if (hipStreamSynchronize(hs) != hipSuccess) return TPD_ERROR_LAUNCH;
+  *live_tiles = c;
+  *total_tiles = s.sw[1].ntiles;
+  // a level-n1 CMW is the set of tiles sharing x_hi and the top n1 d bits;
+  // bit index = (td << n1) | x_hi, td = d >> db
+  const int db = s.sw[0].db;
+  const int lowd = s.n2 - db;  // d bits [db, n2) vary inside one CMW
+  std::vector<uint8_t> live(((size_t)1 << (2 * s.n1)), 0);
+  const uint64_t nb = s.sw[1].ntiles;
+  for (uint64_t b = 0; b < nb; ++b) {
+    if (!((words[b >> 5] >> (b & 31)) & 1u)) continue;
+    const uint64_t xhi = b & (((uint64_t)1 << s.n1) - 1);
+    const uint64_t td = b >> s.n1;
+    const uint64_t dhi = td >> lowd;
+    live[(size_t)((xhi << s.n1) | dhi)] = 1;
+  }
+  uint64_t lp = 0;
+  for (uint8_t v : live) lp += v;
+  *live_prefixes = lp;
+  *prefix_level = s.n1;
+  return TPD_SUCCESS;
+}
+
+tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len) {
+  if (!plan) return TPD_ERROR_INVALID_VALUE;
+  if (!plan->batched) return copy_out(describe(plan->sched), buf, len);
+  char tmp[256];
+  std::snprintf(tmp, sizeof tmp, "{\"batched\":true,\"count\":%d,\"items\":%u,\"grid\":%d,\"dtype\":\"%s\"}",
+                plan->count, plan->nitems, plan->grid, plan->dt == DT_C128 ? "c128" : "c64");
+  return copy_out(tmp, buf, len);
+}
+
+tpd_status_t tpd_decompose_batched(const void* const* ptrs, const int* ns, int count, void* const* out_ptrs,
+                                   tpd_dtype_t dtype, unsigned flags, tpd_stream_t stream) {
+  tpd_status_t st = check_dtype_flags(dtype, flags);
+  if (st) return st;
+  if (count < 0) return TPD_ERROR_INVALID_VALUE;
+  if (count == 0) return TPD_SUCCESS;
+  if (!ptrs || !ns) return TPD_ERROR_INVALID_VALUE;
+  const Dtype dt = (Dtype)dtype;
+  const bool in_place = out_ptrs == nullptr;
+  BatchTables bt;
+  st = build_batch(ns, count, in_place, flags, &bt);
+  if (st) return st;
+  for (int i = 0; i < count; ++i) {
+    void* o = in_place ? (void*)ptrs[i] : out_ptrs[i];
+    st = check_buffers(ptrs[i], o, ns[i], dt);
+    if (st) return st;
+  }
+  int dev;
+  st = current_device(&dev);
+  if (st) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  // table: perm[count] | pad | items[nitems] | in ptrs[count] | out ptrs[count]
+  const size_t off_items = ((sizeof(uint32_t) * (size_t)count + 15) / 16) * 16;
+  const size_t off_in = off_items + sizeof(BatchItem) * bt.items.size();
+  const size_t off_out = off_in + sizeof(void*) * (size_t)count;
+  const size_t total = off_out + sizeof(void*) * (size_t)count;
+  unsigned char* dtab = nullptr;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Workspace& w = g_ws[{dev, hs}];
+  st = ensure_table(w, total);
+  if (st) return st;
+  dtab = (unsigned char*)w.table;
+  unsigned char* host = (unsigned char*)w.host_table;
+  std::memcpy(host, bt.perm.data(), sizeof(uint32_t) * (size_t)count);
+  std::memcpy(host + off_items, bt.items.data(), sizeof(BatchItem) * bt.items.size());
+  std::memcpy(host + off_in, ptrs, sizeof(void*) * (size_t)count);
+  std::memcpy(host + off_out, in_place ? (const void*)ptrs : (const void*)out_ptrs, sizeof(void*) * (size_t)count);
+  if (hipMemcpyAsync(dtab, host, total, hipMemcpyHostToDevice, hs) != hipSuccess) return TPD_ERROR_LAUNCH;
+  if (hipEventRecord(w.staged, hs) != hipSuccess) return TPD_ERROR_LAUNCH;
+  const hipError_t e =
+      launch_batched_perm(dt, (const void* const*)(dtab + off_in), (void* const*)(dtab + off_out),
+                          (const uint32_t*)dtab, (const BatchItem*)(dtab + off_items), (uint32_t)bt.items.size(),
+                          (flags & TPD_FLAG_LAYOUT_MATRIX) ? L_MAT : L_CAN, batched_grid(dt, (uint32_t)bt.items.size()),
+                          hs);
+  return e == hipSuccess ? TPD_SUCCESS : TPD_ERROR_LAUNCH;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// host-side schedule access for the emulator (tpd_emulate.cpp)
+// ---------------------------------------------------------------------------
+namespace tpd {
+tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep, int* n1,
+                           uint64_t* bitmap_words) {
+  tpd_status_t st = check_dtype_flags(dtype, flags);
+  if (st) return st;
+  Schedule s;
+  st = make_schedule(n, (Dtype)dtype, flags, in_place, &s);
+  if (st) return st;
+  for (int i = 0; i < s.nsweep; ++i) sw[i] = s.sw[i];
+  *nsweep = s.nsweep;
+  *n1 = s.n1;
+  *bitmap_words = s.bitmap_words;
+  return TPD_SUCCESS;
+}
+
+tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, std::vector<uint32_t>* perm,
+                               std::vector<BatchItem>* items) {
+  tpd_status_t st = check_dtype_flags(TPD_C128, flags);
+  if (st) return st;
+  BatchTables bt;
+  st = build_batch(ns, count, in_place, flags, &bt);
+  if (st) return st;
+  *perm = std::move(bt.perm);
+  *items = std::move(bt.items);
+  return TPD_SUCCESS;
+}
+}  // namespace tpd

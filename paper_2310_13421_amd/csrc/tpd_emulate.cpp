@@ -1,0 +1,361 @@
+// tpd_emulate.cpp -- sequential host replay of the device schedule.
+//
+// Executes, thread by thread and phase by phase, exactly what the kernels in
+// tpd_kernels.hip execute (same tile decode, thread roles, address maps,
+// LDS exchanges, butterflies and pruning-bitmap reduction), and checks on
+// the way that every address is in range, that every sweep reads and
+// writes each element exactly once, and that in-place tiles write only the
+// addresses they read.  It lets the CPU test-suite exercise the index
+// algebra before any GPU run.  The library never calls it to produce
+// results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "../../include/tpd.h"
+#include "tpd_internal.h"
+
+using namespace tpd;
+
+namespace {
+
+struct Checker {
+  uint64_t count;
+  std::vector<uint8_t> reads, writes;
+  bool ok = true;
+  explicit Checker(uint64_t c) : count(c), reads(c, 0), writes(c, 0) {}
+  void rd(uint64_t a) {
+    if (a >= count) { ok = false; return; }
+    if (reads[a]++) ok = false;
+  }
+  void wr(uint64_t a) {
+    if (a >= count) { ok = false; return; }
+    if (writes[a]++) ok = false;
+  }
+  bool complete() const {
+    for (uint64_t i = 0; i < count; ++i)
+      if (reads[i] != 1 || writes[i] != 1) return false;
+    return true;
+  }
+};
+
+template <class S, class G, int INL, int OUTL>
+tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint32_t* bitmap, Checker& ck) {
+  constexpr Roles RL = make_roles<G>();
+  constexpr int P = G::NPH;
+  constexpr int LAST = P - 1;
+  constexpr uint32_t DM = (1u << G::DB) - 1;
+  constexpr uint32_t XM = (1u << G::XB) - 1;
+  constexpr int NBW = (1 << G::XB) >= 32 ? (1 << G::XB) / 32 : 1;
+  const int n = a.n, xlo = a.xlo, db = a.db;
+  const uint64_t tdmask = ((uint64_t)1 << a.nfix_d) - 1;
+  const bool in_place = (const void*)in == (const void*)out;
+  std::vector<Cx<S>> v((size_t)G::NT * G::E), lds((size_t)1 << G::B);
+  std::vector<uint64_t> rset, wset;
+  uint32_t bits[NBW];
+
+  for (uint64_t tile = 0; tile < a.ntiles; ++tile) {
+    const uint64_t td = tile & tdmask;
+    const uint64_t xf = tile >> a.nfix_d;
+    const uint64_t xfix = (xf & (((uint64_t)1 << xlo) - 1)) | ((xf >> xlo) << (xlo + G::XB));
+    if (a.bitmap_mode == 2) {
+      const uint64_t bit = (td << a.bm_xbits) | xf;
+      if (!((bitmap[bit >> 5] >> (bit & 31)) & 1u)) {
+        // skipped tile: account its addresses as read and written in place
+        for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+          const uint32_t eb = elem_base<G>(RL, 0, tid);
+          for (int j = 0; j < G::E; ++j) {
+            const uint32_t e = eb | elem_reg<G>(RL, 0, j);
+            const uint64_t x = xfix | ((uint64_t)((e >> G::DB) & XM) << xlo);
+            const uint64_t d = (td << G::DB) | (e & DM);
+            const uint64_t ai = layout_addr<INL>(x, d, n, db);
+            const uint64_t ao = layout_addr<OUTL>(x, d, n, db);
+            ck.rd(ai);
+            ck.wr(ao);
+            if (ai < ck.count) {
+              const Cx<S> z = in[ai];
+              if (z.re != (S)0 || z.im != (S)0) return TPD_ERROR_INTERNAL;  // bit must have been set
+            }
+          }
+        }
+        continue;
+      }
+    }
+    for (int w = 0; w < NBW; ++w) bits[w] = 0;
+    rset.clear();
+    wset.clear();
+    for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+      const uint32_t eb0 = elem_base<G>(RL, 0, tid);
+      const uint64_t x = xfix | ((uint64_t)((eb0 >> G::DB) & XM) << xlo);
+      const uint64_t d = (td << G::DB) | (eb0 & DM);
+      const uint64_t base = layout_addr<INL>(x, d, n, db);
+      for (int j = 0; j < G::E; ++j) {
+        uint64_t ad = base;
+        for (int s = 0; s < G::R; ++s)
+          if ((j >> s) & 1) {
+            const uint32_t ei = 1u << RL.reg[0][s];
+            ad ^= layout_addr<INL>((uint64_t)((ei >> G::DB) & XM) << xlo, ei & DM, n, db);
+          }
+        // the delta form must agree with the direct map of the element
+        const uint32_t e = eb0 | elem_reg<G>(RL, 0, j);
+        const uint64_t xd = xfix | ((uint64_t)((e >> G::DB) & XM) << xlo);
+        const uint64_t dd = (td << G::DB) | (e & DM);
+        if (ad != layout_addr<INL>(xd, dd, n, db)) return TPD_ERROR_INTERNAL;
+        ck.rd(ad);
+        if (ad >= ck.count) return TPD_ERROR_INTERNAL;
+        rset.push_back(ad);
+        v[(size_t)tid * G::E + j] = in[ad];
+      }
+    }
+    for (int p = 0; p < P; ++p) {
+      for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+        const uint32_t ebp = elem_base<G>(RL, p, tid);
+        phase_butterflies<G, S>(RL, p, &v[(size_t)tid * G::E], (td << G::DB) | (ebp & DM), xlo);
+      }
+      if (p + 1 < P) {
+        std::vector<uint8_t> seen(lds.size(), 0);
+        for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+          const uint32_t ebp = elem_base<G>(RL, p, tid);
+          for (int j = 0; j < G::E; ++j) {
+            const uint32_t e = ebp | elem_reg<G>(RL, p, j);
+            if (seen[e]++) return TPD_ERROR_INTERNAL;  // two threads own one element
+            lds[e] = v[(size_t)tid * G::E + j];
+          }
+        }
+        for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+          const uint32_t ebn = elem_base<G>(RL, p + 1, tid);
+          for (int j = 0; j < G::E; ++j) v[(size_t)tid * G::E + j] = lds[ebn | elem_reg<G>(RL, p + 1, j)];
+        }
+      }
+    }
+    if (a.bitmap_mode == 1) {
+      // mirror the wave ballot: lanes [0, DB) are the diagonals of a row block
+      constexpr uint32_t gsz = 1u << G::DB;
+      constexpr uint64_t gmask = gsz >= 64 ? ~0ull : ((1ull << gsz) - 1);
+      for (uint32_t w0 = 0; w0 < (uint32_t)G::NT; w0 += 64) {
+        for (int j = 0; j < G::E; ++j) {
+          uint64_t m = 0;
+          for (uint32_t lane = 0; lane < 64 && w0 + lane < (uint32_t)G::NT; ++lane) {
+            const Cx<S>& z = v[(size_t)(w0 + lane) * G::E + j];
+            if (z.re != (S)0 || z.im != (S)0) m |= 1ull << lane;
+          }
+          for (uint32_t lane = 0; lane < 64 && w0 + lane < (uint32_t)G::NT; ++lane) {
+            if ((lane & (gsz - 1)) == 0 && ((m >> lane) & gmask)) {
+              const uint32_t ebl = elem_base<G>(RL, LAST, w0 + lane);
+              const uint32_t xl = ((ebl | elem_reg<G>(RL, LAST, j)) >> G::DB) & XM;
+              bits[xl >> 5] |= 1u << (xl & 31);
+            }
+          }
+        }
+      }
+      for (int t = 0; t < NBW; ++t)
+        if (bits[t]) {
+          const uint64_t b0 = (td << a.bm_xbits) + 32ull * t;
+          bitmap[b0 >> 5] |= bits[t] << (b0 & 31);
+        }
+    }
+    for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+      const uint32_t ebl = elem_base<G>(RL, LAST, tid);
+      const uint64_t x = xfix | ((uint64_t)((ebl >> G::DB) & XM) << xlo);
+      const uint64_t d = (td << G::DB) | (ebl & DM);
+      const uint64_t base = layout_addr<OUTL>(x, d, n, db);
+      for (int j = 0; j < G::E; ++j) {
+        uint64_t ad = base;
+        for (int s = 0; s < G::R; ++s)
+          if ((j >> s) & 1) {
+            const uint32_t eo = 1u << RL.reg[LAST][s];
+            ad ^= layout_addr<OUTL>((uint64_t)((eo >> G::DB) & XM) << xlo, eo & DM, n, db);
+          }
+        const uint32_t e = ebl | elem_reg<G>(RL, LAST, j);
+        const uint64_t xd = xfix | ((uint64_t)((e >> G::DB) & XM) << xlo);
+        const uint64_t dd = (td << G::DB) | (e & DM);
+        if (ad != layout_addr<OUTL>(xd, dd, n, db)) return TPD_ERROR_INTERNAL;
+        ck.wr(ad);
+        if (ad >= ck.count) return TPD_ERROR_INTERNAL;
+        wset.push_back(ad);
+        out[ad] = v[(size_t)tid * G::E + j];
+      }
+    }
+    if (in_place) {
+      std::sort(rset.begin(), rset.end());
+      std::sort(wset.begin(), wset.end());
+      if (rset != wset) return TPD_ERROR_INTERNAL;  // an in-place tile must be closed
+    }
+  }
+  return ck.ok ? TPD_SUCCESS : TPD_ERROR_INTERNAL;
+}
+
+template <class S, int XB, int DB, int ORDER>
+tpd_status_t emulate_layouts(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint32_t* bm,
+                             Checker& ck) {
+  constexpr int R = (XB + DB) < 4 ? (XB + DB) : 4;
+  using G = Geom<XB, DB, 0, R, ORDER>;
+  if (s.in_layout == L_MAT && s.out_layout == L_CAN) return emulate_sweep<S, G, L_MAT, L_CAN>(in, out, a, bm, ck);
+  if (s.in_layout == L_MAT && s.out_layout == L_MAT) return emulate_sweep<S, G, L_MAT, L_MAT>(in, out, a, bm, ck);
+  if (s.in_layout == L_MAT && s.out_layout == L_MID) return emulate_sweep<S, G, L_MAT, L_MID>(in, out, a, bm, ck);
+  if (s.in_layout == L_MID && s.out_layout == L_CAN) return emulate_sweep<S, G, L_MID, L_CAN>(in, out, a, bm, ck);
+  return TPD_ERROR_INTERNAL;
+}
+
+template <class S>
+tpd_status_t emulate_shape(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint32_t* bm,
+                           Checker& ck) {
+#define TPD_CASE(XB_, DB_)                                                                     \
+  if (s.xb == XB_ && s.db == DB_)                                                              \
+    return s.order == 0 ? emulate_layouts<S, XB_, DB_, 0>(s, in, out, a, bm, ck)               \
+                        : emulate_layouts<S, XB_, DB_, 1>(s, in, out, a, bm, ck);
+  TPD_SHAPES(TPD_CASE)
+#undef TPD_CASE
+  return TPD_ERROR_INTERNAL;
+}
+
+// ---- batched ----
+template <class S, class G, int OUTL>
+tpd_status_t emulate_item(const void* const* ptrs, void* const* outs, const uint32_t* perm, const BatchItem& it) {
+  constexpr Roles RL = make_roles<G>();
+  constexpr int P = G::NPH;
+  constexpr int LAST = P - 1;
+  constexpr uint32_t DM = (1u << G::DB) - 1;
+  constexpr uint32_t XM = (1u << G::XB) - 1;
+  const int n = it.n;
+  const uint64_t td = it.tile;
+  const uint64_t count = (uint64_t)1 << (2 * n);
+  std::vector<Cx<S>> v((size_t)G::NT * G::E), lds((size_t)1 << G::B);
+  for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+    const uint32_t e = elem_base<G>(RL, 0, tid);
+    const uint32_t ml = e >> (G::DB + G::XB);
+    for (int j = 0; j < G::E; ++j) {
+      Cx<S> z{(S)0, (S)0};
+      if (ml < it.nmat) {
+        const Cx<S>* in = (const Cx<S>*)ptrs[perm[it.mat0 + ml]];
+        const uint32_t ej = e | elem_reg<G>(RL, 0, j);
+        const uint64_t ad = layout_addr<L_MAT>((ej >> G::DB) & XM, (td << G::DB) | (ej & DM), n, G::DB);
+        if (ad >= count) return TPD_ERROR_INTERNAL;
+        z = in[ad];
+      }
+      v[(size_t)tid * G::E + j] = z;
+    }
+  }
+  for (int p = 0; p < P; ++p) {
+    for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+      const uint32_t ebp = elem_base<G>(RL, p, tid);
+      phase_butterflies<G, S>(RL, p, &v[(size_t)tid * G::E], (td << G::DB) | (ebp & DM), 0);
+    }
+    if (p + 1 < P) {
+      for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+        const uint32_t ebp = elem_base<G>(RL, p, tid);
+        for (int j = 0; j < G::E; ++j) lds[ebp | elem_reg<G>(RL, p, j)] = v[(size_t)tid * G::E + j];
+      }
+      for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+        const uint32_t ebn = elem_base<G>(RL, p + 1, tid);
+        for (int j = 0; j < G::E; ++j) v[(size_t)tid * G::E + j] = lds[ebn | elem_reg<G>(RL, p + 1, j)];
+      }
+    }
+  }
+  for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+    const uint32_t e = elem_base<G>(RL, LAST, tid);
+    const uint32_t ml = e >> (G::DB + G::XB);
+    if (ml >= it.nmat) continue;
+    Cx<S>* out = (Cx<S>*)outs[perm[it.mat0 + ml]];
+    for (int j = 0; j < G::E; ++j) {
+      const uint32_t ej = e | elem_reg<G>(RL, LAST, j);
+      const uint64_t ad = layout_addr<OUTL>((ej >> G::DB) & XM, (td << G::DB) | (ej & DM), n, G::DB);
+      if (ad >= count) return TPD_ERROR_INTERNAL;
+      out[ad] = v[(size_t)tid * G::E + j];
+    }
+  }
+  return TPD_SUCCESS;
+}
+
+template <class S, int OUTL>
+tpd_status_t emulate_item_n(const void* const* ptrs, void* const* outs, const uint32_t* perm, const BatchItem& it) {
+  switch (it.n) {
+    case 0: return emulate_item<S, Geom<0, 0, 8, 0, 0>, OUTL>(ptrs, outs, perm, it);
+    case 1: return emulate_item<S, Geom<1, 1, 8, 2, 0>, OUTL>(ptrs, outs, perm, it);
+    case 2: return emulate_item<S, Geom<2, 2, 8, 4, 0>, OUTL>(ptrs, outs, perm, it);
+    case 3: return emulate_item<S, Geom<3, 3, 6, 4, 0>, OUTL>(ptrs, outs, perm, it);
+    case 4: return emulate_item<S, Geom<4, 4, 4, 4, 0>, OUTL>(ptrs, outs, perm, it);
+    case 5: return emulate_item<S, Geom<5, 5, 2, 4, 0>, OUTL>(ptrs, outs, perm, it);
+    case 6: return emulate_item<S, Geom<6, 6, 0, 4, 0>, OUTL>(ptrs, outs, perm, it);
+    case 7: return emulate_item<S, Geom<7, 5, 0, 4, 0>, OUTL>(ptrs, outs, perm, it);
+    case 8: return emulate_item<S, Geom<8, 4, 0, 4, 0>, OUTL>(ptrs, outs, perm, it);
+    case 9: return emulate_item<S, Geom<9, 3, 0, 4, 0>, OUTL>(ptrs, outs, perm, it);
+  }
+  return TPD_ERROR_INTERNAL;
+}
+
+}  // namespace
+
+namespace tpd {
+// defined in tpd_api.cpp
+tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep, int* n1,
+                           uint64_t* bitmap_words);
+tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, std::vector<uint32_t>* perm,
+                               std::vector<BatchItem>* items);
+}  // namespace tpd
+
+extern "C" tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
+                                          int in_place) {
+  if (!A || !coeffs) return TPD_ERROR_INVALID_VALUE;
+  if (n < 0 || n > 12) return TPD_ERROR_UNSUPPORTED;  // host replay is for small n
+  if (in_place && A != coeffs) return TPD_ERROR_INVALID_VALUE;
+  SweepDesc sw[2];
+  int nsweep = 0, n1 = 0;
+  uint64_t words = 0;
+  tpd_status_t st = host_schedule(n, dtype, flags, in_place != 0, sw, &nsweep, &n1, &words);
+  if (st) return st;
+  const uint64_t count = (uint64_t)1 << (2 * n);
+  const size_t eb = dtype == TPD_C128 ? 16 : 8;
+  if (n == 0) {
+    if (A != coeffs) std::memcpy(coeffs, A, eb);
+    return TPD_SUCCESS;
+  }
+  std::vector<uint32_t> bitmap(words ? words : 1, 0u);
+  for (int i = 0; i < nsweep; ++i) {
+    SweepArgs a{};
+    a.in = i == 0 ? A : coeffs;
+    a.out = coeffs;
+    a.n = n;
+    a.xlo = sw[i].xlo;
+    a.db = sw[i].db;
+    a.nfix_d = n - sw[i].db;
+    a.bitmap = bitmap.data();
+    a.bitmap_mode = sw[i].bitmap_mode;
+    a.bm_xbits = n1;
+    a.ntiles = sw[i].ntiles;
+    Checker ck(count);
+    if (dtype == TPD_C128)
+      st = emulate_shape<double>(sw[i], (const Cx<double>*)a.in, (Cx<double>*)a.out, a, bitmap.data(), ck);
+    else
+      st = emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, bitmap.data(), ck);
+    if (st) return st;
+    if (!ck.complete()) return TPD_ERROR_INTERNAL;
+  }
+  return TPD_SUCCESS;
+}
+
+extern "C" tpd_status_t tpd_debug_emulate_batched(const void* const* ptrs, const int* ns, int count,
+                                                  void* const* out_ptrs, tpd_dtype_t dtype, unsigned flags) {
+  if (count < 0) return TPD_ERROR_INVALID_VALUE;
+  if (count == 0) return TPD_SUCCESS;
+  if (!ptrs || !ns) return TPD_ERROR_INVALID_VALUE;
+  if (dtype != TPD_C128 && dtype != TPD_C64) return TPD_ERROR_INVALID_VALUE;
+  std::vector<uint32_t> perm;
+  std::vector<BatchItem> items;
+  tpd_status_t st = host_batch_tables(ns, count, out_ptrs == nullptr, flags, &perm, &items);
+  if (st) return st;
+  void* const* outs = out_ptrs ? out_ptrs : (void* const*)ptrs;
+  const bool mat = (flags & TPD_FLAG_LAYOUT_MATRIX) != 0;
+  for (const BatchItem& it : items) {
+    if (dtype == TPD_C128)
+      st = mat ? emulate_item_n<double, L_MAT>(ptrs, outs, perm.data(), it)
+               : emulate_item_n<double, L_CAN>(ptrs, outs, perm.data(), it);
+    else
+      st = mat ? emulate_item_n<float, L_MAT>(ptrs, outs, perm.data(), it)
+               : emulate_item_n<float, L_CAN>(ptrs, outs, perm.data(), it);
+    if (st) return st;
+  }
+  return TPD_SUCCESS;
+}

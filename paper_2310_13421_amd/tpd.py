@@ -1,0 +1,315 @@
+"""ctypes binding of libtpd (the C ABI in include/tpd.h).
+
+Argument marshalling only: every step of the decomposition runs in the HIP
+kernels of libtpd.so.  PyTorch supplies device memory and the current HIP
+stream.  If the library is missing the import fails loudly; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpd.so")
+
+TPD_C128 = 0
+TPD_C64 = 1
+FLAG_NO_PRUNE = 0x1
+FLAG_LAYOUT_MATRIX = 0x2
+FLAG_TIMING = 0x4
+FLAG_ORDER_BOTTOM = 0x8
+
+STATUS = {
+    0: "TPD_SUCCESS",
+    1: "TPD_ERROR_INVALID_VALUE",
+    2: "TPD_ERROR_UNSUPPORTED",
+    3: "TPD_ERROR_OUT_OF_MEMORY",
+    4: "TPD_ERROR_LAUNCH",
+    5: "TPD_ERROR_INTERNAL",
+    6: "TPD_ERROR_NO_DEVICE",
+}
+
+# every symbol include/tpd.h declares, with (restype, argtypes)
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_U = ctypes.c_uint
+_U64 = ctypes.c_uint64
+_SZ = ctypes.c_size_t
+_SIGS = {
+    "tpd_max_qubits": (_I, [_I]),
+    "tpd_decompose": (_I, [_P, _I, _P, _P]),
+    "tpd_decompose_ex": (_I, [_P, _I, _P, _I, _U, _P]),
+    "tpd_decompose_batched": (_I, [_P, _P, _I, _P, _I, _U, _P]),
+    "tpd_plan_create": (_I, [_I, _I, _U, _I, _P]),
+    "tpd_plan_create_batched": (_I, [_P, _I, _I, _U, _I, _P]),
+    "tpd_plan_execute": (_I, [_P, _P, _P, _P]),
+    "tpd_plan_execute_batched": (_I, [_P, _P, _P, _P]),
+    "tpd_plan_destroy": (_I, [_P]),
+    "tpd_plan_num_kernels": (_I, [_P]),
+    "tpd_plan_timing": (_I, [_P, _P, _P, _I]),
+    "tpd_plan_prune_stats": (_I, [_P, _P, _P, _P, _P, _P]),
+    "tpd_plan_describe": (_I, [_P, ctypes.c_char_p, _SZ]),
+    "tpd_release_workspace": (_I, []),
+    "tpd_status_string": (ctypes.c_char_p, [_I]),
+    "tpd_index_from_string": (_U64, [ctypes.c_char_p]),
+    "tpd_string_from_index": (_I, [_U64, _I, ctypes.c_char_p, _SZ]),
+    "tpd_schedule_describe": (_I, [_I, _I, _U, _I, ctypes.c_char_p, _SZ]),
+    "tpd_debug_emulate": (_I, [_P, _I, _P, _I, _U, _I]),
+    "tpd_debug_emulate_batched": (_I, [_P, _P, _I, _P, _I, _U]),
+}
+
+
+class TPDError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libtpd.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise TPDError(code, what)
+
+
+# ----------------------------------------------------------------------------
+# host helpers
+# ----------------------------------------------------------------------------
+def index_from_string(s: str) -> int:
+    return int(lib.tpd_index_from_string(s.encode()))
+
+
+def string_from_index(q: int, n: int) -> str:
+    buf = ctypes.create_string_buffer(n + 1)
+    _check(lib.tpd_string_from_index(q, n, buf, n + 1), "tpd_string_from_index")
+    return buf.value.decode()
+
+
+def max_qubits(dtype: int = TPD_C128) -> int:
+    return int(lib.tpd_max_qubits(dtype))
+
+
+def schedule(n: int, dtype: int = TPD_C128, flags: int = 0, in_place: bool = False) -> dict:
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib.tpd_schedule_describe(n, dtype, flags, int(in_place), buf, 4096), "tpd_schedule_describe")
+    return json.loads(buf.value.decode())
+
+
+def _np_dtype(dtype: int):
+    return np.complex128 if dtype == TPD_C128 else np.complex64
+
+
+def emulate(A: np.ndarray, dtype: int = TPD_C128, flags: int = 0, in_place: bool = False) -> np.ndarray:
+    """Host replay of the device schedule (debugging aid for small n)."""
+    A = np.ascontiguousarray(A, dtype=_np_dtype(dtype))
+    n = A.shape[0].bit_length() - 1
+    if in_place:
+        out = A.copy().reshape(-1)
+        _check(lib.tpd_debug_emulate(out.ctypes.data, n, out.ctypes.data, dtype, flags, 1), "tpd_debug_emulate")
+        return out
+    out = np.empty(A.size, _np_dtype(dtype))
+    _check(lib.tpd_debug_emulate(A.ctypes.data, n, out.ctypes.data, dtype, flags, 0), "tpd_debug_emulate")
+    return out
+
+
+def emulate_batched(mats: Sequence[np.ndarray], dtype: int = TPD_C128, flags: int = 0,
+                    in_place: bool = False) -> List[np.ndarray]:
+    mats = [np.ascontiguousarray(m, dtype=_np_dtype(dtype)) for m in mats]
+    ns = (ctypes.c_int * len(mats))(*[m.shape[0].bit_length() - 1 for m in mats])
+    ins = (ctypes.c_void_p * len(mats))(*[m.ctypes.data for m in mats])
+    if in_place:
+        outs_np = [m.copy().reshape(-1) for m in mats]
+        ins = (ctypes.c_void_p * len(mats))(*[o.ctypes.data for o in outs_np])
+        _check(lib.tpd_debug_emulate_batched(ins, ns, len(mats), None, dtype, flags), "emulate_batched")
+        return outs_np
+    outs_np = [np.empty(m.size, _np_dtype(dtype)) for m in mats]
+    outs = (ctypes.c_void_p * len(mats))(*[o.ctypes.data for o in outs_np])
+    _check(lib.tpd_debug_emulate_batched(ins, ns, len(mats), outs, dtype, flags), "emulate_batched")
+    return outs_np
+
+
+# ----------------------------------------------------------------------------
+# device entry points (torch tensors)
+# ----------------------------------------------------------------------------
+def _torch():
+    import torch
+
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return TPD_C128
+    if t.dtype == torch.complex64:
+        return TPD_C64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _flags(layout: str, prune: bool, order_bottom: bool = False) -> int:
+    f = 0
+    if layout == "matrix":
+        f |= FLAG_LAYOUT_MATRIX
+    elif layout != "canonical":
+        raise ValueError("layout must be 'canonical' or 'matrix'")
+    if not prune:
+        f |= FLAG_NO_PRUNE
+    if order_bottom:
+        f |= FLAG_ORDER_BOTTOM
+    return f
+
+
+def _check_matrix(A):
+    if not A.is_cuda or not A.is_contiguous() or A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be a contiguous square CUDA tensor")
+    d = A.shape[0]
+    n = d.bit_length() - 1
+    if (1 << n) != d:
+        raise ValueError("dimension must be a power of two")
+    return n
+
+
+def decompose(A, out=None, *, layout: str = "canonical", prune: bool = True, order_bottom: bool = False,
+              stream=None):
+    """Pauli coefficients of A (2^n x 2^n complex64/complex128 CUDA tensor).
+
+    Returns a 1-D tensor of 4^n coefficients (canonical order: index
+    q = sum_k t_k 4^(n-k)), or the 2^n x 2^n matrix-layout array.  `out` may
+    be A itself for an in-place call (see include/tpd.h)."""
+    torch = _torch()
+    n = _check_matrix(A)
+    dt = _dtype_code(A)
+    if out is None:
+        out = torch.empty(4 ** n, dtype=A.dtype, device=A.device)
+    if out.dtype != A.dtype or not out.is_cuda or not out.is_contiguous() or out.numel() != 4 ** n:
+        raise ValueError("out must be a contiguous CUDA tensor of 4^n elements of A's dtype")
+    _check(lib.tpd_decompose_ex(A.data_ptr(), n, out.data_ptr(), dt, _flags(layout, prune, order_bottom),
+                                _stream(stream)), "tpd_decompose_ex")
+    return out
+
+
+def decompose_batched(mats, outs=None, *, layout: str = "canonical", stream=None):
+    """Decompose a list of square matrices of mixed sizes in one launch.
+    outs=None allocates outputs; outs='inplace' overwrites the inputs."""
+    torch = _torch()
+    if len(mats) == 0:
+        return []
+    dt = _dtype_code(mats[0])
+    ns = [_check_matrix(m) for m in mats]
+    for m in mats:
+        if m.dtype != mats[0].dtype:
+            raise ValueError("all matrices must share one dtype")
+    in_place = isinstance(outs, str) and outs == "inplace"
+    if outs is None:
+        outs = [torch.empty(4 ** n, dtype=mats[0].dtype, device=mats[0].device) for n in ns]
+    cnt = len(mats)
+    c_ns = (ctypes.c_int * cnt)(*ns)
+    c_in = (ctypes.c_void_p * cnt)(*[m.data_ptr() for m in mats])
+    c_out = None if in_place else (ctypes.c_void_p * cnt)(*[o.data_ptr() for o in outs])
+    _check(lib.tpd_decompose_batched(c_in, c_ns, cnt, c_out, dt, _flags(layout, True), _stream(stream)),
+           "tpd_decompose_batched")
+    return mats if in_place else outs
+
+
+class Plan:
+    """Single-matrix plan: all allocation at creation; execute() is
+    graph-capturable.  timing=True records HIP events around each kernel."""
+
+    def __init__(self, n: int, dtype: int = TPD_C128, *, layout: str = "canonical", prune: bool = True,
+                 in_place: bool = False, timing: bool = False, order_bottom: bool = False):
+        self.n = n
+        self.dtype = dtype
+        self.in_place = in_place
+        f = _flags(layout, prune, order_bottom) | (FLAG_TIMING if timing else 0)
+        h = ctypes.c_void_p()
+        _check(lib.tpd_plan_create(n, dtype, f, int(in_place), ctypes.byref(h)), "tpd_plan_create")
+        self._h = h
+
+    def execute(self, A, out, stream=None):
+        _check(lib.tpd_plan_execute(self._h, A.data_ptr(), out.data_ptr(), _stream(stream)), "tpd_plan_execute")
+        return out
+
+    def num_kernels(self) -> int:
+        return int(lib.tpd_plan_num_kernels(self._h))
+
+    def timing(self, reset: bool = False):
+        k = self.num_kernels()
+        ms = (ctypes.c_double * k)()
+        cnt = (ctypes.c_uint64 * k)()
+        _check(lib.tpd_plan_timing(self._h, ms, cnt, int(reset)), "tpd_plan_timing")
+        return [float(v) for v in ms], [int(v) for v in cnt]
+
+    def prune_stats(self, stream=None) -> dict:
+        lt, tt, lp = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        lvl = ctypes.c_int()
+        _check(lib.tpd_plan_prune_stats(self._h, ctypes.byref(lt), ctypes.byref(tt), ctypes.byref(lp),
+                                        ctypes.byref(lvl), _stream(stream)), "tpd_plan_prune_stats")
+        return {"live_tiles": lt.value, "total_tiles": tt.value, "live_prefixes": lp.value,
+                "prefix_level": lvl.value}
+
+    def describe(self) -> dict:
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib.tpd_plan_describe(self._h, buf, 4096), "tpd_plan_describe")
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.tpd_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchedPlan(Plan):
+    """Batched plan over fixed qubit counts; execute() takes device arrays of
+    device pointers (int64 CUDA tensors), graph-capturable."""
+
+    def __init__(self, ns: Sequence[int], dtype: int = TPD_C128, *, layout: str = "canonical",
+                 in_place: bool = False, timing: bool = False):
+        self.ns = list(ns)
+        self.dtype = dtype
+        self.in_place = in_place
+        f = _flags(layout, True) | (FLAG_TIMING if timing else 0)
+        c_ns = (ctypes.c_int * max(1, len(self.ns)))(*self.ns)
+        h = ctypes.c_void_p()
+        _check(lib.tpd_plan_create_batched(c_ns, len(self.ns), dtype, f, int(in_place), ctypes.byref(h)),
+               "tpd_plan_create_batched")
+        self._h = h
+
+    @staticmethod
+    def pointer_table(tensors, device=None):
+        torch = _torch()
+        dev = device or tensors[0].device
+        return torch.tensor([t.data_ptr() for t in tensors], dtype=torch.int64, device=dev)
+
+    def execute(self, d_ptrs, d_out_ptrs=None, stream=None):
+        _check(lib.tpd_plan_execute_batched(self._h, d_ptrs.data_ptr(),
+                                            None if d_out_ptrs is None else d_out_ptrs.data_ptr(),
+                                            _stream(stream)), "tpd_plan_execute_batched")

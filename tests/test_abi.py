@@ -1,0 +1,135 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/tpd.h declares, validates arguments before touching a
+device, and its host helpers and schedule planner behave as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tpd.h")
+
+tpd = pytest.importorskip("paper_2310_13421_amd.tpd")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tpd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(tpd.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding declares a signature for each of them
+    assert set(names) == set(tpd._SIGS)
+
+
+def test_status_strings_and_limits():
+    for code, name in tpd.STATUS.items():
+        assert tpd.lib.tpd_status_string(code).decode() == name
+    assert tpd.max_qubits(tpd.TPD_C128) == 16
+    assert tpd.max_qubits(tpd.TPD_C64) == 16
+    assert tpd.lib.tpd_max_qubits(7) == -1
+
+
+def test_index_helpers():
+    assert tpd.index_from_string("XZ") == 7
+    assert tpd.index_from_string("ZX") == 13
+    assert tpd.index_from_string("YX") == 9
+    assert tpd.index_from_string("I" * 16) == 0
+    assert tpd.index_from_string("Z" * 16) == 4 ** 16 - 1
+    u64max = 2 ** 64 - 1
+    assert tpd.index_from_string("") == u64max
+    assert tpd.index_from_string("XQ") == u64max
+    assert tpd.index_from_string("X" * 33) == u64max
+    for q, n in ((0, 1), (7, 2), (9, 2), (4 ** 16 - 1, 16), (123456789, 16)):
+        s = tpd.string_from_index(q, n)
+        assert len(s) == n and tpd.index_from_string(s) == q
+    buf = ctypes.create_string_buffer(3)
+    assert tpd.lib.tpd_string_from_index(16, 2, buf, 3) != 0  # q >= 4^n
+    assert tpd.lib.tpd_string_from_index(1, 4, buf, 3) != 0   # buffer too small
+
+
+FAKE = 0x100000  # never dereferenced: validation fails or the device check stops first
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, 4, FAKE, 0, 0), 1),            # NULL A
+    ((FAKE, 4, None, 0, 0), 1),            # NULL coeffs
+    ((FAKE + 8, 4, FAKE * 4, 0, 0), 1),    # misaligned complex128
+    ((FAKE, 4, FAKE * 4 + 4, 1, 0), 1),    # misaligned complex64
+    ((FAKE, 4, FAKE + 16, 0, 0), 1),       # partial overlap
+    ((FAKE, 17, FAKE * 64, 0, 0), 2),      # n too large
+    ((FAKE, -1, FAKE * 4, 0, 0), 2),       # n negative
+    ((FAKE, 4, FAKE * 4, 5, 0), 1),        # bad dtype
+    ((FAKE, 4, FAKE * 4, 0, 0x100), 1),    # unknown flag
+    ((FAKE, 8, FAKE, 0, 0), 2),            # in place, canonical, n > 6
+    ((FAKE, 10, FAKE, 0, 0), 2),           # in place, canonical, two sweeps
+])
+def test_decompose_validation_before_device(args, code):
+    A, n, C, dt, fl = args
+    assert tpd.lib.tpd_decompose_ex(A, n, C, dt, fl, None) == code
+
+
+def test_batched_validation():
+    ns = (ctypes.c_int * 2)(3, 10)
+    ptrs = (ctypes.c_void_p * 2)(FAKE, FAKE * 2)
+    outs = (ctypes.c_void_p * 2)(FAKE * 4, FAKE * 8)
+    assert tpd.lib.tpd_decompose_batched(ptrs, ns, 2, outs, 0, 0, None) == 2   # n > 9
+    ns2 = (ctypes.c_int * 2)(3, 8)
+    assert tpd.lib.tpd_decompose_batched(ptrs, ns2, 2, None, 0, 0, None) == 2  # in place canonical n = 8
+    assert tpd.lib.tpd_decompose_batched(ptrs, ns2, -1, outs, 0, 0, None) == 1
+    assert tpd.lib.tpd_decompose_batched(None, ns2, 2, outs, 0, 0, None) == 1
+    assert tpd.lib.tpd_decompose_batched(ptrs, ns2, 0, outs, 0, 0, None) == 0  # empty batch is a no-op
+    assert tpd.lib.tpd_decompose_batched(ptrs, ns2, 2, outs, 3, 0, None) == 1
+
+
+def test_plan_validation():
+    h = ctypes.c_void_p()
+    assert tpd.lib.tpd_plan_create(17, 0, 0, 0, ctypes.byref(h)) == 2
+    assert tpd.lib.tpd_plan_create(4, 9, 0, 0, ctypes.byref(h)) == 1
+    assert tpd.lib.tpd_plan_create(4, 0, 0, 0, None) == 1
+    assert tpd.lib.tpd_plan_execute(None, FAKE, FAKE * 4, None) == 1
+    assert tpd.lib.tpd_plan_destroy(None) == 1
+    assert tpd.lib.tpd_plan_num_kernels(None) == -1
+
+
+@pytest.mark.parametrize("n", range(0, 17))
+def test_schedule_shapes(n):
+    for dt in (tpd.TPD_C128, tpd.TPD_C64):
+        s = tpd.schedule(n, dt)
+        es = 16 if dt == tpd.TPD_C128 else 8
+        assert s["elements"] == 4 ** n
+        assert s["algorithmic_bytes"] == 2 * 4 ** n * es
+        if n == 0:
+            assert s["sweeps"] == []
+            continue
+        sw = s["sweeps"]
+        assert len(sw) == (1 if n <= 8 else 2)
+        # the sweeps transform every x bit exactly once
+        bits = sorted(b for w in sw for b in range(w["xlo"], w["xlo"] + w["xb"]))
+        assert bits == list(range(n))
+        for w in sw:
+            assert w["tiles"] * w["tile_elems"] == 4 ** n
+            assert w["tile_elems"] * es <= 65536  # one workgroup's LDS
+            assert w["threads"] <= 1024
+        if n >= 9:
+            assert sw[0]["bitmap"] == "set" and sw[1]["bitmap"] == "check"
+            assert sw[0]["out"] == "MID" and sw[1]["in"] == "MID" and sw[1]["out"] == "CAN"
+            # coalescing: every run of the first sweep's reads is 2^db elements >= 128 B
+            assert (1 << sw[0]["db"]) * es >= 128
+
+
+def test_schedule_flags():
+    s = tpd.schedule(12, tpd.TPD_C128, tpd.FLAG_LAYOUT_MATRIX, in_place=True)
+    assert s["in_place"] and s["layout"] == "matrix"
+    assert all(w["in"] == "MAT" and w["out"] == "MAT" for w in s["sweeps"])
+    s = tpd.schedule(12, tpd.TPD_C128, tpd.FLAG_NO_PRUNE)
+    assert not s["prune"] and all(w["bitmap"] == "none" for w in s["sweeps"])
+    with pytest.raises(tpd.TPDError):
+        tpd.schedule(12, tpd.TPD_C128, 0, in_place=True)

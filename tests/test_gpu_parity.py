@@ -1,0 +1,449 @@
+"""GPU parity tests: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: complex128 results are compared element by element with the oracle on
+the same seeded inputs -- bitwise where the schedule performs the oracle's
+operations in the paper's level order, else within n u max|a_ij|
+(u = 2^-53), itself far inside the required 1e-12 max|a_ij|; complex64
+within (n + 1) 2^-24 max|a_ij| (<= 2e-6 max|a_ij|); integer inputs bit-exact
+in both precisions.  Sizes span many tiles; full-size configurations are
+checked on sampled strings against the definition, plus Parseval and
+exact invariants.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+tpd = pytest.importorskip("paper_2310_13421_amd.tpd")
+
+DEV = "cuda"
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu_required():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU (run with -m 'not gpu' on CPU-only machines)")
+    yield
+    torch.cuda.synchronize()
+    tpd.lib.tpd_release_workspace()
+
+
+def amax(A):
+    A = np.asarray(A)
+    return float(np.max(np.abs(np.concatenate([A.real.ravel(), A.imag.ravel()]))))
+
+
+def cerr(a, b):
+    d = np.asarray(a, np.complex128) - np.asarray(b, np.complex128)
+    return float(np.max(np.abs(np.concatenate([d.real.ravel(), d.imag.ravel()])))) if d.size else 0.0
+
+
+def same_bits(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.array_equal(a.real, b.real) and np.array_equal(a.imag, b.imag)
+
+
+def to_dev(A, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(A)).to(DEV).to(dtype).contiguous()
+
+
+def spread(v):
+    r = np.zeros_like(v)
+    for b in range(20):
+        r |= ((v >> b) & 1) << (2 * b)
+    return r
+
+
+def deinterleave(q):
+    q = np.asarray(q, np.int64)
+    h = np.zeros_like(q)
+    l = np.zeros_like(q)
+    for b in range(20):
+        l |= ((q >> (2 * b)) & 1) << b
+        h |= ((q >> (2 * b + 1)) & 1) << b
+    return h, l
+
+
+def matrix_to_canonical(coeffs, n):
+    d = 1 << n
+    h = np.arange(d, dtype=np.int64)[:, None]
+    l = np.arange(d, dtype=np.int64)[None, :]
+    q = (spread(h) << 1) | spread(l)
+    out = np.empty(4 ** n, coeffs.dtype)
+    out[q.ravel()] = np.asarray(coeffs).ravel()
+    return out
+
+
+def run(A_host, dtype=torch.complex128, **kw):
+    A = to_dev(A_host, dtype)
+    out = tpd.decompose(A, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def sampled_oracle(A_dev, n, qs, chunk_masks=256):
+    """omega_q for sampled q from the definition, reading only the entries
+    A[i ^ x][i] each string needs (gathered from the device input)."""
+    qs = np.asarray(qs, np.uint64)
+    masks = np.array([O.xy_mask(int(q), n) for q in qs], np.int64)
+    out = np.empty(qs.size, np.complex128)
+    flat = A_dev.view(-1)
+    i = torch.arange(1 << n, device=A_dev.device, dtype=torch.int64)
+    uniq = np.unique(masks)
+    for c0 in range(0, uniq.size, chunk_masks):
+        ms = uniq[c0:c0 + chunk_masks]
+        xs = torch.from_numpy(ms).to(A_dev.device)
+        idx = ((i[None, :] ^ xs[:, None]) << n) + i[None, :]
+        v = flat[idx.reshape(-1)].to(torch.complex128).reshape(len(ms), -1).cpu().numpy()
+        for k, x in enumerate(ms):
+            sel = np.flatnonzero(masks == x)
+            out[sel] = O.weight_from_diagonal(v[k], n, int(x), qs[sel])
+    return out
+
+
+# ----------------------------------------------------------------------------
+# configuration 0: n = 8, complex Gaussian; integer variant
+# ----------------------------------------------------------------------------
+def test_config0_n8_gaussian_vs_definition_all_strings():
+    n = 8
+    A = W.gaussian(n, seed=1)
+    got = run(A)
+    ref = O.weight_sparse(A, np.arange(4 ** n))
+    assert cerr(got, ref) <= 1e-12 * amax(A)
+    assert cerr(got, ref) <= n * U64 * amax(A)
+    assert same_bits(got, O.tpd_recursive(A))  # paper level order: same operations
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_config0_n8_integer_entries_bit_exact(dtype):
+    n = 8
+    A = W.integer(n, seed=1)
+    ref = O.weight_sparse(A, np.arange(4 ** n))
+    got = run(A, dtype).astype(np.complex128)
+    assert same_bits(got, ref)
+
+
+# ----------------------------------------------------------------------------
+# every n up to 12, both layouts, in place and out of place, both dtypes
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("n", list(range(0, 13)))
+def test_sizes_canonical_and_matrix_layout(n):
+    A = W.gaussian(n, seed=40 + n) if n else np.array([[1.25 - 0.5j]])
+    ref = O.tpd_recursive(A)
+    assert same_bits(run(A), ref)
+    got = run(A, layout="matrix")
+    assert same_bits(matrix_to_canonical(got, n), ref)
+    g64 = run(A, torch.complex64).astype(np.complex128)
+    assert cerr(g64, ref) <= (n + 1) * U32 * amax(A)
+
+
+@pytest.mark.parametrize("n", [1, 4, 6, 7, 9, 12])
+def test_in_place(n):
+    A = W.gaussian(n, seed=60 + n)
+    ref = O.tpd_recursive(A)
+    for dtype in (torch.complex128, torch.complex64):
+        T = to_dev(A, dtype)
+        tpd.decompose(T, T.view(-1), layout="matrix")
+        got = matrix_to_canonical(T.cpu().numpy().ravel(), n).astype(np.complex128)
+        if dtype == torch.complex128:
+            assert same_bits(got, ref)
+        else:
+            assert cerr(got, ref) <= (n + 1) * U32 * amax(A)
+        if n <= 6:
+            T = to_dev(A, dtype)
+            tpd.decompose(T, T.view(-1))
+            got = T.cpu().numpy().ravel().astype(np.complex128)
+            assert cerr(got, ref) <= (n + 1) * U32 * amax(A) if dtype == torch.complex64 else same_bits(got, ref)
+    with pytest.raises(tpd.TPDError):
+        T = to_dev(W.gaussian(9, 1))
+        tpd.decompose(T, T.view(-1))  # in place needs the matrix layout for n > 6
+
+
+@pytest.mark.parametrize("n", [10, 12])
+def test_bottom_first_register_order_within_bound(n):
+    A = W.gaussian(n, seed=80 + n)
+    ref = O.tpd_recursive(A)
+    got = run(A, order_bottom=True)
+    assert cerr(got, ref) <= n * U64 * amax(A) * 1.01
+
+
+# ----------------------------------------------------------------------------
+# configuration 1: n = 12 Hermitian
+# ----------------------------------------------------------------------------
+def test_config1_n12_hermitian():
+    n = 12
+    A = W.gaussian(n, seed=2, hermitian=True)
+    got = run(A)
+    ref = O.tpd_recursive(A)
+    assert same_bits(got, ref)
+    assert np.all(got.imag == 0.0)  # Hermitian input: exactly real weights
+    parseval = 2 ** n * np.sum(np.abs(got) ** 2)
+    fro = np.sum(np.abs(A) ** 2)
+    assert abs(parseval - fro) <= 1e-12 * fro
+    qs = W.sampled_strings(n, 10000, seed=2)
+    bf = sampled_oracle(to_dev(A), n, qs)
+    assert cerr(got[qs.astype(np.int64)], bf) <= 1e-12 * amax(A)
+    g64 = run(A, torch.complex64)
+    assert np.all(g64.imag == 0.0)
+    assert cerr(g64.astype(np.complex128), ref) <= (n + 1) * U32 * amax(A)
+
+
+# ----------------------------------------------------------------------------
+# configuration 2: n = 14 structured Hamiltonian, zero-block pruning
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dyadic", [True, False])
+def test_config2_n14_heisenberg_round_trip_and_pruning(dyadic):
+    n = 14
+    terms = W.heisenberg_terms(n, seed=3, n_local=200, dyadic=dyadic)
+    H = W.dense_from_terms_device(terms, n)
+    plan = tpd.Plan(n)
+    out = torch.empty(4 ** n, dtype=torch.complex128, device=DEV)
+    plan.execute(H, out)
+    torch.cuda.synchronize()
+    stats = plan.prune_stats()
+    qs = np.array([W.string_index(s) for s, _ in terms], np.int64)
+    cs = np.array([c for _, c in terms], np.complex128)
+    got = out[torch.from_numpy(qs).to(DEV)].cpu().numpy()
+    scale = float(torch.view_as_real(H).abs().max())
+    rest = out.clone()
+    rest[torch.from_numpy(qs).to(DEV)] = 0
+    resid = float(torch.view_as_real(rest).abs().max())
+    if dyadic:
+        assert same_bits(got, cs)  # exact round trip
+        assert resid == 0.0        # exact zeros everywhere else
+    else:
+        assert cerr(got, cs) <= 1e-12 * scale
+        assert resid <= 1e-12 * scale
+    # pruning: live level-n1 CMWs equal the distinct generating prefixes
+    n1 = stats["prefix_level"]
+    prefixes = {int(q) >> (2 * (n - n1)) for q in qs}
+    if dyadic:
+        assert stats["live_prefixes"] == len(prefixes)
+    else:
+        assert stats["live_prefixes"] >= len(prefixes)
+    assert stats["live_tiles"] < stats["total_tiles"] // 4
+    # sampled strings against the definition (both generating and others)
+    sample = np.concatenate([qs[:50], W.sampled_strings(n, 2000, seed=33).astype(np.int64)])
+    bf = sampled_oracle(H, n, sample)
+    assert cerr(out[torch.from_numpy(sample).to(DEV)].cpu().numpy(), bf) <= 1e-12 * scale
+    # the unpruned schedule gives the same bits
+    out2 = tpd.decompose(H, prune=False)
+    assert torch.equal(torch.view_as_real(out2), torch.view_as_real(out))
+    plan.close()
+
+
+def test_tfim_live_prefixes_closed_form():
+    # transverse-field Ising chain: 2k+1 live CMWs at level k < n
+    n = 12
+    H = W.dense_from_terms_device(W.tfim_terms(n, 1.0, 0.5), n)
+    plan = tpd.Plan(n)
+    out = torch.empty(4 ** n, dtype=torch.complex128, device=DEV)
+    plan.execute(H, out)
+    st = plan.prune_stats()
+    k = st["prefix_level"]
+    assert st["live_prefixes"] == 2 * k + 1
+    nz = torch.nonzero(torch.view_as_real(out).abs().sum(-1)).cpu().numpy().ravel()
+    expect = sorted(W.string_index(s) for s, _ in W.tfim_terms(n, 1.0, 0.5))
+    assert nz.tolist() == expect
+    plan.close()
+
+
+# ----------------------------------------------------------------------------
+# configuration 3: batched uneven workload, one persistent launch, graph replay
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_config3_batched_4096(dtype):
+    ns = W.batched_qubits(4096, seed=4)
+    mats = W.batched_matrices(ns, seed=4)
+    dmats = [to_dev(m, dtype) for m in mats]
+    outs = tpd.decompose_batched(dmats)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k, (o, m) in enumerate(zip(outs, mats)):
+        got = o.cpu().numpy()
+        ref = O.tpd_recursive(m)
+        if dtype == torch.complex128:
+            assert same_bits(got, ref), k
+        else:
+            worst = max(worst, cerr(got.astype(np.complex128), ref) / amax(m))
+            assert cerr(got.astype(np.complex128), ref) <= (int(ns[k]) + 1) * U32 * amax(m), k
+        if k % 2 == 1:
+            assert np.all(got.imag == 0), k  # Hermitian members: real weights
+
+
+def test_batched_plan_graph_capture_and_layouts():
+    ns = [int(v) for v in W.batched_qubits(300, seed=7, lo=0, hi=9)]
+    mats = W.batched_matrices(ns, seed=7)
+    dmats = [to_dev(m) for m in mats]
+    refs = [O.tpd_recursive(m) for m in mats]
+    outs = [torch.full((4 ** n,), float("nan"), dtype=torch.complex128, device=DEV) for n in ns]
+    plan = tpd.BatchedPlan(ns)
+    dp = tpd.BatchedPlan.pointer_table(dmats)
+    do = tpd.BatchedPlan.pointer_table(outs)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.execute(dp, do)  # warm up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.execute(dp, do)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, (o, r) in enumerate(zip(outs, refs)):
+            assert same_bits(o.cpu().numpy(), r), (rep, k)
+    plan.close()
+    # matrix layout, in place (allowed for every n with the matrix layout)
+    dm2 = [to_dev(m) for m in mats]
+    tpd.decompose_batched(dm2, "inplace", layout="matrix")
+    for k, (o, r) in enumerate(zip(dm2, refs)):
+        assert same_bits(matrix_to_canonical(o.cpu().numpy().ravel(), ns[k]), r), k
+
+
+# ----------------------------------------------------------------------------
+# configuration 4: n = 16 Hermitian, complex128 and complex64, sampled strings
+# ----------------------------------------------------------------------------
+def test_config4_n16_sampled_strings_parseval_both_precisions():
+    n = 16
+    torch.cuda.empty_cache()
+    A = W.gaussian_device(n, seed=5, hermitian=True)
+    a_max = float(torch.view_as_real(A).abs().max())
+    fro = float(torch.view_as_real(A).double().square().sum())
+    qs = W.sampled_strings(n, 4000, seed=5)
+    bf = sampled_oracle(A, n, qs)
+    qd = torch.from_numpy(qs.astype(np.int64)).to(DEV)
+
+    out = tpd.decompose(A)
+    torch.cuda.synchronize()
+    got = out[qd].cpu().numpy()
+    assert cerr(got, bf) <= 1e-12 * a_max
+    assert cerr(got, bf) <= n * U64 * a_max
+    assert float(out.imag.abs().max()) == 0.0  # Hermitian: exactly real
+    pars = float(torch.view_as_real(out).square().sum()) * 2 ** n
+    assert abs(pars - fro) <= 1e-12 * fro
+    # in place, matrix layout, on a copy: same bits as the canonical result
+    del out
+    torch.cuda.empty_cache()
+    ref_vals = got
+    B = A.clone()
+    tpd.decompose(B, B.view(-1), layout="matrix")
+    h, l = deinterleave(qs.astype(np.int64))
+    hb = torch.from_numpy(h).to(DEV)
+    lb = torch.from_numpy(l).to(DEV)
+    assert same_bits(B[hb, lb].cpu().numpy(), ref_vals)
+    del B
+    torch.cuda.empty_cache()
+
+    A32 = A.to(torch.complex64)
+    del A
+    torch.cuda.empty_cache()
+    out32 = tpd.decompose(A32)
+    torch.cuda.synchronize()
+    g32 = out32[qd].cpu().numpy().astype(np.complex128)
+    assert cerr(g32, bf) <= 2e-6 * a_max
+    assert cerr(g32, bf) <= (n + 1) * U32 * a_max
+    fro32 = float(torch.view_as_real(A32).double().square().sum())
+    pars32 = float(torch.view_as_real(out32).double().square().sum()) * 2 ** n
+    assert abs(pars32 - fro32) <= 1e-6 * fro32
+    del A32, out32
+    torch.cuda.empty_cache()
+
+
+# ----------------------------------------------------------------------------
+# edge cases, determinism, poison fill, errors
+# ----------------------------------------------------------------------------
+def test_edge_cases():
+    # zero matrix: everything pruned, output all zeros (written over NaN poison)
+    for n in (3, 10, 13):
+        Z = torch.zeros((1 << n, 1 << n), dtype=torch.complex128, device=DEV)
+        out = torch.full((4 ** n,), float("nan"), dtype=torch.complex128, device=DEV)
+        tpd.decompose(Z, out)
+        assert float(torch.view_as_real(out).abs().max()) == 0.0
+    # identity -> e_0 ; single strings -> unit vectors
+    for n in (5, 11):
+        I = torch.eye(1 << n, dtype=torch.complex128, device=DEV)
+        out = tpd.decompose(I).cpu().numpy()
+        e = np.zeros(4 ** n)
+        e[0] = 1
+        assert same_bits(out, e)
+    rng = np.random.default_rng(9)
+    for n in (9, 13):
+        for _ in range(3):
+            s = "".join("IXYZ"[int(v)] for v in rng.integers(0, 4, n))
+            S = W.dense_from_terms_device([(s, 1.0 + 0j)], n)
+            out = tpd.decompose(S)
+            q = W.string_index(s)
+            assert complex(out[q]) == 1.0
+            out[q] = 0
+            assert float(torch.view_as_real(out).abs().max()) == 0.0
+    # NaN propagates along its X/Y mask only
+    n = 11
+    A = torch.zeros((1 << n, 1 << n), dtype=torch.complex128, device=DEV)
+    A[5, 9] = float("nan")
+    out = tpd.decompose(A).cpu().numpy()
+    sample = np.arange(0, 4 ** n, 1013)
+    masks = np.array([O.xy_mask(int(q), n) for q in sample])
+    assert np.all(np.isnan(out[sample[masks == (5 ^ 9)]]))
+    assert np.all(out[sample[masks != (5 ^ 9)]] == 0)
+
+
+def test_determinism_and_poison():
+    n = 13
+    A = W.gaussian_device(n, seed=11)
+    o1 = torch.full((4 ** n,), float("nan"), dtype=torch.complex128, device=DEV)
+    o2 = torch.full((4 ** n,), float("nan"), dtype=torch.complex128, device=DEV)
+    tpd.decompose(A, o1)
+    tpd.decompose(A, o2)
+    assert not bool(torch.isnan(torch.view_as_real(o1)).any())
+    assert torch.equal(torch.view_as_real(o1), torch.view_as_real(o2))
+
+
+def test_device_errors_do_not_launch():
+    A = torch.zeros((16, 16), dtype=torch.complex128, device=DEV)
+    out = torch.empty(256, dtype=torch.complex128, device=DEV)
+    assert tpd.lib.tpd_decompose_ex(A.data_ptr() + 8, 4, out.data_ptr(), 0, 0, None) == 1
+    assert tpd.lib.tpd_decompose_ex(A.data_ptr(), 4, A.data_ptr() + 16, 0, 0, None) == 1
+    assert tpd.lib.tpd_decompose_ex(A.data_ptr(), 17, out.data_ptr(), 0, 0, None) == 2
+    torch.cuda.synchronize()
+
+
+def test_single_plan_graph_capture_and_timing():
+    n = 12
+    A = W.gaussian(n, seed=12)
+    ref = O.tpd_recursive(A)
+    Ad = to_dev(A)
+    out = torch.empty(4 ** n, dtype=torch.complex128, device=DEV)
+    plan = tpd.Plan(n, timing=True)
+    assert plan.num_kernels() == 2
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.execute(Ad, out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    ms, cnt = plan.timing(reset=True)
+    assert cnt == [1, 1] and all(t > 0 for t in ms)
+    plan.close()
+    plan = tpd.Plan(n)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.execute(Ad, out)
+    for _ in range(3):
+        out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert same_bits(out.cpu().numpy(), ref)
+    plan.close()

@@ -1,0 +1,133 @@
+"""CPU checks of the device schedule's index algebra against the oracle.
+
+``tpd.emulate`` replays, on the host and thread by thread, exactly the tile
+decode, thread roles, address maps, LDS exchanges, butterflies and
+pruning-bitmap reduction of the HIP kernels, and checks that every address
+is in range, every sweep reads and writes each element exactly once and
+in-place tiles are closed.  Comparing it with the oracle catches index,
+layout and twiddle mistakes before any GPU run.  In the paper's level
+order the schedule performs the same operations per element as the
+oracle's Algorithm 1, so complex128 results are bitwise equal.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+import workloads as W
+
+tpd = pytest.importorskip("paper_2310_13421_amd.tpd")
+
+
+def spread(v):
+    r = np.zeros_like(v)
+    for b in range(20):
+        r |= ((v >> b) & 1) << (2 * b)
+    return r
+
+
+def matrix_to_canonical(coeffs, n):
+    d = 1 << n
+    h = np.arange(d, dtype=np.int64)[:, None]
+    l = np.arange(d, dtype=np.int64)[None, :]
+    q = (spread(h) << 1) | spread(l)
+    out = np.empty(4 ** n, coeffs.dtype)
+    out[q.ravel()] = np.asarray(coeffs).ravel()
+    return out
+
+
+def same_bits(a, b):
+    return np.array_equal(np.asarray(a).real, np.asarray(b).real) and \
+        np.array_equal(np.asarray(a).imag, np.asarray(b).imag)
+
+
+@pytest.mark.parametrize("n", list(range(0, 12)))
+def test_emulated_schedule_bitwise_equals_algorithm_1(n):
+    A = W.gaussian(n, seed=300 + n) if n else np.array([[0.25 - 3j]])
+    ref = O.tpd_recursive(A)
+    assert same_bits(tpd.emulate(A), ref)
+    got = tpd.emulate(A, flags=tpd.FLAG_LAYOUT_MATRIX)
+    assert same_bits(matrix_to_canonical(got, n), ref)
+
+
+@pytest.mark.parametrize("n", [9, 10, 12])
+def test_emulated_bottom_first_order_within_bound(n):
+    A = W.gaussian(n, seed=400 + n)
+    ref = O.tpd_recursive(A)
+    got = tpd.emulate(A, flags=tpd.FLAG_ORDER_BOTTOM)
+    amax = np.max(np.abs(np.concatenate([A.real.ravel(), A.imag.ravel()])))
+    err = np.max(np.abs(np.concatenate([(got - ref).real, (got - ref).imag])))
+    assert err <= n * 2.0 ** -53 * amax * 1.01
+
+
+@pytest.mark.parametrize("n", [1, 4, 8, 9, 11])
+def test_emulated_complex64_within_fp32_bound(n):
+    A = W.gaussian(n, seed=500 + n)
+    ref = O.tpd_recursive(A)
+    got = tpd.emulate(A, dtype=tpd.TPD_C64)
+    amax = np.max(np.abs(np.concatenate([A.real.ravel(), A.imag.ravel()])))
+    err = np.max(np.abs(np.concatenate([(got - ref).real, (got - ref).imag])))
+    # input rounding to binary32 plus n roundings, each <= 2^-24 max|a|
+    assert err <= (n + 1) * 2.0 ** -24 * amax
+
+
+@pytest.mark.parametrize("n", [3, 6, 9])
+def test_emulated_integer_inputs_exact_both_dtypes(n):
+    A = W.integer(n, seed=600 + n)
+    ref = O.weight_sparse(A, np.arange(4 ** n))
+    assert same_bits(tpd.emulate(A), ref)
+    assert same_bits(tpd.emulate(A, dtype=tpd.TPD_C64).astype(np.complex128), ref)
+
+
+@pytest.mark.parametrize("n", [2, 6, 9, 11])
+def test_emulated_in_place(n):
+    A = W.gaussian(n, seed=700 + n)
+    ref = O.tpd_recursive(A)
+    got = tpd.emulate(A, flags=tpd.FLAG_LAYOUT_MATRIX, in_place=True)
+    assert same_bits(matrix_to_canonical(got, n), ref)
+    if n <= 6:
+        assert same_bits(tpd.emulate(A, in_place=True), ref)
+
+
+def test_emulated_pruning_on_structured_hamiltonian():
+    # dyadic Heisenberg chain plus 4-local strings: exact recovery, exact zeros,
+    # and (the emulator checks it) every skipped second-sweep tile is all zero
+    n = 10
+    terms = W.heisenberg_terms(n, seed=3, n_local=30, dyadic=True)
+    H = W.dense_from_terms(terms, n)
+    expect = np.zeros(4 ** n, np.complex128)
+    for s, c in terms:
+        expect[W.string_index(s)] += c
+    assert same_bits(tpd.emulate(H), expect)
+    assert same_bits(tpd.emulate(H, flags=tpd.FLAG_NO_PRUNE), expect)
+
+
+def test_emulated_nan_propagates_through_pruning():
+    n = 10
+    A = np.zeros((1 << n, 1 << n), np.complex128)
+    A[5, 9] = np.nan
+    got = tpd.emulate(A)
+    x = 5 ^ 9
+    masks = np.array([O.xy_mask(q, n) for q in range(0, 4 ** n, 997)])
+    sample = np.arange(0, 4 ** n, 997)
+    assert np.all(np.isnan(got[sample[masks == x]]))
+    assert np.all(got[sample[masks != x]] == 0)
+
+
+def test_emulated_batched_matches_oracle():
+    ns = W.batched_qubits(120, seed=4, lo=0, hi=9)
+    mats = W.batched_matrices(ns, seed=4)
+    outs = tpd.emulate_batched(mats)
+    for o, m in zip(outs, mats):
+        assert same_bits(o, O.tpd_recursive(m))
+    outs = tpd.emulate_batched(mats, flags=tpd.FLAG_LAYOUT_MATRIX)
+    for o, m, n in zip(outs, mats, ns):
+        assert same_bits(matrix_to_canonical(o, int(n)), O.tpd_recursive(m))
+    outs = tpd.emulate_batched(mats, dtype=tpd.TPD_C64)
+    for o, m, n in zip(outs, mats, ns):
+        ref = O.tpd_recursive(m)
+        amax = np.max(np.abs(np.concatenate([m.real.ravel(), m.imag.ravel()])))
+        assert np.max(np.abs(o - ref)) <= (int(n) + 2) * 2.0 ** -24 * amax
+    small = [m for m, n in zip(mats, ns) if n <= 6]
+    outs = tpd.emulate_batched(small, in_place=True)
+    for o, m in zip(outs, small):
+        assert same_bits(o, O.tpd_recursive(m))
