@@ -57,6 +57,56 @@ def load_traffic(key):
     return t.get("kernels", {}).get(key)
 
 
+def ingest_pmc(fetch_csv, write_csv, out_path):
+    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE, both with --copy-calibration) into profiles/traffic.json.
+    Each counter (KiB per dispatch) is scaled by what it reads for the plain
+    device copy of 2^32 bytes that --copy-calibration runs."""
+    import csv
+    from collections import defaultdict
+
+    copy_bytes = float(1 << 32)
+
+    def per_kernel(path):
+        agg = defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            agg[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)
+        return agg
+
+    fetch, write = per_kernel(fetch_csv), per_kernel(write_csv)
+
+    def calib(agg):
+        vals = [v for name, vs in agg.items() if "copyBuffer" in name for v in vs]
+        vals = [v for v in vals if 0.25 * copy_bytes < v < 4 * copy_bytes]
+        if not vals:
+            raise SystemExit("no plain-copy dispatch of 2^32 bytes in " + str(agg.keys()))
+        return (sum(vals) / len(vals)) / copy_bytes
+
+    fscale, wscale = calib(fetch), calib(write)
+    kernels = {}
+    for name in fetch:
+        if "tpd::k_sweep" not in name or name not in write:
+            continue
+        dt = "c128" if "k_sweep<double" in name else "c64"
+        which = 1 if ", 0, 2>" in name else (2 if ", 2, 1>" in name else 0)
+        if not which:
+            continue
+        es = 16 if dt == "c128" else 8
+        fb = sum(fetch[name]) / len(fetch[name]) / fscale
+        wb = sum(write[name]) / len(write[name]) / wscale
+        alg = 4 ** 16 * es
+        kernels[f"sweep{which}_n16_{dt}"] = {
+            "kernel": name, "fetch_bytes": fb, "write_bytes": wb, "total_bytes": fb + wb,
+            "algorithmic_bytes": 2 * alg, "fetch_over_algorithmic": fb / alg, "write_over_algorithmic": wb / alg,
+        }
+    doc = {"kernel_source_sha": kernel_source_hash(), "fetch_scale": fscale, "write_scale": wscale,
+           "calibration": "plain device copy of 2^32 bytes (__amd_rocclr_copyBuffer via torch copy_)",
+           "kernels": kernels}
+    with open(out_path, "w") as f:
+        json.dump(doc, f, indent=1)
+    return doc
+
+
 def timed_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -137,7 +187,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc counter CSVs and exit")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        doc = ingest_pmc(args.ingest_pmc[0], args.ingest_pmc[1], os.path.join(ROOT, "profiles", "traffic.json"))
+        print(json.dumps(doc, indent=1))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -180,7 +236,8 @@ def main():
     k = max(range(len(avgs)), key=lambda i: avgs[i])
     unit_bytes = 2 * 16  # one complex128 read + one write per coefficient
     achieved = unit_bytes * 4 ** n / (avgs[k] / 1e3) / 1e9
-    tr = load_traffic(f"sweep{k + 1}_n{n}_c128")
+    tr_doc = load_traffic(f"sweep{k + 1}_n{n}_c128")
+    tr = tr_doc["total_bytes"] if tr_doc else None
     roofline = {
         "bound": "hbm",
         "kernel": f"k_sweep (sweep {k + 1} of 2)",

@@ -84,6 +84,7 @@ tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Sched
     w.out_layout = out_l;
     w.bitmap_mode = 0;
     w.order = 0;
+    w.r = 4;
     w.ntiles = (uint64_t)1 << (n - w.db);
     return TPD_SUCCESS;
   }
@@ -101,6 +102,7 @@ tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Sched
   a.out_layout = s->matrix_layout ? L_MAT : L_MID;
   a.bitmap_mode = s->prune ? 1 : 0;
   a.order = 0;
+  a.r = 4;
   a.ntiles = ((uint64_t)1 << s->n2) << (n - db);
   SweepDesc& b = s->sw[1];
   b.xlo = 0;
@@ -110,6 +112,7 @@ tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Sched
   b.out_layout = out_l;
   b.bitmap_mode = s->prune ? 2 : 0;
   b.order = (flags & TPD_FLAG_ORDER_BOTTOM) ? 1 : 0;
+  b.r = 4;
   b.ntiles = ((uint64_t)1 << s->n1) << (n - db);
   const uint64_t bits = ((uint64_t)1 << s->n1) << (n - db);
   s->bitmap_words = (bits + 31) / 32;
@@ -332,25 +335,51 @@ tpd_status_t run_schedule(const Schedule& s, const void* A, void* C, uint32_t* b
   if (s.prune && s.nsweep == 2) {
     if (launch_fill_u32(bitmap, s.bitmap_words, 0u, st) != hipSuccess) return TPD_ERROR_LAUNCH;
   }
-  for (int i = 0; i < s.nsweep; ++i) {
-    const SweepDesc& w = s.sw[i];
-    SweepArgs a{};
-    a.in = (i == 0) ? A : C;
-    a.out = C;
-    a.n = s.n;
-    a.xlo = w.xlo;
-    a.db = w.db;
-    a.nfix_d = s.n - w.db;
-    a.bitmap = bitmap;
-    a.bitmap_mode = w.bitmap_mode;
-    a.bm_xbits = s.n1;
-    a.ntiles = w.ntiles;
-    const int slot = tm ? tm->begin(i, st) : -1;
-    const hipError_t e = launch_sweep(s.dt, w, a, st);
-    if (tm) tm->end(i, slot, st);
-    if (e != hipSuccess) {
-      logf("sweep %d launch failed: %s", i, hipGetErrorString(e));
-      return TPD_ERROR_LAUNCH;
+  // Tuning knobs (read per call): TPD_CHUNK_TD splits a two-sweep schedule
+  // into groups of that many 2^db-diagonal strips, running both sweeps on
+  // one group before the next so the intermediate of a group can stay in
+  // the memory-side cache; TPD_NT=1 selects non-temporal loads and stores.
+  const char* ce = std::getenv("TPD_CHUNK_TD");
+  const uint64_t chunk_env = ce ? (uint64_t)std::strtoull(ce, nullptr, 10) : (uint64_t)0;
+  const char* ne = std::getenv("TPD_NT");
+  const int nt_env = (ne && ne[0] == '1') ? 1 : 0;
+  const char* re = std::getenv("TPD_R");
+  const int r_env = re ? std::atoi(re) : 0;
+  const uint64_t ntd = s.nsweep == 2 ? ((uint64_t)1 << (s.n - s.sw[0].db)) : 0;
+  uint64_t chunk = (s.nsweep == 2 && chunk_env > 0 && chunk_env < ntd) ? chunk_env : 0;
+  if (chunk && (ntd % chunk)) chunk = 0;
+  const uint64_t nchunks = chunk ? ntd / chunk : 1;
+  for (uint64_t c = 0; c < nchunks; ++c) {
+    for (int i = 0; i < s.nsweep; ++i) {
+      SweepDesc w = s.sw[i];
+      if (s.nsweep == 2 && r_env >= 2 && r_env <= 4) w.r = r_env;
+      SweepArgs a{};
+      a.in = (i == 0) ? A : C;
+      a.out = C;
+      a.n = s.n;
+      a.xlo = w.xlo;
+      a.db = w.db;
+      a.nfix_d = s.n - w.db;
+      a.bitmap = bitmap;
+      a.bitmap_mode = w.bitmap_mode;
+      a.bm_xbits = s.n1;
+      a.nt = nt_env;
+      if (chunk) {
+        a.td0 = c * chunk;
+        a.tdn = chunk;
+        a.ntiles = (w.ntiles / ntd) * chunk;
+      } else {
+        a.td0 = 0;
+        a.tdn = 0;
+        a.ntiles = w.ntiles;
+      }
+      const int slot = tm ? tm->begin(i, st) : -1;
+      const hipError_t e = launch_sweep(s.dt, w, a, st);
+      if (tm) tm->end(i, slot, st);
+      if (e != hipSuccess) {
+        logf("sweep %d launch failed: %s", i, hipGetErrorString(e));
+        return TPD_ERROR_LAUNCH;
+      }
     }
   }
   return TPD_SUCCESS;

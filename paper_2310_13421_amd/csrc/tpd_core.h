@@ -80,7 +80,7 @@ TPD_HD uint64_t layout_addr_rt(int L, uint64_t x, uint64_t d, int n, int db) {
 // Each of the 2^(B-R) threads holds 2^R elements in registers.  A sweep runs
 // NPH register phases; between phases the tile is exchanged through LDS.
 // ---------------------------------------------------------------------------
-constexpr int kMaxPh = 3;
+constexpr int kMaxPh = 4;
 
 struct Roles {
   int nph;

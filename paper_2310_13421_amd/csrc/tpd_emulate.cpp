@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -57,8 +58,8 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
   uint32_t bits[NBW];
 
   for (uint64_t tile = 0; tile < a.ntiles; ++tile) {
-    const uint64_t td = tile & tdmask;
-    const uint64_t xf = tile >> a.nfix_d;
+    const uint64_t td = a.tdn ? a.td0 + tile % a.tdn : (tile & tdmask);
+    const uint64_t xf = a.tdn ? tile / a.tdn : (tile >> a.nfix_d);
     const uint64_t xfix = (xf & (((uint64_t)1 << xlo) - 1)) | ((xf >> xlo) << (xlo + G::XB));
     if (a.bitmap_mode == 2) {
       const uint64_t bit = (td << a.bm_xbits) | xf;
@@ -187,10 +188,12 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
   return ck.ok ? TPD_SUCCESS : TPD_ERROR_INTERNAL;
 }
 
-template <class S, int XB, int DB, int ORDER>
+template <class S, int XB, int DB, int ORDER, int RR = 4>
 tpd_status_t emulate_layouts(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint32_t* bm,
                              Checker& ck) {
-  constexpr int R = (XB + DB) < 4 ? (XB + DB) : 4;
+  // at most 1024 threads per tile, at most 16 registers per thread
+  constexpr int R1 = (XB + DB - 10) > RR ? (XB + DB - 10) : RR;
+  constexpr int R = (XB + DB) < R1 ? (XB + DB) : R1;
   using G = Geom<XB, DB, 0, R, ORDER>;
   if (s.in_layout == L_MAT && s.out_layout == L_CAN) return emulate_sweep<S, G, L_MAT, L_CAN>(in, out, a, bm, ck);
   if (s.in_layout == L_MAT && s.out_layout == L_MAT) return emulate_sweep<S, G, L_MAT, L_MAT>(in, out, a, bm, ck);
@@ -202,11 +205,19 @@ tpd_status_t emulate_layouts(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, co
 template <class S>
 tpd_status_t emulate_shape(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint32_t* bm,
                            Checker& ck) {
-#define TPD_CASE(XB_, DB_)                                                                     \
-  if (s.xb == XB_ && s.db == DB_)                                                              \
-    return s.order == 0 ? emulate_layouts<S, XB_, DB_, 0>(s, in, out, a, bm, ck)               \
-                        : emulate_layouts<S, XB_, DB_, 1>(s, in, out, a, bm, ck);
-  TPD_SHAPES(TPD_CASE)
+#define TPD_CASE(XB_, DB_)                                                                              \
+  if (s.xb == XB_ && s.db == DB_) {                                                                     \
+    if (s.r == 2)                                                                                       \
+      return s.order == 0 ? emulate_layouts<S, XB_, DB_, 0, 2>(s, in, out, a, bm, ck)                   \
+                          : emulate_layouts<S, XB_, DB_, 1, 2>(s, in, out, a, bm, ck);                  \
+    if (s.r == 3)                                                                                       \
+      return s.order == 0 ? emulate_layouts<S, XB_, DB_, 0, 3>(s, in, out, a, bm, ck)                   \
+                          : emulate_layouts<S, XB_, DB_, 1, 3>(s, in, out, a, bm, ck);                  \
+    return s.order == 0 ? emulate_layouts<S, XB_, DB_, 0>(s, in, out, a, bm, ck)                        \
+                        : emulate_layouts<S, XB_, DB_, 1>(s, in, out, a, bm, ck);                       \
+  }
+  TPD_SHAPES_ONE(TPD_CASE)
+  TPD_SHAPES_TWO(TPD_CASE)
 #undef TPD_CASE
   return TPD_ERROR_INTERNAL;
 }
@@ -313,7 +324,10 @@ extern "C" tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tp
     return TPD_SUCCESS;
   }
   std::vector<uint32_t> bitmap(words ? words : 1, 0u);
+  const char* re = std::getenv("TPD_R");
+  const int r_env = re ? std::atoi(re) : 0;
   for (int i = 0; i < nsweep; ++i) {
+    if (nsweep == 2 && r_env >= 2 && r_env <= 4) sw[i].r = r_env;
     SweepArgs a{};
     a.in = i == 0 ? A : coeffs;
     a.out = coeffs;

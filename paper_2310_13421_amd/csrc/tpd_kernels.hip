@@ -26,6 +26,28 @@
 
 namespace tpd {
 
+// non-temporal complex loads and stores through native 2-vectors
+typedef double tpd_d2 __attribute__((ext_vector_type(2)));
+typedef float tpd_f2 __attribute__((ext_vector_type(2)));
+template <class S> struct Vec2;
+template <> struct Vec2<double> { using type = tpd_d2; };
+template <> struct Vec2<float> { using type = tpd_f2; };
+
+template <class S>
+__device__ __forceinline__ Cx<S> load_nt(const Cx<S>* p) {
+  using V = typename Vec2<S>::type;
+  const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  return Cx<S>{v.x, v.y};
+}
+template <class S>
+__device__ __forceinline__ void store_nt(Cx<S>* p, const Cx<S>& c) {
+  using V = typename Vec2<S>::type;
+  V v;
+  v.x = c.re;
+  v.y = c.im;
+  __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+}
+
 // ---------------------------------------------------------------------------
 // single-matrix sweep
 // ---------------------------------------------------------------------------
@@ -59,8 +81,8 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   const uint32_t ebl = elem_base<G>(RL, LAST, tid);
 
   for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    const uint64_t td = tile & tdmask;
-    const uint64_t xf = tile >> a.nfix_d;
+    const uint64_t td = a.tdn ? a.td0 + tile % a.tdn : (tile & tdmask);
+    const uint64_t xf = a.tdn ? tile / a.tdn : (tile >> a.nfix_d);
     const uint64_t xfix = (xf & (((uint64_t)1 << xlo) - 1)) | ((xf >> xlo) << (xlo + G::XB));
     if (a.bitmap_mode == 2) {
       const uint64_t bit = (td << a.bm_xbits) | xf;
@@ -79,7 +101,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
 #pragma unroll
         for (int s = 0; s < G::R; ++s)
           if ((j >> s) & 1) ad ^= din[s];
-        v[j] = in[ad];
+        v[j] = a.nt ? load_nt(&in[ad]) : in[ad];
       }
     }
 
@@ -135,7 +157,8 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
 #pragma unroll
         for (int s = 0; s < G::R; ++s)
           if ((j >> s) & 1) ad ^= dout[s];
-        out[ad] = v[j];
+        if (a.nt) store_nt(&out[ad], v[j]);
+        else out[ad] = v[j];
       }
     }
   }
@@ -299,9 +322,11 @@ hipError_t launch_batched_perm(Dtype dt, const void* const* in_ptrs, void* const
 // ---------------------------------------------------------------------------
 // sweep dispatch
 // ---------------------------------------------------------------------------
-template <class S, int XB, int DB, int ORDER, int INL, int OUTL>
+template <class S, int XB, int DB, int ORDER, int INL, int OUTL, int RR = 4>
 static hipError_t launch_one(const SweepArgs& a, hipStream_t st) {
-  constexpr int R = (XB + DB) < 4 ? (XB + DB) : 4;
+  // at most 1024 threads per tile, at most 16 registers per thread
+  constexpr int R1 = (XB + DB - 10) > RR ? (XB + DB - 10) : RR;
+  constexpr int R = (XB + DB) < R1 ? (XB + DB) : R1;
   using G = Geom<XB, DB, 0, R, ORDER>;
   if constexpr (!shape_fits<S>(XB, DB)) {
     return hipErrorInvalidValue;
@@ -313,30 +338,41 @@ static hipError_t launch_one(const SweepArgs& a, hipStream_t st) {
   }
 }
 
-template <class S, int XB, int DB, int ORDER>
-static hipError_t launch_layouts(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
-  if (s.in_layout == L_MAT && s.out_layout == L_CAN) return launch_one<S, XB, DB, ORDER, L_MAT, L_CAN>(a, st);
-  if (s.in_layout == L_MAT && s.out_layout == L_MAT) return launch_one<S, XB, DB, ORDER, L_MAT, L_MAT>(a, st);
-  if (s.in_layout == L_MAT && s.out_layout == L_MID) return launch_one<S, XB, DB, ORDER, L_MAT, L_MID>(a, st);
-  if (s.in_layout == L_MID && s.out_layout == L_CAN) return launch_one<S, XB, DB, ORDER, L_MID, L_CAN>(a, st);
-  return hipErrorInvalidValue;
-}
-
 template <class S>
 static hipError_t dispatch_shape(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
-#define TPD_CASE(XB_, DB_)                                                          \
-  if (s.xb == XB_ && s.db == DB_)                                                   \
-    return s.order == 0 ? launch_layouts<S, XB_, DB_, 0>(s, a, st)                 \
-                        : launch_layouts<S, XB_, DB_, 1>(s, a, st);
-  TPD_SHAPES(TPD_CASE)
+  const bool one = s.in_layout == L_MAT && s.xlo == 0 && s.xb == a.n;
+#define TPD_CASE(XB_, DB_)                                                                   \
+  if (one && s.xb == XB_ && s.db == DB_) {                                                   \
+    if (s.out_layout == L_CAN) return launch_one<S, XB_, DB_, 0, L_MAT, L_CAN>(a, st);       \
+    if (s.out_layout == L_MAT) return launch_one<S, XB_, DB_, 0, L_MAT, L_MAT>(a, st);       \
+  }
+  TPD_SHAPES_ONE(TPD_CASE)
 #undef TPD_CASE
+#define TPD_TWO(XB_, DB_, RR_)                                                                        \
+  if (s.in_layout == L_MAT && s.out_layout == L_MID) return launch_one<S, XB_, DB_, 0, L_MAT, L_MID, RR_>(a, st); \
+  if (s.in_layout == L_MID && s.out_layout == L_CAN)                                                  \
+    return s.order ? launch_one<S, XB_, DB_, 1, L_MID, L_CAN, RR_>(a, st)                            \
+                   : launch_one<S, XB_, DB_, 0, L_MID, L_CAN, RR_>(a, st);                           \
+  if (s.in_layout == L_MAT && s.out_layout == L_MAT)                                                  \
+    return s.order ? launch_one<S, XB_, DB_, 1, L_MAT, L_MAT, RR_>(a, st)                            \
+                   : launch_one<S, XB_, DB_, 0, L_MAT, L_MAT, RR_>(a, st);
+#define TPD_CASE(XB_, DB_)                             \
+  if (!one && s.xb == XB_ && s.db == DB_) {            \
+    if (s.r == 2) { TPD_TWO(XB_, DB_, 2) }             \
+    else if (s.r == 3) { TPD_TWO(XB_, DB_, 3) }        \
+    else { TPD_TWO(XB_, DB_, 4) }                      \
+  }
+  TPD_SHAPES_TWO(TPD_CASE)
+#undef TPD_CASE
+#undef TPD_TWO
   return hipErrorInvalidValue;
 }
 
 bool sweep_supported(Dtype dt, const SweepDesc& s) {
 #define TPD_CASE(XB_, DB_) \
   if (s.xb == XB_ && s.db == DB_) return dt == DT_C128 ? shape_fits<double>(XB_, DB_) : shape_fits<float>(XB_, DB_);
-  TPD_SHAPES(TPD_CASE)
+  TPD_SHAPES_ONE(TPD_CASE)
+  TPD_SHAPES_TWO(TPD_CASE)
 #undef TPD_CASE
   return false;
 }
