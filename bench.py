@@ -27,8 +27,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
 METRIC = "Pauli coeffs/sec + HBM GB/s (% peak) at n=14/16, FP64 vs FP32; batched mats/s"
-KERNEL_SOURCES = ["paper_2310_13421_amd/csrc/tpd_kernels.hip", "paper_2310_13421_amd/csrc/tpd_core.h",
-                  "paper_2310_13421_amd/csrc/tpd_internal.h"]
+KERNEL_SOURCES = ["paper_2310_13421_amd/csrc/tpd_sweep.h", "paper_2310_13421_amd/csrc/tpd_core.h",
+                  "paper_2310_13421_amd/csrc/tpd_internal.h", "paper_2310_13421_amd/csrc/tpd_sweep_c128.hip",
+                  "paper_2310_13421_amd/csrc/tpd_sweep_c64.hip"]
 
 
 def log(msg):
@@ -123,8 +124,13 @@ def kernel_avgs(plan):
     return [m / c if c else 0.0 for m, c in zip(ms, cnt)], cnt
 
 
-def single_matrix_run(tpd, torch, A, n, dtype_code, steps, warmup, esize, in_place=False, layout="canonical"):
+def single_matrix_run(tpd, torch, A, n, dtype_code, steps, warmup, esize, in_place=False, layout="canonical",
+                      tune=True):
     out = A.view(-1) if in_place else torch.empty(4 ** n, dtype=A.dtype, device=A.device)
+    tuned = None
+    if tune and not in_place:
+        # pick the schedule by measurement on these buffers (outside the timed region)
+        tuned = tpd.autotune(A, out, layout=layout).get("chosen")
     plan = tpd.Plan(n, dtype_code, timing=True, in_place=in_place, layout=layout)
     ms = timed_steps(lambda: plan.execute(A, out), steps, warmup, torch)
     avgs, cnt = kernel_avgs(plan)
@@ -140,6 +146,8 @@ def single_matrix_run(tpd, torch, A, n, dtype_code, steps, warmup, esize, in_pla
         "kernel_launches": cnt,
         "sweep_GBps": [sweep_bytes / (a / 1e3) / 1e9 if a else None for a in avgs],
         "sweeps": len(desc["sweeps"]),
+        "schedule": [{k: w[k] for k in ("xb", "db", "r", "grid", "tile_elems", "threads")} for w in desc["sweeps"]],
+        "autotuned": tuned,
     }
     res["pct_peak_algorithmic"] = 100.0 * res["algorithmic_GBps"] / PEAK_HBM_GBPS
     return res, out
@@ -274,6 +282,8 @@ def main():
         "sweeps": main_res["sweeps"],
         "kernel_ms": main_res["kernel_ms"],
         "sweep_GBps": main_res["sweep_GBps"],
+        "schedule": main_res["schedule"],
+        "autotuned": main_res["autotuned"],
         "roofline": roofline,
     }
 
@@ -335,9 +345,11 @@ def main():
             torch.cuda.current_stream().wait_stream(s)
             torch.cuda.synchronize()
             plan.timing(reset=True)
+            btuned = plan.autotune(dp, do)["chosen"]
+            plan.timing(reset=True)
             ms_eager = timed_steps(lambda: plan.execute(dp, do), args.steps, args.warmup, torch)
             kavg, _ = kernel_avgs(plan)
-            plan_g = tpd.BatchedPlan(ns, code)
+            plan_g = tpd.BatchedPlan(ns, code)  # takes the tuned grid as its default
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
                 plan_g.execute(dp, do)
@@ -358,6 +370,7 @@ def main():
                 "per_matrix_launch_loop_ms": ms_loop,
                 "per_matrix_mats_per_s": len(ns) / (ms_loop / 1e3),
                 "speedup_vs_per_matrix": ms_loop / ms_graph,
+                "autotuned": btuned,
                 "algorithmic_GBps": bytes_ / (ms_graph / 1e3) / 1e9,
             }
             plan.close()

@@ -155,6 +155,31 @@ tpd_status_t tpd_plan_prune_stats(tpd_plan_t plan, uint64_t* live_tiles, uint64_
 /* JSON text describing the plan (sweeps, tile shapes, layouts, bytes). */
 tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len);
 
+/* ---- autotuning ---- */
+
+/* Time the candidate two-sweep schedules for (n, dtype, layout, placement)
+ * on the caller's buffers and make the fastest the one every later call and
+ * plan with the same key uses on this process (and, if the environment
+ * variable TPD_AUTOTUNE_CACHE names a file, appended there and reloaded by
+ * later processes).  Candidates: tile widths of 2^3..2^5 (complex128) or
+ * 2^4..2^6 (complex64) XOR-diagonals, 8 or 16 elements per thread, one
+ * workgroup per tile or a persistent grid of 1, 2 or 4 workgroups per CU.
+ * The choice never changes results (same operations in the same order).
+ * Arguments as tpd_decompose_ex; `coeffs` is overwritten; with
+ * A == coeffs the matrix is transformed repeatedly (destroyed).  Allocates
+ * a bitmap, synchronises `stream`.  report/len (optional): JSON of the
+ * candidates' median times and the choice.  n <= 8 has nothing to tune.   */
+tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
+                          tpd_stream_t stream, char* report, size_t len);
+
+/* Time the batched plan's persistent kernel with 1, 2, 3, 4, 6 or 8
+ * workgroups per CU, or one workgroup per work item, and keep the fastest
+ * for this plan (and as the default for later batched plans of the dtype).
+ * d_ptrs / d_out_ptrs as tpd_plan_execute_batched; outputs are
+ * overwritten.  Synchronises `stream`.                                     */
+tpd_status_t tpd_autotune_batched(tpd_plan_t plan, const void* const* d_ptrs, void* const* d_out_ptrs,
+                                  tpd_stream_t stream, char* report, size_t len);
+
 /* Release the per-(device, stream) workspaces held for tpd_decompose*. */
 tpd_status_t tpd_release_workspace(void);
 
@@ -179,6 +204,11 @@ tpd_status_t tpd_schedule_describe(int n, tpd_dtype_t dtype, unsigned flags, int
  * it to produce results.  A / coeffs are HOST pointers.                  */
 tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                                int in_place);
+
+/* As tpd_debug_emulate with a forced two-sweep tile width 2^db and 2^r
+ * elements per thread (db = 0: the default schedule).                    */
+tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
+                                     int in_place, int db, int r);
 
 /* Host replay of the batched schedule for one batch (HOST pointer arrays). */
 tpd_status_t tpd_debug_emulate_batched(const void* const* ptrs, const int* ns, int count, void* const* out_ptrs,

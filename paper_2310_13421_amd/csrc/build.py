@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libtpd.so")
-SOURCES = ["tpd_kernels.hip", "tpd_api.cpp", "tpd_emulate.cpp"]
-HEADERS = ["tpd_core.h", "tpd_internal.h"]
+SOURCES = ["tpd_sweep_c128.hip", "tpd_sweep_c64.hip", "tpd_kernels.hip", "tpd_api.cpp", "tpd_emulate.cpp"]
+HEADERS = ["tpd_core.h", "tpd_internal.h", "tpd_sweep.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -45,7 +45,7 @@ def _run(cmd):
     return time.time() - t0
 
 
-def build(verbose: bool = True, jobs: int = 3) -> str:
+def build(verbose: bool = True, jobs: int = 5) -> str:
     """Compile every source to an object (in parallel) and link libtpd.so."""
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)

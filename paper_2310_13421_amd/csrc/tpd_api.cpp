@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <fstream>
+#include <sstream>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -64,7 +67,32 @@ int single_db(int n) {
   return t[n];
 }
 
-tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Schedule* s) {
+// Tunable choices of a two-sweep schedule: tile width 2^db diagonals,
+// 2^r elements per thread, and the grid (0 = one workgroup per tile, k > 0 =
+// persistent grid of k workgroups per CU).  None of them changes results:
+// every element sees the same operations in the same order.
+struct Tuned {
+  int db = 0, r = 4, grid = 0;
+};
+struct TuneKey {
+  int n, dt, matrix, in_place;
+  bool operator<(const TuneKey& o) const {
+    if (n != o.n) return n < o.n;
+    if (dt != o.dt) return dt < o.dt;
+    if (matrix != o.matrix) return matrix < o.matrix;
+    return in_place < o.in_place;
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, Tuned> g_tuned;  // n = -1: batched kernel grid per dtype
+bool g_tune_loaded = false;
+std::atomic<int> g_cus{0};
+
+int default_db(Dtype dt, int n2) { return (dt == DT_C64 && n2 >= 5) ? 5 : 4; }
+
+void load_tune_cache();
+
+tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, const Tuned* force, Schedule* s) {
   if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
   *s = Schedule{};
   s->n = n;
@@ -85,6 +113,8 @@ tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Sched
     w.bitmap_mode = 0;
     w.order = 0;
     w.r = 4;
+    w.grid = 0;
+    w.is_one = true;
     w.ntiles = (uint64_t)1 << (n - w.db);
     return TPD_SUCCESS;
   }
@@ -92,8 +122,21 @@ tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Sched
   s->nsweep = 2;
   s->n1 = (n + 1) / 2;
   s->n2 = n / 2;
-  const int db = (dt == DT_C64 && s->n2 >= 5) ? 5 : 4;
+  Tuned t;
+  t.db = default_db(dt, s->n2);
+  const bool bottom = (flags & TPD_FLAG_ORDER_BOTTOM) != 0;
+  if (force) {
+    t = *force;
+  } else if (!bottom) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) load_tune_cache();
+    auto it = g_tuned.find(TuneKey{n, (int)dt, s->matrix_layout ? 1 : 0, in_place ? 1 : 0});
+    if (it != g_tuned.end()) t = it->second;
+  }
+  if (t.db > s->n2) return TPD_ERROR_INVALID_VALUE;  // MID needs the low db x bits in sweep 2
+  const int db = t.db;
   s->prune = (flags & TPD_FLAG_NO_PRUNE) == 0;
+  const int cus = g_cus > 0 ? (int)g_cus : 256;
   SweepDesc& a = s->sw[0];
   a.xlo = s->n2;
   a.xb = s->n1;
@@ -102,7 +145,9 @@ tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Sched
   a.out_layout = s->matrix_layout ? L_MAT : L_MID;
   a.bitmap_mode = s->prune ? 1 : 0;
   a.order = 0;
-  a.r = 4;
+  a.r = t.r;
+  a.grid = t.grid > 0 ? t.grid * cus : 0;
+  a.is_one = false;
   a.ntiles = ((uint64_t)1 << s->n2) << (n - db);
   SweepDesc& b = s->sw[1];
   b.xlo = 0;
@@ -111,14 +156,53 @@ tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Sched
   b.in_layout = s->matrix_layout ? L_MAT : L_MID;
   b.out_layout = out_l;
   b.bitmap_mode = s->prune ? 2 : 0;
-  b.order = (flags & TPD_FLAG_ORDER_BOTTOM) ? 1 : 0;
-  b.r = 4;
+  b.order = bottom ? 1 : 0;
+  b.r = bottom ? 4 : t.r;
+  b.grid = a.grid;
+  b.is_one = false;
   b.ntiles = ((uint64_t)1 << s->n1) << (n - db);
   const uint64_t bits = ((uint64_t)1 << s->n1) << (n - db);
   s->bitmap_words = (bits + 31) / 32;
   for (int i = 0; i < 2; ++i)
-    if (!sweep_supported(dt, s->sw[i])) return TPD_ERROR_INTERNAL;
+    if (!sweep_supported(dt, s->sw[i])) return force ? TPD_ERROR_INVALID_VALUE : TPD_ERROR_INTERNAL;
   return TPD_SUCCESS;
+}
+
+tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Schedule* s) {
+  return make_schedule_with(n, dt, flags, in_place, nullptr, s);
+}
+
+// Autotune cache: TPD_AUTOTUNE_CACHE names a text file of lines
+//   tpd-tune-v1 <arch> <cus> <dtype> <n> <matrix> <in_place> <db> <r> <grid>
+// Unreadable or foreign lines are ignored (the built-in defaults apply).
+void load_tune_cache() {
+  g_tune_loaded = true;
+  const char* path = std::getenv("TPD_AUTOTUNE_CACHE");
+  if (!path || !path[0]) return;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    std::string tag, arch;
+    int cus, dt, n, mat, inp, db, r, grid;
+    if (!(is >> tag >> arch >> cus >> dt >> n >> mat >> inp >> db >> r >> grid)) continue;
+    if (tag != "tpd-tune-v1" || arch != "gfx950") continue;
+    if (g_cus > 0 && cus != g_cus) continue;
+    if (dt < 0 || dt > 1 || n < -1 || n > kMaxQubits || r < 3 || r > 4 || grid < 0 || grid > 64) continue;
+    Tuned t;
+    t.db = db;
+    t.r = r;
+    t.grid = grid;
+    g_tuned[TuneKey{n, dt, mat, inp}] = t;
+  }
+}
+
+void save_tune_entry(const TuneKey& k, const Tuned& t) {
+  const char* path = std::getenv("TPD_AUTOTUNE_CACHE");
+  if (!path || !path[0]) return;
+  std::ofstream f(path, std::ios::app);
+  f << "tpd-tune-v1 gfx950 " << (g_cus > 0 ? (int)g_cus : 0) << " " << k.dt << " " << k.n << " " << k.matrix << " "
+    << k.in_place << " " << t.db << " " << t.r << " " << t.grid << "\n";
 }
 
 const char* layout_name(int l) { return l == L_MAT ? "MAT" : (l == L_CAN ? "CAN" : "MID"); }
@@ -138,12 +222,13 @@ std::string describe(const Schedule& s) {
   for (int i = 0; i < s.nsweep; ++i) {
     const SweepDesc& w = s.sw[i];
     const int B = w.xb + w.db;
-    const int R = B < 4 ? B : 4;
+    int R = w.r > B ? B : w.r;
+    if (B - R > 10) R = B - 10;
     std::snprintf(buf, sizeof buf,
                   "%s{\"xlo\":%d,\"xb\":%d,\"db\":%d,\"in\":\"%s\",\"out\":\"%s\",\"bitmap\":\"%s\","
-                  "\"order\":%d,\"tiles\":%llu,\"tile_elems\":%d,\"threads\":%d}",
+                  "\"order\":%d,\"r\":%d,\"grid\":%d,\"tiles\":%llu,\"tile_elems\":%d,\"threads\":%d}",
                   i ? "," : "", w.xlo, w.xb, w.db, layout_name(w.in_layout), layout_name(w.out_layout),
-                  w.bitmap_mode == 1 ? "set" : (w.bitmap_mode == 2 ? "check" : "none"), w.order,
+                  w.bitmap_mode == 1 ? "set" : (w.bitmap_mode == 2 ? "check" : "none"), w.order, R, w.grid,
                   (unsigned long long)w.ntiles, 1 << B, 1 << (B - R));
     j += buf;
   }
@@ -193,7 +278,10 @@ tpd_status_t current_device(int* dev) {
   if (it == g_dev_ok.end()) {
     hipDeviceProp_t p;
     int ok = 0;
-    if (hipGetDeviceProperties(&p, d) == hipSuccess) ok = std::strncmp(p.gcnArchName, "gfx950", 6) == 0;
+    if (hipGetDeviceProperties(&p, d) == hipSuccess) {
+      ok = std::strncmp(p.gcnArchName, "gfx950", 6) == 0;
+      if (ok) g_cus = p.multiProcessorCount;
+    }
     it = g_dev_ok.emplace(d, ok).first;
     logf("device %d arch ok=%d", d, ok);
   }
@@ -335,51 +423,25 @@ tpd_status_t run_schedule(const Schedule& s, const void* A, void* C, uint32_t* b
   if (s.prune && s.nsweep == 2) {
     if (launch_fill_u32(bitmap, s.bitmap_words, 0u, st) != hipSuccess) return TPD_ERROR_LAUNCH;
   }
-  // Tuning knobs (read per call): TPD_CHUNK_TD splits a two-sweep schedule
-  // into groups of that many 2^db-diagonal strips, running both sweeps on
-  // one group before the next so the intermediate of a group can stay in
-  // the memory-side cache; TPD_NT=1 selects non-temporal loads and stores.
-  const char* ce = std::getenv("TPD_CHUNK_TD");
-  const uint64_t chunk_env = ce ? (uint64_t)std::strtoull(ce, nullptr, 10) : (uint64_t)0;
-  const char* ne = std::getenv("TPD_NT");
-  const int nt_env = (ne && ne[0] == '1') ? 1 : 0;
-  const char* re = std::getenv("TPD_R");
-  const int r_env = re ? std::atoi(re) : 0;
-  const uint64_t ntd = s.nsweep == 2 ? ((uint64_t)1 << (s.n - s.sw[0].db)) : 0;
-  uint64_t chunk = (s.nsweep == 2 && chunk_env > 0 && chunk_env < ntd) ? chunk_env : 0;
-  if (chunk && (ntd % chunk)) chunk = 0;
-  const uint64_t nchunks = chunk ? ntd / chunk : 1;
-  for (uint64_t c = 0; c < nchunks; ++c) {
-    for (int i = 0; i < s.nsweep; ++i) {
-      SweepDesc w = s.sw[i];
-      if (s.nsweep == 2 && r_env >= 2 && r_env <= 4) w.r = r_env;
-      SweepArgs a{};
-      a.in = (i == 0) ? A : C;
-      a.out = C;
-      a.n = s.n;
-      a.xlo = w.xlo;
-      a.db = w.db;
-      a.nfix_d = s.n - w.db;
-      a.bitmap = bitmap;
-      a.bitmap_mode = w.bitmap_mode;
-      a.bm_xbits = s.n1;
-      a.nt = nt_env;
-      if (chunk) {
-        a.td0 = c * chunk;
-        a.tdn = chunk;
-        a.ntiles = (w.ntiles / ntd) * chunk;
-      } else {
-        a.td0 = 0;
-        a.tdn = 0;
-        a.ntiles = w.ntiles;
-      }
-      const int slot = tm ? tm->begin(i, st) : -1;
-      const hipError_t e = launch_sweep(s.dt, w, a, st);
-      if (tm) tm->end(i, slot, st);
-      if (e != hipSuccess) {
-        logf("sweep %d launch failed: %s", i, hipGetErrorString(e));
-        return TPD_ERROR_LAUNCH;
-      }
+  for (int i = 0; i < s.nsweep; ++i) {
+    const SweepDesc& w = s.sw[i];
+    SweepArgs a{};
+    a.in = (i == 0) ? A : C;
+    a.out = C;
+    a.n = s.n;
+    a.xlo = w.xlo;
+    a.db = w.db;
+    a.nfix_d = s.n - w.db;
+    a.bitmap = bitmap;
+    a.bitmap_mode = w.bitmap_mode;
+    a.bm_xbits = s.n1;
+    a.ntiles = w.ntiles;
+    const int slot = tm ? tm->begin(i, st) : -1;
+    const hipError_t e = launch_sweep(s.dt, w, a, st);
+    if (tm) tm->end(i, slot, st);
+    if (e != hipSuccess) {
+      logf("sweep %d launch failed: %s", i, hipGetErrorString(e));
+      return TPD_ERROR_LAUNCH;
     }
   }
   return TPD_SUCCESS;
@@ -438,12 +500,15 @@ tpd_status_t build_batch(const int* ns, int count, bool in_place, unsigned flags
 }
 
 int batched_grid(Dtype dt, uint32_t nitems) {
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+  const int cus = g_cus > 0 ? (int)g_cus : 256;
+  int per_cu = dt == DT_C128 ? 2 : 4;  // LDS-limited residency of the 256-thread item loop
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) load_tune_cache();
+    auto it = g_tuned.find(TuneKey{-1, (int)dt, 0, 0});
+    if (it != g_tuned.end()) per_cu = it->second.grid;  // 0: one workgroup per item
   }
-  const int per_cu = dt == DT_C128 ? 2 : 4;  // LDS-limited residency of the 256-thread item loop
+  if (per_cu <= 0) return (int)nitems;
   const int g = cus * per_cu;
   return (uint32_t)g > nitems ? (int)nitems : g;
 }
@@ -809,12 +874,18 @@ tpd_status_t tpd_decompose_batched(const void* const* ptrs, const int* ns, int c
 // host-side schedule access for the emulator (tpd_emulate.cpp)
 // ---------------------------------------------------------------------------
 namespace tpd {
-tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep, int* n1,
-                           uint64_t* bitmap_words) {
+tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, const int* tune, SweepDesc* sw,
+                           int* nsweep, int* n1, uint64_t* bitmap_words) {
   tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   Schedule s;
-  st = make_schedule(n, (Dtype)dtype, flags, in_place, &s);
+  Tuned t;
+  if (tune) {
+    t.db = tune[0];
+    t.r = tune[1];
+    t.grid = tune[2];
+  }
+  st = make_schedule_with(n, (Dtype)dtype, flags, in_place, tune && n > 8 ? &t : nullptr, &s);
   if (st) return st;
   for (int i = 0; i < s.nsweep; ++i) sw[i] = s.sw[i];
   *nsweep = s.nsweep;
@@ -835,3 +906,188 @@ tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned
   return TPD_SUCCESS;
 }
 }  // namespace tpd
+
+// ---------------------------------------------------------------------------
+// autotuning
+// ---------------------------------------------------------------------------
+namespace {
+double median3(std::vector<float>& v) {
+  std::sort(v.begin(), v.end());
+  return v.empty() ? 0.0 : v[v.size() / 2];
+}
+}  // namespace
+
+extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
+                                     tpd_stream_t stream, char* report, size_t len) {
+  tpd_status_t st = check_dtype_flags(dtype, flags);
+  if (st) return st;
+  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  const Dtype dt = (Dtype)dtype;
+  st = check_buffers(A, coeffs, n, dt);
+  if (st) return st;
+  const bool in_place = A == coeffs;
+  Schedule base;
+  st = make_schedule(n, dt, flags & ~TPD_FLAG_ORDER_BOTTOM, in_place, &base);
+  if (st) return st;
+  int dev;
+  st = current_device(&dev);
+  if (st) return st;
+  std::string rep;
+  if (base.nsweep != 2) {
+    rep = "{\"tuned\":false,\"reason\":\"single-sweep schedule has no tunables\"}";
+    return report ? copy_out(rep, report, len) : TPD_SUCCESS;
+  }
+  hipStream_t hs = (hipStream_t)stream;
+  // in place every run transforms the previous result; pruning is switched
+  // off while timing so that vanishing values cannot skip work
+  const unsigned tflags = (flags & ~TPD_FLAG_ORDER_BOTTOM) | (in_place ? TPD_FLAG_NO_PRUNE : 0u);
+  const int dbs128[3] = {3, 4, 5}, dbs64[3] = {4, 5, 6};
+  const int* dbs = dt == DT_C128 ? dbs128 : dbs64;
+  const int rs[2] = {4, 3};
+  const int grids[4] = {0, 1, 2, 4};
+  std::vector<Tuned> cands;
+  uint64_t max_words = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int r : rs)
+      for (int g : grids) {
+        Tuned t;
+        t.db = dbs[i];
+        t.r = r;
+        t.grid = g;
+        Schedule sc;
+        if (make_schedule_with(n, dt, tflags, in_place, &t, &sc) != TPD_SUCCESS) continue;
+        cands.push_back(t);
+        if (sc.bitmap_words > max_words) max_words = sc.bitmap_words;
+      }
+  if (cands.empty()) return TPD_ERROR_INTERNAL;
+  uint32_t* bm = nullptr;
+  {
+    void* p = nullptr;
+    st = dev_alloc(&p, (size_t)max_words * 4);
+    if (st) return st;
+    bm = (uint32_t*)p;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    (void)hipFree(bm);
+    return TPD_ERROR_OUT_OF_MEMORY;
+  }
+  double best = 1e300;
+  Tuned best_t = cands[0];
+  rep = "{\"tuned\":true,\"n\":" + std::to_string(n) + ",\"dtype\":\"" + (dt == DT_C128 ? "c128" : "c64") +
+        "\",\"candidates\":[";
+  bool first = true;
+  for (const Tuned& t : cands) {
+    Schedule sc;
+    if (make_schedule_with(n, dt, tflags, in_place, &t, &sc) != TPD_SUCCESS) continue;
+    st = run_schedule(sc, A, coeffs, bm, hs, nullptr);  // warm-up
+    if (st) break;
+    std::vector<float> ms;
+    for (int rep_i = 0; rep_i < 3 && !st; ++rep_i) {
+      if (hipEventRecord(e0, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
+      if (!st) st = run_schedule(sc, A, coeffs, bm, hs, nullptr);
+      if (!st && hipEventRecord(e1, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
+      float t_ms = 0;
+      if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t_ms, e0, e1) != hipSuccess))
+        st = TPD_ERROR_LAUNCH;
+      ms.push_back(t_ms);
+    }
+    if (st) break;
+    const double med = median3(ms);
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s{\"db\":%d,\"r\":%d,\"grid_per_cu\":%d,\"ms\":%.4f}", first ? "" : ",", t.db,
+                  t.r, t.grid, med);
+    rep += buf;
+    first = false;
+    if (med < best) {
+      best = med;
+      best_t = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(hs);
+  (void)hipFree(bm);
+  if (st) return st;
+  const TuneKey key{n, (int)dt, (flags & TPD_FLAG_LAYOUT_MATRIX) ? 1 : 0, in_place ? 1 : 0};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) load_tune_cache();
+    g_tuned[key] = best_t;
+    save_tune_entry(key, best_t);
+  }
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "],\"chosen\":{\"db\":%d,\"r\":%d,\"grid_per_cu\":%d,\"ms\":%.4f}}", best_t.db,
+                best_t.r, best_t.grid, best);
+  rep += buf;
+  logf("autotune %s", rep.c_str());
+  return report ? copy_out(rep, report, len) : TPD_SUCCESS;
+}
+
+extern "C" tpd_status_t tpd_autotune_batched(tpd_plan_t plan, const void* const* d_ptrs, void* const* d_out_ptrs,
+                                             tpd_stream_t stream, char* report, size_t len) {
+  if (!plan || !plan->batched || !d_ptrs) return TPD_ERROR_INVALID_VALUE;
+  if (!d_out_ptrs && !plan->in_place) return TPD_ERROR_INVALID_VALUE;
+  if (plan->nitems == 0) return TPD_SUCCESS;
+  hipStream_t hs = (hipStream_t)stream;
+  const int cus = g_cus > 0 ? (int)g_cus : 256;
+  const int mults[7] = {1, 2, 3, 4, 6, 8, 0};  // 0: one workgroup per item
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return TPD_ERROR_OUT_OF_MEMORY;
+  }
+  const int layout = (plan->flags & TPD_FLAG_LAYOUT_MATRIX) ? L_MAT : L_CAN;
+  void* const* outs = d_out_ptrs ? d_out_ptrs : (void* const*)d_ptrs;
+  double best = 1e300;
+  int best_m = 2, best_grid = plan->grid;
+  std::string rep = "{\"tuned\":true,\"batched\":true,\"candidates\":[";
+  tpd_status_t st = TPD_SUCCESS;
+  for (int i = 0; i < 7 && !st; ++i) {
+    const int m = mults[i];
+    int grid = m > 0 ? m * cus : (int)plan->nitems;
+    if ((uint32_t)grid > plan->nitems) grid = (int)plan->nitems;
+    std::vector<float> ms;
+    for (int k = 0; k < 6 && !st; ++k) {
+      if (hipEventRecord(e0, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
+      if (!st && launch_batched_perm(plan->dt, d_ptrs, outs, plan->d_perm, plan->d_items, plan->nitems, layout,
+                                     grid, hs) != hipSuccess)
+        st = TPD_ERROR_LAUNCH;
+      if (!st && hipEventRecord(e1, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
+      float t_ms = 0;
+      if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t_ms, e0, e1) != hipSuccess))
+        st = TPD_ERROR_LAUNCH;
+      if (k > 0) ms.push_back(t_ms);  // the first launch is a warm-up
+    }
+    if (st) break;
+    const double med = median3(ms);
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "%s{\"grid_per_cu\":%d,\"grid\":%d,\"ms\":%.4f}", i ? "," : "", m, grid, med);
+    rep += buf;
+    if (med < best) {
+      best = med;
+      best_m = m;
+      best_grid = grid;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  plan->grid = best_grid;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) load_tune_cache();
+    Tuned t;
+    t.db = 0;
+    t.r = 4;
+    t.grid = best_m;
+    const TuneKey key{-1, (int)plan->dt, 0, 0};
+    g_tuned[key] = t;
+    save_tune_entry(key, t);
+  }
+  char buf[128];
+  std::snprintf(buf, sizeof buf, "],\"chosen\":{\"grid_per_cu\":%d,\"grid\":%d,\"ms\":%.4f}}", best_m, best_grid, best);
+  rep += buf;
+  return report ? copy_out(rep, report, len) : TPD_SUCCESS;
+}

@@ -58,8 +58,8 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
   uint32_t bits[NBW];
 
   for (uint64_t tile = 0; tile < a.ntiles; ++tile) {
-    const uint64_t td = a.tdn ? a.td0 + tile % a.tdn : (tile & tdmask);
-    const uint64_t xf = a.tdn ? tile / a.tdn : (tile >> a.nfix_d);
+    const uint64_t td = tile & tdmask;
+    const uint64_t xf = tile >> a.nfix_d;
     const uint64_t xfix = (xf & (((uint64_t)1 << xlo) - 1)) | ((xf >> xlo) << (xlo + G::XB));
     if (a.bitmap_mode == 2) {
       const uint64_t bit = (td << a.bm_xbits) | xf;
@@ -188,10 +188,10 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
   return ck.ok ? TPD_SUCCESS : TPD_ERROR_INTERNAL;
 }
 
-template <class S, int XB, int DB, int ORDER, int RR = 4>
+template <class S, int XB, int DB, int ORDER, int RR>
 tpd_status_t emulate_layouts(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint32_t* bm,
                              Checker& ck) {
-  // at most 1024 threads per tile, at most 16 registers per thread
+  // same thread-count cap as the device launcher
   constexpr int R1 = (XB + DB - 10) > RR ? (XB + DB - 10) : RR;
   constexpr int R = (XB + DB) < R1 ? (XB + DB) : R1;
   using G = Geom<XB, DB, 0, R, ORDER>;
@@ -202,23 +202,44 @@ tpd_status_t emulate_layouts(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, co
   return TPD_ERROR_INTERNAL;
 }
 
+template <class S, int XB, int DB>
+tpd_status_t emulate_r(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint32_t* bm,
+                       Checker& ck) {
+  if (s.order == 1) return emulate_layouts<S, XB, DB, 1, 4>(s, in, out, a, bm, ck);
+  if (s.r == 3) return emulate_layouts<S, XB, DB, 0, 3>(s, in, out, a, bm, ck);
+  return emulate_layouts<S, XB, DB, 0, 4>(s, in, out, a, bm, ck);
+}
+
+template <class S, int DB>
+tpd_status_t emulate_xb(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint32_t* bm,
+                        Checker& ck) {
+  switch (s.xb) {
+    case 4: return emulate_r<S, 4, DB>(s, in, out, a, bm, ck);
+    case 5: return emulate_r<S, 5, DB>(s, in, out, a, bm, ck);
+    case 6: return emulate_r<S, 6, DB>(s, in, out, a, bm, ck);
+    case 7: return emulate_r<S, 7, DB>(s, in, out, a, bm, ck);
+    case 8: return emulate_r<S, 8, DB>(s, in, out, a, bm, ck);
+  }
+  return TPD_ERROR_INTERNAL;
+}
+
 template <class S>
 tpd_status_t emulate_shape(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint32_t* bm,
                            Checker& ck) {
-#define TPD_CASE(XB_, DB_)                                                                              \
-  if (s.xb == XB_ && s.db == DB_) {                                                                     \
-    if (s.r == 2)                                                                                       \
-      return s.order == 0 ? emulate_layouts<S, XB_, DB_, 0, 2>(s, in, out, a, bm, ck)                   \
-                          : emulate_layouts<S, XB_, DB_, 1, 2>(s, in, out, a, bm, ck);                  \
-    if (s.r == 3)                                                                                       \
-      return s.order == 0 ? emulate_layouts<S, XB_, DB_, 0, 3>(s, in, out, a, bm, ck)                   \
-                          : emulate_layouts<S, XB_, DB_, 1, 3>(s, in, out, a, bm, ck);                  \
-    return s.order == 0 ? emulate_layouts<S, XB_, DB_, 0>(s, in, out, a, bm, ck)                        \
-                        : emulate_layouts<S, XB_, DB_, 1>(s, in, out, a, bm, ck);                       \
-  }
-  TPD_SHAPES_ONE(TPD_CASE)
-  TPD_SHAPES_TWO(TPD_CASE)
+  if (s.is_one) {
+#define TPD_CASE(XB_, DB_) \
+    if (s.xb == XB_ && s.db == DB_) return emulate_layouts<S, XB_, DB_, 0, 4>(s, in, out, a, bm, ck);
+    TPD_CASE(1, 1) TPD_CASE(2, 2) TPD_CASE(3, 3) TPD_CASE(4, 4) TPD_CASE(5, 5) TPD_CASE(6, 6) TPD_CASE(7, 5)
+    TPD_CASE(8, 4)
 #undef TPD_CASE
+    return TPD_ERROR_INTERNAL;
+  }
+  switch (s.db) {
+    case 3: return emulate_xb<S, 3>(s, in, out, a, bm, ck);
+    case 4: return emulate_xb<S, 4>(s, in, out, a, bm, ck);
+    case 5: return emulate_xb<S, 5>(s, in, out, a, bm, ck);
+    case 6: return emulate_xb<S, 6>(s, in, out, a, bm, ck);
+  }
   return TPD_ERROR_INTERNAL;
 }
 
@@ -301,21 +322,22 @@ tpd_status_t emulate_item_n(const void* const* ptrs, void* const* outs, const ui
 
 namespace tpd {
 // defined in tpd_api.cpp
-tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep, int* n1,
-                           uint64_t* bitmap_words);
+tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, const int* tune, SweepDesc* sw,
+                           int* nsweep, int* n1, uint64_t* bitmap_words);
 tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, std::vector<uint32_t>* perm,
                                std::vector<BatchItem>* items);
 }  // namespace tpd
 
-extern "C" tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
-                                          int in_place) {
+extern "C" tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype,
+                                                unsigned flags, int in_place, int db, int r) {
   if (!A || !coeffs) return TPD_ERROR_INVALID_VALUE;
   if (n < 0 || n > 12) return TPD_ERROR_UNSUPPORTED;  // host replay is for small n
   if (in_place && A != coeffs) return TPD_ERROR_INVALID_VALUE;
   SweepDesc sw[2];
   int nsweep = 0, n1 = 0;
   uint64_t words = 0;
-  tpd_status_t st = host_schedule(n, dtype, flags, in_place != 0, sw, &nsweep, &n1, &words);
+  const int tune[3] = {db, r, 0};
+  tpd_status_t st = host_schedule(n, dtype, flags, in_place != 0, db > 0 ? tune : nullptr, sw, &nsweep, &n1, &words);
   if (st) return st;
   const uint64_t count = (uint64_t)1 << (2 * n);
   const size_t eb = dtype == TPD_C128 ? 16 : 8;
@@ -324,10 +346,7 @@ extern "C" tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tp
     return TPD_SUCCESS;
   }
   std::vector<uint32_t> bitmap(words ? words : 1, 0u);
-  const char* re = std::getenv("TPD_R");
-  const int r_env = re ? std::atoi(re) : 0;
   for (int i = 0; i < nsweep; ++i) {
-    if (nsweep == 2 && r_env >= 2 && r_env <= 4) sw[i].r = r_env;
     SweepArgs a{};
     a.in = i == 0 ? A : coeffs;
     a.out = coeffs;
@@ -348,6 +367,11 @@ extern "C" tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tp
     if (!ck.complete()) return TPD_ERROR_INTERNAL;
   }
   return TPD_SUCCESS;
+}
+
+extern "C" tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
+                                          int in_place) {
+  return tpd_debug_emulate_tuned(A, n, coeffs, dtype, flags, in_place, 0, 0);
 }
 
 extern "C" tpd_status_t tpd_debug_emulate_batched(const void* const* ptrs, const int* ns, int count,

@@ -17,7 +17,9 @@ struct SweepDesc {
   int in_layout, out_layout;
   int bitmap_mode;  // 0 none, 1 set (first sweep), 2 check (second sweep)
   int order;        // register-phase order: 0 top levels first, 1 bottom first
-  int r;            // log2 of the elements each thread holds (2, 3 or 4)
+  int r;            // log2 of the elements each thread holds (3 or 4)
+  int grid;         // 0: one workgroup per tile; > 0: persistent grid of that size
+  bool is_one;      // the single sweep of an n <= 8 schedule
   uint64_t ntiles;
 };
 
@@ -31,10 +33,7 @@ struct SweepArgs {
   uint32_t* bitmap;  // 32-bit words, one bit per second-sweep tile
   int bitmap_mode;
   int bm_xbits;      // x bits of the first sweep (bit index = (td << bm_xbits) | x_hi)
-  uint64_t ntiles;   // tiles of this launch
-  uint64_t td0;      // first d-group of this launch
-  uint64_t tdn;      // d-groups per launch (tile = xf * tdn + (td - td0))
-  int nt;            // 1: non-temporal loads and stores
+  uint64_t ntiles;
 };
 
 // Batched work item: `nmat` matrices of the same n starting at `mat0`
@@ -64,16 +63,11 @@ hipError_t launch_batched_perm(Dtype dt, const void* const* in_ptrs, void* const
                                const BatchItem* items, uint32_t nitems, int layout, int grid, hipStream_t st);
 hipError_t launch_popcount(const uint32_t* p, uint64_t words, unsigned long long* out, hipStream_t st);
 
-// (xb, db) sweep tile shapes: one-sweep n = 1..8 (MAT -> CAN / MAT), and
-// the halves of the two-sweep schedule with db = 4 (complex128) or 5
-// (complex64): first sweeps MAT -> MID / MAT, second sweeps MID -> CAN / MAT
-#define TPD_SHAPES_ONE(X) X(1, 1) X(2, 2) X(3, 3) X(4, 4) X(5, 5) X(6, 6) X(7, 5) X(8, 4)
-#define TPD_SHAPES_TWO(X) X(4, 4) X(5, 4) X(6, 4) X(7, 4) X(8, 4) X(5, 5) X(6, 5) X(7, 5) X(8, 5)
-
-// a sweep tile must fit the 64 KiB of LDS one workgroup may allocate
+// a sweep tile (plus its small bitmap scratch) must fit the LDS of one
+// workgroup; gfx950 gives a workgroup up to 160 KiB, tiles use <= 128 KiB
 template <class S>
 constexpr bool shape_fits(int xb, int db) {
-  return ((size_t)sizeof(Cx<S>) << (xb + db)) <= 65536;
+  return ((size_t)sizeof(Cx<S>) << (xb + db)) <= 131072;
 }
 
 // batched tile geometry per n (shared with the host emulator and planner)

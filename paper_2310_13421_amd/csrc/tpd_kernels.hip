@@ -26,144 +26,6 @@
 
 namespace tpd {
 
-// non-temporal complex loads and stores through native 2-vectors
-typedef double tpd_d2 __attribute__((ext_vector_type(2)));
-typedef float tpd_f2 __attribute__((ext_vector_type(2)));
-template <class S> struct Vec2;
-template <> struct Vec2<double> { using type = tpd_d2; };
-template <> struct Vec2<float> { using type = tpd_f2; };
-
-template <class S>
-__device__ __forceinline__ Cx<S> load_nt(const Cx<S>* p) {
-  using V = typename Vec2<S>::type;
-  const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
-  return Cx<S>{v.x, v.y};
-}
-template <class S>
-__device__ __forceinline__ void store_nt(Cx<S>* p, const Cx<S>& c) {
-  using V = typename Vec2<S>::type;
-  V v;
-  v.x = c.re;
-  v.y = c.im;
-  __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
-}
-
-// ---------------------------------------------------------------------------
-// single-matrix sweep
-// ---------------------------------------------------------------------------
-template <class S, class G, int INL, int OUTL>
-__global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
-  static constexpr Roles RL = make_roles<G>();
-  constexpr int P = G::NPH;
-  constexpr int LAST = P - 1;
-  constexpr uint32_t DM = (1u << G::DB) - 1;
-  constexpr uint32_t XM = (1u << G::XB) - 1;
-  constexpr int NBW = (1 << G::XB) >= 32 ? (1 << G::XB) / 32 : 1;
-  __shared__ Cx<S> lds[(P > 1) ? (1 << G::B) : 1];
-  __shared__ uint32_t bits[NBW];
-
-  const uint32_t tid = threadIdx.x;
-  const Cx<S>* __restrict__ in = (const Cx<S>*)a.in;
-  Cx<S>* __restrict__ out = (Cx<S>*)a.out;
-  const int n = a.n, xlo = a.xlo, db = a.db;
-  const uint64_t tdmask = ((uint64_t)1 << a.nfix_d) - 1;
-
-  // register-slot address deltas (layouts are XOR-linear in (x, d))
-  uint64_t din[G::R], dout[G::R];
-#pragma unroll
-  for (int s = 0; s < G::R; ++s) {
-    const uint32_t ei = 1u << RL.reg[0][s];
-    din[s] = layout_addr<INL>((uint64_t)((ei >> G::DB) & XM) << xlo, ei & DM, n, db);
-    const uint32_t eo = 1u << RL.reg[LAST][s];
-    dout[s] = layout_addr<OUTL>((uint64_t)((eo >> G::DB) & XM) << xlo, eo & DM, n, db);
-  }
-  const uint32_t eb0 = elem_base<G>(RL, 0, tid);
-  const uint32_t ebl = elem_base<G>(RL, LAST, tid);
-
-  for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    const uint64_t td = a.tdn ? a.td0 + tile % a.tdn : (tile & tdmask);
-    const uint64_t xf = a.tdn ? tile / a.tdn : (tile >> a.nfix_d);
-    const uint64_t xfix = (xf & (((uint64_t)1 << xlo) - 1)) | ((xf >> xlo) << (xlo + G::XB));
-    if (a.bitmap_mode == 2) {
-      const uint64_t bit = (td << a.bm_xbits) | xf;
-      if (!((a.bitmap[bit >> 5] >> (bit & 31)) & 1u)) continue;  // zero subtree
-    }
-    if (a.bitmap_mode == 1 && tid < NBW) bits[tid] = 0;
-
-    Cx<S> v[G::E];
-    {
-      const uint64_t x = xfix | ((uint64_t)((eb0 >> G::DB) & XM) << xlo);
-      const uint64_t d = (td << G::DB) | (eb0 & DM);
-      const uint64_t base = layout_addr<INL>(x, d, n, db);
-#pragma unroll
-      for (int j = 0; j < G::E; ++j) {
-        uint64_t ad = base;
-#pragma unroll
-        for (int s = 0; s < G::R; ++s)
-          if ((j >> s) & 1) ad ^= din[s];
-        v[j] = a.nt ? load_nt(&in[ad]) : in[ad];
-      }
-    }
-
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const uint32_t ebp = elem_base<G>(RL, p, tid);
-      phase_butterflies<G, S>(RL, p, v, (td << G::DB) | (ebp & DM), xlo);
-      if (p + 1 < P) {
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < G::E; ++j) lds[ebp | elem_reg<G>(RL, p, j)] = v[j];
-        __syncthreads();
-        const uint32_t ebn = elem_base<G>(RL, p + 1, tid);
-#pragma unroll
-        for (int j = 0; j < G::E; ++j) v[j] = lds[ebn | elem_reg<G>(RL, p + 1, j)];
-      }
-    }
-
-    if (a.bitmap_mode == 1) {
-      // OR "any nonzero" over the 2^DB diagonals (lanes [0, DB)) of each row
-      // block; one bit per second-sweep tile (td, x_hi).  NaN counts as nonzero.
-      const uint32_t lane = tid & 63u;
-      constexpr uint32_t gsz = 1u << G::DB;
-      constexpr uint64_t gmask = gsz >= 64 ? ~0ull : ((1ull << gsz) - 1);
-      if (P == 1) __syncthreads();
-#pragma unroll
-      for (int j = 0; j < G::E; ++j) {
-        const bool nz = (v[j].re != (S)0) || (v[j].im != (S)0);
-        const uint64_t m = __ballot(nz);
-        if ((lane & (gsz - 1)) == 0 && ((m >> lane) & gmask)) {
-          const uint32_t xl = ((ebl | elem_reg<G>(RL, LAST, j)) >> G::DB) & XM;
-          atomicOr(&bits[xl >> 5], 1u << (xl & 31));
-        }
-      }
-      __syncthreads();
-      if (tid < NBW) {
-        const uint32_t w = bits[tid];
-        if (w) {
-          const uint64_t b0 = (td << a.bm_xbits) + 32ull * tid;
-          atomicOr(&a.bitmap[b0 >> 5], w << (b0 & 31));
-        }
-      }
-    }
-
-    if (P == 1 && INL != OUTL) __syncthreads();  // in place: all loads before any store
-    {
-      const uint64_t x = xfix | ((uint64_t)((ebl >> G::DB) & XM) << xlo);
-      const uint64_t d = (td << G::DB) | (ebl & DM);
-      const uint64_t base = layout_addr<OUTL>(x, d, n, db);
-#pragma unroll
-      for (int j = 0; j < G::E; ++j) {
-        uint64_t ad = base;
-#pragma unroll
-        for (int s = 0; s < G::R; ++s)
-          if ((j >> s) & 1) ad ^= dout[s];
-        if (a.nt) store_nt(&out[ad], v[j]);
-        else out[ad] = v[j];
-      }
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // batched persistent kernel: one work item = packed whole matrices (n <= 6)
 // or one d-group tile of one matrix (n = 7..9); every item is a single sweep.
@@ -320,66 +182,20 @@ hipError_t launch_batched_perm(Dtype dt, const void* const* in_ptrs, void* const
 }
 
 // ---------------------------------------------------------------------------
-// sweep dispatch
+// sweep dispatch (instantiations live in tpd_sweep_c128.hip / tpd_sweep_c64.hip)
 // ---------------------------------------------------------------------------
-template <class S, int XB, int DB, int ORDER, int INL, int OUTL, int RR = 4>
-static hipError_t launch_one(const SweepArgs& a, hipStream_t st) {
-  // at most 1024 threads per tile, at most 16 registers per thread
-  constexpr int R1 = (XB + DB - 10) > RR ? (XB + DB - 10) : RR;
-  constexpr int R = (XB + DB) < R1 ? (XB + DB) : R1;
-  using G = Geom<XB, DB, 0, R, ORDER>;
-  if constexpr (!shape_fits<S>(XB, DB)) {
-    return hipErrorInvalidValue;
-  } else {
-  uint64_t grid = a.ntiles;
-  if (grid > 0x7FFFFFFFull) grid = 0x7FFFFFFFull;
-  hipLaunchKernelGGL((k_sweep<S, G, INL, OUTL>), dim3((unsigned)grid), dim3(G::NT), 0, st, a);
-  return hipGetLastError();
-  }
-}
-
-template <class S>
-static hipError_t dispatch_shape(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
-  const bool one = s.in_layout == L_MAT && s.xlo == 0 && s.xb == a.n;
-#define TPD_CASE(XB_, DB_)                                                                   \
-  if (one && s.xb == XB_ && s.db == DB_) {                                                   \
-    if (s.out_layout == L_CAN) return launch_one<S, XB_, DB_, 0, L_MAT, L_CAN>(a, st);       \
-    if (s.out_layout == L_MAT) return launch_one<S, XB_, DB_, 0, L_MAT, L_MAT>(a, st);       \
-  }
-  TPD_SHAPES_ONE(TPD_CASE)
-#undef TPD_CASE
-#define TPD_TWO(XB_, DB_, RR_)                                                                        \
-  if (s.in_layout == L_MAT && s.out_layout == L_MID) return launch_one<S, XB_, DB_, 0, L_MAT, L_MID, RR_>(a, st); \
-  if (s.in_layout == L_MID && s.out_layout == L_CAN)                                                  \
-    return s.order ? launch_one<S, XB_, DB_, 1, L_MID, L_CAN, RR_>(a, st)                            \
-                   : launch_one<S, XB_, DB_, 0, L_MID, L_CAN, RR_>(a, st);                           \
-  if (s.in_layout == L_MAT && s.out_layout == L_MAT)                                                  \
-    return s.order ? launch_one<S, XB_, DB_, 1, L_MAT, L_MAT, RR_>(a, st)                            \
-                   : launch_one<S, XB_, DB_, 0, L_MAT, L_MAT, RR_>(a, st);
-#define TPD_CASE(XB_, DB_)                             \
-  if (!one && s.xb == XB_ && s.db == DB_) {            \
-    if (s.r == 2) { TPD_TWO(XB_, DB_, 2) }             \
-    else if (s.r == 3) { TPD_TWO(XB_, DB_, 3) }        \
-    else { TPD_TWO(XB_, DB_, 4) }                      \
-  }
-  TPD_SHAPES_TWO(TPD_CASE)
-#undef TPD_CASE
-#undef TPD_TWO
-  return hipErrorInvalidValue;
-}
+bool sweep_supported_c128(const SweepDesc& s);
+bool sweep_supported_c64(const SweepDesc& s);
+hipError_t launch_sweep_c128(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
+hipError_t launch_sweep_c64(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
 
 bool sweep_supported(Dtype dt, const SweepDesc& s) {
-#define TPD_CASE(XB_, DB_) \
-  if (s.xb == XB_ && s.db == DB_) return dt == DT_C128 ? shape_fits<double>(XB_, DB_) : shape_fits<float>(XB_, DB_);
-  TPD_SHAPES_ONE(TPD_CASE)
-  TPD_SHAPES_TWO(TPD_CASE)
-#undef TPD_CASE
-  return false;
+  return dt == DT_C128 ? sweep_supported_c128(s) : sweep_supported_c64(s);
 }
 
 hipError_t launch_sweep(Dtype dt, const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
   if (a.ntiles == 0) return hipSuccess;
-  return dt == DT_C128 ? dispatch_shape<double>(s, a, st) : dispatch_shape<float>(s, a, st);
+  return dt == DT_C128 ? launch_sweep_c128(s, a, st) : launch_sweep_c64(s, a, st);
 }
 
 }  // namespace tpd

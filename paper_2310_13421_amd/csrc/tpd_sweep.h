@@ -1,0 +1,202 @@
+// tpd_sweep.h -- the single-matrix sweep kernel template and its
+// per-dtype dispatch (instantiated once per dtype in tpd_sweep_c128.hip and
+// tpd_sweep_c64.hip so the two compile in parallel).
+//
+// One launch = one HBM sweep over a single matrix: every tile of
+// 2^XB rows x 2^DB XOR-diagonals is loaded (16 B/8 B per element, runs of
+// 2^DB elements), transformed on its XB levels through register phases of
+// R levels with LDS exchanges between phases, and stored.  See tpd_core.h
+// for the coordinates and layouts and tpd_kernels.hip for the schedules.
+#pragma once
+#include "tpd_internal.h"
+
+namespace tpd {
+
+// ---------------------------------------------------------------------------
+// single-matrix sweep
+// ---------------------------------------------------------------------------
+template <class S, class G, int INL, int OUTL>
+__global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
+  static constexpr Roles RL = make_roles<G>();
+  constexpr int P = G::NPH;
+  constexpr int LAST = P - 1;
+  constexpr uint32_t DM = (1u << G::DB) - 1;
+  constexpr uint32_t XM = (1u << G::XB) - 1;
+  constexpr int NBW = (1 << G::XB) >= 32 ? (1 << G::XB) / 32 : 1;
+  __shared__ Cx<S> lds[(P > 1) ? (1 << G::B) : 1];
+  __shared__ uint32_t bits[NBW];
+
+  const uint32_t tid = threadIdx.x;
+  const Cx<S>* __restrict__ in = (const Cx<S>*)a.in;
+  Cx<S>* __restrict__ out = (Cx<S>*)a.out;
+  const int n = a.n, xlo = a.xlo, db = a.db;
+  const uint64_t tdmask = ((uint64_t)1 << a.nfix_d) - 1;
+
+  // register-slot address deltas (layouts are XOR-linear in (x, d))
+  uint64_t din[G::R], dout[G::R];
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) {
+    const uint32_t ei = 1u << RL.reg[0][s];
+    din[s] = layout_addr<INL>((uint64_t)((ei >> G::DB) & XM) << xlo, ei & DM, n, db);
+    const uint32_t eo = 1u << RL.reg[LAST][s];
+    dout[s] = layout_addr<OUTL>((uint64_t)((eo >> G::DB) & XM) << xlo, eo & DM, n, db);
+  }
+  const uint32_t eb0 = elem_base<G>(RL, 0, tid);
+  const uint32_t ebl = elem_base<G>(RL, LAST, tid);
+
+  for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const uint64_t td = tile & tdmask;
+    const uint64_t xf = tile >> a.nfix_d;
+    const uint64_t xfix = (xf & (((uint64_t)1 << xlo) - 1)) | ((xf >> xlo) << (xlo + G::XB));
+    if (a.bitmap_mode == 2) {
+      const uint64_t bit = (td << a.bm_xbits) | xf;
+      if (!((a.bitmap[bit >> 5] >> (bit & 31)) & 1u)) continue;  // zero subtree
+    }
+    if (a.bitmap_mode == 1 && tid < NBW) bits[tid] = 0;
+
+    Cx<S> v[G::E];
+    {
+      const uint64_t x = xfix | ((uint64_t)((eb0 >> G::DB) & XM) << xlo);
+      const uint64_t d = (td << G::DB) | (eb0 & DM);
+      const uint64_t base = layout_addr<INL>(x, d, n, db);
+#pragma unroll
+      for (int j = 0; j < G::E; ++j) {
+        uint64_t ad = base;
+#pragma unroll
+        for (int s = 0; s < G::R; ++s)
+          if ((j >> s) & 1) ad ^= din[s];
+        v[j] = in[ad];
+      }
+    }
+
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const uint32_t ebp = elem_base<G>(RL, p, tid);
+      phase_butterflies<G, S>(RL, p, v, (td << G::DB) | (ebp & DM), xlo);
+      if (p + 1 < P) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < G::E; ++j) lds[ebp | elem_reg<G>(RL, p, j)] = v[j];
+        __syncthreads();
+        const uint32_t ebn = elem_base<G>(RL, p + 1, tid);
+#pragma unroll
+        for (int j = 0; j < G::E; ++j) v[j] = lds[ebn | elem_reg<G>(RL, p + 1, j)];
+      }
+    }
+
+    if (a.bitmap_mode == 1) {
+      // OR "any nonzero" over the 2^DB diagonals (lanes [0, DB)) of each row
+      // block; one bit per second-sweep tile (td, x_hi).  NaN counts as nonzero.
+      const uint32_t lane = tid & 63u;
+      constexpr uint32_t gsz = 1u << G::DB;
+      constexpr uint64_t gmask = gsz >= 64 ? ~0ull : ((1ull << gsz) - 1);
+      if (P == 1) __syncthreads();
+#pragma unroll
+      for (int j = 0; j < G::E; ++j) {
+        const bool nz = (v[j].re != (S)0) || (v[j].im != (S)0);
+        const uint64_t m = __ballot(nz);
+        if ((lane & (gsz - 1)) == 0 && ((m >> lane) & gmask)) {
+          const uint32_t xl = ((ebl | elem_reg<G>(RL, LAST, j)) >> G::DB) & XM;
+          atomicOr(&bits[xl >> 5], 1u << (xl & 31));
+        }
+      }
+      __syncthreads();
+      if (tid < NBW) {
+        const uint32_t w = bits[tid];
+        if (w) {
+          const uint64_t b0 = (td << a.bm_xbits) + 32ull * tid;
+          atomicOr(&a.bitmap[b0 >> 5], w << (b0 & 31));
+        }
+      }
+    }
+
+    if (P == 1 && INL != OUTL) __syncthreads();  // in place: all loads before any store
+    {
+      const uint64_t x = xfix | ((uint64_t)((ebl >> G::DB) & XM) << xlo);
+      const uint64_t d = (td << G::DB) | (ebl & DM);
+      const uint64_t base = layout_addr<OUTL>(x, d, n, db);
+#pragma unroll
+      for (int j = 0; j < G::E; ++j) {
+        uint64_t ad = base;
+#pragma unroll
+        for (int s = 0; s < G::R; ++s)
+          if ((j >> s) & 1) ad ^= dout[s];
+        out[ad] = v[j];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch of one instantiation
+// ---------------------------------------------------------------------------
+template <class S, int XB, int DB, int ORDER, int INL, int OUTL, int RR>
+hipError_t launch_one(const SweepArgs& a, int grid_req, hipStream_t st) {
+  // at most 1024 threads per tile, at most 16 registers per thread
+  constexpr int R1 = (XB + DB - 10) > RR ? (XB + DB - 10) : RR;
+  constexpr int R = (XB + DB) < R1 ? (XB + DB) : R1;
+  using G = Geom<XB, DB, 0, R, ORDER>;
+  if constexpr (!shape_fits<S>(XB, DB)) {
+    return hipErrorInvalidValue;
+  } else {
+    // one workgroup per tile, or a persistent grid that loops over tiles;
+    // HIP needs grid * block < 2^32 threads
+    uint64_t grid = grid_req > 0 ? (uint64_t)grid_req : a.ntiles;
+    if (grid > a.ntiles) grid = a.ntiles;
+    const uint64_t cap = 0xFFFFFFFFull / (uint64_t)G::NT;
+    if (grid > cap) grid = cap;
+    hipLaunchKernelGGL((k_sweep<S, G, INL, OUTL>), dim3((unsigned)grid), dim3(G::NT), 0, st, a);
+    return hipGetLastError();
+  }
+}
+
+// one-sweep shapes (n <= 8): MAT -> CAN or MAT -> MAT, R = 4
+#define TPD_ONE_SHAPES(X) X(1, 1) X(2, 2) X(3, 3) X(4, 4) X(5, 5) X(6, 6) X(7, 5) X(8, 4)
+
+template <class S>
+hipError_t dispatch_one(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
+#define TPD_CASE(XB_, DB_)                                                                           \
+  if (s.xb == XB_ && s.db == DB_) {                                                                  \
+    if (s.out_layout == L_CAN) return launch_one<S, XB_, DB_, 0, L_MAT, L_CAN, 4>(a, s.grid, st);    \
+    if (s.out_layout == L_MAT) return launch_one<S, XB_, DB_, 0, L_MAT, L_MAT, 4>(a, s.grid, st);    \
+  }
+  TPD_ONE_SHAPES(TPD_CASE)
+#undef TPD_CASE
+  return hipErrorInvalidValue;
+}
+
+// two-sweep halves: XB in 4..8 for the tile widths DB of one dtype and
+// register depths R in {3, 4}; the bottom-first phase order only for the
+// default tile width at R = 4
+template <class S, int XB, int DB, int RR>
+hipError_t dispatch_two_layouts(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
+  if (s.in_layout == L_MAT && s.out_layout == L_MID) return launch_one<S, XB, DB, 0, L_MAT, L_MID, RR>(a, s.grid, st);
+  if (s.in_layout == L_MID && s.out_layout == L_CAN) return launch_one<S, XB, DB, 0, L_MID, L_CAN, RR>(a, s.grid, st);
+  if (s.in_layout == L_MAT && s.out_layout == L_MAT) return launch_one<S, XB, DB, 0, L_MAT, L_MAT, RR>(a, s.grid, st);
+  return hipErrorInvalidValue;
+}
+template <class S, int XB, int DB>
+hipError_t dispatch_two_bottom(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
+  if (s.in_layout == L_MID && s.out_layout == L_CAN) return launch_one<S, XB, DB, 1, L_MID, L_CAN, 4>(a, s.grid, st);
+  if (s.in_layout == L_MAT && s.out_layout == L_MAT) return launch_one<S, XB, DB, 1, L_MAT, L_MAT, 4>(a, s.grid, st);
+  return hipErrorInvalidValue;
+}
+template <class S, int XB, int DB>
+hipError_t dispatch_two_r(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
+  if (s.order == 1) return dispatch_two_bottom<S, XB, DB>(s, a, st);
+  if (s.r == 3) return dispatch_two_layouts<S, XB, DB, 3>(s, a, st);
+  return dispatch_two_layouts<S, XB, DB, 4>(s, a, st);
+}
+template <class S, int DB>
+hipError_t dispatch_two_xb(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
+  switch (s.xb) {
+    case 4: return dispatch_two_r<S, 4, DB>(s, a, st);
+    case 5: return dispatch_two_r<S, 5, DB>(s, a, st);
+    case 6: return dispatch_two_r<S, 6, DB>(s, a, st);
+    case 7: return dispatch_two_r<S, 7, DB>(s, a, st);
+    case 8: return dispatch_two_r<S, 8, DB>(s, a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace tpd

@@ -55,6 +55,9 @@ _SIGS = {
     "tpd_plan_prune_stats": (_I, [_P, _P, _P, _P, _P, _P]),
     "tpd_plan_describe": (_I, [_P, ctypes.c_char_p, _SZ]),
     "tpd_release_workspace": (_I, []),
+    "tpd_autotune": (_I, [_P, _I, _P, _I, _U, _P, ctypes.c_char_p, _SZ]),
+    "tpd_autotune_batched": (_I, [_P, _P, _P, _P, ctypes.c_char_p, _SZ]),
+    "tpd_debug_emulate_tuned": (_I, [_P, _I, _P, _I, _U, _I, _I, _I]),
     "tpd_status_string": (ctypes.c_char_p, [_I]),
     "tpd_index_from_string": (_U64, [ctypes.c_char_p]),
     "tpd_string_from_index": (_I, [_U64, _I, ctypes.c_char_p, _SZ]),
@@ -116,16 +119,20 @@ def _np_dtype(dtype: int):
     return np.complex128 if dtype == TPD_C128 else np.complex64
 
 
-def emulate(A: np.ndarray, dtype: int = TPD_C128, flags: int = 0, in_place: bool = False) -> np.ndarray:
-    """Host replay of the device schedule (debugging aid for small n)."""
+def emulate(A: np.ndarray, dtype: int = TPD_C128, flags: int = 0, in_place: bool = False, db: int = 0,
+            r: int = 0) -> np.ndarray:
+    """Host replay of the device schedule (debugging aid for small n);
+    db/r force a two-sweep tile width 2^db and 2^r elements per thread."""
     A = np.ascontiguousarray(A, dtype=_np_dtype(dtype))
     n = A.shape[0].bit_length() - 1
     if in_place:
         out = A.copy().reshape(-1)
-        _check(lib.tpd_debug_emulate(out.ctypes.data, n, out.ctypes.data, dtype, flags, 1), "tpd_debug_emulate")
+        _check(lib.tpd_debug_emulate_tuned(out.ctypes.data, n, out.ctypes.data, dtype, flags, 1, db, r),
+               "tpd_debug_emulate")
         return out
     out = np.empty(A.size, _np_dtype(dtype))
-    _check(lib.tpd_debug_emulate(A.ctypes.data, n, out.ctypes.data, dtype, flags, 0), "tpd_debug_emulate")
+    _check(lib.tpd_debug_emulate_tuned(A.ctypes.data, n, out.ctypes.data, dtype, flags, 0, db, r),
+           "tpd_debug_emulate")
     return out
 
 
@@ -209,6 +216,19 @@ def decompose(A, out=None, *, layout: str = "canonical", prune: bool = True, ord
     _check(lib.tpd_decompose_ex(A.data_ptr(), n, out.data_ptr(), dt, _flags(layout, prune, order_bottom),
                                 _stream(stream)), "tpd_decompose_ex")
     return out
+
+
+def autotune(A, out=None, *, layout: str = "canonical", prune: bool = True, stream=None) -> dict:
+    """Autotune the schedule for A's (n, dtype, layout, placement) on these
+    buffers; later calls with the same key use the choice."""
+    torch = _torch()
+    n = _check_matrix(A)
+    if out is None:
+        out = torch.empty(4 ** n, dtype=A.dtype, device=A.device)
+    buf = ctypes.create_string_buffer(8192)
+    _check(lib.tpd_autotune(A.data_ptr(), n, out.data_ptr(), _dtype_code(A), _flags(layout, prune), _stream(stream),
+                            buf, 8192), "tpd_autotune")
+    return json.loads(buf.value.decode())
 
 
 def decompose_batched(mats, outs=None, *, layout: str = "canonical", stream=None):
@@ -308,6 +328,13 @@ class BatchedPlan(Plan):
         torch = _torch()
         dev = device or tensors[0].device
         return torch.tensor([t.data_ptr() for t in tensors], dtype=torch.int64, device=dev)
+
+    def autotune(self, d_ptrs, d_out_ptrs=None, stream=None) -> dict:
+        buf = ctypes.create_string_buffer(8192)
+        _check(lib.tpd_autotune_batched(self._h, d_ptrs.data_ptr(),
+                                        None if d_out_ptrs is None else d_out_ptrs.data_ptr(), _stream(stream),
+                                        buf, 8192), "tpd_autotune_batched")
+        return json.loads(buf.value.decode())
 
     def execute(self, d_ptrs, d_out_ptrs=None, stream=None):
         _check(lib.tpd_plan_execute_batched(self._h, d_ptrs.data_ptr(),

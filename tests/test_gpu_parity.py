@@ -447,3 +447,33 @@ def test_single_plan_graph_capture_and_timing():
         torch.cuda.synchronize()
         assert same_bits(out.cpu().numpy(), ref)
     plan.close()
+
+
+def test_autotune_keeps_results_bitwise():
+    for n, dtype in ((11, torch.complex128), (12, torch.complex64)):
+        A = to_dev(W.gaussian(n, seed=90 + n), dtype)
+        before = tpd.decompose(A).clone()
+        rep = tpd.autotune(A)
+        assert rep["tuned"] and len(rep["candidates"]) >= 4
+        after = tpd.decompose(A)
+        assert torch.equal(torch.view_as_real(before), torch.view_as_real(after))
+        if dtype == torch.complex128:
+            assert same_bits(after.cpu().numpy(), O.tpd_recursive(W.gaussian(n, seed=90 + n)))
+    rep = tpd.autotune(to_dev(W.gaussian(6, 1)))
+    assert rep["tuned"] is False
+    # batched plan autotune
+    ns = [int(v) for v in W.batched_qubits(200, seed=13)]
+    mats = W.batched_matrices(ns, seed=13)
+    dm = [to_dev(m) for m in mats]
+    outs = [torch.empty(4 ** n, dtype=torch.complex128, device=DEV) for n in ns]
+    plan = tpd.BatchedPlan(ns)
+    dp, do = tpd.BatchedPlan.pointer_table(dm), tpd.BatchedPlan.pointer_table(outs)
+    rep = plan.autotune(dp, do)
+    assert rep["tuned"] and rep["chosen"]["grid"] > 0
+    for o in outs:
+        o.fill_(float("nan"))
+    plan.execute(dp, do)
+    torch.cuda.synchronize()
+    for k, (o, m) in enumerate(zip(outs, mats)):
+        assert same_bits(o.cpu().numpy(), O.tpd_recursive(m)), k
+    plan.close()

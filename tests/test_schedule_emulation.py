@@ -131,3 +131,33 @@ def test_emulated_batched_matches_oracle():
     outs = tpd.emulate_batched(small, in_place=True)
     for o, m in zip(outs, small):
         assert same_bits(o, O.tpd_recursive(m))
+
+
+@pytest.mark.parametrize("n", [9, 10, 12])
+def test_every_tunable_schedule_is_bitwise_the_same(n):
+    # the autotuner may pick any tile width / register depth: all must give
+    # the oracle's bits (complex128) and stay within the bound (complex64)
+    A = W.gaussian(n, seed=800 + n)
+    ref = O.tpd_recursive(A)
+    amax = np.max(np.abs(np.concatenate([A.real.ravel(), A.imag.ravel()])))
+    n2 = n // 2
+    for db in (3, 4, 5):
+        for r in (3, 4):
+            if db > n2:
+                with pytest.raises(tpd.TPDError):
+                    tpd.emulate(A, db=db, r=r)
+                continue
+            assert same_bits(tpd.emulate(A, db=db, r=r), ref), (db, r)
+            got = tpd.emulate(A, flags=tpd.FLAG_LAYOUT_MATRIX, in_place=True, db=db, r=r)
+            assert same_bits(matrix_to_canonical(got, n), ref), (db, r)
+    c64 = None
+    for db in (4, 5, 6):
+        for r in (3, 4):
+            if db > n2:
+                continue
+            got = tpd.emulate(A, dtype=tpd.TPD_C64, db=db, r=r)
+            if c64 is None:
+                c64 = got
+            assert np.array_equal(got, c64), (db, r)  # same bits for every schedule
+            err = np.max(np.abs(np.concatenate([(got - ref).real, (got - ref).imag])))
+            assert err <= (n + 1) * 2.0 ** -24 * amax
