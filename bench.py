@@ -125,13 +125,13 @@ def kernel_avgs(plan):
 
 
 def single_matrix_run(tpd, torch, A, n, dtype_code, steps, warmup, esize, in_place=False, layout="canonical",
-                      tune=True):
+                      tune=True, hermitian=False):
     out = A.view(-1) if in_place else torch.empty(4 ** n, dtype=A.dtype, device=A.device)
     tuned = None
     if tune and not in_place:
         # pick the schedule by measurement on these buffers (outside the timed region)
-        tuned = tpd.autotune(A, out, layout=layout).get("chosen")
-    plan = tpd.Plan(n, dtype_code, timing=True, in_place=in_place, layout=layout)
+        tuned = tpd.autotune(A, out, layout=layout, hermitian=hermitian).get("chosen")
+    plan = tpd.Plan(n, dtype_code, timing=True, in_place=in_place, layout=layout, hermitian=hermitian)
     ms = timed_steps(lambda: plan.execute(A, out), steps, warmup, torch)
     avgs, cnt = kernel_avgs(plan)
     plan.timing(reset=True)
@@ -190,8 +190,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=16)
-    ap.add_argument("--extras", default="fp32,inplace,n14,batched",
-                    help="comma list of fp32,inplace,n14,batched, or 'none'")
+    ap.add_argument("--extras", default="hermitian,fp32,inplace,n14,batched",
+                    help="comma list of hermitian,fp32,inplace,n14,batched, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
@@ -288,6 +288,13 @@ def main():
     }
 
     steps_x = max(3, min(args.steps, 10))
+    if "hermitian" in extras:
+        log("extra: Hermitian mode (representatives only, real weights), complex128")
+        r, o = single_matrix_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16, hermitian=True)
+        r["speedup_vs_general"] = main_res["ms_per_step"] / r["ms_per_step"]
+        result["hermitian_c128"] = r
+        del o
+        torch.cuda.empty_cache()
     if "inplace" in extras:
         log("extra: in place, matrix layout, complex128")
         B = A.clone()
@@ -304,7 +311,14 @@ def main():
         r, o32 = single_matrix_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8)
         r["speedup_vs_c128"] = main_res["ms_per_step"] / r["ms_per_step"]
         result["fp32"] = r
-        del o32, A32
+        del o32
+        torch.cuda.empty_cache()
+        if "hermitian" in extras:
+            r, o32 = single_matrix_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8, hermitian=True)
+            r["speedup_vs_c128_general"] = main_res["ms_per_step"] / r["ms_per_step"]
+            result["hermitian_c64"] = r
+            del o32
+        del A32
         torch.cuda.empty_cache()
     if A is not None:
         del A

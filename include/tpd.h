@@ -80,7 +80,18 @@ typedef enum {
 #define TPD_FLAG_LAYOUT_MATRIX 0x2u /* coefficients in the matrix layout (see above) */
 #define TPD_FLAG_TIMING 0x4u        /* plans only: record per-kernel HIP events */
 #define TPD_FLAG_ORDER_BOTTOM 0x8u  /* register phases bottom level first (tuning) */
-#define TPD_FLAGS_ALL 0xFu
+#define TPD_FLAG_HERMITIAN 0x10u    /* caller promises A = A^H (see below) */
+#define TPD_FLAGS_ALL 0x1Fu
+
+/* TPD_FLAG_HERMITIAN: for a Hermitian A every weight is real (section
+ * "Results" discusses the real-symmetric promise; Hermitian => real follows
+ * from the definition).  Entry A[r][c] is the conjugate of A[c][r], and every
+ * cumulative matrix weight of a Hermitian matrix is again Hermitian, so the
+ * two-sweep schedule (n >= 9) reads and writes about half of the first
+ * sweep's data and half of the second sweep's input, rebuilds the rest by
+ * conjugation on chip, and stores the weights with imaginary parts +0.0.
+ * The real parts are bitwise those of the general schedule.  Results are
+ * undefined if A is not Hermitian.  n <= 8 runs the general schedule.     */
 
 /* Largest supported n: 16 for both dtypes (the two-sweep tile schedule and
  * 288 GB of HBM for an out-of-place n = 16 C128 pair). */

@@ -115,6 +115,7 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
     w.r = 4;
     w.grid = 0;
     w.is_one = true;
+    w.herm = 0;
     w.ntiles = (uint64_t)1 << (n - w.db);
     return TPD_SUCCESS;
   }
@@ -148,6 +149,7 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
   a.r = t.r;
   a.grid = t.grid > 0 ? t.grid * cus : 0;
   a.is_one = false;
+  a.herm = (flags & TPD_FLAG_HERMITIAN) ? 1 : 0;
   a.ntiles = ((uint64_t)1 << s->n2) << (n - db);
   SweepDesc& b = s->sw[1];
   b.xlo = 0;
@@ -160,6 +162,7 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
   b.r = bottom ? 4 : t.r;
   b.grid = a.grid;
   b.is_one = false;
+  b.herm = a.herm;
   b.ntiles = ((uint64_t)1 << s->n1) << (n - db);
   const uint64_t bits = ((uint64_t)1 << s->n1) << (n - db);
   s->bitmap_words = (bits + 31) / 32;
@@ -214,9 +217,10 @@ std::string describe(const Schedule& s) {
   std::string j;
   std::snprintf(buf, sizeof buf,
                 "{\"n\":%d,\"dtype\":\"%s\",\"layout\":\"%s\",\"in_place\":%s,\"prune\":%s,"
-                "\"elements\":%llu,\"algorithmic_bytes\":%llu,\"bitmap_words\":%llu,\"sweeps\":[",
+                "\"hermitian\":%s,\"elements\":%llu,\"algorithmic_bytes\":%llu,\"bitmap_words\":%llu,\"sweeps\":[",
                 s.n, s.dt == DT_C128 ? "c128" : "c64", s.matrix_layout ? "matrix" : "canonical",
-                s.in_place ? "true" : "false", s.prune ? "true" : "false", (unsigned long long)count,
+                s.in_place ? "true" : "false", s.prune ? "true" : "false",
+                (s.nsweep == 2 && s.sw[0].herm) ? "true" : "false", (unsigned long long)count,
                 (unsigned long long)(2 * count * eb), (unsigned long long)s.bitmap_words);
   j += buf;
   for (int i = 0; i < s.nsweep; ++i) {
@@ -435,6 +439,7 @@ tpd_status_t run_schedule(const Schedule& s, const void* A, void* C, uint32_t* b
     a.bitmap = bitmap;
     a.bitmap_mode = w.bitmap_mode;
     a.bm_xbits = s.n1;
+    a.herm = w.herm;
     a.ntiles = w.ntiles;
     const int slot = tm ? tm->begin(i, st) : -1;
     const hipError_t e = launch_sweep(s.dt, w, a, st);

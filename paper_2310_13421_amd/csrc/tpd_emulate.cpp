@@ -84,6 +84,27 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
         continue;
       }
     }
+    uint64_t hm = 0;
+    if (a.herm) {
+      const int n2 = xlo ? xlo : G::XB;
+      const uint64_t dlh = td & (((uint64_t)1 << (n2 - G::DB)) - 1);
+      if (dlh) hm = (uint64_t)1 << (63 - __builtin_clzll(dlh) + G::DB);
+      if (xlo && (xf & hm)) {
+        // first sweep skips a non-representative row block: nothing is read
+        // or written (account its addresses so completeness still checks)
+        for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+          const uint32_t eb = elem_base<G>(RL, 0, tid);
+          for (int j = 0; j < G::E; ++j) {
+            const uint32_t e = eb | elem_reg<G>(RL, 0, j);
+            const uint64_t x = xfix | ((uint64_t)((e >> G::DB) & XM) << xlo);
+            const uint64_t d = (td << G::DB) | (e & DM);
+            ck.rd(layout_addr<INL>(x, d, n, db));
+            ck.wr(layout_addr<OUTL>(x, d, n, db));
+          }
+        }
+        continue;
+      }
+    }
     for (int w = 0; w < NBW; ++w) bits[w] = 0;
     rset.clear();
     wset.clear();
@@ -107,7 +128,31 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
         ck.rd(ad);
         if (ad >= ck.count) return TPD_ERROR_INTERNAL;
         rset.push_back(ad);
-        v[(size_t)tid * G::E + j] = in[ad];
+        if (hm && !xlo && (((uint64_t)((e >> G::DB) & XM)) & hm)) v[(size_t)tid * G::E + j] = Cx<S>{(S)0, (S)0};
+        else v[(size_t)tid * G::E + j] = in[ad];
+      }
+    }
+    if (hm && !xlo) {
+      const uint64_t dlo_hi = (td << G::DB) & ((((uint64_t)1 << G::XB) - 1));
+      std::vector<uint8_t> seen(lds.size(), 0);
+      for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+        const uint32_t eb0 = elem_base<G>(RL, 0, tid);
+        for (int j = 0; j < G::E; ++j) {
+          const uint32_t e = eb0 | elem_reg<G>(RL, 0, j);
+          if (((uint64_t)((e >> G::DB) & XM)) & hm) continue;
+          const uint32_t dlo = (uint32_t)(dlo_hi | (e & DM));
+          const uint32_t ep = e ^ (dlo << G::DB);
+          if (seen[e]++ || seen[ep]++) return TPD_ERROR_INTERNAL;  // each slot filled exactly once
+          const Cx<S> z = v[(size_t)tid * G::E + j];
+          lds[e] = z;
+          lds[ep] = Cx<S>{z.re, -z.im};
+        }
+      }
+      for (size_t e = 0; e < seen.size(); ++e)
+        if (seen[e] != 1) return TPD_ERROR_INTERNAL;
+      for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+        const uint32_t eb0 = elem_base<G>(RL, 0, tid);
+        for (int j = 0; j < G::E; ++j) v[(size_t)tid * G::E + j] = lds[eb0 | elem_reg<G>(RL, 0, j)];
       }
     }
     for (int p = 0; p < P; ++p) {
@@ -176,6 +221,7 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
         ck.wr(ad);
         if (ad >= ck.count) return TPD_ERROR_INTERNAL;
         wset.push_back(ad);
+        if (a.herm && !xlo) v[(size_t)tid * G::E + j].im = (S)0;
         out[ad] = v[(size_t)tid * G::E + j];
       }
     }
@@ -357,6 +403,7 @@ extern "C" tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coef
     a.bitmap = bitmap.data();
     a.bitmap_mode = sw[i].bitmap_mode;
     a.bm_xbits = n1;
+    a.herm = sw[i].herm;
     a.ntiles = sw[i].ntiles;
     Checker ck(count);
     if (dtype == TPD_C128)

@@ -20,6 +20,7 @@ struct SweepDesc {
   int r;            // log2 of the elements each thread holds (3 or 4)
   int grid;         // 0: one workgroup per tile; > 0: persistent grid of that size
   bool is_one;      // the single sweep of an n <= 8 schedule
+  int herm;         // 1: the input is Hermitian (read representatives only)
   uint64_t ntiles;
 };
 
@@ -33,6 +34,7 @@ struct SweepArgs {
   uint32_t* bitmap;  // 32-bit words, one bit per second-sweep tile
   int bitmap_mode;
   int bm_xbits;      // x bits of the first sweep (bit index = (td << bm_xbits) | x_hi)
+  int herm;          // 1: Hermitian input, two-sweep schedule
   uint64_t ntiles;
 };
 

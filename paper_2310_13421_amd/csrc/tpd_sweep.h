@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   constexpr uint32_t DM = (1u << G::DB) - 1;
   constexpr uint32_t XM = (1u << G::XB) - 1;
   constexpr int NBW = (1 << G::XB) >= 32 ? (1 << G::XB) / 32 : 1;
-  __shared__ Cx<S> lds[(P > 1) ? (1 << G::B) : 1];
+  __shared__ Cx<S> lds[1 << G::B];
   __shared__ uint32_t bits[NBW];
 
   const uint32_t tid = threadIdx.x;
@@ -52,6 +52,18 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
       const uint64_t bit = (td << a.bm_xbits) | xf;
       if (!((a.bitmap[bit >> 5] >> (bit & 31)) & 1u)) continue;  // zero subtree
     }
+    // Hermitian input: entry (x, d) is the conjugate of (x ^ d, d), and so is
+    // every intermediate value inside one cumulative matrix weight.  With
+    // dlh = the d bits of this tile above the diagonal group, below n2, and m
+    // the top set bit of d's low n2 bits, only rows with x bit m = 0 are
+    // needed ("representatives"); the others follow by conjugation.
+    uint64_t hm = 0;  // 1 << m when representatives can be used, else 0
+    if (a.herm) {
+      const int n2 = xlo ? xlo : G::XB;
+      const uint64_t dlh = td & (((uint64_t)1 << (n2 - G::DB)) - 1);
+      if (dlh) hm = (uint64_t)1 << (63 - __builtin_clzll(dlh) + G::DB);
+      if (xlo && (xf & hm)) continue;  // first sweep: a non-representative row block
+    }
     if (a.bitmap_mode == 1 && tid < NBW) bits[tid] = 0;
 
     Cx<S> v[G::E];
@@ -65,8 +77,26 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
 #pragma unroll
         for (int s = 0; s < G::R; ++s)
           if ((j >> s) & 1) ad ^= din[s];
-        v[j] = in[ad];
+        const uint32_t e = eb0 | elem_reg<G>(RL, 0, j);
+        if (hm && !xlo && (((uint64_t)((e >> G::DB) & XM)) & hm)) v[j] = Cx<S>{(S)0, (S)0};
+        else v[j] = in[ad];
       }
+    }
+    if (hm && !xlo) {
+      // second sweep: rebuild the non-representative rows by conjugation
+      const uint64_t dlo_hi = (td << G::DB) & ((((uint64_t)1 << G::XB) - 1));
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < G::E; ++j) {
+        const uint32_t e = eb0 | elem_reg<G>(RL, 0, j);
+        if (((uint64_t)((e >> G::DB) & XM)) & hm) continue;
+        const uint32_t dlo = (uint32_t)(dlo_hi | (e & DM));
+        lds[e] = v[j];
+        lds[e ^ (dlo << G::DB)] = Cx<S>{v[j].re, -v[j].im};
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < G::E; ++j) v[j] = lds[eb0 | elem_reg<G>(RL, 0, j)];
     }
 
 #pragma unroll
@@ -115,12 +145,14 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
       const uint64_t x = xfix | ((uint64_t)((ebl >> G::DB) & XM) << xlo);
       const uint64_t d = (td << G::DB) | (ebl & DM);
       const uint64_t base = layout_addr<OUTL>(x, d, n, db);
+      const bool real_out = a.herm && !xlo;  // Hermitian weights are real
 #pragma unroll
       for (int j = 0; j < G::E; ++j) {
         uint64_t ad = base;
 #pragma unroll
         for (int s = 0; s < G::R; ++s)
           if ((j >> s) & 1) ad ^= dout[s];
+        if (real_out) v[j].im = (S)0;
         out[ad] = v[j];
       }
     }

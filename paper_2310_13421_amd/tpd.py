@@ -23,6 +23,7 @@ FLAG_NO_PRUNE = 0x1
 FLAG_LAYOUT_MATRIX = 0x2
 FLAG_TIMING = 0x4
 FLAG_ORDER_BOTTOM = 0x8
+FLAG_HERMITIAN = 0x10
 
 STATUS = {
     0: "TPD_SUCCESS",
@@ -130,7 +131,7 @@ def emulate(A: np.ndarray, dtype: int = TPD_C128, flags: int = 0, in_place: bool
         _check(lib.tpd_debug_emulate_tuned(out.ctypes.data, n, out.ctypes.data, dtype, flags, 1, db, r),
                "tpd_debug_emulate")
         return out
-    out = np.empty(A.size, _np_dtype(dtype))
+    out = np.full(A.size, np.nan, _np_dtype(dtype))  # poison: every element must be written
     _check(lib.tpd_debug_emulate_tuned(A.ctypes.data, n, out.ctypes.data, dtype, flags, 0, db, r),
            "tpd_debug_emulate")
     return out
@@ -176,8 +177,8 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _flags(layout: str, prune: bool, order_bottom: bool = False) -> int:
-    f = 0
+def _flags(layout: str, prune: bool, order_bottom: bool = False, hermitian: bool = False) -> int:
+    f = FLAG_HERMITIAN if hermitian else 0
     if layout == "matrix":
         f |= FLAG_LAYOUT_MATRIX
     elif layout != "canonical":
@@ -200,7 +201,7 @@ def _check_matrix(A):
 
 
 def decompose(A, out=None, *, layout: str = "canonical", prune: bool = True, order_bottom: bool = False,
-              stream=None):
+              hermitian: bool = False, stream=None):
     """Pauli coefficients of A (2^n x 2^n complex64/complex128 CUDA tensor).
 
     Returns a 1-D tensor of 4^n coefficients (canonical order: index
@@ -213,12 +214,13 @@ def decompose(A, out=None, *, layout: str = "canonical", prune: bool = True, ord
         out = torch.empty(4 ** n, dtype=A.dtype, device=A.device)
     if out.dtype != A.dtype or not out.is_cuda or not out.is_contiguous() or out.numel() != 4 ** n:
         raise ValueError("out must be a contiguous CUDA tensor of 4^n elements of A's dtype")
-    _check(lib.tpd_decompose_ex(A.data_ptr(), n, out.data_ptr(), dt, _flags(layout, prune, order_bottom),
-                                _stream(stream)), "tpd_decompose_ex")
+    _check(lib.tpd_decompose_ex(A.data_ptr(), n, out.data_ptr(), dt,
+                                _flags(layout, prune, order_bottom, hermitian), _stream(stream)), "tpd_decompose_ex")
     return out
 
 
-def autotune(A, out=None, *, layout: str = "canonical", prune: bool = True, stream=None) -> dict:
+def autotune(A, out=None, *, layout: str = "canonical", prune: bool = True, hermitian: bool = False,
+             stream=None) -> dict:
     """Autotune the schedule for A's (n, dtype, layout, placement) on these
     buffers; later calls with the same key use the choice."""
     torch = _torch()
@@ -226,8 +228,8 @@ def autotune(A, out=None, *, layout: str = "canonical", prune: bool = True, stre
     if out is None:
         out = torch.empty(4 ** n, dtype=A.dtype, device=A.device)
     buf = ctypes.create_string_buffer(8192)
-    _check(lib.tpd_autotune(A.data_ptr(), n, out.data_ptr(), _dtype_code(A), _flags(layout, prune), _stream(stream),
-                            buf, 8192), "tpd_autotune")
+    _check(lib.tpd_autotune(A.data_ptr(), n, out.data_ptr(), _dtype_code(A), _flags(layout, prune, False, hermitian),
+                            _stream(stream), buf, 8192), "tpd_autotune")
     return json.loads(buf.value.decode())
 
 
@@ -259,11 +261,11 @@ class Plan:
     graph-capturable.  timing=True records HIP events around each kernel."""
 
     def __init__(self, n: int, dtype: int = TPD_C128, *, layout: str = "canonical", prune: bool = True,
-                 in_place: bool = False, timing: bool = False, order_bottom: bool = False):
+                 in_place: bool = False, timing: bool = False, order_bottom: bool = False, hermitian: bool = False):
         self.n = n
         self.dtype = dtype
         self.in_place = in_place
-        f = _flags(layout, prune, order_bottom) | (FLAG_TIMING if timing else 0)
+        f = _flags(layout, prune, order_bottom, hermitian) | (FLAG_TIMING if timing else 0)
         h = ctypes.c_void_p()
         _check(lib.tpd_plan_create(n, dtype, f, int(in_place), ctypes.byref(h)), "tpd_plan_create")
         self._h = h

@@ -346,6 +346,14 @@ def test_config4_n16_sampled_strings_parseval_both_precisions():
     del B
     torch.cuda.empty_cache()
 
+    # Hermitian mode: half the reads, real output, bitwise the same real parts
+    outh = tpd.decompose(A, hermitian=True)
+    torch.cuda.synchronize()
+    gh = outh[qd].cpu().numpy()
+    assert np.array_equal(gh.real, ref_vals.real) and np.all(gh.imag == 0)
+    del outh
+    torch.cuda.empty_cache()
+
     A32 = A.to(torch.complex64)
     del A
     torch.cuda.empty_cache()
@@ -477,3 +485,27 @@ def test_autotune_keeps_results_bitwise():
     for k, (o, m) in enumerate(zip(outs, mats)):
         assert same_bits(o.cpu().numpy(), O.tpd_recursive(m)), k
     plan.close()
+
+
+@pytest.mark.parametrize("n", [9, 12, 13])
+def test_hermitian_mode(n):
+    A = W.gaussian(n, seed=70 + n, hermitian=True)
+    ref = O.tpd_recursive(A)
+    for dtype in (torch.complex128, torch.complex64):
+        Ad = to_dev(A, dtype)
+        gen = tpd.decompose(Ad)
+        for layout in ("canonical", "matrix"):
+            out = torch.full((4 ** n,), float("nan"), dtype=dtype, device=DEV)
+            tpd.decompose(Ad, out, hermitian=True, layout=layout)
+            got = out.cpu().numpy()
+            if layout == "matrix":
+                got = matrix_to_canonical(got, n)
+            assert np.all(got.imag == 0)
+            assert np.array_equal(got.real, gen.cpu().numpy().real)
+            if dtype == torch.complex128:
+                assert same_bits(got, ref)
+        # in place, matrix layout
+        T = Ad.clone()
+        tpd.decompose(T, T.view(-1), hermitian=True, layout="matrix")
+        got = matrix_to_canonical(T.cpu().numpy().ravel(), n)
+        assert np.array_equal(got.real, gen.cpu().numpy().real) and np.all(got.imag == 0)

@@ -161,3 +161,25 @@ def test_every_tunable_schedule_is_bitwise_the_same(n):
             assert np.array_equal(got, c64), (db, r)  # same bits for every schedule
             err = np.max(np.abs(np.concatenate([(got - ref).real, (got - ref).imag])))
             assert err <= (n + 1) * 2.0 ** -24 * amax
+
+
+@pytest.mark.parametrize("n", [9, 10, 12])
+def test_emulated_hermitian_mode_reads_half_and_matches(n):
+    # representatives only + conjugation on chip: bitwise the general result,
+    # imaginary parts exactly +0, and no read of the skipped (NaN-poisoned)
+    # half of the intermediate
+    A = W.gaussian(n, seed=900 + n, hermitian=True)
+    ref = O.tpd_recursive(A)
+    for dt in (tpd.TPD_C128, tpd.TPD_C64):
+        for db in (0, 3, 4, 5, 6):
+            try:
+                gen = tpd.emulate(A, dt, db=db)
+            except tpd.TPDError:
+                continue
+            got = tpd.emulate(A, dt, tpd.FLAG_HERMITIAN, db=db)
+            assert np.array_equal(got.real, gen.real) and np.all(got.imag == 0)
+            if dt == tpd.TPD_C128:
+                assert same_bits(got, ref)
+        got = tpd.emulate(A, dt, tpd.FLAG_HERMITIAN | tpd.FLAG_LAYOUT_MATRIX, in_place=True)
+        gen = tpd.emulate(A, dt, tpd.FLAG_LAYOUT_MATRIX, in_place=True)
+        assert np.array_equal(got.real, gen.real) and np.all(got.imag == 0)
