@@ -28,8 +28,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBPS = 8000.0
 METRIC = "Pauli coeffs/sec + HBM GB/s (% peak) at n=14/16, FP64 vs FP32; batched mats/s"
 KERNEL_SOURCES = ["paper_2310_13421_amd/csrc/tpd_sweep.h", "paper_2310_13421_amd/csrc/tpd_core.h",
-                  "paper_2310_13421_amd/csrc/tpd_internal.h", "paper_2310_13421_amd/csrc/tpd_sweep_c128.hip",
-                  "paper_2310_13421_amd/csrc/tpd_sweep_c64.hip"]
+                  "paper_2310_13421_amd/csrc/tpd_internal.h"]
 
 
 def log(msg):
@@ -37,8 +36,13 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """Hash of every device source (kernels, their headers, instantiation units)."""
+    import glob
+
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    files = sorted(set(KERNEL_SOURCES) | {os.path.relpath(p, ROOT) for p in
+                                          glob.glob(os.path.join(ROOT, "paper_2310_13421_amd", "csrc", "*.hip"))})
+    for rel in files:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -110,6 +110,19 @@ tpd_status_t tpd_decompose(const void* A, int n, void* coeffs, tpd_stream_t stre
 tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                               tpd_stream_t stream);
 
+/* Inverse transform (synthesis), eq. (PauliDecomposition) read left to
+ * right: A = sum_t w_t sigma^t, by the same n levels with the inverse
+ * slicing step (u, v) = (s + t conj(w), s - t conj(w)), w = i on X/Y
+ * diagonals, no scaling.
+ *   coeffs [in]  device, 4^n weights, canonical order or (with
+ *                TPD_FLAG_LAYOUT_MATRIX) the matrix layout
+ *   A      [out] device, 2^n x 2^n row-major; may equal coeffs with
+ *                TPD_FLAG_LAYOUT_MATRIX (any n) or for n <= 6
+ *   flags  TPD_FLAG_LAYOUT_MATRIX only (TPD_FLAG_NO_PRUNE is accepted and
+ *          ignored); anything else is TPD_ERROR_INVALID_VALUE.            */
+tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,
+                               tpd_stream_t stream);
+
 /* Decompose `count` independent matrices of mixed sizes in one persistent
  * kernel launch (the paper's motivation: many time steps of a
  * time-dependent Hamiltonian, section "Introduction").
@@ -173,8 +186,8 @@ tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len);
  * plan with the same key uses on this process (and, if the environment
  * variable TPD_AUTOTUNE_CACHE names a file, appended there and reloaded by
  * later processes).  Candidates: tile widths of 2^3..2^5 (complex128) or
- * 2^4..2^6 (complex64) XOR-diagonals, 8 or 16 elements per thread, one
- * workgroup per tile or a persistent grid of 1, 2 or 4 workgroups per CU.
+ * 2^4..2^6 (complex64) XOR-diagonals, one workgroup per tile or a
+ * persistent grid of 1, 2 or 4 workgroups per CU.
  * The choice never changes results (same operations in the same order).
  * Arguments as tpd_decompose_ex; `coeffs` is overwritten; with
  * A == coeffs the matrix is transformed repeatedly (destroyed).  Allocates
@@ -216,10 +229,14 @@ tpd_status_t tpd_schedule_describe(int n, tpd_dtype_t dtype, unsigned flags, int
 tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                                int in_place);
 
-/* As tpd_debug_emulate with a forced two-sweep tile width 2^db and 2^r
- * elements per thread (db = 0: the default schedule).                    */
+/* As tpd_debug_emulate with a forced two-sweep tile width 2^db (db = 0:
+ * the default schedule); r must be 0 or 4 (elements per thread = 16).    */
 tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                                      int in_place, int db, int r);
+
+/* Host replay of the synthesis schedule (HOST pointers, small n). */
+tpd_status_t tpd_debug_emulate_synth(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,
+                                     int in_place);
 
 /* Host replay of the batched schedule for one batch (HOST pointer arrays). */
 tpd_status_t tpd_debug_emulate_batched(const void* const* ptrs, const int* ns, int count, void* const* out_ptrs,

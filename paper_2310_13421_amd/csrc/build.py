@@ -15,7 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libtpd.so")
-SOURCES = ["tpd_sweep_c128.hip", "tpd_sweep_c64.hip", "tpd_kernels.hip", "tpd_api.cpp", "tpd_emulate.cpp"]
+SOURCES = ["tpd_sweep_c128_db3.hip", "tpd_sweep_c128_db4.hip", "tpd_sweep_c128_db5.hip", "tpd_sweep_c64_db4.hip",
+           "tpd_sweep_c64_db5.hip", "tpd_sweep_c64_db6.hip", "tpd_sweep_c128.hip", "tpd_sweep_c64.hip",
+           "tpd_kernels.hip", "tpd_emulate.cpp", "tpd_api.cpp"]
 HEADERS = ["tpd_core.h", "tpd_internal.h", "tpd_sweep.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -45,8 +47,10 @@ def _run(cmd):
     return time.time() - t0
 
 
-def build(verbose: bool = True, jobs: int = 5) -> str:
+def build(verbose: bool = True, jobs: int = 0) -> str:
     """Compile every source to an object (in parallel) and link libtpd.so."""
+    if jobs <= 0:
+        jobs = max(1, min(len(SOURCES), os.cpu_count() or 4, int(os.environ.get("MAX_JOBS", "16"))))
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
     procs = []
@@ -54,7 +58,13 @@ def build(verbose: bool = True, jobs: int = 5) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(HERE, src), "-o", obj]
+        if src == "tpd_emulate.cpp":
+            # host replay used by the tests: plain host C++ (no device pass), -O1
+            cmd = ["g++", "-O1", "-std=c++20", "-fPIC", "-ffp-contract=off", "-D__HIP_PLATFORM_AMD__",
+                   "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), "-c", os.path.join(HERE, src),
+                   "-o", obj]
+        else:
+            cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(HERE, src), "-o", obj]
         procs.append((src, cmd))
     t0 = time.time()
     running = []

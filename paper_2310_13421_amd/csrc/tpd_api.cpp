@@ -116,6 +116,7 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
     w.grid = 0;
     w.is_one = true;
     w.herm = 0;
+    w.inv = false;
     w.ntiles = (uint64_t)1 << (n - w.db);
     return TPD_SUCCESS;
   }
@@ -150,6 +151,7 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
   a.grid = t.grid > 0 ? t.grid * cus : 0;
   a.is_one = false;
   a.herm = (flags & TPD_FLAG_HERMITIAN) ? 1 : 0;
+  a.inv = false;
   a.ntiles = ((uint64_t)1 << s->n2) << (n - db);
   SweepDesc& b = s->sw[1];
   b.xlo = 0;
@@ -163,6 +165,7 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
   b.grid = a.grid;
   b.is_one = false;
   b.herm = a.herm;
+  b.inv = false;
   b.ntiles = ((uint64_t)1 << s->n1) << (n - db);
   const uint64_t bits = ((uint64_t)1 << s->n1) << (n - db);
   s->bitmap_words = (bits + 31) / 32;
@@ -173,6 +176,67 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
 
 tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Schedule* s) {
   return make_schedule_with(n, dt, flags, in_place, nullptr, s);
+}
+
+// Inverse transform (synthesis A = sum_t w_t sigma^t): the same levels with
+// the inverse butterfly.  n <= 8: one sweep CAN|MAT -> MAT.  n >= 9: the low
+// n2 levels first (tiles of fixed high rows, reading the canonical order's
+// closed 16-run sets, writing 2^db-column runs of A), then the high n1 levels
+// in place on A.
+tpd_status_t make_synth_schedule(int n, Dtype dt, unsigned flags, bool in_place, Schedule* s) {
+  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  *s = Schedule{};
+  s->n = n;
+  s->dt = dt;
+  s->matrix_layout = (flags & TPD_FLAG_LAYOUT_MATRIX) != 0;
+  s->in_place = in_place;
+  if (n == 0) return TPD_SUCCESS;
+  const int in_l = s->matrix_layout ? L_MAT : L_CAN;
+  auto base = [&](SweepDesc& w) {
+    w.in_layout = in_l;
+    w.out_layout = L_MAT;
+    w.bitmap_mode = 0;
+    w.order = 0;
+    w.r = 4;
+    w.grid = 0;
+    w.herm = 0;
+    w.inv = true;
+  };
+  if (n <= 8) {
+    if (in_place && !s->matrix_layout && n > 6) return TPD_ERROR_UNSUPPORTED;
+    s->nsweep = 1;
+    SweepDesc& w = s->sw[0];
+    base(w);
+    w.xlo = 0;
+    w.xb = n;
+    w.db = single_db(n);
+    w.is_one = true;
+    w.ntiles = (uint64_t)1 << (n - w.db);
+  } else {
+    if (in_place && !s->matrix_layout) return TPD_ERROR_UNSUPPORTED;
+    s->nsweep = 2;
+    s->n1 = (n + 1) / 2;
+    s->n2 = n / 2;
+    const int db = default_db(dt, s->n2);
+    SweepDesc& a = s->sw[0];
+    base(a);
+    a.xlo = 0;
+    a.xb = s->n2;
+    a.db = db;
+    a.is_one = false;
+    a.ntiles = ((uint64_t)1 << s->n1) << (n - db);
+    SweepDesc& b = s->sw[1];
+    base(b);
+    b.in_layout = L_MAT;
+    b.xlo = s->n2;
+    b.xb = s->n1;
+    b.db = db;
+    b.is_one = false;
+    b.ntiles = ((uint64_t)1 << s->n2) << (n - db);
+  }
+  for (int i = 0; i < s->nsweep; ++i)
+    if (!sweep_supported(dt, s->sw[i])) return TPD_ERROR_INTERNAL;
+  return TPD_SUCCESS;
 }
 
 // Autotune cache: TPD_AUTOTUNE_CACHE names a text file of lines
@@ -191,7 +255,7 @@ void load_tune_cache() {
     if (!(is >> tag >> arch >> cus >> dt >> n >> mat >> inp >> db >> r >> grid)) continue;
     if (tag != "tpd-tune-v1" || arch != "gfx950") continue;
     if (g_cus > 0 && cus != g_cus) continue;
-    if (dt < 0 || dt > 1 || n < -1 || n > kMaxQubits || r < 3 || r > 4 || grid < 0 || grid > 64) continue;
+    if (dt < 0 || dt > 1 || n < -1 || n > kMaxQubits || r != 4 || grid < 0 || grid > 64) continue;
     Tuned t;
     t.db = db;
     t.r = r;
@@ -624,6 +688,24 @@ tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dt
   return run_schedule(s, A, coeffs, bm, hs, nullptr);
 }
 
+tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,
+                               tpd_stream_t stream) {
+  tpd_status_t st = check_dtype_flags(dtype, flags);
+  if (st) return st;
+  if (flags & ~(TPD_FLAG_LAYOUT_MATRIX | TPD_FLAG_NO_PRUNE)) return TPD_ERROR_INVALID_VALUE;
+  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  const Dtype dt = (Dtype)dtype;
+  st = check_buffers(coeffs, A, n, dt);
+  if (st) return st;
+  Schedule s;
+  st = make_synth_schedule(n, dt, flags, coeffs == A, &s);
+  if (st) return st;
+  int dev;
+  st = current_device(&dev);
+  if (st) return st;
+  return run_schedule(s, coeffs, A, nullptr, (hipStream_t)stream, nullptr);
+}
+
 tpd_status_t tpd_decompose(const void* A, int n, void* coeffs, tpd_stream_t stream) {
   return tpd_decompose_ex(A, n, coeffs, TPD_C128, 0u, stream);
 }
@@ -899,6 +981,17 @@ tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, cons
   return TPD_SUCCESS;
 }
 
+tpd_status_t host_synth_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep) {
+  tpd_status_t st = check_dtype_flags(dtype, flags);
+  if (st) return st;
+  Schedule s;
+  st = make_synth_schedule(n, (Dtype)dtype, flags, in_place, &s);
+  if (st) return st;
+  for (int i = 0; i < s.nsweep; ++i) sw[i] = s.sw[i];
+  *nsweep = s.nsweep;
+  return TPD_SUCCESS;
+}
+
 tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, std::vector<uint32_t>* perm,
                                std::vector<BatchItem>* items) {
   tpd_status_t st = check_dtype_flags(TPD_C128, flags);
@@ -948,7 +1041,7 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
   const unsigned tflags = (flags & ~TPD_FLAG_ORDER_BOTTOM) | (in_place ? TPD_FLAG_NO_PRUNE : 0u);
   const int dbs128[3] = {3, 4, 5}, dbs64[3] = {4, 5, 6};
   const int* dbs = dt == DT_C128 ? dbs128 : dbs64;
-  const int rs[2] = {4, 3};
+  const int rs[1] = {4};
   const int grids[4] = {0, 1, 2, 4};
   std::vector<Tuned> cands;
   uint64_t max_words = 0;

@@ -186,11 +186,23 @@ TPD_HD void butterfly(Cx<S>& u, Cx<S>& v, bool tw) {
   v.im = tw ? dr : di;
 }
 
+// inverse of butterfly(): (s, t) -> (s + t*conj(w), s - t*conj(w)), w = tw ? i : 1
+// (synthesis A = sum_t w_t sigma^t, no scaling)
+template <class S>
+TPD_HD void butterfly_inv(Cx<S>& u, Cx<S>& v, bool tw) {
+  const S tr = tw ? v.im : v.re, ti = tw ? -v.re : v.im;  // t * conj(w)
+  const S sr = u.re, si = u.im;
+  u.re = sr + tr;
+  u.im = si + ti;
+  v.re = sr - tr;
+  v.im = si - ti;
+}
+
 // run the butterflies of phase p on a thread's registers.  d_thread is the
 // d coordinate of register 0 (twiddle bits); x bit of transform slot s is
 // xlo + (reg bit - DB).  Registers whose d differs (dl passengers) take
 // their own twiddle bit.
-template <class G, class S>
+template <class G, class S, bool INV = false>
 TPD_HD void phase_butterflies(const Roles& r, int p, Cx<S>* v, uint64_t d_thread, int xlo) {
   for (int s = 0; s < r.nxf[p]; ++s) {
     const int xbit = xlo + (r.reg[p][s] - G::DB);
@@ -203,7 +215,8 @@ TPD_HD void phase_butterflies(const Roles& r, int p, Cx<S>* v, uint64_t d_thread
       for (int t = 0; t < G::R; ++t)
         if (r.reg[p][t] >= 0 && r.reg[p][t] < G::DB && ((j >> t) & 1)) dj ^= (uint64_t)1 << r.reg[p][t];
       const bool tw = (dj >> xbit) & 1u;
-      butterfly(v[j], v[j | (1 << s)], tw);
+      if constexpr (INV) butterfly_inv(v[j], v[j | (1 << s)], tw);
+      else butterfly(v[j], v[j | (1 << s)], tw);
     }
   }
 }

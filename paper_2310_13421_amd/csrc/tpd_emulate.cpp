@@ -42,7 +42,7 @@ struct Checker {
   }
 };
 
-template <class S, class G, int INL, int OUTL>
+template <class S, class G, int INL, int OUTL, bool INV = false>
 tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint32_t* bitmap, Checker& ck) {
   constexpr Roles RL = make_roles<G>();
   constexpr int P = G::NPH;
@@ -158,7 +158,7 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
     for (int p = 0; p < P; ++p) {
       for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
         const uint32_t ebp = elem_base<G>(RL, p, tid);
-        phase_butterflies<G, S>(RL, p, &v[(size_t)tid * G::E], (td << G::DB) | (ebp & DM), xlo);
+        phase_butterflies<G, S, INV>(RL, p, &v[(size_t)tid * G::E], (td << G::DB) | (ebp & DM), xlo);
       }
       if (p + 1 < P) {
         std::vector<uint8_t> seen(lds.size(), 0);
@@ -241,6 +241,11 @@ tpd_status_t emulate_layouts(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, co
   constexpr int R1 = (XB + DB - 10) > RR ? (XB + DB - 10) : RR;
   constexpr int R = (XB + DB) < R1 ? (XB + DB) : R1;
   using G = Geom<XB, DB, 0, R, ORDER>;
+  if (s.inv) {
+    if (s.in_layout == L_CAN && s.out_layout == L_MAT) return emulate_sweep<S, G, L_CAN, L_MAT, true>(in, out, a, bm, ck);
+    if (s.in_layout == L_MAT && s.out_layout == L_MAT) return emulate_sweep<S, G, L_MAT, L_MAT, true>(in, out, a, bm, ck);
+    return TPD_ERROR_INTERNAL;
+  }
   if (s.in_layout == L_MAT && s.out_layout == L_CAN) return emulate_sweep<S, G, L_MAT, L_CAN>(in, out, a, bm, ck);
   if (s.in_layout == L_MAT && s.out_layout == L_MAT) return emulate_sweep<S, G, L_MAT, L_MAT>(in, out, a, bm, ck);
   if (s.in_layout == L_MAT && s.out_layout == L_MID) return emulate_sweep<S, G, L_MAT, L_MID>(in, out, a, bm, ck);
@@ -252,7 +257,6 @@ template <class S, int XB, int DB>
 tpd_status_t emulate_r(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint32_t* bm,
                        Checker& ck) {
   if (s.order == 1) return emulate_layouts<S, XB, DB, 1, 4>(s, in, out, a, bm, ck);
-  if (s.r == 3) return emulate_layouts<S, XB, DB, 0, 3>(s, in, out, a, bm, ck);
   return emulate_layouts<S, XB, DB, 0, 4>(s, in, out, a, bm, ck);
 }
 
@@ -372,7 +376,46 @@ tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, cons
                            int* nsweep, int* n1, uint64_t* bitmap_words);
 tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, std::vector<uint32_t>* perm,
                                std::vector<BatchItem>* items);
+tpd_status_t host_synth_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep);
 }  // namespace tpd
+
+extern "C" tpd_status_t tpd_debug_emulate_synth(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,
+                                                int in_place) {
+  if (!coeffs || !A) return TPD_ERROR_INVALID_VALUE;
+  if (n < 0 || n > 12) return TPD_ERROR_UNSUPPORTED;
+  if (in_place && coeffs != A) return TPD_ERROR_INVALID_VALUE;
+  SweepDesc sw[2];
+  int nsweep = 0;
+  tpd_status_t st = host_synth_schedule(n, dtype, flags, in_place != 0, sw, &nsweep);
+  if (st) return st;
+  const uint64_t count = (uint64_t)1 << (2 * n);
+  const size_t eb = dtype == TPD_C128 ? 16 : 8;
+  if (n == 0) {
+    if (coeffs != A) std::memcpy(A, coeffs, eb);
+    return TPD_SUCCESS;
+  }
+  for (int i = 0; i < nsweep; ++i) {
+    SweepArgs a{};
+    a.in = i == 0 ? coeffs : A;
+    a.out = A;
+    a.n = n;
+    a.xlo = sw[i].xlo;
+    a.db = sw[i].db;
+    a.nfix_d = n - sw[i].db;
+    a.bitmap = nullptr;
+    a.bitmap_mode = 0;
+    a.herm = 0;
+    a.ntiles = sw[i].ntiles;
+    Checker ck(count);
+    if (dtype == TPD_C128)
+      st = emulate_shape<double>(sw[i], (const Cx<double>*)a.in, (Cx<double>*)a.out, a, nullptr, ck);
+    else
+      st = emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, nullptr, ck);
+    if (st) return st;
+    if (!ck.complete()) return TPD_ERROR_INTERNAL;
+  }
+  return TPD_SUCCESS;
+}
 
 extern "C" tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype,
                                                 unsigned flags, int in_place, int db, int r) {

@@ -21,6 +21,7 @@ struct SweepDesc {
   int grid;         // 0: one workgroup per tile; > 0: persistent grid of that size
   bool is_one;      // the single sweep of an n <= 8 schedule
   int herm;         // 1: the input is Hermitian (read representatives only)
+  bool inv;         // inverse butterflies (synthesis)
   uint64_t ntiles;
 };
 

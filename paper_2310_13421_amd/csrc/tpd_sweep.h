@@ -15,7 +15,7 @@ namespace tpd {
 // ---------------------------------------------------------------------------
 // single-matrix sweep
 // ---------------------------------------------------------------------------
-template <class S, class G, int INL, int OUTL>
+template <class S, class G, int INL, int OUTL, bool INV = false>
 __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   static constexpr Roles RL = make_roles<G>();
   constexpr int P = G::NPH;
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const uint32_t ebp = elem_base<G>(RL, p, tid);
-      phase_butterflies<G, S>(RL, p, v, (td << G::DB) | (ebp & DM), xlo);
+      phase_butterflies<G, S, INV>(RL, p, v, (td << G::DB) | (ebp & DM), xlo);
       if (p + 1 < P) {
         __syncthreads();
 #pragma unroll
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
 // ---------------------------------------------------------------------------
 // launch of one instantiation
 // ---------------------------------------------------------------------------
-template <class S, int XB, int DB, int ORDER, int INL, int OUTL, int RR>
+template <class S, int XB, int DB, int ORDER, int INL, int OUTL, int RR, bool INV = false>
 hipError_t launch_one(const SweepArgs& a, int grid_req, hipStream_t st) {
   // at most 1024 threads per tile, at most 16 registers per thread
   constexpr int R1 = (XB + DB - 10) > RR ? (XB + DB - 10) : RR;
@@ -177,7 +177,7 @@ hipError_t launch_one(const SweepArgs& a, int grid_req, hipStream_t st) {
     if (grid > a.ntiles) grid = a.ntiles;
     const uint64_t cap = 0xFFFFFFFFull / (uint64_t)G::NT;
     if (grid > cap) grid = cap;
-    hipLaunchKernelGGL((k_sweep<S, G, INL, OUTL>), dim3((unsigned)grid), dim3(G::NT), 0, st, a);
+    hipLaunchKernelGGL((k_sweep<S, G, INL, OUTL, INV>), dim3((unsigned)grid), dim3(G::NT), 0, st, a);
     return hipGetLastError();
   }
 }
@@ -197,9 +197,9 @@ hipError_t dispatch_one(const SweepDesc& s, const SweepArgs& a, hipStream_t st) 
   return hipErrorInvalidValue;
 }
 
-// two-sweep halves: XB in 4..8 for the tile widths DB of one dtype and
-// register depths R in {3, 4}; the bottom-first phase order only for the
-// default tile width at R = 4
+// two-sweep halves: XB in 4..8 for the tile widths DB of one dtype, 16
+// elements per thread; the bottom-first phase order only for the default
+// tile width
 template <class S, int XB, int DB, int RR>
 hipError_t dispatch_two_layouts(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
   if (s.in_layout == L_MAT && s.out_layout == L_MID) return launch_one<S, XB, DB, 0, L_MAT, L_MID, RR>(a, s.grid, st);
@@ -216,7 +216,6 @@ hipError_t dispatch_two_bottom(const SweepDesc& s, const SweepArgs& a, hipStream
 template <class S, int XB, int DB>
 hipError_t dispatch_two_r(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
   if (s.order == 1) return dispatch_two_bottom<S, XB, DB>(s, a, st);
-  if (s.r == 3) return dispatch_two_layouts<S, XB, DB, 3>(s, a, st);
   return dispatch_two_layouts<S, XB, DB, 4>(s, a, st);
 }
 template <class S, int DB>
@@ -228,6 +227,41 @@ hipError_t dispatch_two_xb(const SweepDesc& s, const SweepArgs& a, hipStream_t s
     case 7: return dispatch_two_r<S, 7, DB>(s, a, st);
     case 8: return dispatch_two_r<S, 8, DB>(s, a, st);
   }
+  return hipErrorInvalidValue;
+}
+
+// inverse transform (synthesis): one sweep CAN|MAT -> MAT for n <= 8; two
+// sweeps for n >= 9 (low levels CAN|MAT -> MAT, then high levels MAT -> MAT
+// in place), default tile widths only
+template <class S, int XB, int DB>
+hipError_t dispatch_inv_layouts(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
+  if (s.out_layout != L_MAT) return hipErrorInvalidValue;
+  if (s.in_layout == L_CAN) return launch_one<S, XB, DB, 0, L_CAN, L_MAT, 4, true>(a, s.grid, st);
+  if (s.in_layout == L_MAT) return launch_one<S, XB, DB, 0, L_MAT, L_MAT, 4, true>(a, s.grid, st);
+  return hipErrorInvalidValue;
+}
+template <class S, int DB>
+hipError_t dispatch_inv_two(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
+  switch (s.xb) {
+    case 4: return dispatch_inv_layouts<S, 4, DB>(s, a, st);
+    case 5: return dispatch_inv_layouts<S, 5, DB>(s, a, st);
+    case 6: return dispatch_inv_layouts<S, 6, DB>(s, a, st);
+    case 7: return dispatch_inv_layouts<S, 7, DB>(s, a, st);
+    case 8: return dispatch_inv_layouts<S, 8, DB>(s, a, st);
+  }
+  return hipErrorInvalidValue;
+}
+template <class S>
+hipError_t dispatch_inv(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
+  if (s.is_one) {
+#define TPD_CASE(XB_, DB_) \
+    if (s.xb == XB_ && s.db == DB_) return dispatch_inv_layouts<S, XB_, DB_>(s, a, st);
+    TPD_ONE_SHAPES(TPD_CASE)
+#undef TPD_CASE
+    return hipErrorInvalidValue;
+  }
+  if (s.db == 4) return dispatch_inv_two<S, 4>(s, a, st);
+  if (s.db == 5) return dispatch_inv_two<S, 5>(s, a, st);
   return hipErrorInvalidValue;
 }
 

@@ -59,6 +59,8 @@ _SIGS = {
     "tpd_autotune": (_I, [_P, _I, _P, _I, _U, _P, ctypes.c_char_p, _SZ]),
     "tpd_autotune_batched": (_I, [_P, _P, _P, _P, ctypes.c_char_p, _SZ]),
     "tpd_debug_emulate_tuned": (_I, [_P, _I, _P, _I, _U, _I, _I, _I]),
+    "tpd_synthesize_ex": (_I, [_P, _I, _P, _I, _U, _P]),
+    "tpd_debug_emulate_synth": (_I, [_P, _I, _P, _I, _U, _I]),
     "tpd_status_string": (ctypes.c_char_p, [_I]),
     "tpd_index_from_string": (_U64, [ctypes.c_char_p]),
     "tpd_string_from_index": (_I, [_U64, _I, ctypes.c_char_p, _SZ]),
@@ -135,6 +137,18 @@ def emulate(A: np.ndarray, dtype: int = TPD_C128, flags: int = 0, in_place: bool
     _check(lib.tpd_debug_emulate_tuned(A.ctypes.data, n, out.ctypes.data, dtype, flags, 0, db, r),
            "tpd_debug_emulate")
     return out
+
+
+def emulate_synth(w: np.ndarray, n: int, dtype: int = TPD_C128, flags: int = 0, in_place: bool = False):
+    """Host replay of the synthesis schedule (small n)."""
+    w = np.ascontiguousarray(np.asarray(w).reshape(-1), dtype=_np_dtype(dtype))
+    if in_place:
+        out = w.copy()
+        _check(lib.tpd_debug_emulate_synth(out.ctypes.data, n, out.ctypes.data, dtype, flags, 1), "emulate_synth")
+        return out.reshape(1 << n, 1 << n)
+    out = np.full(w.size, np.nan, _np_dtype(dtype))
+    _check(lib.tpd_debug_emulate_synth(w.ctypes.data, n, out.ctypes.data, dtype, flags, 0), "emulate_synth")
+    return out.reshape(1 << n, 1 << n)
 
 
 def emulate_batched(mats: Sequence[np.ndarray], dtype: int = TPD_C128, flags: int = 0,
@@ -227,10 +241,31 @@ def autotune(A, out=None, *, layout: str = "canonical", prune: bool = True, herm
     n = _check_matrix(A)
     if out is None:
         out = torch.empty(4 ** n, dtype=A.dtype, device=A.device)
+    if out.dtype != A.dtype or not out.is_cuda or not out.is_contiguous() or out.numel() != 4 ** n:
+        raise ValueError("out must be a contiguous CUDA tensor of 4^n elements of A's dtype")
     buf = ctypes.create_string_buffer(8192)
     _check(lib.tpd_autotune(A.data_ptr(), n, out.data_ptr(), _dtype_code(A), _flags(layout, prune, False, hermitian),
                             _stream(stream), buf, 8192), "tpd_autotune")
     return json.loads(buf.value.decode())
+
+
+def synthesize(coeffs, out=None, *, layout: str = "canonical", stream=None):
+    """Inverse transform: A = sum_t w_t sigma^t from 4^n weights (canonical
+    order, or the matrix layout).  Returns the 2^n x 2^n matrix."""
+    torch = _torch()
+    if not coeffs.is_cuda or not coeffs.is_contiguous():
+        raise ValueError("coeffs must be a contiguous CUDA tensor")
+    m = coeffs.numel()
+    n = (m.bit_length() - 1) // 2
+    if 4 ** n != m:
+        raise ValueError("coeffs must hold 4^n values")
+    if out is None:
+        out = torch.empty((1 << n, 1 << n), dtype=coeffs.dtype, device=coeffs.device)
+    if out.dtype != coeffs.dtype or not out.is_cuda or not out.is_contiguous() or out.numel() != m:
+        raise ValueError("out must be a contiguous CUDA tensor of 4^n elements of coeffs' dtype")
+    _check(lib.tpd_synthesize_ex(coeffs.data_ptr(), n, out.data_ptr(), _dtype_code(coeffs), _flags(layout, True),
+                                 _stream(stream)), "tpd_synthesize_ex")
+    return out
 
 
 def decompose_batched(mats, outs=None, *, layout: str = "canonical", stream=None):

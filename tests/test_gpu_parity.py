@@ -509,3 +509,78 @@ def test_hermitian_mode(n):
         tpd.decompose(T, T.view(-1), hermitian=True, layout="matrix")
         got = matrix_to_canonical(T.cpu().numpy().ravel(), n)
         assert np.array_equal(got.real, gen.cpu().numpy().real) and np.all(got.imag == 0)
+
+
+# ----------------------------------------------------------------------------
+# inverse transform (synthesis) and round trips
+# ----------------------------------------------------------------------------
+def canonical_to_matrix(w, n):
+    d = 1 << n
+    h = np.arange(d, dtype=np.int64)[:, None]
+    l = np.arange(d, dtype=np.int64)[None, :]
+    q = (spread(h) << 1) | spread(l)
+    return np.asarray(w).reshape(-1)[q.ravel()].copy()
+
+
+@pytest.mark.parametrize("n", [0, 1, 4, 8, 9, 12])
+def test_synthesize_vs_oracle(n):
+    rng = np.random.default_rng(1200 + n)
+    w = rng.standard_normal(4 ** n) + 1j * rng.standard_normal(4 ** n)
+    ref = O.synthesize(w, n)
+    # level tree (n u 2^n max|w|) plus the oracle's sequential sum (2^n u 2^n max|w|)
+    bound64 = (n + (1 << n)) * U64 * (1 << n) * amax(w)
+    for dtype, bound in ((torch.complex128, bound64),
+                         (torch.complex64, (n + 1) * U32 * (1 << n) * amax(w) * 1.01 + bound64)):
+        got = tpd.synthesize(to_dev(w, dtype)).cpu().numpy()
+        assert cerr(got, ref) <= bound, (n, dtype)
+        wm = to_dev(canonical_to_matrix(w, n), dtype)
+        gm = tpd.synthesize(wm, layout="matrix").cpu().numpy()
+        assert same_bits(gm, got)
+        T = wm.clone()
+        tpd.synthesize(T, T.view(1 << n, 1 << n), layout="matrix")
+        assert same_bits(T.view(1 << n, 1 << n).cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("n", [3, 10, 13])
+def test_synthesize_integer_exact_and_round_trip(n):
+    rng = np.random.default_rng(1300 + n)
+    w = (rng.integers(-8, 9, 4 ** n) + 1j * rng.integers(-8, 9, 4 ** n)).astype(np.complex128)
+    for dtype in (torch.complex128, torch.complex64):
+        A = tpd.synthesize(to_dev(w, dtype))
+        if n <= 10:
+            assert same_bits(A.cpu().numpy().astype(np.complex128), O.synthesize(w, n))
+        back = tpd.decompose(A).cpu().numpy().astype(np.complex128)
+        assert same_bits(back, w), (n, dtype)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_n16_round_trip_in_place_integer_exact(dtype):
+    # 4^16 integer weights synthesized in place into the 65536 x 65536 matrix
+    # and decomposed back in place: exact at full size.  With the forward
+    # transform checked at this size against the definition, the exact round
+    # trip pins the synthesis as its inverse.
+    n = 16
+    m = 4 ** n
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(16)
+    re = torch.randint(-8, 9, (m,), generator=gen, device=DEV, dtype=torch.int8)
+    im = torch.randint(-8, 9, (m,), generator=gen, device=DEV, dtype=torch.int8)
+    T = torch.empty(m, dtype=dtype, device=DEV)
+    Tr = torch.view_as_real(T)
+    step = 1 << 28
+    for c in range(0, m, step):
+        Tr[c:c + step, 0].copy_(re[c:c + step])
+        Tr[c:c + step, 1].copy_(im[c:c + step])
+    M = T.view(1 << n, 1 << n)
+    tpd.synthesize(T, M, layout="matrix")
+    # Tr(A) = 2^n w_(I...I); the identity string sits at index 0 of either layout
+    tr = M.diagonal().to(torch.complex128).sum().item()
+    assert tr == complex(float(re[0]), float(im[0])) * (1 << n)
+    torch.cuda.synchronize()
+    tpd.decompose(M, T, layout="matrix")
+    torch.cuda.synchronize()
+    for c in range(0, m, step):
+        assert torch.equal(Tr[c:c + step, 0], re[c:c + step].to(Tr.dtype))
+        assert torch.equal(Tr[c:c + step, 1], im[c:c + step].to(Tr.dtype))
+    del T, re, im
+    torch.cuda.empty_cache()

