@@ -76,10 +76,29 @@ class TPDError(RuntimeError):
         super().__init__(f"{what}: {STATUS.get(code, code)}")
 
 
+def _hip_runtimes():
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+    except OSError:
+        return []
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libtpd.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    # torch ships its own HIP runtime under the same soname.  Loading torch
+    # first makes the library bind to that runtime, so device pointers and
+    # streams created by torch are valid in it; loaded the other way round
+    # the process would hold two runtimes with separate device state.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise ImportError("more than one HIP runtime is loaded in this process: " + ", ".join(runtimes))
     for name, (res, args) in _SIGS.items():
         f = getattr(lib, name)
         f.restype = res

@@ -133,3 +133,9 @@ def test_schedule_flags():
     assert not s["prune"] and all(w["bitmap"] == "none" for w in s["sweeps"])
     with pytest.raises(tpd.TPDError):
         tpd.schedule(12, tpd.TPD_C128, 0, in_place=True)
+
+
+def test_single_hip_runtime_in_process():
+    # the library must share torch's HIP runtime (same soname, different file)
+    import torch  # noqa: F401
+    assert len(tpd._hip_runtimes()) <= 1, tpd._hip_runtimes()
