@@ -123,6 +123,53 @@ tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dt
 tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,
                                tpd_stream_t stream);
 
+/* Partial decomposition: the weights of requested strings only (section
+ * "Methods", the partial variant of Fig. 2 / Algorithm 3).  The paper slices
+ * only the children in the request tree; here the unit of skipping is a
+ * tile: a first-sweep d-group (2^db XOR-diagonals, all rows) runs only if a
+ * requested string has its X/Y mask in that group, and a second-sweep tile
+ * only if a requested string lies in it (and, with pruning, its cumulative
+ * matrix weight is nonzero).  n <= 8 computes everything.  Requested values
+ * are bitwise those of tpd_decompose_ex with the same dtype and flags.
+ *   A      [in]  device matrix, as tpd_decompose_ex (not modified unless
+ *                coeffs == A)
+ *   coeffs [out] device, 4^n elements of work/output, layout per flags; on
+ *                return it holds the requested weights at their positions,
+ *                every other element is unspecified.  May equal A with the
+ *                same rules as tpd_decompose_ex.
+ *   req    [in]  device array[count] of canonical indices q, any order,
+ *                repeats allowed; q >= 4^n yields NaN + NaN i
+ *   count  [in]  number of requests (0: nothing is enqueued)
+ *   values [out] device array[count] of complex dtype, values[s] = w_req[s]
+ *   flags  TPD_FLAG_NO_PRUNE, TPD_FLAG_LAYOUT_MATRIX, TPD_FLAG_HERMITIAN,
+ *          TPD_FLAG_ORDER_BOTTOM; TPD_FLAG_TIMING is TPD_ERROR_INVALID_VALUE
+ * Workspace: two request bitmaps (2^(n-db) and 2^(n1+n-db) bits) per
+ * (device, stream), plus the pruning bitmap.                              */
+tpd_status_t tpd_decompose_partial(const void* A, int n, void* coeffs, const uint64_t* req, uint64_t count,
+                                   void* values, tpd_dtype_t dtype, unsigned flags, tpd_stream_t stream);
+
+/* Sparse-list output: the nonzero weights as (q, w) pairs, the list L that
+ * Algorithms 1 and 2 return (section "Methods").  Ordered stream
+ * compaction of a coefficient array: an element is kept unless both |re|
+ * and |im| are <= tol (compared in the dtype's precision, tol rounded to
+ * it; NaN is kept).  Pairs appear in storage order: ascending q for the
+ * canonical layout, ascending (row h, column l) for the matrix layout.
+ *   coeffs   [in]  device, 4^n coefficients (canonical, or matrix layout
+ *                  with TPD_FLAG_LAYOUT_MATRIX; no other flag)
+ *   tol      [in]  >= 0 (0: exact nonzeros); negative or NaN is
+ *                  TPD_ERROR_INVALID_VALUE
+ *   q_out    [out] device array[capacity] of canonical indices
+ *   w_out    [out] device array[capacity] of complex dtype
+ *   capacity [in]  entries available; only the first `capacity` pairs are
+ *                  written (q_out and w_out may be NULL when it is 0)
+ *   count    [out] device, one uint64: the total number of kept pairs
+ *                  (may exceed capacity)
+ * Cost: one read of the array to count per chunk of 4096 elements, an
+ * exclusive scan of the chunk counts, and a second read of the chunks that
+ * hold kept elements.  Workspace: 12 bytes per chunk per (device, stream). */
+tpd_status_t tpd_compact(const void* coeffs, int n, tpd_dtype_t dtype, unsigned flags, double tol, uint64_t* q_out,
+                         void* w_out, uint64_t capacity, uint64_t* count, tpd_stream_t stream);
+
 /* Decompose `count` independent matrices of mixed sizes in one persistent
  * kernel launch (the paper's motivation: many time steps of a
  * time-dependent Hamiltonian, section "Introduction").
@@ -233,6 +280,14 @@ tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tpd_dtype_t d
  * the default schedule); r must be 0 or 4 (elements per thread = 16).    */
 tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                                      int in_place, int db, int r);
+
+/* Host replays of the partial decomposition (request marking, tile skips,
+ * gather) and of the compaction (same chunks, order and clipping); HOST
+ * pointers, n <= 12, otherwise the arguments of the device calls.         */
+tpd_status_t tpd_debug_emulate_partial(const void* A, int n, void* coeffs, const uint64_t* req, uint64_t count,
+                                       void* values, tpd_dtype_t dtype, unsigned flags, int in_place);
+tpd_status_t tpd_debug_emulate_compact(const void* coeffs, int n, tpd_dtype_t dtype, unsigned flags, double tol,
+                                       uint64_t* q_out, void* w_out, uint64_t capacity, uint64_t* count);
 
 /* Host replay of the synthesis schedule (HOST pointers, small n). */
 tpd_status_t tpd_debug_emulate_synth(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,

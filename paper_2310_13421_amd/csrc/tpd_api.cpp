@@ -178,6 +178,23 @@ tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Sched
   return make_schedule_with(n, dt, flags, in_place, nullptr, s);
 }
 
+// partial decomposition: the same sweeps, the second one always checking
+// its tile bitmap (requests, ANDed with the live tiles when pruning)
+tpd_status_t make_partial_schedule(int n, Dtype dt, unsigned flags, bool in_place, const Tuned* force,
+                                   Schedule* s) {
+  tpd_status_t st = make_schedule_with(n, dt, flags, in_place, force, s);
+  if (st) return st;
+  if (s->nsweep == 2) {
+    s->sw[0].bitmap_mode = s->prune ? 1 : 0;
+    s->sw[1].bitmap_mode = 2;
+  }
+  return TPD_SUCCESS;
+}
+
+uint64_t group_words_of(const Schedule& s) {
+  return s.nsweep == 2 ? ((((uint64_t)1 << (s.n - s.sw[0].db)) + 31) / 32) : 0;
+}
+
 // Inverse transform (synthesis A = sum_t w_t sigma^t): the same levels with
 // the inverse butterfly.  n <= 8: one sweep CAN|MAT -> MAT.  n >= 9: the low
 // n2 levels first (tiles of fixed high rows, reading the canonical order's
@@ -378,6 +395,10 @@ tpd_status_t dev_alloc(void** p, size_t bytes) {
 struct Workspace {
   uint32_t* bitmap = nullptr;
   uint64_t bitmap_words = 0;
+  uint32_t* req = nullptr;  // partial decomposition: d-group bits, then second-sweep tile bits
+  uint64_t req_words = 0;
+  void* sel = nullptr;  // compaction: per-chunk counts and offsets, total
+  size_t sel_bytes = 0;
   unsigned long long* counter = nullptr;
   void* table = nullptr;  // batched tables (perm, items, pointer arrays)
   size_t table_bytes = 0;
@@ -397,6 +418,30 @@ tpd_status_t ensure_bitmap(Workspace& w, uint64_t words) {
   if (st) return st;
   w.bitmap = (uint32_t*)p;
   w.bitmap_words = words;
+  return TPD_SUCCESS;
+}
+
+tpd_status_t ensure_words(uint32_t** p, uint64_t* have, uint64_t words) {
+  if (*have >= words) return TPD_SUCCESS;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *have = 0;
+  void* q;
+  tpd_status_t st = dev_alloc(&q, words * 4);
+  if (st) return st;
+  *p = (uint32_t*)q;
+  *have = words;
+  return TPD_SUCCESS;
+}
+
+tpd_status_t ensure_sel(Workspace& w, size_t bytes) {
+  if (w.sel_bytes >= bytes) return TPD_SUCCESS;
+  if (w.sel) (void)hipFree(w.sel);
+  w.sel = nullptr;
+  w.sel_bytes = 0;
+  tpd_status_t st = dev_alloc(&w.sel, bytes);
+  if (st) return st;
+  w.sel_bytes = bytes;
   return TPD_SUCCESS;
 }
 
@@ -481,6 +526,30 @@ struct Timing {
 // ---------------------------------------------------------------------------
 // single-matrix execution
 // ---------------------------------------------------------------------------
+tpd_status_t launch_sweep_i(const Schedule& s, int i, const void* A, void* C, uint32_t* bitmap,
+                            const uint32_t* req, hipStream_t st) {
+  const SweepDesc& w = s.sw[i];
+  SweepArgs a{};
+  a.in = (i == 0) ? A : C;
+  a.out = C;
+  a.n = s.n;
+  a.xlo = w.xlo;
+  a.db = w.db;
+  a.nfix_d = s.n - w.db;
+  a.bitmap = bitmap;
+  a.bitmap_mode = w.bitmap_mode;
+  a.bm_xbits = s.n1;
+  a.herm = w.herm;
+  a.req = req;
+  a.ntiles = w.ntiles;
+  const hipError_t e = launch_sweep(s.dt, w, a, st);
+  if (e != hipSuccess) {
+    logf("sweep %d launch failed: %s", i, hipGetErrorString(e));
+    return TPD_ERROR_LAUNCH;
+  }
+  return TPD_SUCCESS;
+}
+
 tpd_status_t run_schedule(const Schedule& s, const void* A, void* C, uint32_t* bitmap, hipStream_t st,
                           Timing* tm) {
   const size_t eb = elem_bytes(s.dt);
@@ -492,27 +561,37 @@ tpd_status_t run_schedule(const Schedule& s, const void* A, void* C, uint32_t* b
     if (launch_fill_u32(bitmap, s.bitmap_words, 0u, st) != hipSuccess) return TPD_ERROR_LAUNCH;
   }
   for (int i = 0; i < s.nsweep; ++i) {
-    const SweepDesc& w = s.sw[i];
-    SweepArgs a{};
-    a.in = (i == 0) ? A : C;
-    a.out = C;
-    a.n = s.n;
-    a.xlo = w.xlo;
-    a.db = w.db;
-    a.nfix_d = s.n - w.db;
-    a.bitmap = bitmap;
-    a.bitmap_mode = w.bitmap_mode;
-    a.bm_xbits = s.n1;
-    a.herm = w.herm;
-    a.ntiles = w.ntiles;
     const int slot = tm ? tm->begin(i, st) : -1;
-    const hipError_t e = launch_sweep(s.dt, w, a, st);
+    const tpd_status_t e = launch_sweep_i(s, i, A, C, bitmap, nullptr, st);
     if (tm) tm->end(i, slot, st);
-    if (e != hipSuccess) {
-      logf("sweep %d launch failed: %s", i, hipGetErrorString(e));
-      return TPD_ERROR_LAUNCH;
-    }
+    if (e) return e;
   }
+  return TPD_SUCCESS;
+}
+
+// Partial decomposition (the paper's Algorithm 3 at tile granularity): a
+// d-group of the first sweep runs only if some requested string lies in it,
+// a second-sweep tile only if one lies in it (and, with pruning, it is
+// live); then the requested weights are gathered.  n <= 8: the whole single
+// sweep, then the gather.
+tpd_status_t run_partial(const Schedule& s, const void* A, void* C, const uint64_t* req, uint64_t count,
+                         void* values, uint32_t* live, uint32_t* groups, uint64_t group_words, uint32_t* tiles,
+                         hipStream_t st) {
+  if (s.nsweep == 2) {
+    if (launch_fill_u32(groups, group_words + s.bitmap_words, 0u, st) != hipSuccess) return TPD_ERROR_LAUNCH;
+    if (launch_mark_requests(req, count, s.n, s.n1, s.sw[0].db, groups, tiles, st) != hipSuccess)
+      return TPD_ERROR_LAUNCH;
+    if (s.prune && launch_fill_u32(live, s.bitmap_words, 0u, st) != hipSuccess) return TPD_ERROR_LAUNCH;
+    tpd_status_t e = launch_sweep_i(s, 0, A, C, live, groups, st);
+    if (e) return e;
+    if (s.prune && launch_and_u32(tiles, live, s.bitmap_words, st) != hipSuccess) return TPD_ERROR_LAUNCH;
+    e = launch_sweep_i(s, 1, A, C, tiles, nullptr, st);
+    if (e) return e;
+  } else {
+    tpd_status_t e = run_schedule(s, A, C, nullptr, st, nullptr);
+    if (e) return e;
+  }
+  if (launch_gather(s.dt, C, s.n, s.matrix_layout, req, count, values, st) != hipSuccess) return TPD_ERROR_LAUNCH;
   return TPD_SUCCESS;
 }
 
@@ -706,6 +785,87 @@ tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t d
   return run_schedule(s, coeffs, A, nullptr, (hipStream_t)stream, nullptr);
 }
 
+tpd_status_t tpd_decompose_partial(const void* A, int n, void* coeffs, const uint64_t* req, uint64_t count,
+                                   void* values, tpd_dtype_t dtype, unsigned flags, tpd_stream_t stream) {
+  tpd_status_t st = check_dtype_flags(dtype, flags);
+  if (st) return st;
+  if (flags & TPD_FLAG_TIMING) return TPD_ERROR_INVALID_VALUE;
+  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  const Dtype dt = (Dtype)dtype;
+  st = check_buffers(A, coeffs, n, dt);
+  if (st) return st;
+  if (count > 0 && (!req || !values)) return TPD_ERROR_INVALID_VALUE;
+  if (((uintptr_t)req % 8) || ((uintptr_t)values % elem_bytes(dt))) return TPD_ERROR_INVALID_VALUE;
+  Schedule s;
+  st = make_partial_schedule(n, dt, flags, A == coeffs, nullptr, &s);
+  if (st) return st;
+  if (count == 0) return TPD_SUCCESS;
+  int dev;
+  st = current_device(&dev);
+  if (st) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  uint32_t *live = nullptr, *groups = nullptr, *tiles = nullptr;
+  const uint64_t gw = group_words_of(s);
+  if (n == 0) {
+    if (A != coeffs && hipMemcpyAsync(coeffs, A, elem_bytes(dt), hipMemcpyDeviceToDevice, hs) != hipSuccess)
+      return TPD_ERROR_LAUNCH;
+    return launch_gather(dt, coeffs, 0, s.matrix_layout, req, count, values, hs) == hipSuccess ? TPD_SUCCESS
+                                                                                              : TPD_ERROR_LAUNCH;
+  }
+  if (s.nsweep == 2) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace& w = g_ws[{dev, hs}];
+    if (s.prune) {
+      st = ensure_bitmap(w, s.bitmap_words);
+      if (st) return st;
+      live = w.bitmap;
+    }
+    st = ensure_words(&w.req, &w.req_words, gw + s.bitmap_words);
+    if (st) return st;
+    groups = w.req;
+    tiles = w.req + gw;
+  }
+  logf("decompose_partial n=%d count=%llu %s", n, (unsigned long long)count, describe(s).c_str());
+  return run_partial(s, A, coeffs, req, count, values, live, groups, gw, tiles, hs);
+}
+
+tpd_status_t tpd_compact(const void* coeffs, int n, tpd_dtype_t dtype, unsigned flags, double tol, uint64_t* q_out,
+                         void* w_out, uint64_t capacity, uint64_t* count, tpd_stream_t stream) {
+  tpd_status_t st = check_dtype_flags(dtype, flags);
+  if (st) return st;
+  if (flags & ~TPD_FLAG_LAYOUT_MATRIX) return TPD_ERROR_INVALID_VALUE;
+  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  const Dtype dt = (Dtype)dtype;
+  if (!coeffs || !count || ((uintptr_t)coeffs % elem_bytes(dt)) || ((uintptr_t)count % 8))
+    return TPD_ERROR_INVALID_VALUE;
+  if (!(tol >= 0.0)) return TPD_ERROR_INVALID_VALUE;  // negative or NaN
+  if (capacity > 0 && (!q_out || !w_out || ((uintptr_t)q_out % 8) || ((uintptr_t)w_out % elem_bytes(dt))))
+    return TPD_ERROR_INVALID_VALUE;
+  int dev;
+  st = current_device(&dev);
+  if (st) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  const uint64_t elems = (uint64_t)1 << (2 * n);
+  const uint64_t nchunks = (elems + kCompactChunk - 1) / kCompactChunk;
+  uint32_t* counts;
+  uint64_t* offsets;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace& w = g_ws[{dev, hs}];
+    const size_t cbytes = ((nchunks * 4 + 255) / 256) * 256;
+    st = ensure_sel(w, cbytes + nchunks * 8);
+    if (st) return st;
+    counts = (uint32_t*)w.sel;
+    offsets = (uint64_t*)((char*)w.sel + cbytes);
+  }
+  const bool mat = (flags & TPD_FLAG_LAYOUT_MATRIX) != 0;
+  if (launch_compact_count(dt, coeffs, elems, tol, counts, hs) != hipSuccess) return TPD_ERROR_LAUNCH;
+  if (launch_compact_scan(counts, nchunks, offsets, count, hs) != hipSuccess) return TPD_ERROR_LAUNCH;
+  if (launch_compact_write(dt, coeffs, n, mat, tol, counts, offsets, capacity, q_out, w_out, hs) != hipSuccess)
+    return TPD_ERROR_LAUNCH;
+  return TPD_SUCCESS;
+}
+
 tpd_status_t tpd_decompose(const void* A, int n, void* coeffs, tpd_stream_t stream) {
   return tpd_decompose_ex(A, n, coeffs, TPD_C128, 0u, stream);
 }
@@ -716,6 +876,8 @@ tpd_status_t tpd_release_workspace(void) {
     Workspace& w = kv.second;
     if (w.staged) (void)hipEventSynchronize(w.staged);
     if (w.bitmap) (void)hipFree(w.bitmap);
+    if (w.req) (void)hipFree(w.req);
+    if (w.sel) (void)hipFree(w.sel);
     if (w.counter) (void)hipFree(w.counter);
     if (w.table) (void)hipFree(w.table);
     if (w.host_table) (void)hipHostFree(w.host_table);
@@ -978,6 +1140,22 @@ tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, cons
   *nsweep = s.nsweep;
   *n1 = s.n1;
   *bitmap_words = s.bitmap_words;
+  return TPD_SUCCESS;
+}
+
+tpd_status_t host_partial_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep,
+                                   int* n1, uint64_t* bitmap_words, int* prune) {
+  tpd_status_t st = check_dtype_flags(dtype, flags);
+  if (st) return st;
+  if (flags & TPD_FLAG_TIMING) return TPD_ERROR_INVALID_VALUE;
+  Schedule s;
+  st = make_partial_schedule(n, (Dtype)dtype, flags, in_place, nullptr, &s);
+  if (st) return st;
+  for (int i = 0; i < s.nsweep; ++i) sw[i] = s.sw[i];
+  *nsweep = s.nsweep;
+  *n1 = s.n1;
+  *bitmap_words = s.bitmap_words;
+  *prune = s.prune ? 1 : 0;
   return TPD_SUCCESS;
 }
 

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -26,6 +27,13 @@ struct Checker {
   uint64_t count;
   std::vector<uint8_t> reads, writes;
   bool ok = true;
+  // second-sweep tiles skipped by the bitmap must hold zeros; with partial
+  // requests only the requested tiles that are not live (null: no
+  // restriction; zero_check false: no tile)
+  const uint32_t* live = nullptr;
+  const uint32_t* requested = nullptr;
+  bool zero_check = true;
+  static bool bit(const uint32_t* m, uint64_t b) { return (m[b >> 5] >> (b & 31)) & 1u; }
   explicit Checker(uint64_t c) : count(c), reads(c, 0), writes(c, 0) {}
   void rd(uint64_t a) {
     if (a >= count) { ok = false; return; }
@@ -61,10 +69,35 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
     const uint64_t td = tile & tdmask;
     const uint64_t xf = tile >> a.nfix_d;
     const uint64_t xfix = (xf & (((uint64_t)1 << xlo) - 1)) | ((xf >> xlo) << (xlo + G::XB));
+    if (a.req && !((a.req[td >> 5] >> (td & 31)) & 1u)) {
+      // d-group without requested strings: nothing is read or written
+      // (account its addresses so completeness still checks)
+      for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+        const uint32_t eb = elem_base<G>(RL, 0, tid);
+        for (int j = 0; j < G::E; ++j) {
+          const uint32_t e = eb | elem_reg<G>(RL, 0, j);
+          const uint64_t x = xfix | ((uint64_t)((e >> G::DB) & XM) << xlo);
+          const uint64_t d = (td << G::DB) | (e & DM);
+          ck.rd(layout_addr<INL>(x, d, n, db));
+          ck.wr(layout_addr<OUTL>(x, d, n, db));
+        }
+      }
+      continue;
+    }
     if (a.bitmap_mode == 2) {
       const uint64_t bit = (td << a.bm_xbits) | xf;
       if (!((bitmap[bit >> 5] >> (bit & 31)) & 1u)) {
         // skipped tile: account its addresses as read and written in place
+        const bool must_be_zero = ck.zero_check && (!ck.requested || Checker::bit(ck.requested, bit)) &&
+                                  (!ck.live || !Checker::bit(ck.live, bit));
+        // Hermitian second sweep: rows that are not representatives were
+        // never written by the first sweep and are not read
+        uint64_t hskip = 0;
+        if (a.herm && !xlo) {
+          constexpr int kLh = G::XB > G::DB ? G::XB - G::DB : 0;
+          const uint64_t dlh = td & (((uint64_t)1 << kLh) - 1);
+          if (dlh) hskip = (uint64_t)1 << (63 - __builtin_clzll(dlh) + G::DB);
+        }
         for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
           const uint32_t eb = elem_base<G>(RL, 0, tid);
           for (int j = 0; j < G::E; ++j) {
@@ -75,7 +108,7 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
             const uint64_t ao = layout_addr<OUTL>(x, d, n, db);
             ck.rd(ai);
             ck.wr(ao);
-            if (ai < ck.count) {
+            if (must_be_zero && ai < ck.count && !(((uint64_t)((e >> G::DB) & XM)) & hskip)) {
               const Cx<S> z = in[ai];
               if (z.re != (S)0 || z.im != (S)0) return TPD_ERROR_INTERNAL;  // bit must have been set
             }
@@ -377,6 +410,8 @@ tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, cons
 tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, std::vector<uint32_t>* perm,
                                std::vector<BatchItem>* items);
 tpd_status_t host_synth_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep);
+tpd_status_t host_partial_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep,
+                                   int* n1, uint64_t* bitmap_words, int* prune);
 }  // namespace tpd
 
 extern "C" tpd_status_t tpd_debug_emulate_synth(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,
@@ -485,5 +520,125 @@ extern "C" tpd_status_t tpd_debug_emulate_batched(const void* const* ptrs, const
                : emulate_item_n<float, L_CAN>(ptrs, outs, perm.data(), it);
     if (st) return st;
   }
+  return TPD_SUCCESS;
+}
+
+extern "C" tpd_status_t tpd_debug_emulate_partial(const void* A, int n, void* coeffs, const uint64_t* req,
+                                                  uint64_t count, void* values, tpd_dtype_t dtype, unsigned flags,
+                                                  int in_place) {
+  if (!A || !coeffs || (count && (!req || !values))) return TPD_ERROR_INVALID_VALUE;
+  if (n < 0 || n > 12) return TPD_ERROR_UNSUPPORTED;
+  if (in_place && A != coeffs) return TPD_ERROR_INVALID_VALUE;
+  SweepDesc sw[2];
+  int nsweep = 0, n1 = 0, prune = 0;
+  uint64_t words = 0;
+  tpd_status_t st = host_partial_schedule(n, dtype, flags, in_place != 0, sw, &nsweep, &n1, &words, &prune);
+  if (st) return st;
+  const uint64_t elems = (uint64_t)1 << (2 * n);
+  const size_t eb = dtype == TPD_C128 ? 16 : 8;
+  const bool mat = (flags & TPD_FLAG_LAYOUT_MATRIX) != 0;
+  if (n == 0) {
+    if (A != coeffs) std::memcpy(coeffs, A, eb);
+  } else if (nsweep == 1) {
+    st = tpd_debug_emulate_tuned(A, n, coeffs, dtype, flags, in_place, 0, 0);
+    if (st) return st;
+  } else {
+    const int db = sw[0].db;
+    const uint64_t gw = (((uint64_t)1 << (n - db)) + 31) / 32;
+    std::vector<uint32_t> groups(gw, 0u), tiles(words, 0u), live(words, 0u);
+    for (uint64_t i = 0; i < count; ++i) {
+      if (req[i] >= elems) continue;
+      uint64_t g, t;
+      request_bits(req[i], n, n1, db, &g, &t);
+      groups[g >> 5] |= 1u << (g & 31);
+      tiles[t >> 5] |= 1u << (t & 31);
+    }
+    const std::vector<uint32_t> requested = tiles;
+    for (int i = 0; i < 2; ++i) {
+      SweepArgs a{};
+      a.in = i == 0 ? A : coeffs;
+      a.out = coeffs;
+      a.n = n;
+      a.xlo = sw[i].xlo;
+      a.db = db;
+      a.nfix_d = n - db;
+      a.bitmap = i == 0 ? live.data() : tiles.data();
+      a.bitmap_mode = sw[i].bitmap_mode;
+      a.bm_xbits = n1;
+      a.herm = sw[i].herm;
+      a.req = i == 0 ? groups.data() : nullptr;
+      a.ntiles = sw[i].ntiles;
+      Checker ck(elems);
+      ck.live = live.data();
+      ck.requested = requested.data();
+      ck.zero_check = prune != 0;
+      if (dtype == TPD_C128)
+        st = emulate_shape<double>(sw[i], (const Cx<double>*)a.in, (Cx<double>*)a.out, a, a.bitmap, ck);
+      else
+        st = emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, a.bitmap, ck);
+      if (st) return st;
+      if (!ck.complete()) return TPD_ERROR_INTERNAL;
+      if (i == 0 && prune)
+        for (uint64_t w = 0; w < words; ++w) tiles[w] &= live[w];
+    }
+  }
+  for (uint64_t i = 0; i < count; ++i) {
+    const uint64_t q = req[i];
+    char* dst = (char*)values + i * eb;
+    if (q >= elems) {
+      if (dtype == TPD_C128) {
+        const double nan2[2] = {std::nan(""), std::nan("")};
+        std::memcpy(dst, nan2, eb);
+      } else {
+        const float nan2[2] = {std::nanf(""), std::nanf("")};
+        std::memcpy(dst, nan2, eb);
+      }
+      continue;
+    }
+    std::memcpy(dst, (const char*)coeffs + storage_of_q(q, n, mat) * eb, eb);
+  }
+  return TPD_SUCCESS;
+}
+
+// host replay of the ordered compaction: the same chunks, per-chunk counts,
+// exclusive offsets, capacity clipping and (j, wave, lane) storage order
+extern "C" tpd_status_t tpd_debug_emulate_compact(const void* coeffs, int n, tpd_dtype_t dtype, unsigned flags,
+                                                  double tol, uint64_t* q_out, void* w_out, uint64_t capacity,
+                                                  uint64_t* count) {
+  if (!coeffs || !count || (capacity && (!q_out || !w_out))) return TPD_ERROR_INVALID_VALUE;
+  if (dtype != TPD_C128 && dtype != TPD_C64) return TPD_ERROR_INVALID_VALUE;
+  if (flags & ~TPD_FLAG_LAYOUT_MATRIX) return TPD_ERROR_INVALID_VALUE;
+  if (n < 0 || n > 12) return TPD_ERROR_UNSUPPORTED;
+  if (!(tol >= 0.0)) return TPD_ERROR_INVALID_VALUE;
+  const bool mat = (flags & TPD_FLAG_LAYOUT_MATRIX) != 0;
+  const uint64_t elems = (uint64_t)1 << (2 * n);
+  const uint64_t nchunks = (elems + kCompactChunk - 1) / kCompactChunk;
+  const size_t eb = dtype == TPD_C128 ? 16 : 8;
+  auto kept = [&](uint64_t i) {
+    if (dtype == TPD_C128) {
+      const double* v = (const double*)coeffs + 2 * i;
+      return keep_coeff<double>(v[0], v[1], tol);
+    }
+    const float* v = (const float*)coeffs + 2 * i;
+    return keep_coeff<float>(v[0], v[1], (float)tol);
+  };
+  std::vector<uint32_t> counts(nchunks, 0u);
+  for (uint64_t c = 0; c < nchunks; ++c)
+    for (uint64_t i = c * kCompactChunk; i < std::min(elems, (c + 1) * kCompactChunk); ++i) counts[c] += kept(i);
+  uint64_t run = 0;
+  for (uint64_t c = 0; c < nchunks; ++c) {
+    uint64_t pos = run;
+    run += counts[c];
+    if (!counts[c]) continue;
+    for (uint64_t i = c * kCompactChunk; i < std::min(elems, (c + 1) * kCompactChunk); ++i) {
+      if (!kept(i)) continue;
+      if (pos < capacity) {
+        q_out[pos] = q_of_storage(i, n, mat);
+        std::memcpy((char*)w_out + pos * eb, (const char*)coeffs + i * eb, eb);
+      }
+      ++pos;
+    }
+  }
+  *count = run;
   return TPD_SUCCESS;
 }

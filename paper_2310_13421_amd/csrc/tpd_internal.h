@@ -36,6 +36,7 @@ struct SweepArgs {
   int bitmap_mode;
   int bm_xbits;      // x bits of the first sweep (bit index = (td << bm_xbits) | x_hi)
   int herm;          // 1: Hermitian input, two-sweep schedule
+  const uint32_t* req;  // partial decomposition: bit per d-group td, tiles of unset groups are skipped (null: all)
   uint64_t ntiles;
 };
 
@@ -65,6 +66,72 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t words, uint32_t value, hipStrea
 hipError_t launch_batched_perm(Dtype dt, const void* const* in_ptrs, void* const* out_ptrs, const uint32_t* perm,
                                const BatchItem* items, uint32_t nitems, int layout, int grid, hipStream_t st);
 hipError_t launch_popcount(const uint32_t* p, uint64_t words, unsigned long long* out, hipStream_t st);
+
+// selection kernels (tpd_select.hip)
+hipError_t launch_mark_requests(const uint64_t* req, uint64_t count, int n, int n1, int db, uint32_t* req_groups,
+                                uint32_t* req_tiles, hipStream_t st);
+hipError_t launch_and_u32(uint32_t* dst, const uint32_t* src, uint64_t words, hipStream_t st);
+hipError_t launch_gather(Dtype dt, const void* coeffs, int n, bool matrix_layout, const uint64_t* req,
+                         uint64_t count, void* values, hipStream_t st);
+constexpr uint32_t kCompactChunk = 4096;  // elements per compaction workgroup (256 threads x 16)
+hipError_t launch_compact_count(Dtype dt, const void* coeffs, uint64_t elems, double tol, uint32_t* counts,
+                                hipStream_t st);
+hipError_t launch_compact_scan(const uint32_t* counts, uint64_t nchunks, uint64_t* offsets, uint64_t* total,
+                               hipStream_t st);
+hipError_t launch_compact_write(Dtype dt, const void* coeffs, int n, bool matrix_layout, double tol,
+                                const uint32_t* counts, const uint64_t* offsets, uint64_t capacity,
+                                uint64_t* q_out, void* w_out, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// index maps shared by the selection kernels and their host replay
+// ---------------------------------------------------------------------------
+// even bits of q packed (the low bits of the Pauli digits: the column index)
+__host__ __device__ inline uint64_t pack_even_bits(uint64_t q) {
+  q &= 0x5555555555555555ull;
+  q = (q | (q >> 1)) & 0x3333333333333333ull;
+  q = (q | (q >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+  q = (q | (q >> 4)) & 0x00FF00FF00FF00FFull;
+  q = (q | (q >> 8)) & 0x0000FFFF0000FFFFull;
+  q = (q | (q >> 16)) & 0x00000000FFFFFFFFull;
+  return q;
+}
+__host__ __device__ inline uint64_t spread_bits(uint64_t v) {
+  v &= 0x00000000FFFFFFFFull;
+  v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
+  v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
+  v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
+  v = (v | (v << 2)) & 0x3333333333333333ull;
+  v = (v | (v << 1)) & 0x5555555555555555ull;
+  return v;
+}
+// canonical index q -> element offset in the canonical or matrix layout
+// (matrix layout: row = hi bits of the digits, column = lo bits)
+__host__ __device__ inline uint64_t storage_of_q(uint64_t q, int n, bool matrix_layout) {
+  if (!matrix_layout) return q;
+  return (pack_even_bits(q >> 1) << n) | pack_even_bits(q);
+}
+__host__ __device__ inline uint64_t q_of_storage(uint64_t a, int n, bool matrix_layout) {
+  if (!matrix_layout) return a;
+  const uint64_t lo = a & (((uint64_t)1 << n) - 1);
+  return (spread_bits(a >> n) << 1) | spread_bits(lo);
+}
+// the two request bits of canonical string q in a two-sweep schedule: its
+// d-group td = (row ^ col) >> db (first sweep) and its second-sweep tile
+// (td << n1) | (row >> (n - n1))
+__host__ __device__ inline void request_bits(uint64_t q, int n, int n1, int db, uint64_t* group, uint64_t* tile) {
+  const uint64_t row = pack_even_bits(q >> 1), col = pack_even_bits(q);
+  const uint64_t td = (row ^ col) >> db;
+  *group = td;
+  *tile = (td << n1) | (row >> (n - n1));
+}
+// a coefficient is kept in the sparse list unless both parts are within tol
+// (compared in the coefficient's own precision; NaN is kept)
+template <class S>
+__host__ __device__ inline bool keep_coeff(S re, S im, S tol) {
+  const S ar = re < (S)0 ? -re : re;
+  const S ai = im < (S)0 ? -im : im;
+  return !(ar <= tol && ai <= tol);
+}
 
 // a sweep tile (plus its small bitmap scratch) must fit the LDS of one
 // workgroup; gfx950 gives a workgroup up to 160 KiB, tiles use <= 128 KiB

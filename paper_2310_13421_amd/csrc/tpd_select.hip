@@ -1,0 +1,239 @@
+// tpd_select.hip -- kernels that select strings: request marking and
+// gathering for the partial decomposition (the paper's Algorithm 3 at tile
+// granularity) and ordered stream compaction of the nonzero weights into a
+// sparse (q, w) list (the list L that Algorithms 1 and 2 return).
+//
+// All of them are memory-bound and simple: grid-stride loops over 64-bit
+// element indices, coalesced 8/16-byte loads, integer atomics only on
+// request bitmaps.
+#include "tpd_internal.h"
+
+namespace tpd {
+
+// ---------------------------------------------------------------------------
+// partial decomposition: request bitmaps and gather
+// ---------------------------------------------------------------------------
+__global__ void k_mark_requests(const uint64_t* __restrict__ req, uint64_t count, int n, int n1, int db,
+                                uint32_t* groups, uint32_t* tiles) {
+  const uint64_t lim = (uint64_t)1 << (2 * n);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t q = req[i];
+    if (q >= lim) continue;  // answered with NaN by the gather
+    uint64_t g, t;
+    request_bits(q, n, n1, db, &g, &t);
+    atomicOr(&groups[g >> 5], 1u << (g & 31));
+    atomicOr(&tiles[t >> 5], 1u << (t & 31));
+  }
+}
+
+__global__ void k_and_u32(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, uint64_t words) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] &= src[i];
+}
+
+template <class S>
+__global__ void k_gather(const Cx<S>* __restrict__ c, int n, int matrix_layout, const uint64_t* __restrict__ req,
+                         uint64_t count, Cx<S>* __restrict__ values) {
+  const uint64_t lim = (uint64_t)1 << (2 * n);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t q = req[i];
+    Cx<S> v;
+    if (q < lim) {
+      v = c[storage_of_q(q, n, matrix_layout != 0)];
+    } else {
+      v.re = __builtin_nan("");
+      v.im = __builtin_nan("");
+    }
+    values[i] = v;
+  }
+}
+
+static unsigned grid_for(uint64_t items, unsigned block, unsigned cap) {
+  uint64_t g = (items + block - 1) / block;
+  if (g > cap) g = cap;
+  return g ? (unsigned)g : 1u;
+}
+
+hipError_t launch_mark_requests(const uint64_t* req, uint64_t count, int n, int n1, int db, uint32_t* groups,
+                                uint32_t* tiles, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_requests, dim3(grid_for(count, 256, 8192)), dim3(256), 0, st, req, count, n, n1, db,
+                     groups, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_and_u32(uint32_t* dst, const uint32_t* src, uint64_t words, hipStream_t st) {
+  if (words == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_and_u32, dim3(grid_for(words, 256, 4096)), dim3(256), 0, st, dst, src, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(Dtype dt, const void* coeffs, int n, bool matrix_layout, const uint64_t* req,
+                         uint64_t count, void* values, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const unsigned g = grid_for(count, 256, 16384);
+  if (dt == DT_C128)
+    hipLaunchKernelGGL(k_gather<double>, dim3(g), dim3(256), 0, st, (const Cx<double>*)coeffs, n,
+                       (int)matrix_layout, req, count, (Cx<double>*)values);
+  else
+    hipLaunchKernelGGL(k_gather<float>, dim3(g), dim3(256), 0, st, (const Cx<float>*)coeffs, n,
+                       (int)matrix_layout, req, count, (Cx<float>*)values);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ordered compaction: count per chunk, exclusive scan, write
+// ---------------------------------------------------------------------------
+// A chunk is kCompactChunk consecutive storage elements, handled by one
+// workgroup of 256 threads; element (chunk, j, tid) = chunk * 4096 +
+// j * 256 + tid, so every load instruction of a wave reads 64 consecutive
+// elements and storage order is (j, wave, lane) order.
+constexpr int kCT = 256;
+constexpr int kCJ = (int)(kCompactChunk / kCT);  // 16
+
+template <class S>
+__global__ void __launch_bounds__(kCT) k_compact_count(const Cx<S>* __restrict__ c, uint64_t elems, S tol,
+                                                       uint32_t* __restrict__ counts) {
+  __shared__ uint32_t wsum[kCT / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kCompactChunk;
+  const uint32_t tid = threadIdx.x;
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int j = 0; j < kCJ; ++j) {
+    const uint64_t i = base + (uint64_t)j * kCT + tid;
+    bool k = false;
+    if (i < elems) {
+      const Cx<S> v = c[i];
+      k = keep_coeff<S>(v.re, v.im, tol);
+    }
+    cnt += (uint32_t)__popcll(__ballot(k));
+  }
+  if ((tid & 63) == 0) wsum[tid >> 6] = cnt;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kCT / 64; ++w) t += wsum[w];
+    counts[blockIdx.x] = t;
+  }
+}
+
+// one workgroup of 1024 threads; thread t owns a contiguous range of chunks
+__global__ void __launch_bounds__(1024) k_compact_scan(const uint32_t* __restrict__ counts, uint64_t nchunks,
+                                                       uint64_t* __restrict__ offsets, uint64_t* __restrict__ total) {
+  __shared__ uint64_t part[1024];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t per = (nchunks + 1023) / 1024;
+  const uint64_t b = (uint64_t)tid * per;
+  const uint64_t e = b + per < nchunks ? b + per : nchunks;
+  uint64_t s = 0;
+  for (uint64_t k = b; k < e; ++k) s += counts[k];
+  part[tid] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the 1024 partial sums
+  for (uint32_t o = 1; o < 1024; o <<= 1) {
+    const uint64_t add = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += add;
+    __syncthreads();
+  }
+  uint64_t run = part[tid] - s;  // exclusive
+  for (uint64_t k = b; k < e; ++k) {
+    offsets[k] = run;
+    run += counts[k];
+  }
+  if (tid == 1023) *total = part[1023];
+}
+
+template <class S>
+__global__ void __launch_bounds__(kCT) k_compact_write(const Cx<S>* __restrict__ c, uint64_t elems, int n,
+                                                       int matrix_layout, S tol,
+                                                       const uint32_t* __restrict__ counts,
+                                                       const uint64_t* __restrict__ offsets, uint64_t capacity,
+                                                       uint64_t* __restrict__ q_out, Cx<S>* __restrict__ w_out) {
+  __shared__ uint32_t cnt[kCJ * (kCT / 64)];
+  __shared__ uint32_t excl[kCJ * (kCT / 64)];
+  const uint64_t chunk = blockIdx.x;
+  if (counts[chunk] == 0) return;  // uniform per workgroup
+  const uint64_t off0 = offsets[chunk];
+  if (off0 >= capacity) return;
+  const uint64_t base = chunk * kCompactChunk;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  constexpr int NW = kCT / 64;
+
+  Cx<S> v[kCJ];
+  uint64_t m[kCJ];
+#pragma unroll
+  for (int j = 0; j < kCJ; ++j) {
+    const uint64_t i = base + (uint64_t)j * kCT + tid;
+    bool k = false;
+    if (i < elems) {
+      v[j] = c[i];
+      k = keep_coeff<S>(v[j].re, v[j].im, tol);
+    }
+    m[j] = __ballot(k);
+    if (lane == 0) cnt[j * NW + wave] = (uint32_t)__popcll(m[j]);
+  }
+  __syncthreads();
+  if (wave == 0) {
+    // exclusive scan of the kCJ * NW = 64 (j, wave) counts in storage order
+    const uint32_t x = cnt[lane];
+    uint32_t inc = x;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o);
+      if ((int)lane >= o) inc += y;
+    }
+    excl[lane] = inc - x;
+  }
+  __syncthreads();
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+#pragma unroll
+  for (int j = 0; j < kCJ; ++j) {
+    if (!((m[j] >> lane) & 1ull)) continue;
+    const uint64_t pos = off0 + excl[j * NW + wave] + (uint64_t)__popcll(m[j] & below);
+    if (pos >= capacity) continue;
+    const uint64_t i = base + (uint64_t)j * kCT + tid;
+    q_out[pos] = q_of_storage(i, n, matrix_layout != 0);
+    w_out[pos] = v[j];
+  }
+}
+
+hipError_t launch_compact_count(Dtype dt, const void* coeffs, uint64_t elems, double tol, uint32_t* counts,
+                                hipStream_t st) {
+  const uint64_t nchunks = (elems + kCompactChunk - 1) / kCompactChunk;
+  if (nchunks == 0) return hipSuccess;
+  if (dt == DT_C128)
+    hipLaunchKernelGGL(k_compact_count<double>, dim3((unsigned)nchunks), dim3(kCT), 0, st,
+                       (const Cx<double>*)coeffs, elems, tol, counts);
+  else
+    hipLaunchKernelGGL(k_compact_count<float>, dim3((unsigned)nchunks), dim3(kCT), 0, st,
+                       (const Cx<float>*)coeffs, elems, (float)tol, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_scan(const uint32_t* counts, uint64_t nchunks, uint64_t* offsets, uint64_t* total,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, st, counts, nchunks, offsets, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_write(Dtype dt, const void* coeffs, int n, bool matrix_layout, double tol,
+                                const uint32_t* counts, const uint64_t* offsets, uint64_t capacity,
+                                uint64_t* q_out, void* w_out, hipStream_t st) {
+  const uint64_t elems = (uint64_t)1 << (2 * n);
+  const uint64_t nchunks = (elems + kCompactChunk - 1) / kCompactChunk;
+  if (capacity == 0 || nchunks == 0) return hipSuccess;
+  if (dt == DT_C128)
+    hipLaunchKernelGGL(k_compact_write<double>, dim3((unsigned)nchunks), dim3(kCT), 0, st,
+                       (const Cx<double>*)coeffs, elems, n, (int)matrix_layout, tol, counts, offsets, capacity,
+                       q_out, (Cx<double>*)w_out);
+  else
+    hipLaunchKernelGGL(k_compact_write<float>, dim3((unsigned)nchunks), dim3(kCT), 0, st,
+                       (const Cx<float>*)coeffs, elems, n, (int)matrix_layout, (float)tol, counts, offsets,
+                       capacity, q_out, (Cx<float>*)w_out);
+  return hipGetLastError();
+}
+
+}  // namespace tpd

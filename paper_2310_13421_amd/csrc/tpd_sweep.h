@@ -48,6 +48,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
     const uint64_t td = tile & tdmask;
     const uint64_t xf = tile >> a.nfix_d;
     const uint64_t xfix = (xf & (((uint64_t)1 << xlo) - 1)) | ((xf >> xlo) << (xlo + G::XB));
+    if (a.req && !((a.req[td >> 5] >> (td & 31)) & 1u)) continue;  // no requested string in this d-group
     if (a.bitmap_mode == 2) {
       const uint64_t bit = (td << a.bm_xbits) | xf;
       if (!((a.bitmap[bit >> 5] >> (bit & 31)) & 1u)) continue;  // zero subtree

@@ -67,6 +67,10 @@ _SIGS = {
     "tpd_schedule_describe": (_I, [_I, _I, _U, _I, ctypes.c_char_p, _SZ]),
     "tpd_debug_emulate": (_I, [_P, _I, _P, _I, _U, _I]),
     "tpd_debug_emulate_batched": (_I, [_P, _P, _I, _P, _I, _U]),
+    "tpd_decompose_partial": (_I, [_P, _I, _P, _P, _U64, _P, _I, _U, _P]),
+    "tpd_compact": (_I, [_P, _I, _I, _U, ctypes.c_double, _P, _P, _U64, _P, _P]),
+    "tpd_debug_emulate_partial": (_I, [_P, _I, _P, _P, _U64, _P, _I, _U, _I]),
+    "tpd_debug_emulate_compact": (_I, [_P, _I, _I, _U, ctypes.c_double, _P, _P, _U64, _P]),
 }
 
 
@@ -168,6 +172,34 @@ def emulate_synth(w: np.ndarray, n: int, dtype: int = TPD_C128, flags: int = 0, 
     out = np.full(w.size, np.nan, _np_dtype(dtype))
     _check(lib.tpd_debug_emulate_synth(w.ctypes.data, n, out.ctypes.data, dtype, flags, 0), "emulate_synth")
     return out.reshape(1 << n, 1 << n)
+
+
+def emulate_partial(A: np.ndarray, req, dtype: int = TPD_C128, flags: int = 0, in_place: bool = False):
+    """Host replay of the partial decomposition; returns (values, work) with
+    the work array NaN-poisoned before the call (out of place)."""
+    A = np.ascontiguousarray(A, dtype=_np_dtype(dtype))
+    n = A.shape[0].bit_length() - 1
+    q = np.ascontiguousarray(np.asarray(req, dtype=np.uint64).reshape(-1))
+    vals = np.full(q.size, np.nan, _np_dtype(dtype))
+    work = A.copy().reshape(-1) if in_place else np.full(A.size, np.nan, _np_dtype(dtype))
+    src = work if in_place else A
+    _check(lib.tpd_debug_emulate_partial(src.ctypes.data, n, work.ctypes.data, q.ctypes.data, q.size,
+                                         vals.ctypes.data, dtype, flags, int(in_place)), "tpd_debug_emulate_partial")
+    return vals, work
+
+
+def emulate_compact(coeffs: np.ndarray, n: int, tol: float = 0.0, capacity: Optional[int] = None,
+                    dtype: int = TPD_C128, flags: int = 0):
+    """Host replay of the compaction; returns (q, w, total)."""
+    c = np.ascontiguousarray(np.asarray(coeffs).reshape(-1), dtype=_np_dtype(dtype))
+    cap = c.size if capacity is None else int(capacity)
+    q = np.zeros(max(cap, 1), np.uint64)
+    w = np.zeros(max(cap, 1), _np_dtype(dtype))
+    total = np.zeros(1, np.uint64)
+    _check(lib.tpd_debug_emulate_compact(c.ctypes.data, n, dtype, flags, tol, q.ctypes.data, w.ctypes.data, cap,
+                                         total.ctypes.data), "tpd_debug_emulate_compact")
+    k = min(cap, int(total[0]))
+    return q[:k], w[:k], int(total[0])
 
 
 def emulate_batched(mats: Sequence[np.ndarray], dtype: int = TPD_C128, flags: int = 0,
@@ -285,6 +317,62 @@ def synthesize(coeffs, out=None, *, layout: str = "canonical", stream=None):
     _check(lib.tpd_synthesize_ex(coeffs.data_ptr(), n, out.data_ptr(), _dtype_code(coeffs), _flags(layout, True),
                                  _stream(stream)), "tpd_synthesize_ex")
     return out
+
+
+def decompose_partial(A, req, values=None, work=None, *, layout: str = "canonical", prune: bool = True,
+                      hermitian: bool = False, stream=None):
+    """Weights of the requested strings only (canonical indices `req`, a
+    CUDA int64/uint64 tensor or a sequence).  `work` is the 4^n work array
+    (allocated if None; may be A itself for an in-place call in the matrix
+    layout).  Returns `values`, one complex per request."""
+    torch = _torch()
+    n = _check_matrix(A)
+    dt = _dtype_code(A)
+    if not torch.is_tensor(req):
+        req = torch.tensor(np.asarray(req, dtype=np.int64), device=A.device)
+    if not req.is_cuda or req.dtype not in (torch.int64, torch.uint64) or not req.is_contiguous():
+        raise ValueError("req must be a contiguous CUDA int64 tensor of canonical indices")
+    count = req.numel()
+    if values is None:
+        values = torch.empty(count, dtype=A.dtype, device=A.device)
+    if values.dtype != A.dtype or not values.is_cuda or not values.is_contiguous() or values.numel() != count:
+        raise ValueError("values must be a contiguous CUDA tensor of len(req) elements of A's dtype")
+    if work is None:
+        work = torch.empty(4 ** n, dtype=A.dtype, device=A.device)
+    if work.dtype != A.dtype or not work.is_cuda or not work.is_contiguous() or work.numel() != 4 ** n:
+        raise ValueError("work must be a contiguous CUDA tensor of 4^n elements of A's dtype")
+    _check(lib.tpd_decompose_partial(A.data_ptr(), n, work.data_ptr(), req.data_ptr(), count, values.data_ptr(), dt,
+                                     _flags(layout, prune, False, hermitian), _stream(stream)),
+           "tpd_decompose_partial")
+    return values
+
+
+def compact(coeffs, *, tol: float = 0.0, capacity: Optional[int] = None, layout: str = "canonical", stream=None):
+    """Sparse list of the kept weights: (q int64 tensor, w tensor, total).
+    With capacity None the count is read back first (one synchronisation)
+    and the lists are sized to it."""
+    torch = _torch()
+    if not coeffs.is_cuda or not coeffs.is_contiguous():
+        raise ValueError("coeffs must be a contiguous CUDA tensor")
+    m = coeffs.numel()
+    n = (m.bit_length() - 1) // 2
+    if 4 ** n != m:
+        raise ValueError("coeffs must hold 4^n values")
+    dt = _dtype_code(coeffs)
+    flags = FLAG_LAYOUT_MATRIX if layout == "matrix" else 0
+    if layout not in ("canonical", "matrix"):
+        raise ValueError("layout must be 'canonical' or 'matrix'")
+    total = torch.zeros(1, dtype=torch.int64, device=coeffs.device)
+    if capacity is None:
+        _check(lib.tpd_compact(coeffs.data_ptr(), n, dt, flags, float(tol), None, None, 0, total.data_ptr(),
+                               _stream(stream)), "tpd_compact")
+        capacity = int(total.item())
+    q = torch.empty(max(capacity, 1), dtype=torch.int64, device=coeffs.device)
+    w = torch.empty(max(capacity, 1), dtype=coeffs.dtype, device=coeffs.device)
+    _check(lib.tpd_compact(coeffs.data_ptr(), n, dt, flags, float(tol), q.data_ptr(), w.data_ptr(), capacity,
+                           total.data_ptr(), _stream(stream)), "tpd_compact")
+    k = min(capacity, int(total.item()))
+    return q[:k], w[:k], int(total.item())
 
 
 def decompose_batched(mats, outs=None, *, layout: str = "canonical", stream=None):

@@ -76,6 +76,24 @@ def test_decompose_validation_before_device(args, code):
     assert tpd.lib.tpd_decompose_ex(A, n, C, dt, fl, None) == code
 
 
+def test_partial_and_compact_validation():
+    P = tpd.lib.tpd_decompose_partial
+    assert P(FAKE, 4, FAKE * 4, FAKE * 8, 0, FAKE * 16, 0, 0, None) == 0      # nothing requested: no-op
+    assert P(FAKE, 4, FAKE * 4, None, 5, FAKE * 16, 0, 0, None) == 1          # NULL requests
+    assert P(FAKE, 4, FAKE * 4, FAKE * 8, 5, None, 0, 0, None) == 1           # NULL values
+    assert P(FAKE, 4, FAKE * 4, FAKE * 8 + 4, 5, FAKE * 16, 0, 0, None) == 1  # misaligned requests
+    assert P(FAKE, 4, FAKE * 4, FAKE * 8, 5, FAKE * 16, 0, 0x4, None) == 1    # timing flag
+    assert P(FAKE, 17, FAKE * 64, FAKE * 8, 5, FAKE * 16, 0, 0, None) == 2    # n too large
+    assert P(FAKE, 10, FAKE, FAKE * 8, 5, FAKE * 16, 0, 0, None) == 2         # in place canonical
+    C = tpd.lib.tpd_compact
+    assert C(FAKE, 4, 0, 0, -1.0, FAKE * 2, FAKE * 4, 8, FAKE * 8, None) == 1           # negative tol
+    assert C(FAKE, 4, 0, 0, float("nan"), FAKE * 2, FAKE * 4, 8, FAKE * 8, None) == 1   # NaN tol
+    assert C(FAKE, 4, 0, 0x1, 0.0, FAKE * 2, FAKE * 4, 8, FAKE * 8, None) == 1          # flag
+    assert C(FAKE, 4, 0, 0, 0.0, None, FAKE * 4, 8, FAKE * 8, None) == 1                # NULL list
+    assert C(FAKE, 4, 0, 0, 0.0, FAKE * 2, FAKE * 4, 8, None, None) == 1                # NULL count
+    assert C(FAKE, 17, 0, 0, 0.0, FAKE * 2, FAKE * 4, 8, FAKE * 8, None) == 2           # n too large
+
+
 def test_batched_validation():
     ns = (ctypes.c_int * 2)(3, 10)
     ptrs = (ctypes.c_void_p * 2)(FAKE, FAKE * 2)

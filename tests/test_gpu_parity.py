@@ -584,3 +584,128 @@ def test_n16_round_trip_in_place_integer_exact(dtype):
         assert torch.equal(Tr[c:c + step, 1], im[c:c + step].to(Tr.dtype))
     del T, re, im
     torch.cuda.empty_cache()
+
+
+# ----------------------------------------------------------------------------
+# partial decomposition and sparse-list output
+# ----------------------------------------------------------------------------
+def two_local(n):
+    qs = {0}
+    for i in range(n):
+        for a in (1, 2, 3):
+            qs.add(a << (2 * (n - 1 - i)))
+            for j in range(i + 1, n):
+                for b in (1, 2, 3):
+                    qs.add((a << (2 * (n - 1 - i))) | (b << (2 * (n - 1 - j))))
+    return np.array(sorted(qs), np.int64)
+
+
+@pytest.mark.parametrize("n", [0, 3, 8, 9, 12])
+def test_partial_vs_algorithm_3(n):
+    A = W.gaussian(n, seed=1400 + n) if n else np.array([[1.5 - 0.25j]])
+    rng = np.random.default_rng(1500 + n)
+    q = np.concatenate([rng.integers(0, 4 ** n, 300, dtype=np.int64), two_local(n) if n else [0]])
+    ref = O.tpd_partial(A, q)
+    Ad = to_dev(A)
+    qd = torch.from_numpy(q).to(DEV)
+    got = tpd.decompose_partial(Ad, qd).cpu().numpy()
+    assert same_bits(got, ref)
+    if n >= 9:
+        g2 = tpd.decompose_partial(Ad.clone(), qd, work=None, layout="matrix", prune=False).cpu().numpy()
+        assert same_bits(g2, ref)
+        T = Ad.clone()
+        g3 = tpd.decompose_partial(T, qd, work=T.view(-1), layout="matrix").cpu().numpy()
+        assert same_bits(g3, ref)
+        g64 = tpd.decompose_partial(to_dev(A, torch.complex64), qd).cpu().numpy()
+        assert cerr(g64, ref) <= (n + 1) * U32 * amax(A) * 1.5
+
+
+def test_config2_n14_partial_and_sparse_list():
+    n = 14
+    terms = W.heisenberg_terms(n, seed=3, dyadic=True)
+    expect = {}
+    for s, c in terms:
+        expect[W.string_index(s)] = expect.get(W.string_index(s), 0) + c
+    expect = {k: v for k, v in expect.items() if v != 0}
+    H = W.dense_from_terms_device(terms, n)
+    # partial: the generating strings, every 2-local string and some others
+    rng = np.random.default_rng(14)
+    q = np.unique(np.concatenate([np.array(sorted(expect), np.int64), two_local(n),
+                                  rng.integers(0, 4 ** n, 500, dtype=np.int64)]))
+    vals = tpd.decompose_partial(H, torch.from_numpy(q).to(DEV)).cpu().numpy()
+    want = np.array([expect.get(int(k), 0) for k in q], np.complex128)
+    assert same_bits(vals, want)
+    # sparse list of the full decomposition: exactly the generating terms
+    out = tpd.decompose(H)
+    qs, ws, total = tpd.compact(out)
+    assert total == len(expect)
+    assert np.array_equal(qs.cpu().numpy(), np.array(sorted(expect), np.int64))
+    assert same_bits(ws.cpu().numpy(), np.array([expect[k] for k in sorted(expect)]))
+    # capacity smaller than the list: the first entries, the full count
+    q2, w2, t2 = tpd.compact(out, capacity=10)
+    assert t2 == total and np.array_equal(q2.cpu().numpy(), qs.cpu().numpy()[:10])
+    # matrix layout: the same pairs in (row, col) order
+    M = tpd.decompose(H, layout="matrix")
+    qm, wm, tm = tpd.compact(M.view(-1), layout="matrix")
+    assert tm == total
+    order = np.argsort(qm.cpu().numpy())
+    assert np.array_equal(qm.cpu().numpy()[order], qs.cpu().numpy())
+    assert same_bits(wm.cpu().numpy()[order], ws.cpu().numpy())
+
+
+def selection(c, tol, matrix=False, n=None):
+    c = np.asarray(c).reshape(-1)
+    t = c.real.dtype.type(tol)
+    keep = ~((np.abs(c.real) <= t) & (np.abs(c.imag) <= t))
+    idx = np.flatnonzero(keep).astype(np.int64)
+    if matrix:
+        h, l = idx >> n, idx & ((1 << n) - 1)
+        return (spread(h) << 1) | spread(l), c[idx]
+    return idx, c[idx]
+
+
+@pytest.mark.parametrize("n", [0, 5, 8, 11, 13])
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_compaction_vs_selection(n, dtype):
+    rng = np.random.default_rng(2200 + n)
+    m = 4 ** n
+    c = (rng.standard_normal(m) + 1j * rng.standard_normal(m)) * (rng.random(m) < 0.03)
+    c[rng.integers(0, m, 3)] = 1e-9
+    c[rng.integers(0, m, 2)] = np.nan
+    c = c.astype(np.complex128 if dtype == torch.complex128 else np.complex64)
+    cd = torch.from_numpy(c).to(DEV)
+    for tol in (0.0, 1e-6):
+        for matrix in (False, True):
+            qe, we = selection(c, tol, matrix, n)
+            q, w, total = tpd.compact(cd, tol=tol, layout="matrix" if matrix else "canonical")
+            assert total == qe.size
+            assert np.array_equal(q.cpu().numpy(), qe)
+            assert np.array_equal(w.cpu().numpy().view(np.uint8), we.view(np.uint8))
+
+
+def test_n16_partial_and_count_at_full_size():
+    # 2-local requests on the n = 16 dense Hermitian matrix: values against
+    # the definition, then bitwise against the full decomposition; the
+    # compaction count of the dense result exceeds 2^32 - 1 only if every
+    # weight is nonzero, so it is checked against torch's count
+    n = 16
+    torch.cuda.empty_cache()
+    A = W.gaussian_device(n, seed=5, hermitian=True)
+    a_max = float(torch.view_as_real(A).abs().max())
+    q = two_local(n)
+    qd = torch.from_numpy(q).to(DEV)
+    work = torch.empty(4 ** n, dtype=A.dtype, device=DEV)
+    vals = tpd.decompose_partial(A, qd, work=work).cpu().numpy()
+    bf = sampled_oracle(A, n, q)
+    assert cerr(vals, bf) <= n * U64 * a_max
+    tpd.decompose(A, work)
+    assert same_bits(work[qd].cpu().numpy(), vals)
+    del A
+    torch.cuda.empty_cache()
+    total_dev = torch.zeros(1, dtype=torch.int64, device=DEV)
+    assert tpd.lib.tpd_compact(work.data_ptr(), n, tpd.TPD_C128, 0, 0.0, None, None, 0, total_dev.data_ptr(),
+                               None) == 0
+    nz = int(((work.real != 0) | (work.imag != 0)).sum().item())
+    assert int(total_dev.item()) == nz
+    del work
+    torch.cuda.empty_cache()
