@@ -48,18 +48,26 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(key):
+def load_traffic(kernel_name, n):
     """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE and
-    WRITE_SIZE scaled by a plain-copy calibration), if taken on the current
-    kernel sources."""
+    WRITE_SIZE scaled by a plain-copy calibration) for this kernel at this
+    n, if taken on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha") != kernel_source_hash():
+    if t.get("kernel_source_sha") != kernel_source_hash() or t.get("n") != n:
         return None
-    return t.get("kernels", {}).get(key)
+    return t.get("kernels", {}).get(kernel_name)
+
+
+def sweep_kernel_name(dt, sched, which):
+    """Symbol of the sweep kernel a two-sweep schedule launches (as the
+    profiler prints it)."""
+    s = sched[which - 1]
+    lay = "0, 2" if which == 1 else "2, 1"
+    return f"void tpd::k_sweep<{dt}, tpd::Geom<{s['xb']}, {s['db']}, 0, {s['r']}, 0>, {lay}, false>(tpd::SweepArgs)"
 
 
 def ingest_pmc(fetch_csv, write_csv, out_path):
@@ -93,18 +101,19 @@ def ingest_pmc(fetch_csv, write_csv, out_path):
         if "tpd::k_sweep" not in name or name not in write:
             continue
         dt = "c128" if "k_sweep<double" in name else "c64"
-        which = 1 if ", 0, 2>" in name else (2 if ", 2, 1>" in name else 0)
+        which = 1 if ", 0, 2, false>" in name else (2 if ", 2, 1, false>" in name else 0)
         if not which:
             continue
         es = 16 if dt == "c128" else 8
         fb = sum(fetch[name]) / len(fetch[name]) / fscale
         wb = sum(write[name]) / len(write[name]) / wscale
         alg = 4 ** 16 * es
-        kernels[f"sweep{which}_n16_{dt}"] = {
-            "kernel": name, "fetch_bytes": fb, "write_bytes": wb, "total_bytes": fb + wb,
+        kernels[name] = {
+            "sweep": which, "dtype": dt, "dispatches": len(fetch[name]),
+            "fetch_bytes": fb, "write_bytes": wb, "total_bytes": fb + wb,
             "algorithmic_bytes": 2 * alg, "fetch_over_algorithmic": fb / alg, "write_over_algorithmic": wb / alg,
         }
-    doc = {"kernel_source_sha": kernel_source_hash(), "fetch_scale": fscale, "write_scale": wscale,
+    doc = {"kernel_source_sha": kernel_source_hash(), "n": 16, "fetch_scale": fscale, "write_scale": wscale,
            "calibration": "plain device copy of 2^32 bytes (__amd_rocclr_copyBuffer via torch copy_)",
            "kernels": kernels}
     with open(out_path, "w") as f:
@@ -244,15 +253,36 @@ def main():
     del out
     torch.cuda.empty_cache()
 
+    # attainable-bandwidth context on this device: a plain device-to-device
+    # copy of 4 GiB (torch copy_), median of 5, read + write bytes / time
+    csrc = torch.empty(1 << 29, dtype=torch.float64, device="cuda")
+    cdst = torch.empty_like(csrc)
+    csrc.fill_(1.0)
+    cdst.copy_(csrc)
+    ctimes = []
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cdst.copy_(csrc)
+        e1.record()
+        torch.cuda.synchronize()
+        ctimes.append(e0.elapsed_time(e1))
+    copy_gbps = 2 * csrc.numel() * 8 / (sorted(ctimes)[2] / 1e3) / 1e9
+    del csrc, cdst
+    torch.cuda.empty_cache()
+    log(f"plain copy on this device: {copy_gbps:.0f} GB/s")
+
     avgs = main_res["kernel_ms"]
     k = max(range(len(avgs)), key=lambda i: avgs[i])
     unit_bytes = 2 * 16  # one complex128 read + one write per coefficient
     achieved = unit_bytes * 4 ** n / (avgs[k] / 1e3) / 1e9
-    tr_doc = load_traffic(f"sweep{k + 1}_n{n}_c128")
+    kname = sweep_kernel_name("double", main_res["schedule"], k + 1)
+    tr_doc = load_traffic(kname, n)
     tr = tr_doc["total_bytes"] if tr_doc else None
     roofline = {
         "bound": "hbm",
-        "kernel": f"k_sweep (sweep {k + 1} of 2)",
+        "kernel": f"k_sweep (sweep {k + 1} of 2): {kname}",
         "achieved": achieved,
         "peak": PEAK_HBM_GBPS,
         "unit": "GB/s",
@@ -289,6 +319,8 @@ def main():
         "schedule": main_res["schedule"],
         "autotuned": main_res["autotuned"],
         "roofline": roofline,
+        "torch_copy_GBps_same_device": copy_gbps,
+        "frac_of_copy": achieved / copy_gbps,
     }
 
     steps_x = max(3, min(args.steps, 10))

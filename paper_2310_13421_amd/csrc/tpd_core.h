@@ -88,6 +88,14 @@ struct Roles {
   int reg[kMaxPh][4];    // tile bit held by register slot s (-1 = unused)
   int lane[kMaxPh][6];   // tile bit held by lane bit b
   int wave[kMaxPh][4];   // tile bit held by wave bit b
+  // store mapping for the canonical order (st_ok): lanes hold d0, x0, d1,
+  // x1, d2, x2, which are the six lowest bits of q, so every store
+  // instruction of a wave writes 64 consecutive coefficients; registers and
+  // waves take d3, x3, d4, x4, ... and then the remaining x bits
+  bool st_ok;
+  int st_reg[4];
+  int st_lane[6];
+  int st_wave[4];
 };
 
 template <int XB_, int DB_, int MB_, int R_, int ORDER_>
@@ -148,6 +156,23 @@ constexpr Roles make_roles() {
       used[b] = true;
     }
   }
+  // canonical-order store mapping
+  r.st_ok = G::LB == 6 && G::DB >= 3 && G::XB >= 3 && G::MB == 0;
+  for (int s = 0; s < 4; ++s) r.st_reg[s] = -1;
+  for (int s = 0; s < 6; ++s) r.st_lane[s] = -1;
+  for (int s = 0; s < 4; ++s) r.st_wave[s] = -1;
+  if (r.st_ok) {
+    int order[32] = {};
+    int k = 0;
+    for (int b = 0; b < G::DB || b < G::XB; ++b) {
+      if (b < G::DB) order[k++] = b;           // d bit b
+      if (b < G::XB) order[k++] = G::DB + b;   // x bit b
+    }
+    int i = 0;
+    for (int l = 0; l < 6; ++l) r.st_lane[l] = order[i++];
+    for (int s = 0; s < G::R; ++s) r.st_reg[s] = order[i++];
+    for (int w = 0; w < G::WB; ++w) r.st_wave[w] = order[i++];
+  }
   return r;
 }
 
@@ -163,6 +188,20 @@ template <class G>
 TPD_HD constexpr uint32_t elem_reg(const Roles& r, int p, uint32_t j) {
   uint32_t e = 0;
   for (int s = 0; s < G::R; ++s) e |= ((j >> s) & 1u) << r.reg[p][s];
+  return e;
+}
+// the same for the canonical-order store mapping
+template <class G>
+TPD_HD uint32_t elem_base_st(const Roles& r, uint32_t tid) {
+  uint32_t e = 0;
+  for (int b = 0; b < G::LB; ++b) e |= ((tid >> b) & 1u) << r.st_lane[b];
+  for (int b = 0; b < G::WB; ++b) e |= ((tid >> (G::LB + b)) & 1u) << r.st_wave[b];
+  return e;
+}
+template <class G>
+TPD_HD constexpr uint32_t elem_reg_st(const Roles& r, uint32_t j) {
+  uint32_t e = 0;
+  for (int s = 0; s < G::R; ++s) e |= ((j >> s) & 1u) << r.st_reg[s];
   return e;
 }
 

@@ -235,8 +235,30 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
           bitmap[b0 >> 5] |= bits[t] << (b0 & 31);
         }
     }
+    // canonical-order output: one more pass through LDS into the store mapping
+    constexpr bool REMAP = OUTL == L_CAN && RL.st_ok;
+    if (REMAP) {
+      std::vector<uint8_t> seen(lds.size(), 0);
+      for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+        const uint32_t ebl = elem_base<G>(RL, LAST, tid);
+        for (int j = 0; j < G::E; ++j) {
+          const uint32_t e = ebl | elem_reg<G>(RL, LAST, j);
+          if (seen[e]++) return TPD_ERROR_INTERNAL;
+          lds[e] = v[(size_t)tid * G::E + j];
+        }
+      }
+      std::vector<uint8_t> got(lds.size(), 0);
+      for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+        const uint32_t ebs = elem_base_st<G>(RL, tid);
+        for (int j = 0; j < G::E; ++j) {
+          const uint32_t e = ebs | elem_reg_st<G>(RL, j);
+          if (got[e]++) return TPD_ERROR_INTERNAL;  // the store mapping is a bijection
+          v[(size_t)tid * G::E + j] = lds[e];
+        }
+      }
+    }
     for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
-      const uint32_t ebl = elem_base<G>(RL, LAST, tid);
+      const uint32_t ebl = REMAP ? elem_base_st<G>(RL, tid) : elem_base<G>(RL, LAST, tid);
       const uint64_t x = xfix | ((uint64_t)((ebl >> G::DB) & XM) << xlo);
       const uint64_t d = (td << G::DB) | (ebl & DM);
       const uint64_t base = layout_addr<OUTL>(x, d, n, db);
@@ -244,10 +266,22 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
         uint64_t ad = base;
         for (int s = 0; s < G::R; ++s)
           if ((j >> s) & 1) {
-            const uint32_t eo = 1u << RL.reg[LAST][s];
+            const uint32_t eo = 1u << (REMAP ? RL.st_reg[s] : RL.reg[LAST][s]);
             ad ^= layout_addr<OUTL>((uint64_t)((eo >> G::DB) & XM) << xlo, eo & DM, n, db);
           }
-        const uint32_t e = ebl | elem_reg<G>(RL, LAST, j);
+        const uint32_t e = ebl | (REMAP ? elem_reg_st<G>(RL, j) : elem_reg<G>(RL, LAST, j));
+        if (REMAP && j == 0 && (tid & 63) == 0) {
+          // a wave's store instruction covers 64 consecutive coefficients
+          uint64_t lo = ~0ull, hi = 0;
+          for (uint32_t l = 0; l < 64; ++l) {
+            const uint32_t el = elem_base_st<G>(RL, tid + l) | elem_reg_st<G>(RL, 0);
+            const uint64_t a2 = layout_addr<OUTL>(xfix | ((uint64_t)((el >> G::DB) & XM) << xlo),
+                                                  (td << G::DB) | (el & DM), n, db);
+            lo = a2 < lo ? a2 : lo;
+            hi = a2 > hi ? a2 : hi;
+          }
+          if (hi - lo != 63) return TPD_ERROR_INTERNAL;
+        }
         const uint64_t xd = xfix | ((uint64_t)((e >> G::DB) & XM) << xlo);
         const uint64_t dd = (td << G::DB) | (e & DM);
         if (ad != layout_addr<OUTL>(xd, dd, n, db)) return TPD_ERROR_INTERNAL;

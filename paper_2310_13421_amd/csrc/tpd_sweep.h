@@ -15,6 +15,17 @@ namespace tpd {
 // ---------------------------------------------------------------------------
 // single-matrix sweep
 // ---------------------------------------------------------------------------
+// A bitmap word that is the same for the whole workgroup and constant for
+// the kernel's lifetime (written by an earlier launch), read through the
+// constant address space: the load is a scalar one, counted apart from the
+// vector memory operations, so deciding on the next tile does not wait for
+// the current tile's stores to complete.
+__device__ inline uint32_t uniform_word(const uint32_t* p, uint64_t w) {
+  typedef const uint32_t __attribute__((address_space(4)))* cptr;
+  const uint32_t wi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)w);
+  return *(cptr)(p + wi);
+}
+
 template <class S, class G, int INL, int OUTL, bool INV = false>
 __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   static constexpr Roles RL = make_roles<G>();
@@ -32,57 +43,98 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   const int n = a.n, xlo = a.xlo, db = a.db;
   const uint64_t tdmask = ((uint64_t)1 << a.nfix_d) - 1;
 
+  // Canonical-order output: the tile is passed once more through LDS so that
+  // each store instruction writes 64 consecutive coefficients (whole cache
+  // lines) instead of the last phase's 32-byte pieces.
+  constexpr bool REMAP = OUTL == L_CAN && RL.st_ok;
+
   // register-slot address deltas (layouts are XOR-linear in (x, d))
   uint64_t din[G::R], dout[G::R];
 #pragma unroll
   for (int s = 0; s < G::R; ++s) {
     const uint32_t ei = 1u << RL.reg[0][s];
     din[s] = layout_addr<INL>((uint64_t)((ei >> G::DB) & XM) << xlo, ei & DM, n, db);
-    const uint32_t eo = 1u << RL.reg[LAST][s];
+    const uint32_t eo = 1u << (REMAP ? RL.st_reg[s] : RL.reg[LAST][s]);
     dout[s] = layout_addr<OUTL>((uint64_t)((eo >> G::DB) & XM) << xlo, eo & DM, n, db);
   }
   const uint32_t eb0 = elem_base<G>(RL, 0, tid);
   const uint32_t ebl = elem_base<G>(RL, LAST, tid);
+  const uint32_t ebo = REMAP ? elem_base_st<G>(RL, tid) : ebl;  // element base of the stores
 
-  for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    const uint64_t td = tile & tdmask;
-    const uint64_t xf = tile >> a.nfix_d;
-    const uint64_t xfix = (xf & (((uint64_t)1 << xlo) - 1)) | ((xf >> xlo) << (xlo + G::XB));
-    if (a.req && !((a.req[td >> 5] >> (td & 31)) & 1u)) continue;  // no requested string in this d-group
+  // Tile decode.  A tile is skipped (nothing read or written) when no
+  // requested string lies in its d-group, when the pruning bitmap marks its
+  // cumulative matrix weight zero, or in the first sweep of a Hermitian
+  // input when its row block holds no representatives.
+  struct Tile {
+    uint64_t td, xf, xfix, hm;
+  };
+  auto decode = [&](uint64_t tile, Tile& t) -> bool {
+    t.td = tile & tdmask;
+    t.xf = tile >> a.nfix_d;
+    t.xfix = (t.xf & (((uint64_t)1 << xlo) - 1)) | ((t.xf >> xlo) << (xlo + G::XB));
+    if (a.req && !((uniform_word(a.req, t.td >> 5) >> (t.td & 31)) & 1u)) return false;
     if (a.bitmap_mode == 2) {
-      const uint64_t bit = (td << a.bm_xbits) | xf;
-      if (!((a.bitmap[bit >> 5] >> (bit & 31)) & 1u)) continue;  // zero subtree
+      const uint64_t bit = (t.td << a.bm_xbits) | t.xf;
+      if (!((uniform_word(a.bitmap, bit >> 5) >> (bit & 31)) & 1u)) return false;  // zero subtree
     }
-    // Hermitian input: entry (x, d) is the conjugate of (x ^ d, d), and so is
-    // every intermediate value inside one cumulative matrix weight.  With
-    // dlh = the d bits of this tile above the diagonal group, below n2, and m
-    // the top set bit of d's low n2 bits, only rows with x bit m = 0 are
+    // Hermitian input: entry (x, d) is the conjugate of (x ^ d, d), and so
+    // is every intermediate value inside one cumulative matrix weight.  With
+    // dlh = the d bits of this tile above the diagonal group, below n2, and
+    // m the top set bit of d's low n2 bits, only rows with x bit m = 0 are
     // needed ("representatives"); the others follow by conjugation.
-    uint64_t hm = 0;  // 1 << m when representatives can be used, else 0
+    t.hm = 0;  // 1 << m when representatives can be used, else 0
     if (a.herm) {
       const int n2 = xlo ? xlo : G::XB;
-      const uint64_t dlh = td & (((uint64_t)1 << (n2 - G::DB)) - 1);
-      if (dlh) hm = (uint64_t)1 << (63 - __builtin_clzll(dlh) + G::DB);
-      if (xlo && (xf & hm)) continue;  // first sweep: a non-representative row block
+      const uint64_t dlh = t.td & (((uint64_t)1 << (n2 - G::DB)) - 1);
+      if (dlh) t.hm = (uint64_t)1 << (63 - __builtin_clzll(dlh) + G::DB);
+      if (xlo && (t.xf & t.hm)) return false;  // first sweep: a non-representative row block
     }
+    return true;
+  };
+  auto next_tile = [&](uint64_t tile, Tile& t) -> uint64_t {
+    while (tile < a.ntiles && !decode(tile, t)) tile += gridDim.x;
+    return tile;
+  };
+  auto load = [&](const Tile& t, Cx<S>* v) {
+    const uint64_t x = t.xfix | ((uint64_t)((eb0 >> G::DB) & XM) << xlo);
+    const uint64_t d = (t.td << G::DB) | (eb0 & DM);
+    const uint64_t base = layout_addr<INL>(x, d, n, db);
+#pragma unroll
+    for (int j = 0; j < G::E; ++j) {
+      uint64_t ad = base;
+#pragma unroll
+      for (int s = 0; s < G::R; ++s)
+        if ((j >> s) & 1) ad ^= din[s];
+      const uint32_t e = eb0 | elem_reg<G>(RL, 0, j);
+      if (t.hm && !xlo && (((uint64_t)((e >> G::DB) & XM)) & t.hm)) v[j] = Cx<S>{(S)0, (S)0};
+      else v[j] = in[ad];
+    }
+  };
+
+  // Persistent grids (gridDim.x < ntiles) keep the next tile's loads in
+  // flight while the current tile is transformed and stored.  Workgroups of
+  // 1024 threads have 128 registers per thread and no room for a second
+  // copy of the tile: they load at the top of each iteration.
+  constexpr bool PF = G::NT < 1024;
+  Tile cur, nxt;
+  uint64_t tile = next_tile(blockIdx.x, cur);
+  Cx<S> pf[PF ? G::E : 1];
+  if (PF && tile < a.ntiles) load(cur, pf);
+  while (tile < a.ntiles) {
+    Cx<S> v[G::E];
+    uint64_t after;
+    if constexpr (PF) {
+#pragma unroll
+      for (int j = 0; j < G::E; ++j) v[j] = pf[j];
+      after = next_tile(tile + gridDim.x, nxt);
+      if (after < a.ntiles) load(nxt, pf);
+    } else {
+      load(cur, v);
+      after = next_tile(tile + gridDim.x, nxt);
+    }
+    const uint64_t td = cur.td, hm = cur.hm, xfix = cur.xfix;
     if (a.bitmap_mode == 1 && tid < NBW) bits[tid] = 0;
 
-    Cx<S> v[G::E];
-    {
-      const uint64_t x = xfix | ((uint64_t)((eb0 >> G::DB) & XM) << xlo);
-      const uint64_t d = (td << G::DB) | (eb0 & DM);
-      const uint64_t base = layout_addr<INL>(x, d, n, db);
-#pragma unroll
-      for (int j = 0; j < G::E; ++j) {
-        uint64_t ad = base;
-#pragma unroll
-        for (int s = 0; s < G::R; ++s)
-          if ((j >> s) & 1) ad ^= din[s];
-        const uint32_t e = eb0 | elem_reg<G>(RL, 0, j);
-        if (hm && !xlo && (((uint64_t)((e >> G::DB) & XM)) & hm)) v[j] = Cx<S>{(S)0, (S)0};
-        else v[j] = in[ad];
-      }
-    }
     if (hm && !xlo) {
       // second sweep: rebuild the non-representative rows by conjugation
       const uint64_t dlo_hi = (td << G::DB) & ((((uint64_t)1 << G::XB) - 1));
@@ -141,10 +193,19 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
       }
     }
 
-    if (P == 1 && INL != OUTL) __syncthreads();  // in place: all loads before any store
+    if constexpr (REMAP) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < G::E; ++j) lds[ebl | elem_reg<G>(RL, LAST, j)] = v[j];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < G::E; ++j) v[j] = lds[ebo | elem_reg_st<G>(RL, j)];
+    } else if (P == 1 && INL != OUTL) {
+      __syncthreads();  // in place: all loads before any store
+    }
     {
-      const uint64_t x = xfix | ((uint64_t)((ebl >> G::DB) & XM) << xlo);
-      const uint64_t d = (td << G::DB) | (ebl & DM);
+      const uint64_t x = xfix | ((uint64_t)((ebo >> G::DB) & XM) << xlo);
+      const uint64_t d = (td << G::DB) | (ebo & DM);
       const uint64_t base = layout_addr<OUTL>(x, d, n, db);
       const bool real_out = a.herm && !xlo;  // Hermitian weights are real
 #pragma unroll
@@ -157,6 +218,8 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
         out[ad] = v[j];
       }
     }
+    cur = nxt;
+    tile = after;
   }
 }
 
