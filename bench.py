@@ -70,11 +70,26 @@ def sweep_kernel_name(dt, sched, which):
     return f"void tpd::k_sweep<{dt}, tpd::Geom<{s['xb']}, {s['db']}, 0, {s['r']}, 0>, {lay}, false>(tpd::SweepArgs)"
 
 
-def ingest_pmc(fetch_csv, write_csv, out_path):
-    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+def ingest_pmc(pairs, out_path):
+    """Turn pairs of rocprofv3 --pmc runs of this script (FETCH_SIZE, then
     WRITE_SIZE, both with --copy-calibration) into profiles/traffic.json.
     Each counter (KiB per dispatch) is scaled by what it reads for the plain
-    device copy of 2^32 bytes that --copy-calibration runs."""
+    device copy of 2^32 bytes that --copy-calibration runs.  A kernel seen in
+    several pairs takes the figures of the last one."""
+    kernels, scales = {}, []
+    for fetch_csv, write_csv in pairs:
+        ks, fs, ws = ingest_pair(fetch_csv, write_csv)
+        kernels.update(ks)
+        scales.append({"fetch_scale": fs, "write_scale": ws})
+    doc = {"kernel_source_sha": kernel_source_hash(), "n": 16, "scales": scales,
+           "calibration": "plain device copy of 2^32 bytes (__amd_rocclr_copyBuffer via torch copy_)",
+           "kernels": kernels}
+    with open(out_path, "w") as f:
+        json.dump(doc, f, indent=1)
+    return doc
+
+
+def ingest_pair(fetch_csv, write_csv):
     import csv
     from collections import defaultdict
 
@@ -113,12 +128,7 @@ def ingest_pmc(fetch_csv, write_csv, out_path):
             "fetch_bytes": fb, "write_bytes": wb, "total_bytes": fb + wb,
             "algorithmic_bytes": 2 * alg, "fetch_over_algorithmic": fb / alg, "write_over_algorithmic": wb / alg,
         }
-    doc = {"kernel_source_sha": kernel_source_hash(), "n": 16, "fetch_scale": fscale, "write_scale": wscale,
-           "calibration": "plain device copy of 2^32 bytes (__amd_rocclr_copyBuffer via torch copy_)",
-           "kernels": kernels}
-    with open(out_path, "w") as f:
-        json.dump(doc, f, indent=1)
-    return doc
+    return kernels, fscale, wscale
 
 
 def timed_steps(fn, steps, warmup, torch):
@@ -137,11 +147,14 @@ def kernel_avgs(plan):
     return [m / c if c else 0.0 for m, c in zip(ms, cnt)], cnt
 
 
+TUNE = True  # cleared by --no-autotune
+
+
 def single_matrix_run(tpd, torch, A, n, dtype_code, steps, warmup, esize, in_place=False, layout="canonical",
                       tune=True, hermitian=False):
     out = A.view(-1) if in_place else torch.empty(4 ** n, dtype=A.dtype, device=A.device)
     tuned = None
-    if tune and not in_place:
+    if tune and TUNE and not in_place:
         # pick the schedule by measurement on these buffers (outside the timed region)
         tuned = tpd.autotune(A, out, layout=layout, hermitian=hermitian).get("chosen")
     plan = tpd.Plan(n, dtype_code, timing=True, in_place=in_place, layout=layout, hermitian=hermitian)
@@ -206,13 +219,21 @@ def main():
     ap.add_argument("--extras", default="hermitian,fp32,inplace,n14,batched",
                     help="comma list of hermitian,fp32,inplace,n14,batched, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the schedules already chosen (TPD_AUTOTUNE_CACHE) instead of timing candidates")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write profiles/traffic.json from two rocprofv3 --pmc counter CSVs and exit")
+    ap.add_argument("--ingest-pmc", nargs="+", metavar="CSV",
+                    help="write profiles/traffic.json from pairs of rocprofv3 --pmc counter CSVs "
+                         "(FETCH_SIZE, WRITE_SIZE, ...) and exit")
     args = ap.parse_args()
+    global TUNE
+    TUNE = not args.no_autotune
     if args.ingest_pmc:
-        doc = ingest_pmc(args.ingest_pmc[0], args.ingest_pmc[1], os.path.join(ROOT, "profiles", "traffic.json"))
+        if len(args.ingest_pmc) % 2:
+            raise SystemExit("--ingest-pmc takes FETCH_SIZE/WRITE_SIZE CSV pairs")
+        pairs = list(zip(args.ingest_pmc[0::2], args.ingest_pmc[1::2]))
+        doc = ingest_pmc(pairs, os.path.join(ROOT, "profiles", "traffic.json"))
         print(json.dumps(doc, indent=1))
         return
 
@@ -395,7 +416,7 @@ def main():
             torch.cuda.current_stream().wait_stream(s)
             torch.cuda.synchronize()
             plan.timing(reset=True)
-            btuned = plan.autotune(dp, do)["chosen"]
+            btuned = plan.autotune(dp, do)["chosen"] if TUNE else None
             plan.timing(reset=True)
             ms_eager = timed_steps(lambda: plan.execute(dp, do), args.steps, args.warmup, torch)
             kavg, _ = kernel_avgs(plan)

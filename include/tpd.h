@@ -228,8 +228,8 @@ tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len);
 
 /* ---- autotuning ---- */
 
-/* Time the candidate two-sweep schedules for (n, dtype, layout, placement)
- * on the caller's buffers and make the fastest the one every later call and
+/* Time the candidate two-sweep schedules for (n, dtype, layout, placement,
+ * TPD_FLAG_HERMITIAN) on the caller's buffers and make the fastest the one every later call and
  * plan with the same key uses on this process (and, if the environment
  * variable TPD_AUTOTUNE_CACHE names a file, appended there and reloaded by
  * later processes).  Candidates: tile widths of 2^3..2^5 (complex128) or

@@ -75,12 +75,13 @@ struct Tuned {
   int db = 0, r = 4, grid = 0;
 };
 struct TuneKey {
-  int n, dt, matrix, in_place;
+  int n, dt, matrix, in_place, herm;
   bool operator<(const TuneKey& o) const {
     if (n != o.n) return n < o.n;
     if (dt != o.dt) return dt < o.dt;
     if (matrix != o.matrix) return matrix < o.matrix;
-    return in_place < o.in_place;
+    if (in_place != o.in_place) return in_place < o.in_place;
+    return herm < o.herm;
   }
 };
 std::mutex g_tune_mu;
@@ -132,7 +133,8 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
   } else if (!bottom) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (!g_tune_loaded) load_tune_cache();
-    auto it = g_tuned.find(TuneKey{n, (int)dt, s->matrix_layout ? 1 : 0, in_place ? 1 : 0});
+    auto it = g_tuned.find(TuneKey{n, (int)dt, s->matrix_layout ? 1 : 0, in_place ? 1 : 0,
+                                   (flags & TPD_FLAG_HERMITIAN) ? 1 : 0});
     if (it != g_tuned.end()) t = it->second;
   }
   if (t.db > s->n2) return TPD_ERROR_INVALID_VALUE;  // MID needs the low db x bits in sweep 2
@@ -257,7 +259,7 @@ tpd_status_t make_synth_schedule(int n, Dtype dt, unsigned flags, bool in_place,
 }
 
 // Autotune cache: TPD_AUTOTUNE_CACHE names a text file of lines
-//   tpd-tune-v1 <arch> <cus> <dtype> <n> <matrix> <in_place> <db> <r> <grid>
+//   tpd-tune-v2 <arch> <cus> <dtype> <n> <matrix> <in_place> <hermitian> <db> <r> <grid>
 // Unreadable or foreign lines are ignored (the built-in defaults apply).
 void load_tune_cache() {
   g_tune_loaded = true;
@@ -268,16 +270,16 @@ void load_tune_cache() {
   while (std::getline(f, line)) {
     std::istringstream is(line);
     std::string tag, arch;
-    int cus, dt, n, mat, inp, db, r, grid;
-    if (!(is >> tag >> arch >> cus >> dt >> n >> mat >> inp >> db >> r >> grid)) continue;
-    if (tag != "tpd-tune-v1" || arch != "gfx950") continue;
+    int cus, dt, n, mat, inp, herm, db, r, grid;
+    if (!(is >> tag >> arch >> cus >> dt >> n >> mat >> inp >> herm >> db >> r >> grid)) continue;
+    if (tag != "tpd-tune-v2" || arch != "gfx950") continue;
     if (g_cus > 0 && cus != g_cus) continue;
     if (dt < 0 || dt > 1 || n < -1 || n > kMaxQubits || r != 4 || grid < 0 || grid > 64) continue;
     Tuned t;
     t.db = db;
     t.r = r;
     t.grid = grid;
-    g_tuned[TuneKey{n, dt, mat, inp}] = t;
+    g_tuned[TuneKey{n, dt, mat, inp, herm}] = t;
   }
 }
 
@@ -285,8 +287,8 @@ void save_tune_entry(const TuneKey& k, const Tuned& t) {
   const char* path = std::getenv("TPD_AUTOTUNE_CACHE");
   if (!path || !path[0]) return;
   std::ofstream f(path, std::ios::app);
-  f << "tpd-tune-v1 gfx950 " << (g_cus > 0 ? (int)g_cus : 0) << " " << k.dt << " " << k.n << " " << k.matrix << " "
-    << k.in_place << " " << t.db << " " << t.r << " " << t.grid << "\n";
+  f << "tpd-tune-v2 gfx950 " << (g_cus > 0 ? (int)g_cus : 0) << " " << k.dt << " " << k.n << " " << k.matrix << " "
+    << k.in_place << " " << k.herm << " " << t.db << " " << t.r << " " << t.grid << "\n";
 }
 
 const char* layout_name(int l) { return l == L_MAT ? "MAT" : (l == L_CAN ? "CAN" : "MID"); }
@@ -653,7 +655,7 @@ int batched_grid(Dtype dt, uint32_t nitems) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (!g_tune_loaded) load_tune_cache();
-    auto it = g_tuned.find(TuneKey{-1, (int)dt, 0, 0});
+    auto it = g_tuned.find(TuneKey{-1, (int)dt, 0, 0, 0});
     if (it != g_tuned.end()) per_cu = it->second.grid;  // 0: one workgroup per item
   }
   if (per_cu <= 0) return (int)nitems;
@@ -1286,7 +1288,8 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
   (void)hipStreamSynchronize(hs);
   (void)hipFree(bm);
   if (st) return st;
-  const TuneKey key{n, (int)dt, (flags & TPD_FLAG_LAYOUT_MATRIX) ? 1 : 0, in_place ? 1 : 0};
+  const TuneKey key{n, (int)dt, (flags & TPD_FLAG_LAYOUT_MATRIX) ? 1 : 0, in_place ? 1 : 0,
+                    (flags & TPD_FLAG_HERMITIAN) ? 1 : 0};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (!g_tune_loaded) load_tune_cache();
@@ -1358,7 +1361,7 @@ extern "C" tpd_status_t tpd_autotune_batched(tpd_plan_t plan, const void* const*
     t.db = 0;
     t.r = 4;
     t.grid = best_m;
-    const TuneKey key{-1, (int)plan->dt, 0, 0};
+    const TuneKey key{-1, (int)plan->dt, 0, 0, 0};
     g_tuned[key] = t;
     save_tune_entry(key, t);
   }
