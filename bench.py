@@ -151,13 +151,14 @@ TUNE = True  # cleared by --no-autotune
 
 
 def single_matrix_run(tpd, torch, A, n, dtype_code, steps, warmup, esize, in_place=False, layout="canonical",
-                      tune=True, hermitian=False):
+                      tune=True, hermitian=False, prune=True):
     out = A.view(-1) if in_place else torch.empty(4 ** n, dtype=A.dtype, device=A.device)
     tuned = None
-    if tune and TUNE and not in_place:
-        # pick the schedule by measurement on these buffers (outside the timed region)
-        tuned = tpd.autotune(A, out, layout=layout, hermitian=hermitian).get("chosen")
-    plan = tpd.Plan(n, dtype_code, timing=True, in_place=in_place, layout=layout, hermitian=hermitian)
+    if tune and TUNE:
+        # pick the schedule by measurement on these buffers (outside the timed
+        # region; in place this transforms A repeatedly)
+        tuned = tpd.autotune(A, out, layout=layout, prune=prune, hermitian=hermitian).get("chosen")
+    plan = tpd.Plan(n, dtype_code, timing=True, in_place=in_place, layout=layout, hermitian=hermitian, prune=prune)
     ms = timed_steps(lambda: plan.execute(A, out), steps, warmup, torch)
     avgs, cnt = kernel_avgs(plan)
     plan.timing(reset=True)
@@ -216,8 +217,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=16)
-    ap.add_argument("--extras", default="hermitian,fp32,inplace,n14,batched",
-                    help="comma list of hermitian,fp32,inplace,n14,batched, or 'none'")
+    ap.add_argument("--extras", default="synth,partial,hermitian,fp32,inplace,n14,batched",
+                    help="comma list of synth,partial,hermitian,fp32,inplace,n14,batched, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the schedules already chosen (TPD_AUTOTUNE_CACHE) instead of timing candidates")
@@ -345,6 +346,66 @@ def main():
     }
 
     steps_x = max(3, min(args.steps, 10))
+
+    def event_ms(fn, reps):
+        """Median over reps of fn's device time (events on the current stream)."""
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2]
+
+    if extras & {"synth", "partial"}:
+        coeffs = tpd.decompose(A)
+        torch.cuda.synchronize()
+        if "synth" in extras:
+            log("extra: synthesis A = sum w_t sigma^t from the n=16 weights, complex128")
+            M = torch.empty((2 ** n, 2 ** n), dtype=A.dtype, device="cuda")
+            ms = event_ms(lambda: tpd.synthesize(coeffs, M), steps_x)
+            err_num, a_max = 0.0, 0.0
+            for r0 in range(0, 2 ** n, 2048):  # chunked: no full-size temporaries
+                err_num = max(err_num, float((M[r0:r0 + 2048] - A[r0:r0 + 2048]).abs().max()))
+                a_max = max(a_max, float(A[r0:r0 + 2048].abs().max()))
+            err = err_num / a_max
+            result["synthesis_c128"] = {
+                "ms_per_step": ms, "coeffs_per_s": 4 ** n / (ms / 1e3),
+                "algorithmic_GBps": 2 * 2 * 4 ** n * 16 / (ms / 1e3) / 1e9,
+                "round_trip_max_rel_err": err,
+            }
+            # compaction of the dense weights, count only (one read of 4^n values)
+            total = torch.zeros(1, dtype=torch.int64, device="cuda")
+            cms = event_ms(lambda: tpd.lib.tpd_compact(coeffs.data_ptr(), n, tpd.TPD_C128, 0, 0.0, None, None, 0,
+                                                       total.data_ptr(), None), steps_x)
+            result["compact_count_dense_c128"] = {
+                "ms": cms, "read_GBps": 4 ** n * 16 / (cms / 1e3) / 1e9, "kept": int(total.item()),
+            }
+            del M
+            torch.cuda.empty_cache()
+        if "partial" in extras:
+            log("extra: partial decomposition of the n=16 matrix, all 1- and 2-local strings")
+            qs = {0}
+            for i in range(n):
+                for a in (1, 2, 3):
+                    qs.add(a << (2 * (n - 1 - i)))
+                    for j in range(i + 1, n):
+                        for b in (1, 2, 3):
+                            qs.add((a << (2 * (n - 1 - i))) | (b << (2 * (n - 1 - j))))
+            req = torch.tensor(sorted(qs), dtype=torch.int64, device="cuda")
+            vals = torch.empty(req.numel(), dtype=A.dtype, device="cuda")
+            ms = event_ms(lambda: tpd.decompose_partial(A, req, vals, work=coeffs), steps_x)
+            result["partial_2local_c128"] = {
+                "requests": int(req.numel()), "ms": ms, "speedup_vs_full": main_res["ms_per_step"] / ms,
+            }
+        del coeffs
+        torch.cuda.empty_cache()
+
     if "hermitian" in extras:
         log("extra: Hermitian mode (representatives only, real weights), complex128")
         r, o = single_matrix_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16, hermitian=True)
@@ -393,7 +454,17 @@ def main():
         r["live_tile_fraction"] = st["live_tiles"] / st["total_tiles"]
         r["live_prefixes_level"] = st["prefix_level"]
         r["live_prefixes"] = st["live_prefixes"]
-        rn, o2 = single_matrix_run(tpd, torch, H, n14, tpd.TPD_C128, steps_x, 1, 16)
+        rn, o2 = single_matrix_run(tpd, torch, H, n14, tpd.TPD_C128, steps_x, 1, 16, tune=False, prune=False)
+        r["ms_per_step_no_prune"] = rn["ms_per_step"]
+        r["speedup_from_pruning"] = rn["ms_per_step"] / r["ms_per_step"]
+        # sparse list of the weights (the paper's output form)
+        q, w, total = tpd.compact(o)
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        cms = event_ms(lambda: tpd.lib.tpd_compact(o.data_ptr(), n14, tpd.TPD_C128, 0, 0.0, q.data_ptr(), w.data_ptr(),
+                                                   total, cnt.data_ptr(), None), steps_x)
+        assert int(cnt.item()) == total
+        _, _, total_tol = tpd.compact(o, tol=1e-12, capacity=0)
+        r["sparse_list"] = {"pairs": total, "compact_ms": cms, "pairs_above_1e-12": total_tol}
         result["n14_structured"] = r
         del H, o, o2
         torch.cuda.empty_cache()
