@@ -281,6 +281,15 @@ tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tpd_dtype_t d
 tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                                      int in_place, int db, int r);
 
+/* One decomposition on the device with a forced two-sweep schedule: tile
+ * width 2^db, 2^r elements per thread (r = 4), grid_per_cu workgroups per
+ * CU (0 = one per tile).  For tests that every tunable schedule gives the
+ * same bits; arguments and errors otherwise as tpd_decompose_ex, and
+ * TPD_ERROR_INVALID_VALUE for a schedule that does not exist.  n <= 8
+ * ignores the schedule arguments.                                         */
+tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
+                                       int db, int r, int grid_per_cu, tpd_stream_t stream);
+
 /* Host replays of the partial decomposition (request marking, tile skips,
  * gather) and of the compaction (same chunks, order and clipping); HOST
  * pointers, n <= 12, otherwise the arguments of the device calls.         */

@@ -310,7 +310,7 @@ std::string describe(const Schedule& s) {
     const SweepDesc& w = s.sw[i];
     const int B = w.xb + w.db;
     int R = w.r > B ? B : w.r;
-    if (B - R > 10) R = B - 10;
+    if (B - R > 9) R = B - 9;
     std::snprintf(buf, sizeof buf,
                   "%s{\"xlo\":%d,\"xb\":%d,\"db\":%d,\"in\":\"%s\",\"out\":\"%s\",\"bitmap\":\"%s\","
                   "\"order\":%d,\"r\":%d,\"grid\":%d,\"tiles\":%llu,\"tile_elems\":%d,\"threads\":%d}",
@@ -1194,6 +1194,38 @@ double median3(std::vector<float>& v) {
   return v.empty() ? 0.0 : v[v.size() / 2];
 }
 }  // namespace
+
+extern "C" tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype,
+                                                  unsigned flags, int db, int r, int grid_per_cu,
+                                                  tpd_stream_t stream) {
+  tpd_status_t st = check_dtype_flags(dtype, flags);
+  if (st) return st;
+  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  if (grid_per_cu < 0 || grid_per_cu > 64) return TPD_ERROR_INVALID_VALUE;
+  const Dtype dt = (Dtype)dtype;
+  st = check_buffers(A, coeffs, n, dt);
+  if (st) return st;
+  int dev;
+  st = current_device(&dev);
+  if (st) return st;
+  Tuned t;
+  t.db = db;
+  t.r = r;
+  t.grid = grid_per_cu;
+  Schedule s;
+  st = make_schedule_with(n, dt, flags, A == coeffs, n > 8 ? &t : nullptr, &s);
+  if (st) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  uint32_t* bm = nullptr;
+  if (s.prune && s.nsweep == 2) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace& w = g_ws[{dev, hs}];
+    st = ensure_bitmap(w, s.bitmap_words);
+    if (st) return st;
+    bm = w.bitmap;
+  }
+  return run_schedule(s, A, coeffs, bm, hs, nullptr);
+}
 
 extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                                      tpd_stream_t stream, char* report, size_t len) {

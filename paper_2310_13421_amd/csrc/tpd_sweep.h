@@ -111,28 +111,9 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
     }
   };
 
-  // Persistent grids (gridDim.x < ntiles) keep the next tile's loads in
-  // flight while the current tile is transformed and stored.  Workgroups of
-  // 1024 threads have 128 registers per thread and no room for a second
-  // copy of the tile: they load at the top of each iteration.
-  constexpr bool PF = G::NT < 1024;
-  Tile cur, nxt;
-  uint64_t tile = next_tile(blockIdx.x, cur);
-  Cx<S> pf[PF ? G::E : 1];
-  if (PF && tile < a.ntiles) load(cur, pf);
-  while (tile < a.ntiles) {
-    Cx<S> v[G::E];
-    uint64_t after;
-    if constexpr (PF) {
-#pragma unroll
-      for (int j = 0; j < G::E; ++j) v[j] = pf[j];
-      after = next_tile(tile + gridDim.x, nxt);
-      if (after < a.ntiles) load(nxt, pf);
-    } else {
-      load(cur, v);
-      after = next_tile(tile + gridDim.x, nxt);
-    }
-    const uint64_t td = cur.td, hm = cur.hm, xfix = cur.xfix;
+  // Transform one loaded tile and store it.
+  auto process = [&](const Tile& t, Cx<S>* v) {
+    const uint64_t td = t.td, hm = t.hm, xfix = t.xfix;
     if (a.bitmap_mode == 1 && tid < NBW) bits[tid] = 0;
 
     if (hm && !xlo) {
@@ -218,8 +199,40 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
         out[ad] = v[j];
       }
     }
-    cur = nxt;
-    tile = after;
+  };
+
+  // Persistent grids (gridDim.x < ntiles) issue the next tile's loads before
+  // transforming and storing the current one.  The first tile is peeled off
+  // so that the loop is entered with the same operations in flight as on
+  // its back edge (next loads, then current stores): the copy of the
+  // prefetched data then waits for those loads only, never for the stores.
+  // Workgroups of 1024 threads have 128 registers per thread and no room
+  // for a second copy of the tile: they load at the top of each iteration.
+  constexpr bool PF = G::NT < 1024;
+  if constexpr (PF) {
+    Tile cur, nxt;
+    const uint64_t first = next_tile(blockIdx.x, cur);
+    if (first >= a.ntiles) return;
+    Cx<S> v[G::E], pf[G::E];
+    load(cur, v);
+    uint64_t next = next_tile(first + gridDim.x, nxt);
+    if (next < a.ntiles) load(nxt, pf);
+    process(cur, v);
+    while (next < a.ntiles) {
+#pragma unroll
+      for (int j = 0; j < G::E; ++j) v[j] = pf[j];
+      cur = nxt;
+      next = next_tile(next + gridDim.x, nxt);
+      if (next < a.ntiles) load(nxt, pf);
+      process(cur, v);
+    }
+  } else {
+    Tile cur;
+    for (uint64_t tile = next_tile(blockIdx.x, cur); tile < a.ntiles; tile = next_tile(tile + gridDim.x, cur)) {
+      Cx<S> v[G::E];
+      load(cur, v);
+      process(cur, v);
+    }
   }
 }
 
@@ -228,8 +241,8 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
 // ---------------------------------------------------------------------------
 template <class S, int XB, int DB, int ORDER, int INL, int OUTL, int RR, bool INV = false>
 hipError_t launch_one(const SweepArgs& a, int grid_req, hipStream_t st) {
-  // at most 1024 threads per tile, at most 16 registers per thread
-  constexpr int R1 = (XB + DB - 10) > RR ? (XB + DB - 10) : RR;
+  // at most 512 threads per tile (tiles of 2^14 elements: 32 per thread)
+  constexpr int R1 = (XB + DB - 9) > RR ? (XB + DB - 9) : RR;
   constexpr int R = (XB + DB) < R1 ? (XB + DB) : R1;
   using G = Geom<XB, DB, 0, R, ORDER>;
   if constexpr (!shape_fits<S>(XB, DB)) {

@@ -68,6 +68,7 @@ _SIGS = {
     "tpd_debug_emulate": (_I, [_P, _I, _P, _I, _U, _I]),
     "tpd_debug_emulate_batched": (_I, [_P, _P, _I, _P, _I, _U]),
     "tpd_decompose_partial": (_I, [_P, _I, _P, _P, _U64, _P, _I, _U, _P]),
+    "tpd_debug_decompose_tuned": (_I, [_P, _I, _P, _I, _U, _I, _I, _I, _P]),
     "tpd_compact": (_I, [_P, _I, _I, _U, ctypes.c_double, _P, _P, _U64, _P, _P]),
     "tpd_debug_emulate_partial": (_I, [_P, _I, _P, _P, _U64, _P, _I, _U, _I]),
     "tpd_debug_emulate_compact": (_I, [_P, _I, _I, _U, ctypes.c_double, _P, _P, _U64, _P]),
@@ -281,6 +282,21 @@ def decompose(A, out=None, *, layout: str = "canonical", prune: bool = True, ord
         raise ValueError("out must be a contiguous CUDA tensor of 4^n elements of A's dtype")
     _check(lib.tpd_decompose_ex(A.data_ptr(), n, out.data_ptr(), dt,
                                 _flags(layout, prune, order_bottom, hermitian), _stream(stream)), "tpd_decompose_ex")
+    return out
+
+
+def decompose_tuned(A, out=None, *, db: int, grid_per_cu: int = 0, r: int = 4, layout: str = "canonical",
+                    prune: bool = True, hermitian: bool = False, stream=None):
+    """decompose() with a forced two-sweep schedule (test aid)."""
+    torch = _torch()
+    n = _check_matrix(A)
+    if out is None:
+        out = torch.empty(4 ** n, dtype=A.dtype, device=A.device)
+    if out.dtype != A.dtype or not out.is_cuda or not out.is_contiguous() or out.numel() != 4 ** n:
+        raise ValueError("out must be a contiguous CUDA tensor of 4^n elements of A's dtype")
+    _check(lib.tpd_debug_decompose_tuned(A.data_ptr(), n, out.data_ptr(), _dtype_code(A),
+                                         _flags(layout, prune, False, hermitian), db, r, grid_per_cu,
+                                         _stream(stream)), "tpd_debug_decompose_tuned")
     return out
 
 

@@ -709,3 +709,31 @@ def test_n16_partial_and_count_at_full_size():
     assert int(total_dev.item()) == nz
     del work
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype,dbs", [(torch.complex64, (4, 5, 6)), (torch.complex128, (3, 4, 5))])
+def test_n15_every_schedule_same_bits(dtype, dbs):
+    # n = 15: the first sweep fuses 8 levels, so complex64 tiles of 2^6
+    # diagonals hold 2^14 elements (32 per thread); every tile width and grid
+    # gives the default schedule's bits, which match the definition on
+    # sampled strings
+    n = 15
+    torch.cuda.empty_cache()
+    A = W.gaussian_device(n, seed=15, dtype=dtype)
+    ref = tpd.decompose(A)
+    qs = W.sampled_strings(n, 600, seed=15)
+    qd = torch.from_numpy(qs.astype(np.int64)).to(DEV)
+    bf = sampled_oracle(A, n, qs)
+    a_max = float(torch.view_as_real(A).abs().max())
+    tol = n * U64 * a_max if dtype == torch.complex128 else (n + 1) * U32 * a_max
+    assert cerr(ref[qd].cpu().numpy(), bf) <= tol
+    out = torch.empty_like(ref)
+    for db in dbs:
+        for g in (0, 1, 4):
+            out.fill_(float("nan"))
+            tpd.decompose_tuned(A, out, db=db, grid_per_cu=g)
+            assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref)), (db, g)
+    with pytest.raises(tpd.TPDError):
+        tpd.decompose_tuned(A, out, db=9)
+    del A, ref, out
+    torch.cuda.empty_cache()
