@@ -180,9 +180,10 @@ def single_matrix_run(tpd, torch, A, n, dtype_code, steps, warmup, esize, in_pla
     return res, out
 
 
-def cpu_baseline(n_sample=13, min_seconds=10.0):
+def cpu_baseline(tpd, torch, n_sample=13, min_seconds=10.0):
     """The oracle's Algorithm 1 (plain single-threaded C, binary64) on a
-    Hermitian matrix of the workload's distribution at n = n_sample."""
+    Hermitian matrix of the workload's distribution at n = n_sample; its
+    result also gives the GPU path's error on the same matrix."""
     import numpy as np
 
     from oracle import oracle as O
@@ -192,12 +193,19 @@ def cpu_baseline(n_sample=13, min_seconds=10.0):
     reps = 0
     t0 = time.perf_counter()
     while True:
-        O.tpd_recursive(A)
+        ref = O.tpd_recursive(A)
         reps += 1
         el = time.perf_counter() - t0
         if el >= min_seconds:
             break
     rate = reps * 4 ** n_sample / el
+    a_max = float(np.max(np.abs(np.concatenate([A.real.ravel(), A.imag.ravel()]))))
+    errs = {}
+    for name, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
+        got = tpd.decompose(torch.from_numpy(A).to("cuda").to(dt)).cpu().numpy().astype(np.complex128)
+        d = got - ref
+        errs[name] = float(np.max(np.abs(np.concatenate([d.real, d.imag])))) / a_max
+    errs["c128_bitwise"] = bool(errs["c128"] == 0.0)
     del A, np
     return {
         "value": rate,
@@ -208,6 +216,7 @@ def cpu_baseline(n_sample=13, min_seconds=10.0):
                    f"n={n_sample} matrix of the workload's distribution, {reps} run(s), {el:.1f} s; its cost per "
                    f"coefficient grows with n, so the n=16 rate is about {n_sample}/16 of this"),
         "seconds": el,
+        "gpu_max_abs_err_over_max_abs_a": errs,
     }
 
 
@@ -523,7 +532,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")
-        result["cpu_baseline"] = cpu_baseline()
+        result["cpu_baseline"] = cpu_baseline(tpd, torch)
     print(json.dumps(result), flush=True)
 
 
