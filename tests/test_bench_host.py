@@ -1,0 +1,75 @@
+"""Host-side logic of bench.py: PMC ingestion and its calibration, kernel
+symbols of a schedule, traffic lookup keyed by source hash, and the
+one-GPU guard.  No GPU is used."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+K1 = "void tpd::k_sweep<double, tpd::Geom<8, 5, 0, 4, 0>, 0, 2, false>(tpd::SweepArgs)"
+K2 = "void tpd::k_sweep<double, tpd::Geom<8, 5, 0, 4, 0>, 2, 1, false>(tpd::SweepArgs)"
+COPY = "__amd_rocclr_copyBuffer"
+
+
+def write_csv(path, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Value"])
+        w.writeheader()
+        for name, kib in rows:
+            w.writerow({"Kernel_Name": name, "Counter_Value": kib})
+
+
+def test_ingest_scales_by_the_copy_and_keys_by_symbol(tmp_path, monkeypatch):
+    alg = 4 ** 16 * 16  # bytes read (or written) by one complex128 sweep at n = 16
+    copy = 1 << 32
+    # FETCH_SIZE reads half the true bytes, WRITE_SIZE the true bytes
+    fetch = [(COPY, 0.5 * copy / 1024), (K1, 0.5 * alg / 1024), (K2, 0.5 * 1.01 * alg / 1024)]
+    write = [(COPY, copy / 1024), (K1, alg / 1024), (K2, 1.02 * alg / 1024)]
+    f1, w1 = tmp_path / "f.csv", tmp_path / "w.csv"
+    write_csv(f1, fetch)
+    write_csv(w1, write)
+    out = tmp_path / "traffic.json"
+    doc = bench.ingest_pmc([(str(f1), str(w1))], str(out))
+    assert abs(doc["scales"][0]["fetch_scale"] - 0.5) < 1e-12
+    k1, k2 = doc["kernels"][K1], doc["kernels"][K2]
+    assert k1["sweep"] == 1 and k2["sweep"] == 2
+    assert abs(k1["total_bytes"] - 2 * alg) < 1e-3 * alg
+    assert abs(k2["fetch_over_algorithmic"] - 1.01) < 1e-9 and abs(k2["write_over_algorithmic"] - 1.02) < 1e-9
+    # lookup: matching sources and n, then a changed source hash
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "profiles")
+    doc["kernel_source_sha"] = "x"
+    with open(tmp_path / "profiles" / "traffic.json", "w") as f:
+        json.dump(doc, f)
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "x")
+    assert bench.load_traffic(K2, 16)["total_bytes"] == k2["total_bytes"]
+    assert bench.load_traffic(K2, 15) is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "y")
+    assert bench.load_traffic(K2, 16) is None
+
+
+def test_ingest_needs_the_copy_calibration(tmp_path):
+    f1, w1 = tmp_path / "f.csv", tmp_path / "w.csv"
+    write_csv(f1, [(K1, 1.0)])
+    write_csv(w1, [(K1, 1.0)])
+    with pytest.raises(SystemExit):
+        bench.ingest_pmc([(str(f1), str(w1))], str(tmp_path / "t.json"))
+
+
+def test_kernel_symbol_of_a_schedule():
+    sched = [{"xb": 8, "db": 5, "r": 4}, {"xb": 8, "db": 5, "r": 4}]
+    assert bench.sweep_kernel_name("double", sched, 1) == K1
+    assert bench.sweep_kernel_name("double", sched, 2) == K2
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
