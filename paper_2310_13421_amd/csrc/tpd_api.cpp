@@ -310,7 +310,7 @@ std::string describe(const Schedule& s) {
     const SweepDesc& w = s.sw[i];
     const int B = w.xb + w.db;
     int R = w.r > B ? B : w.r;
-    if (B - R > 9) R = B - 9;
+    if (B - R > 10) R = B - 10;
     std::snprintf(buf, sizeof buf,
                   "%s{\"xlo\":%d,\"xb\":%d,\"db\":%d,\"in\":\"%s\",\"out\":\"%s\",\"bitmap\":\"%s\","
                   "\"order\":%d,\"r\":%d,\"grid\":%d,\"tiles\":%llu,\"tile_elems\":%d,\"threads\":%d}",

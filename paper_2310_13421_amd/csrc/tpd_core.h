@@ -85,7 +85,7 @@ constexpr int kMaxPh = 4;
 struct Roles {
   int nph;
   int nxf[kMaxPh];       // transform slots of phase p are reg slots 0..nxf-1
-  int reg[kMaxPh][5];    // tile bit held by register slot s (-1 = unused)
+  int reg[kMaxPh][4];    // tile bit held by register slot s (-1 = unused)
   int lane[kMaxPh][6];   // tile bit held by lane bit b
   int wave[kMaxPh][4];   // tile bit held by wave bit b
   // store mapping for the canonical order (st_ok): lanes hold d0, x0, d1,
@@ -93,7 +93,7 @@ struct Roles {
   // instruction of a wave writes 64 consecutive coefficients; registers and
   // waves take d3, x3, d4, x4, ... and then the remaining x bits
   bool st_ok;
-  int st_reg[5];
+  int st_reg[4];
   int st_lane[6];
   int st_wave[4];
 };
@@ -108,7 +108,7 @@ struct Geom {
   static constexpr int LB = TB < 6 ? TB : 6;
   static constexpr int WB = TB - LB;
   static constexpr int NPH = XB == 0 ? 1 : (XB + R - 1) / R;
-  static_assert(R >= 0 && R <= 5, "at most 32 elements per thread");
+  static_assert(R >= 0 && R <= 4, "at most 16 elements per thread");
   static_assert(TB >= 0 && WB <= 4, "at most 16 waves");
   static_assert(NPH <= kMaxPh, "too many register phases");
   static_assert(R <= XB + DB, "registers must hold x or d bits of one matrix");
@@ -121,7 +121,7 @@ constexpr Roles make_roles() {
   r.nph = G::NPH;
   for (int p = 0; p < kMaxPh; ++p) {
     r.nxf[p] = 0;
-    for (int s = 0; s < 5; ++s) r.reg[p][s] = -1;
+    for (int s = 0; s < 4; ++s) r.reg[p][s] = -1;
     for (int s = 0; s < 6; ++s) r.lane[p][s] = -1;
     for (int s = 0; s < 4; ++s) r.wave[p][s] = -1;
   }
@@ -158,7 +158,7 @@ constexpr Roles make_roles() {
   }
   // canonical-order store mapping
   r.st_ok = G::LB == 6 && G::DB >= 3 && G::XB >= 3 && G::MB == 0;
-  for (int s = 0; s < 5; ++s) r.st_reg[s] = -1;
+  for (int s = 0; s < 4; ++s) r.st_reg[s] = -1;
   for (int s = 0; s < 6; ++s) r.st_lane[s] = -1;
   for (int s = 0; s < 4; ++s) r.st_wave[s] = -1;
   if (r.st_ok) {

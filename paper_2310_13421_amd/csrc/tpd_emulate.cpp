@@ -305,7 +305,7 @@ template <class S, int XB, int DB, int ORDER, int RR>
 tpd_status_t emulate_layouts(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint32_t* bm,
                              Checker& ck) {
   // same thread-count cap as the device launcher
-  constexpr int R1 = (XB + DB - 9) > RR ? (XB + DB - 9) : RR;
+  constexpr int R1 = (XB + DB - 10) > RR ? (XB + DB - 10) : RR;
   constexpr int R = (XB + DB) < R1 ? (XB + DB) : R1;
   using G = Geom<XB, DB, 0, R, ORDER>;
   if (s.inv) {

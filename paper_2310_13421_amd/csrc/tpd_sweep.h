@@ -241,8 +241,8 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
 // ---------------------------------------------------------------------------
 template <class S, int XB, int DB, int ORDER, int INL, int OUTL, int RR, bool INV = false>
 hipError_t launch_one(const SweepArgs& a, int grid_req, hipStream_t st) {
-  // at most 512 threads per tile (tiles of 2^14 elements: 32 per thread)
-  constexpr int R1 = (XB + DB - 9) > RR ? (XB + DB - 9) : RR;
+  // at most 1024 threads per tile, at most 16 elements per thread
+  constexpr int R1 = (XB + DB - 10) > RR ? (XB + DB - 10) : RR;
   constexpr int R = (XB + DB) < R1 ? (XB + DB) : R1;
   using G = Geom<XB, DB, 0, R, ORDER>;
   if constexpr (!shape_fits<S>(XB, DB)) {

@@ -714,9 +714,9 @@ def test_n16_partial_and_count_at_full_size():
 @pytest.mark.parametrize("dtype,dbs", [(torch.complex64, (4, 5, 6)), (torch.complex128, (3, 4, 5))])
 def test_n15_every_schedule_same_bits(dtype, dbs):
     # n = 15: the first sweep fuses 8 levels, so complex64 tiles of 2^6
-    # diagonals hold 2^14 elements (32 per thread); every tile width and grid
-    # gives the default schedule's bits, which match the definition on
-    # sampled strings
+    # diagonals hold 2^14 elements (1024 threads, no prefetch); every tile
+    # width and grid gives the default schedule's bits, which match the
+    # definition on sampled strings
     n = 15
     torch.cuda.empty_cache()
     A = W.gaussian_device(n, seed=15, dtype=dtype)
