@@ -62,11 +62,14 @@ def load_traffic(kernel_name, n):
     return t.get("kernels", {}).get(kernel_name)
 
 
+LAYOUT_CODE = {"MAT": 0, "CAN": 1, "MID": 2}
+
+
 def sweep_kernel_name(dt, sched, which):
     """Symbol of the sweep kernel a two-sweep schedule launches (as the
     profiler prints it)."""
     s = sched[which - 1]
-    lay = "0, 2" if which == 1 else "2, 1"
+    lay = f"{LAYOUT_CODE[s['in']]}, {LAYOUT_CODE[s['out']]}"
     return f"void tpd::k_sweep<{dt}, tpd::Geom<{s['xb']}, {s['db']}, 0, {s['r']}, 0>, {lay}, false>(tpd::SweepArgs)"
 
 
@@ -116,9 +119,10 @@ def ingest_pair(fetch_csv, write_csv):
         if "tpd::k_sweep" not in name or name not in write:
             continue
         dt = "c128" if "k_sweep<double" in name else "c64"
-        which = 1 if ", 0, 2, false>" in name else (2 if ", 2, 1, false>" in name else 0)
+        which = {", 0, 2, false>": 1, ", 2, 1, false>": 2, ", 0, 0, false>": 12}.get(
+            next((k for k in (", 0, 2, false>", ", 2, 1, false>", ", 0, 0, false>") if k in name), ""), 0)
         if not which:
-            continue
+            continue  # 12: matrix layout in place, both sweeps share the symbol
         es = 16 if dt == "c128" else 8
         fb = sum(fetch[name]) / len(fetch[name]) / fscale
         wb = sum(write[name]) / len(write[name]) / wscale
@@ -173,11 +177,61 @@ def single_matrix_run(tpd, torch, A, n, dtype_code, steps, warmup, esize, in_pla
         "kernel_launches": cnt,
         "sweep_GBps": [sweep_bytes / (a / 1e3) / 1e9 if a else None for a in avgs],
         "sweeps": len(desc["sweeps"]),
-        "schedule": [{k: w[k] for k in ("xb", "db", "r", "grid", "tile_elems", "threads")} for w in desc["sweeps"]],
+        "schedule": [{k: w[k] for k in ("xb", "db", "r", "grid", "tile_elems", "threads", "in", "out")}
+                     for w in desc["sweeps"]],
         "autotuned": tuned,
     }
     res["pct_peak_algorithmic"] = 100.0 * res["algorithmic_GBps"] / PEAK_HBM_GBPS
     return res, out
+
+
+def inplace_run(tpd, torch, A0, n, dtype_code, steps, warmup, esize, hermitian=False):
+    """In-place decomposition (matrix layout) of a copy of A0, the copy
+    restored from A0 before every step outside the timed region (repeated
+    in-place transforms would shrink the values towards zero, where pruning
+    and subnormals change the work).  Each step is timed with HIP events
+    around the decomposition alone."""
+    B = torch.empty_like(A0)
+    flat = B.view(-1)
+    tuned = None
+    if TUNE:
+        B.copy_(A0)
+        tuned = tpd.autotune(B, flat, layout="matrix", hermitian=hermitian).get("chosen")
+    plan = tpd.Plan(n, dtype_code, timing=True, in_place=True, layout="matrix", hermitian=hermitian)
+    times = []
+    for step in range(warmup + steps):
+        if step == warmup:
+            plan.timing(reset=True)
+        B.copy_(A0)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.execute(B, flat)
+        e1.record()
+        torch.cuda.synchronize()
+        if step >= warmup:
+            times.append(e0.elapsed_time(e1))
+    avgs, cnt = kernel_avgs(plan)
+    desc = plan.describe()
+    plan.close()
+    ms = sum(times) / len(times)
+    sweep_bytes = 2 * 4 ** n * esize
+    res = {
+        "ms_per_step": ms,
+        "ms_min": min(times),
+        "coeffs_per_s": 4 ** n / (ms / 1e3),
+        "algorithmic_GBps": sweep_bytes / (ms / 1e3) / 1e9,
+        "kernel_ms": avgs,
+        "kernel_launches": cnt,
+        "sweep_GBps": [sweep_bytes / (a / 1e3) / 1e9 if a else None for a in avgs],
+        "sweeps": len(desc["sweeps"]),
+        "schedule": [{k: w[k] for k in ("xb", "db", "r", "grid", "tile_elems", "threads", "in", "out")}
+                     for w in desc["sweeps"]],
+        "autotuned": tuned,
+    }
+    res["pct_peak_algorithmic"] = 100.0 * res["algorithmic_GBps"] / PEAK_HBM_GBPS
+    return res, B
 
 
 def cpu_baseline(tpd, torch, n_sample=13, min_seconds=10.0):
@@ -226,8 +280,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=16)
-    ap.add_argument("--extras", default="synth,partial,hermitian,fp32,inplace,n14,batched",
-                    help="comma list of synth,partial,hermitian,fp32,inplace,n14,batched, or 'none'")
+    ap.add_argument("--extras", default="synth,partial,hermitian,outofplace,fp32,n14dense,n14,batched",
+                    help="comma list of synth,partial,hermitian,outofplace,fp32,n14dense,n14,batched, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the schedules already chosen (TPD_AUTOTUNE_CACHE) instead of timing candidates")
@@ -277,11 +331,12 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
 
-    log(f"main: n={n} complex128 out of place, {args.warmup} warmup + {args.steps} timed steps")
-    main_res, out = single_matrix_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16)
+    log(f"main: n={n} complex128 in place (matrix layout), {args.warmup} warmup + {args.steps} timed steps, "
+        f"input restored before each")
+    main_res, B = inplace_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16)
     log(f"main: {main_res['ms_per_step']:.3f} ms/step, {main_res['coeffs_per_s']:.3e} coeffs/s, "
         f"kernels {main_res['kernel_ms']}")
-    del out
+    del B
     torch.cuda.empty_cache()
 
     # attainable-bandwidth context on this device: a plain device-to-device
@@ -336,11 +391,12 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"dense Hermitian {2 ** n}x{2 ** n} complex128 (n={n}), A=(G+G^H)/2, G complex N(0,1) "
-                        f"seed 5; out of place, canonical order, pruning on",
+                        f"seed 5; in place (coefficients in the matrix layout), input restored from a pristine "
+                        f"copy before each timed step (untimed), pruning on",
             "n": n,
             "precision": "complex128",
-            "layout": "canonical",
-            "placement": "out-of-place",
+            "layout": "matrix",
+            "placement": "in-place",
         },
         "hbm_GBps_algorithmic": main_res["algorithmic_GBps"],
         "pct_peak_algorithmic": main_res["pct_peak_algorithmic"],
@@ -409,41 +465,47 @@ def main():
             req = torch.tensor(sorted(qs), dtype=torch.int64, device="cuda")
             vals = torch.empty(req.numel(), dtype=A.dtype, device="cuda")
             ms = event_ms(lambda: tpd.decompose_partial(A, req, vals, work=coeffs), steps_x)
+            full_ms = event_ms(lambda: tpd.decompose(A, coeffs), steps_x)
             result["partial_2local_c128"] = {
-                "requests": int(req.numel()), "ms": ms, "speedup_vs_full": main_res["ms_per_step"] / ms,
+                "requests": int(req.numel()), "ms": ms, "full_out_of_place_ms": full_ms,
+                "speedup_vs_full": full_ms / ms,
             }
         del coeffs
         torch.cuda.empty_cache()
 
     if "hermitian" in extras:
-        log("extra: Hermitian mode (representatives only, real weights), complex128")
-        r, o = single_matrix_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16, hermitian=True)
+        log("extra: Hermitian mode (representatives only, real weights), complex128, in place")
+        r, B = inplace_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16, hermitian=True)
         r["speedup_vs_general"] = main_res["ms_per_step"] / r["ms_per_step"]
         result["hermitian_c128"] = r
-        del o
-        torch.cuda.empty_cache()
-    if "inplace" in extras:
-        log("extra: in place, matrix layout, complex128")
-        B = A.clone()
-        r, _ = single_matrix_run(tpd, torch, B, n, tpd.TPD_C128, steps_x, 1, 16, in_place=True, layout="matrix")
-        result["inplace_c128"] = r
         del B
         torch.cuda.empty_cache()
+    if "outofplace" in extras:
+        log("extra: out of place, canonical order, complex128")
+        r, o = single_matrix_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16)
+        result["out_of_place_canonical_c128"] = r
+        del o
+        torch.cuda.empty_cache()
     if "fp32" in extras:
-        log("extra: complex64")
+        log("extra: complex64 (round-to-nearest copy of the same matrix), in place")
         A32 = A.to(torch.complex64)
         del A
         A = None
         torch.cuda.empty_cache()
-        r, o32 = single_matrix_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8)
+        r, B32 = inplace_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8)
         r["speedup_vs_c128"] = main_res["ms_per_step"] / r["ms_per_step"]
         result["fp32"] = r
-        del o32
+        del B32
         torch.cuda.empty_cache()
         if "hermitian" in extras:
-            r, o32 = single_matrix_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8, hermitian=True)
+            r, B32 = inplace_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8, hermitian=True)
             r["speedup_vs_c128_general"] = main_res["ms_per_step"] / r["ms_per_step"]
             result["hermitian_c64"] = r
+            del B32
+            torch.cuda.empty_cache()
+        if "outofplace" in extras:
+            r, o32 = single_matrix_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8)
+            result["fp32_out_of_place_canonical"] = r
             del o32
         del A32
         torch.cuda.empty_cache()
@@ -451,6 +513,24 @@ def main():
         del A
         torch.cuda.empty_cache()
 
+    if "n14dense" in extras:
+        log("extra: n=14 dense Hermitian, complex128 and complex64, out of place and in place")
+        n14 = 14
+        H = W.gaussian_device(n14, seed=14, hermitian=True)
+        d = {}
+        for name, dt, code, es in (("c128", torch.complex128, tpd.TPD_C128, 16),
+                                   ("c64", torch.complex64, tpd.TPD_C64, 8)):
+            Hd = H if dt == torch.complex128 else H.to(dt)
+            r, o = single_matrix_run(tpd, torch, Hd, n14, code, args.steps, args.warmup, es)
+            d[name] = r
+            del o
+            r, B = inplace_run(tpd, torch, Hd, n14, code, args.steps, args.warmup, es)
+            d[name + "_in_place"] = r
+            del B, Hd
+            torch.cuda.empty_cache()
+        result["n14_dense"] = d
+        del H
+        torch.cuda.empty_cache()
     if "n14" in extras:
         log("extra: n=14 Heisenberg chain + 200 4-local strings, pruning")
         n14 = 14

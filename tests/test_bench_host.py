@@ -64,9 +64,12 @@ def test_ingest_needs_the_copy_calibration(tmp_path):
 
 
 def test_kernel_symbol_of_a_schedule():
-    sched = [{"xb": 8, "db": 5, "r": 4}, {"xb": 8, "db": 5, "r": 4}]
+    sched = [{"xb": 8, "db": 5, "r": 4, "in": "MAT", "out": "MID"}, {"xb": 8, "db": 5, "r": 4, "in": "MID", "out": "CAN"}]
     assert bench.sweep_kernel_name("double", sched, 1) == K1
     assert bench.sweep_kernel_name("double", sched, 2) == K2
+    inplace = [{"xb": 8, "db": 4, "r": 4, "in": "MAT", "out": "MAT"}] * 2
+    assert bench.sweep_kernel_name("float", inplace, 2) == \
+        "void tpd::k_sweep<float, tpd::Geom<8, 4, 0, 4, 0>, 0, 0, false>(tpd::SweepArgs)"
 
 
 def test_more_than_one_gpu_is_refused():
