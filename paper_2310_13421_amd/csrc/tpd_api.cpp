@@ -605,7 +605,7 @@ struct BatchTables {
   std::vector<BatchItem> items;
 };
 
-tpd_status_t build_batch(const int* ns, int count, bool in_place, unsigned flags, BatchTables* bt) {
+tpd_status_t build_batch(const int* ns, int count, bool in_place, unsigned flags, Dtype dt, BatchTables* bt) {
   const bool matrix_layout = (flags & TPD_FLAG_LAYOUT_MATRIX) != 0;
   for (int i = 0; i < count; ++i) {
     if (ns[i] < 0 || ns[i] > kMaxBatchQubits) return TPD_ERROR_UNSUPPORTED;
@@ -621,7 +621,7 @@ tpd_status_t build_batch(const int* ns, int count, bool in_place, unsigned flags
     const int n = ns[bt->perm[pos]];
     int end = pos;
     while (end < count && ns[bt->perm[end]] == n) ++end;
-    const BatchGeom g = batch_geom(n);
+    const BatchGeom g = batch_geom(n, batch_tile_bits(dt));
     if (g.mb > 0) {
       const int per = 1 << g.mb;
       for (int m = pos; m < end; m += per) {
@@ -651,7 +651,7 @@ tpd_status_t build_batch(const int* ns, int count, bool in_place, unsigned flags
 
 int batched_grid(Dtype dt, uint32_t nitems) {
   const int cus = g_cus > 0 ? (int)g_cus : 256;
-  int per_cu = dt == DT_C128 ? 2 : 4;  // LDS-limited residency of the 256-thread item loop
+  int per_cu = 2;  // LDS-limited residency of the item loop (64 KiB tile per workgroup)
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (!g_tune_loaded) load_tune_cache();
@@ -931,7 +931,7 @@ tpd_status_t tpd_plan_create_batched(const int* ns, int count, tpd_dtype_t dtype
   if (st) return st;
   if (count < 0 || (count > 0 && !ns)) return TPD_ERROR_INVALID_VALUE;
   BatchTables bt;
-  st = build_batch(ns, count, in_place != 0, flags, &bt);
+  st = build_batch(ns, count, in_place != 0, flags, (Dtype)dtype, &bt);
   if (st) return st;
   int dev;
   st = current_device(&dev);
@@ -1082,7 +1082,7 @@ tpd_status_t tpd_decompose_batched(const void* const* ptrs, const int* ns, int c
   const Dtype dt = (Dtype)dtype;
   const bool in_place = out_ptrs == nullptr;
   BatchTables bt;
-  st = build_batch(ns, count, in_place, flags, &bt);
+  st = build_batch(ns, count, in_place, flags, dt, &bt);
   if (st) return st;
   for (int i = 0; i < count; ++i) {
     void* o = in_place ? (void*)ptrs[i] : out_ptrs[i];
@@ -1172,12 +1172,12 @@ tpd_status_t host_synth_schedule(int n, int dtype, unsigned flags, bool in_place
   return TPD_SUCCESS;
 }
 
-tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, std::vector<uint32_t>* perm,
-                               std::vector<BatchItem>* items) {
-  tpd_status_t st = check_dtype_flags(TPD_C128, flags);
+tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, int dtype,
+                               std::vector<uint32_t>* perm, std::vector<BatchItem>* items) {
+  tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   BatchTables bt;
-  st = build_batch(ns, count, in_place, flags, &bt);
+  st = build_batch(ns, count, in_place, flags, (Dtype)dtype, &bt);
   if (st) return st;
   *perm = std::move(bt.perm);
   *items = std::move(bt.items);

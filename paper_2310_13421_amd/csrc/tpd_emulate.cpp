@@ -420,17 +420,18 @@ tpd_status_t emulate_item(const void* const* ptrs, void* const* outs, const uint
 
 template <class S, int OUTL>
 tpd_status_t emulate_item_n(const void* const* ptrs, void* const* outs, const uint32_t* perm, const BatchItem& it) {
+  constexpr int BT = batch_tile_bits(sizeof(S) == 8 ? DT_C128 : DT_C64);
   switch (it.n) {
-    case 0: return emulate_item<S, Geom<0, 0, 8, 0, 0>, OUTL>(ptrs, outs, perm, it);
-    case 1: return emulate_item<S, Geom<1, 1, 8, 2, 0>, OUTL>(ptrs, outs, perm, it);
-    case 2: return emulate_item<S, Geom<2, 2, 8, 4, 0>, OUTL>(ptrs, outs, perm, it);
-    case 3: return emulate_item<S, Geom<3, 3, 6, 4, 0>, OUTL>(ptrs, outs, perm, it);
-    case 4: return emulate_item<S, Geom<4, 4, 4, 4, 0>, OUTL>(ptrs, outs, perm, it);
-    case 5: return emulate_item<S, Geom<5, 5, 2, 4, 0>, OUTL>(ptrs, outs, perm, it);
-    case 6: return emulate_item<S, Geom<6, 6, 0, 4, 0>, OUTL>(ptrs, outs, perm, it);
-    case 7: return emulate_item<S, Geom<7, 5, 0, 4, 0>, OUTL>(ptrs, outs, perm, it);
-    case 8: return emulate_item<S, Geom<8, 4, 0, 4, 0>, OUTL>(ptrs, outs, perm, it);
-    case 9: return emulate_item<S, Geom<9, 3, 0, 4, 0>, OUTL>(ptrs, outs, perm, it);
+    case 0: return emulate_item<S, typename BatchShape<0, BT>::G, OUTL>(ptrs, outs, perm, it);
+    case 1: return emulate_item<S, typename BatchShape<1, BT>::G, OUTL>(ptrs, outs, perm, it);
+    case 2: return emulate_item<S, typename BatchShape<2, BT>::G, OUTL>(ptrs, outs, perm, it);
+    case 3: return emulate_item<S, typename BatchShape<3, BT>::G, OUTL>(ptrs, outs, perm, it);
+    case 4: return emulate_item<S, typename BatchShape<4, BT>::G, OUTL>(ptrs, outs, perm, it);
+    case 5: return emulate_item<S, typename BatchShape<5, BT>::G, OUTL>(ptrs, outs, perm, it);
+    case 6: return emulate_item<S, typename BatchShape<6, BT>::G, OUTL>(ptrs, outs, perm, it);
+    case 7: return emulate_item<S, typename BatchShape<7, BT>::G, OUTL>(ptrs, outs, perm, it);
+    case 8: return emulate_item<S, typename BatchShape<8, BT>::G, OUTL>(ptrs, outs, perm, it);
+    case 9: return emulate_item<S, typename BatchShape<9, BT>::G, OUTL>(ptrs, outs, perm, it);
   }
   return TPD_ERROR_INTERNAL;
 }
@@ -441,8 +442,8 @@ namespace tpd {
 // defined in tpd_api.cpp
 tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, const int* tune, SweepDesc* sw,
                            int* nsweep, int* n1, uint64_t* bitmap_words);
-tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, std::vector<uint32_t>* perm,
-                               std::vector<BatchItem>* items);
+tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, int dtype,
+                               std::vector<uint32_t>* perm, std::vector<BatchItem>* items);
 tpd_status_t host_synth_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep);
 tpd_status_t host_partial_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep,
                                    int* n1, uint64_t* bitmap_words, int* prune);
@@ -541,7 +542,7 @@ extern "C" tpd_status_t tpd_debug_emulate_batched(const void* const* ptrs, const
   if (dtype != TPD_C128 && dtype != TPD_C64) return TPD_ERROR_INVALID_VALUE;
   std::vector<uint32_t> perm;
   std::vector<BatchItem> items;
-  tpd_status_t st = host_batch_tables(ns, count, out_ptrs == nullptr, flags, &perm, &items);
+  tpd_status_t st = host_batch_tables(ns, count, out_ptrs == nullptr, flags, dtype, &perm, &items);
   if (st) return st;
   void* const* outs = out_ptrs ? out_ptrs : (void* const*)ptrs;
   const bool mat = (flags & TPD_FLAG_LAYOUT_MATRIX) != 0;

@@ -140,10 +140,27 @@ constexpr bool shape_fits(int xb, int db) {
   return ((size_t)sizeof(Cx<S>) << (xb + db)) <= 131072;
 }
 
-// batched tile geometry per n (shared with the host emulator and planner)
+// Batched tile geometry (shared with the host emulator and planner): tiles
+// of 2^BT elements, 2^(BT-4) threads, one 64 KiB LDS tile for either dtype
+// (complex128: BT = 12, complex64: BT = 13).  n <= 6: 2^mb whole matrices
+// per item; n >= 7: one d-group of 2^db diagonals of one matrix per item.
 struct BatchGeom {
   int xb, db, mb, r;  // packed matrices per item = 2^mb
 };
-BatchGeom batch_geom(int n);
+constexpr int batch_tile_bits(Dtype dt) { return dt == DT_C128 ? 12 : 13; }
+template <int N, int BT>
+struct BatchShape {
+  static constexpr int XB = N;
+  static constexpr int DB = N <= 6 ? N : BT - N;
+  static constexpr int MB = N <= 2 ? BT - 4 : (N <= 6 ? BT - 2 * N : 0);
+  static constexpr int R = N == 0 ? 0 : (N == 1 ? 2 : 4);
+  using G = Geom<XB, DB, MB, R, 0>;
+  static_assert(G::NT == (1 << (BT - 4)), "every batched item uses the whole workgroup");
+};
+constexpr BatchGeom batch_geom(int n, int bt) {
+  return n < 0 || n > 9 ? BatchGeom{-1, -1, -1, -1}
+                        : BatchGeom{n, n <= 6 ? n : bt - n, n <= 2 ? bt - 4 : (n <= 6 ? bt - 2 * n : 0),
+                                    n == 0 ? 0 : (n == 1 ? 2 : 4)};
+}
 
 }  // namespace tpd

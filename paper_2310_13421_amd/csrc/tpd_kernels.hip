@@ -30,22 +30,6 @@ namespace tpd {
 // batched persistent kernel: one work item = packed whole matrices (n <= 6)
 // or one d-group tile of one matrix (n = 7..9); every item is a single sweep.
 // ---------------------------------------------------------------------------
-BatchGeom batch_geom(int n) {
-  switch (n) {
-    case 0: return {0, 0, 8, 0};
-    case 1: return {1, 1, 8, 2};
-    case 2: return {2, 2, 8, 4};
-    case 3: return {3, 3, 6, 4};
-    case 4: return {4, 4, 4, 4};
-    case 5: return {5, 5, 2, 4};
-    case 6: return {6, 6, 0, 4};
-    case 7: return {7, 5, 0, 4};
-    case 8: return {8, 4, 0, 4};
-    case 9: return {9, 3, 0, 4};
-    default: return {-1, -1, -1, -1};
-  }
-}
-
 template <class S, class G, int OUTL>
 __device__ __noinline__ void batched_item(const BatchArgs& a, const BatchItem& it, Cx<S>* lds) {
   static constexpr Roles RL = make_roles<G>();
@@ -105,29 +89,29 @@ __device__ __noinline__ void batched_item(const BatchArgs& a, const BatchItem& i
   }
 }
 
-template <class S, int OUTL>
+template <class S, int OUTL, int BT>
 __device__ __forceinline__ void batched_dispatch(const BatchArgs& a, const BatchItem& it, Cx<S>* lds) {
   switch (it.n) {
-    case 0: batched_item<S, Geom<0, 0, 8, 0, 0>, OUTL>(a, it, lds); break;
-    case 1: batched_item<S, Geom<1, 1, 8, 2, 0>, OUTL>(a, it, lds); break;
-    case 2: batched_item<S, Geom<2, 2, 8, 4, 0>, OUTL>(a, it, lds); break;
-    case 3: batched_item<S, Geom<3, 3, 6, 4, 0>, OUTL>(a, it, lds); break;
-    case 4: batched_item<S, Geom<4, 4, 4, 4, 0>, OUTL>(a, it, lds); break;
-    case 5: batched_item<S, Geom<5, 5, 2, 4, 0>, OUTL>(a, it, lds); break;
-    case 6: batched_item<S, Geom<6, 6, 0, 4, 0>, OUTL>(a, it, lds); break;
-    case 7: batched_item<S, Geom<7, 5, 0, 4, 0>, OUTL>(a, it, lds); break;
-    case 8: batched_item<S, Geom<8, 4, 0, 4, 0>, OUTL>(a, it, lds); break;
-    case 9: batched_item<S, Geom<9, 3, 0, 4, 0>, OUTL>(a, it, lds); break;
+    case 0: batched_item<S, typename BatchShape<0, BT>::G, OUTL>(a, it, lds); break;
+    case 1: batched_item<S, typename BatchShape<1, BT>::G, OUTL>(a, it, lds); break;
+    case 2: batched_item<S, typename BatchShape<2, BT>::G, OUTL>(a, it, lds); break;
+    case 3: batched_item<S, typename BatchShape<3, BT>::G, OUTL>(a, it, lds); break;
+    case 4: batched_item<S, typename BatchShape<4, BT>::G, OUTL>(a, it, lds); break;
+    case 5: batched_item<S, typename BatchShape<5, BT>::G, OUTL>(a, it, lds); break;
+    case 6: batched_item<S, typename BatchShape<6, BT>::G, OUTL>(a, it, lds); break;
+    case 7: batched_item<S, typename BatchShape<7, BT>::G, OUTL>(a, it, lds); break;
+    case 8: batched_item<S, typename BatchShape<8, BT>::G, OUTL>(a, it, lds); break;
+    case 9: batched_item<S, typename BatchShape<9, BT>::G, OUTL>(a, it, lds); break;
     default: break;
   }
 }
 
-template <class S, int OUTL>
-__global__ void __launch_bounds__(256) k_batched(BatchArgs a) {
-  __shared__ Cx<S> lds[4096];
+template <class S, int OUTL, int BT>
+__global__ void __launch_bounds__(1 << (BT - 4)) k_batched(BatchArgs a) {
+  __shared__ Cx<S> lds[1 << BT];
   for (uint32_t i = blockIdx.x; i < a.nitems; i += gridDim.x) {
     const BatchItem it = a.items[i];
-    batched_dispatch<S, OUTL>(a, it, lds);
+    batched_dispatch<S, OUTL, BT>(a, it, lds);
     __syncthreads();  // the next item reuses the LDS tile
   }
 }
@@ -171,12 +155,17 @@ hipError_t launch_batched_perm(Dtype dt, const void* const* in_ptrs, void* const
   BatchArgs a{in_ptrs, out_ptrs, perm, items, nitems, layout};
   if (a.nitems == 0) return hipSuccess;
   if (grid <= 0 || (uint32_t)grid > a.nitems) grid = (int)a.nitems;
+  constexpr int B128 = batch_tile_bits(DT_C128), B64 = batch_tile_bits(DT_C64);
   if (dt == DT_C128) {
-    if (layout == L_CAN) hipLaunchKernelGGL((k_batched<double, L_CAN>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_batched<double, L_MAT>), dim3(grid), dim3(256), 0, st, a);
+    if (layout == L_CAN)
+      hipLaunchKernelGGL((k_batched<double, L_CAN, B128>), dim3(grid), dim3(1 << (B128 - 4)), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_batched<double, L_MAT, B128>), dim3(grid), dim3(1 << (B128 - 4)), 0, st, a);
   } else {
-    if (layout == L_CAN) hipLaunchKernelGGL((k_batched<float, L_CAN>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_batched<float, L_MAT>), dim3(grid), dim3(256), 0, st, a);
+    if (layout == L_CAN)
+      hipLaunchKernelGGL((k_batched<float, L_CAN, B64>), dim3(grid), dim3(1 << (B64 - 4)), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_batched<float, L_MAT, B64>), dim3(grid), dim3(1 << (B64 - 4)), 0, st, a);
   }
   return hipGetLastError();
 }
