@@ -106,7 +106,9 @@ int tpd_max_qubits(tpd_dtype_t dtype);
 tpd_status_t tpd_decompose(const void* A, int n, void* coeffs, tpd_stream_t stream);
 
 /* Same, with the dtype and flags (TPD_FLAG_NO_PRUNE, TPD_FLAG_LAYOUT_MATRIX,
- * TPD_FLAG_ORDER_BOTTOM) chosen by the caller. */
+ * TPD_FLAG_ORDER_BOTTOM, TPD_FLAG_HERMITIAN) chosen by the caller.  coeffs
+ * may equal A (in place) for any n with TPD_FLAG_LAYOUT_MATRIX and for
+ * n <= 6 in the canonical order; otherwise TPD_ERROR_UNSUPPORTED.        */
 tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                               tpd_stream_t stream);
 
@@ -229,12 +231,13 @@ tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len);
 /* ---- autotuning ---- */
 
 /* Time the candidate two-sweep schedules for (n, dtype, layout, placement,
- * TPD_FLAG_HERMITIAN) on the caller's buffers and make the fastest the one every later call and
- * plan with the same key uses on this process (and, if the environment
- * variable TPD_AUTOTUNE_CACHE names a file, appended there and reloaded by
- * later processes).  Candidates: tile widths of 2^3..2^5 (complex128) or
- * 2^4..2^6 (complex64) XOR-diagonals, one workgroup per tile or a
- * persistent grid of 1, 2 or 4 workgroups per CU.
+ * TPD_FLAG_HERMITIAN) on the caller's buffers and make the fastest the one
+ * every later call and plan with the same key uses on this process (and,
+ * if the environment variable TPD_AUTOTUNE_CACHE names a file, appended
+ * there and reloaded by later processes).  Candidates: tile widths of
+ * 2^3..2^5 (complex128) or 2^4..2^6 (complex64) XOR-diagonals, one
+ * workgroup per tile or a persistent grid of 1, 2 or 4 workgroups per CU
+ * (which load the next tile while transforming the current one).
  * The choice never changes results (same operations in the same order).
  * Arguments as tpd_decompose_ex; `coeffs` is overwritten; with
  * A == coeffs the matrix is transformed repeatedly (destroyed).  Allocates
