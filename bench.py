@@ -36,12 +36,14 @@ def log(msg):
 
 
 def kernel_source_hash():
-    """Hash of every device source (kernels, their headers, instantiation units)."""
+    """Hash of the sources of the sweep kernel (its headers and the
+    instantiation units), the kernel whose traffic profiles/traffic.json
+    records."""
     import glob
 
     h = hashlib.sha256()
-    files = sorted(set(KERNEL_SOURCES) | {os.path.relpath(p, ROOT) for p in
-                                          glob.glob(os.path.join(ROOT, "paper_2310_13421_amd", "csrc", "*.hip"))})
+    files = sorted(set(KERNEL_SOURCES) | {os.path.relpath(p, ROOT) for p in glob.glob(
+        os.path.join(ROOT, "paper_2310_13421_amd", "csrc", "tpd_sweep_c*.hip"))})
     for rel in files:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
