@@ -737,3 +737,55 @@ def test_n15_every_schedule_same_bits(dtype, dbs):
         tpd.decompose_tuned(A, out, db=9)
     del A, ref, out
     torch.cuda.empty_cache()
+
+
+def test_partial_with_hermitian_flag_and_in_place():
+    n = 12
+    A = W.gaussian(n, seed=1600, hermitian=True)
+    rng = np.random.default_rng(1601)
+    q = np.concatenate([rng.integers(0, 4 ** n, 500, dtype=np.int64), two_local(n)])
+    ref = O.tpd_partial(A, q)
+    Ad = to_dev(A)
+    qd = torch.from_numpy(q).to(DEV)
+    got = tpd.decompose_partial(Ad, qd, hermitian=True).cpu().numpy()
+    assert np.array_equal(got.real, ref.real) and np.all(got.imag == 0)
+    T = Ad.clone()
+    got = tpd.decompose_partial(T, qd, work=T.view(-1), layout="matrix", hermitian=True).cpu().numpy()
+    assert np.array_equal(got.real, ref.real) and np.all(got.imag == 0)
+
+
+def test_concurrent_streams_use_separate_workspaces():
+    # pruned decompositions, partial decompositions and compactions on two
+    # streams at once: each stream has its own bitmaps and scan buffers
+    n = 11
+    mats = [W.dense_from_terms(W.heisenberg_terms(n, seed=s, n_local=40, dyadic=True), n) for s in (21, 22)]
+    refs = [O.tpd_recursive(m) for m in mats]
+    req = torch.from_numpy(two_local(n)).to(DEV)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    devs = [to_dev(m) for m in mats]
+    torch.cuda.synchronize()
+    outs, vals, lists = [], [], []
+    for rep in range(3):
+        outs.clear(); vals.clear(); lists.clear()
+        for s, Ad in zip(streams, devs):
+            with torch.cuda.stream(s):
+                o = tpd.decompose(Ad)
+                v = tpd.decompose_partial(Ad, req)
+                q = torch.empty(5000, dtype=torch.int64, device=DEV)
+                w = torch.empty(5000, dtype=Ad.dtype, device=DEV)
+                cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
+                assert tpd.lib.tpd_compact(o.data_ptr(), n, tpd.TPD_C128, 0, 0.0, q.data_ptr(), w.data_ptr(), 5000,
+                                           cnt.data_ptr(), ctypes_stream(s)) == 0
+                outs.append(o); vals.append(v); lists.append((q, w, cnt))
+        torch.cuda.synchronize()
+        for o, v, (q, w, cnt), ref in zip(outs, vals, lists, refs):
+            assert same_bits(o.cpu().numpy(), ref)
+            assert same_bits(v.cpu().numpy(), ref[two_local(n)])
+            nz = np.flatnonzero(ref)
+            k = int(cnt.item())
+            assert k == nz.size and np.array_equal(q[:k].cpu().numpy(), nz)
+            assert same_bits(w[:k].cpu().numpy(), ref[nz])
+
+
+def ctypes_stream(s):
+    return s.cuda_stream
