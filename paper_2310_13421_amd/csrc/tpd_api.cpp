@@ -154,7 +154,8 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
   a.is_one = false;
   a.herm = (flags & TPD_FLAG_HERMITIAN) ? 1 : 0;
   a.inv = false;
-  a.ntiles = ((uint64_t)1 << s->n2) << (n - db);
+  // Hermitian: only the tiles holding representatives (herm_first_tile)
+  a.ntiles = a.herm ? herm_first_tiles(s->n2, db, n - db) : ((uint64_t)1 << s->n2) << (n - db);
   SweepDesc& b = s->sw[1];
   b.xlo = 0;
   b.xb = s->n2;

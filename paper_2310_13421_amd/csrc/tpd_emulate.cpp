@@ -65,9 +65,39 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
   std::vector<uint64_t> rset, wset;
   uint32_t bits[NBW];
 
+  // Hermitian first sweep: the enumeration covers exactly the tiles with
+  // representatives; the others are accounted here (nothing is read or
+  // written there), so the completeness check also proves the enumeration
+  // is a bijection onto the needed tiles
+  if (a.herm && xlo) {
+    const uint64_t all = ((uint64_t)1 << xlo) << a.nfix_d;
+    for (uint64_t tile = 0; tile < all; ++tile) {
+      const uint64_t td = tile & tdmask;
+      const uint64_t xf = tile >> a.nfix_d;
+      const uint64_t dlh = td & (((uint64_t)1 << (xlo - G::DB)) - 1);
+      const uint64_t hm = dlh ? (uint64_t)1 << (63 - __builtin_clzll(dlh) + G::DB) : 0;
+      if (!(xf & hm)) continue;
+      const uint64_t xfix = (xf & (((uint64_t)1 << xlo) - 1)) | ((xf >> xlo) << (xlo + G::XB));
+      for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+        const uint32_t eb = elem_base<G>(RL, 0, tid);
+        for (int j = 0; j < G::E; ++j) {
+          const uint32_t e = eb | elem_reg<G>(RL, 0, j);
+          const uint64_t x = xfix | ((uint64_t)((e >> G::DB) & XM) << xlo);
+          const uint64_t d = (td << G::DB) | (e & DM);
+          ck.rd(layout_addr<INL>(x, d, n, db));
+          ck.wr(layout_addr<OUTL>(x, d, n, db));
+        }
+      }
+    }
+  }
   for (uint64_t tile = 0; tile < a.ntiles; ++tile) {
-    const uint64_t td = tile & tdmask;
-    const uint64_t xf = tile >> a.nfix_d;
+    uint64_t td, xf;
+    if (a.herm && xlo) {
+      herm_first_tile(tile, xlo, G::DB, a.nfix_d, &xf, &td);
+    } else {
+      td = tile & tdmask;
+      xf = tile >> a.nfix_d;
+    }
     const uint64_t xfix = (xf & (((uint64_t)1 << xlo) - 1)) | ((xf >> xlo) << (xlo + G::XB));
     if (a.req && !((a.req[td >> 5] >> (td & 31)) & 1u)) {
       // d-group without requested strings: nothing is read or written
@@ -123,19 +153,8 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
       const uint64_t dlh = td & (((uint64_t)1 << (n2 - G::DB)) - 1);
       if (dlh) hm = (uint64_t)1 << (63 - __builtin_clzll(dlh) + G::DB);
       if (xlo && (xf & hm)) {
-        // first sweep skips a non-representative row block: nothing is read
-        // or written (account its addresses so completeness still checks)
-        for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
-          const uint32_t eb = elem_base<G>(RL, 0, tid);
-          for (int j = 0; j < G::E; ++j) {
-            const uint32_t e = eb | elem_reg<G>(RL, 0, j);
-            const uint64_t x = xfix | ((uint64_t)((e >> G::DB) & XM) << xlo);
-            const uint64_t d = (td << G::DB) | (e & DM);
-            ck.rd(layout_addr<INL>(x, d, n, db));
-            ck.wr(layout_addr<OUTL>(x, d, n, db));
-          }
-        }
-        continue;
+        // the enumeration must never produce a non-representative block
+        return TPD_ERROR_INTERNAL;
       }
     }
     for (int w = 0; w < NBW; ++w) bits[w] = 0;

@@ -124,6 +124,38 @@ __host__ __device__ inline void request_bits(uint64_t q, int n, int n1, int db, 
   *group = td;
   *tile = (td << n1) | (row >> (n - n1));
 }
+// Hermitian first sweep: the tiles (fixed low x bits xf, d-group td) whose
+// row block holds representatives, enumerated without gaps so that every
+// workgroup of a persistent grid gets the same amount of work.  With
+// L = n2 - db and dlh = td mod 2^L: a tile is needed when dlh = 0, or when xf
+// has bit m = msb(dlh) + db clear.  t < 2^(n2-1+nfix_d): xf is t's high part
+// with a zero inserted at bit m (dlh != 0) or with its top bit clear
+// (dlh = 0); beyond: the dlh = 0 groups with xf's top bit set.
+__host__ __device__ inline uint64_t herm_first_tiles(int n2, int db, int nfix_d) {
+  return ((uint64_t)1 << (n2 - 1 + nfix_d)) + ((uint64_t)1 << (n2 - 1 + nfix_d - (n2 - db)));
+}
+__host__ __device__ inline void herm_first_tile(uint64_t t, int n2, int db, int nfix_d, uint64_t* xf, uint64_t* td) {
+  const int L = n2 - db;
+  const uint64_t part = (uint64_t)1 << (n2 - 1 + nfix_d);
+  if (t < part) {
+    const uint64_t xc = t >> nfix_d;
+    const uint64_t d = t & (((uint64_t)1 << nfix_d) - 1);
+    const uint64_t dlh = d & (((uint64_t)1 << L) - 1);
+    *td = d;
+    if (dlh) {
+      const int m = 63 - __builtin_clzll(dlh) + db;
+      *xf = ((xc >> m) << (m + 1)) | (xc & (((uint64_t)1 << m) - 1));
+    } else {
+      *xf = xc;
+    }
+  } else {
+    const uint64_t u = t - part;
+    const int hb = nfix_d - L;
+    *td = (u & (((uint64_t)1 << hb) - 1)) << L;
+    *xf = (u >> hb) | ((uint64_t)1 << (n2 - 1));
+  }
+}
+
 // a coefficient is kept in the sparse list unless both parts are within tol
 // (compared in the coefficient's own precision; NaN is kept)
 template <class S>

@@ -69,8 +69,12 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
     uint64_t td, xf, xfix, hm;
   };
   auto decode = [&](uint64_t tile, Tile& t) -> bool {
-    t.td = tile & tdmask;
-    t.xf = tile >> a.nfix_d;
+    if (a.herm && xlo) {
+      herm_first_tile(tile, xlo, G::DB, a.nfix_d, &t.xf, &t.td);
+    } else {
+      t.td = tile & tdmask;
+      t.xf = tile >> a.nfix_d;
+    }
     t.xfix = (t.xf & (((uint64_t)1 << xlo) - 1)) | ((t.xf >> xlo) << (xlo + G::XB));
     if (a.req && !((uniform_word(a.req, t.td >> 5) >> (t.td & 31)) & 1u)) return false;
     if (a.bitmap_mode == 2) {
@@ -87,7 +91,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
       const int n2 = xlo ? xlo : G::XB;
       const uint64_t dlh = t.td & (((uint64_t)1 << (n2 - G::DB)) - 1);
       if (dlh) t.hm = (uint64_t)1 << (63 - __builtin_clzll(dlh) + G::DB);
-      if (xlo && (t.xf & t.hm)) return false;  // first sweep: a non-representative row block
+      if (xlo && (t.xf & t.hm)) return false;  // first sweep: never enumerated (herm_first_tile)
     }
     return true;
   };
