@@ -128,11 +128,14 @@ tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t d
 /* Partial decomposition: the weights of requested strings only (section
  * "Methods", the partial variant of Fig. 2 / Algorithm 3).  The paper slices
  * only the children in the request tree; here the unit of skipping is a
- * tile: a first-sweep d-group (2^db XOR-diagonals, all rows) runs only if a
- * requested string has its X/Y mask in that group, and a second-sweep tile
- * only if a requested string lies in it (and, with pruning, its cumulative
- * matrix weight is nonzero).  n <= 8 computes everything.  Requested values
- * are bitwise those of tpd_decompose_ex with the same dtype and flags.
+ * tile: a first-sweep d-group (2^db XOR-diagonals, all rows; the narrowest
+ * tile width is used) runs only if a requested string has its X/Y mask in
+ * that group, and a second-sweep tile only if a requested string lies in it
+ * (and, with pruning, its cumulative matrix weight is nonzero).  The groups
+ * and tiles to run are compacted into device work lists, so the cost
+ * follows the work requested.  n <= 8 computes everything.  Requested
+ * values are bitwise those of tpd_decompose_ex with the same dtype and
+ * flags.
  *   A      [in]  device matrix, as tpd_decompose_ex (not modified unless
  *                coeffs == A)
  *   coeffs [out] device, 4^n elements of work/output, layout per flags; on
@@ -145,8 +148,9 @@ tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t d
  *   values [out] device array[count] of complex dtype, values[s] = w_req[s]
  *   flags  TPD_FLAG_NO_PRUNE, TPD_FLAG_LAYOUT_MATRIX, TPD_FLAG_HERMITIAN,
  *          TPD_FLAG_ORDER_BOTTOM; TPD_FLAG_TIMING is TPD_ERROR_INVALID_VALUE
- * Workspace: two request bitmaps (2^(n-db) and 2^(n1+n-db) bits) per
- * (device, stream), plus the pruning bitmap.                              */
+ * Workspace: two request bitmaps (2^(n-db) and 2^(n1+n-db) bits) and two
+ * work lists (32-bit entries, one per bit) per (device, stream), plus the
+ * pruning bitmap.                                                         */
 tpd_status_t tpd_decompose_partial(const void* A, int n, void* coeffs, const uint64_t* req, uint64_t count,
                                    void* values, tpd_dtype_t dtype, unsigned flags, tpd_stream_t stream);
 

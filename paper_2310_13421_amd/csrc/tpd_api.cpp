@@ -185,6 +185,11 @@ tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Sched
 // its tile bitmap (requests, ANDed with the live tiles when pruning)
 tpd_status_t make_partial_schedule(int n, Dtype dt, unsigned flags, bool in_place, const Tuned* force,
                                    Schedule* s) {
+  // the narrowest tile width: a d-group holding one requested string costs
+  // one tile per row block, so narrower groups read less for sparse requests
+  Tuned narrow;
+  narrow.db = dt == DT_C128 ? 3 : 4;
+  if (!force && n > 8 && !(flags & TPD_FLAG_ORDER_BOTTOM)) force = &narrow;
   tpd_status_t st = make_schedule_with(n, dt, flags, in_place, force, s);
   if (st) return st;
   if (s->nsweep == 2) {
@@ -400,6 +405,8 @@ struct Workspace {
   uint64_t bitmap_words = 0;
   uint32_t* req = nullptr;  // partial decomposition: d-group bits, then second-sweep tile bits
   uint64_t req_words = 0;
+  uint32_t* lists = nullptr;  // partial decomposition: 2 counts (padded), d-group list, tile list
+  uint64_t list_words = 0;
   void* sel = nullptr;  // compaction: per-chunk counts and offsets, total
   size_t sel_bytes = 0;
   unsigned long long* counter = nullptr;
@@ -572,24 +579,72 @@ tpd_status_t run_schedule(const Schedule& s, const void* A, void* C, uint32_t* b
   return TPD_SUCCESS;
 }
 
-// Partial decomposition (the paper's Algorithm 3 at tile granularity): a
-// d-group of the first sweep runs only if some requested string lies in it,
-// a second-sweep tile only if one lies in it (and, with pruning, it is
-// live); then the requested weights are gathered.  n <= 8: the whole single
-// sweep, then the gather.
+// Partial decomposition (the paper's Algorithm 3 at tile granularity): the
+// d-groups of the first sweep that hold a requested string, and the
+// second-sweep tiles that hold one (and, with pruning, are live), become
+// device work lists; each sweep then runs a persistent grid over its list
+// only, so the launch costs nothing for the groups and tiles left out.  The
+// requested weights are then gathered.  n <= 8: the whole single sweep,
+// then the gather.  Hermitian first sweeps keep their own tile enumeration
+// and skip unrequested d-groups by the bitmap (in a persistent grid too).
+struct PartialLists {
+  uint32_t* counts;  // [0]: d-groups, [1]: second-sweep tiles
+  uint32_t* groups;  // list of d-groups
+  uint32_t* tiles;   // list of second-sweep tiles
+};
+
 tpd_status_t run_partial(const Schedule& s, const void* A, void* C, const uint64_t* req, uint64_t count,
                          void* values, uint32_t* live, uint32_t* groups, uint64_t group_words, uint32_t* tiles,
-                         hipStream_t st) {
+                         const PartialLists& pl, hipStream_t st) {
   if (s.nsweep == 2) {
+    const int cus = g_cus > 0 ? (int)g_cus : 256;
     if (launch_fill_u32(groups, group_words + s.bitmap_words, 0u, st) != hipSuccess) return TPD_ERROR_LAUNCH;
+    if (launch_fill_u32(pl.counts, 2, 0u, st) != hipSuccess) return TPD_ERROR_LAUNCH;
     if (launch_mark_requests(req, count, s.n, s.n1, s.sw[0].db, groups, tiles, st) != hipSuccess)
       return TPD_ERROR_LAUNCH;
+    const bool group_list = !s.sw[0].herm;
+    if (group_list && launch_bits_to_list(groups, group_words, pl.groups, &pl.counts[0], st) != hipSuccess)
+      return TPD_ERROR_LAUNCH;
     if (s.prune && launch_fill_u32(live, s.bitmap_words, 0u, st) != hipSuccess) return TPD_ERROR_LAUNCH;
-    tpd_status_t e = launch_sweep_i(s, 0, A, C, live, groups, st);
-    if (e) return e;
-    if (s.prune && launch_and_u32(tiles, live, s.bitmap_words, st) != hipSuccess) return TPD_ERROR_LAUNCH;
-    e = launch_sweep_i(s, 1, A, C, tiles, nullptr, st);
-    if (e) return e;
+    for (int i = 0; i < 2; ++i) {
+      SweepDesc w = s.sw[i];
+      if (w.grid <= 0) w.grid = 2 * cus;  // persistent over the work list
+      SweepArgs a{};
+      a.in = i == 0 ? A : C;
+      a.out = C;
+      a.n = s.n;
+      a.xlo = w.xlo;
+      a.db = w.db;
+      a.nfix_d = s.n - w.db;
+      a.bm_xbits = s.n1;
+      a.herm = w.herm;
+      if (i == 0) {
+        a.bitmap = live;
+        a.bitmap_mode = w.bitmap_mode;  // sets the live bits when pruning
+        if (group_list) {
+          a.list = pl.groups;
+          a.list_count = &pl.counts[0];
+          a.list_shift = w.xlo;  // the first sweep fixes the low n2 x bits
+        } else {
+          a.req = groups;
+        }
+      } else {
+        if (s.prune && launch_and_u32(tiles, live, s.bitmap_words, st) != hipSuccess) return TPD_ERROR_LAUNCH;
+        if (launch_bits_to_list(tiles, s.bitmap_words, pl.tiles, &pl.counts[1], st) != hipSuccess)
+          return TPD_ERROR_LAUNCH;
+        a.bitmap = nullptr;
+        a.bitmap_mode = 0;  // the list holds requested (and live) tiles only
+        a.list = pl.tiles;
+        a.list_count = &pl.counts[1];
+        a.list_shift = 0;
+      }
+      a.ntiles = w.ntiles;
+      const hipError_t e = launch_sweep(s.dt, w, a, st);
+      if (e != hipSuccess) {
+        logf("partial sweep %d launch failed: %s", i, hipGetErrorString(e));
+        return TPD_ERROR_LAUNCH;
+      }
+    }
   } else {
     tpd_status_t e = run_schedule(s, A, C, nullptr, st, nullptr);
     if (e) return e;
@@ -808,6 +863,7 @@ tpd_status_t tpd_decompose_partial(const void* A, int n, void* coeffs, const uin
   if (st) return st;
   hipStream_t hs = (hipStream_t)stream;
   uint32_t *live = nullptr, *groups = nullptr, *tiles = nullptr;
+  PartialLists pl{nullptr, nullptr, nullptr};
   const uint64_t gw = group_words_of(s);
   if (n == 0) {
     if (A != coeffs && hipMemcpyAsync(coeffs, A, elem_bytes(dt), hipMemcpyDeviceToDevice, hs) != hipSuccess)
@@ -827,9 +883,14 @@ tpd_status_t tpd_decompose_partial(const void* A, int n, void* coeffs, const uin
     if (st) return st;
     groups = w.req;
     tiles = w.req + gw;
+    st = ensure_words(&w.lists, &w.list_words, 64 + 32 * (gw + s.bitmap_words));
+    if (st) return st;
+    pl.counts = w.lists;
+    pl.groups = w.lists + 64;
+    pl.tiles = w.lists + 64 + 32 * gw;
   }
   logf("decompose_partial n=%d count=%llu %s", n, (unsigned long long)count, describe(s).c_str());
-  return run_partial(s, A, coeffs, req, count, values, live, groups, gw, tiles, hs);
+  return run_partial(s, A, coeffs, req, count, values, live, groups, gw, tiles, pl, hs);
 }
 
 tpd_status_t tpd_compact(const void* coeffs, int n, tpd_dtype_t dtype, unsigned flags, double tol, uint64_t* q_out,
@@ -880,6 +941,7 @@ tpd_status_t tpd_release_workspace(void) {
     if (w.staged) (void)hipEventSynchronize(w.staged);
     if (w.bitmap) (void)hipFree(w.bitmap);
     if (w.req) (void)hipFree(w.req);
+    if (w.lists) (void)hipFree(w.lists);
     if (w.sel) (void)hipFree(w.sel);
     if (w.counter) (void)hipFree(w.counter);
     if (w.table) (void)hipFree(w.table);

@@ -90,13 +90,30 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
       }
     }
   }
-  for (uint64_t tile = 0; tile < a.ntiles; ++tile) {
+  // work lists (partial decomposition): the listed tiles are processed; the
+  // others are accounted after the loop (nothing is read or written there)
+  const uint64_t lcount = a.list ? (uint64_t)a.list_count[0] : 0;
+  const uint64_t ntiles = a.list ? lcount << a.list_shift : a.ntiles;
+  const uint64_t xfbits = (uint64_t)(n - G::XB);
+  std::vector<uint8_t> listed(a.list ? ((size_t)1 << (xfbits + a.nfix_d)) : 0, 0);
+  for (uint64_t tile = 0; tile < ntiles; ++tile) {
     uint64_t td, xf;
-    if (a.herm && xlo) {
+    if (a.list && a.list_shift) {
+      xf = tile / lcount;
+      td = a.list[tile - xf * lcount];
+    } else if (a.list) {
+      const uint64_t lt = a.list[tile];
+      td = lt >> a.bm_xbits;
+      xf = lt & (((uint64_t)1 << a.bm_xbits) - 1);
+    } else if (a.herm && xlo) {
       herm_first_tile(tile, xlo, G::DB, a.nfix_d, &xf, &td);
     } else {
       td = tile & tdmask;
       xf = tile >> a.nfix_d;
+    }
+    if (a.list) {
+      if (td > tdmask || xf >= ((uint64_t)1 << xfbits)) return TPD_ERROR_INTERNAL;
+      if (listed[(xf << a.nfix_d) | td]++) return TPD_ERROR_INTERNAL;  // listed twice
     }
     const uint64_t xfix = (xf & (((uint64_t)1 << xlo) - 1)) | ((xf >> xlo) << (xlo + G::XB));
     if (a.req && !((a.req[td >> 5] >> (td & 31)) & 1u)) {
@@ -315,6 +332,23 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
       std::sort(rset.begin(), rset.end());
       std::sort(wset.begin(), wset.end());
       if (rset != wset) return TPD_ERROR_INTERNAL;  // an in-place tile must be closed
+    }
+  }
+  if (a.list) {
+    for (uint64_t nt = 0; nt < listed.size(); ++nt) {
+      if (listed[nt]) continue;
+      const uint64_t td = nt & tdmask, xf = nt >> a.nfix_d;
+      const uint64_t xfix = (xf & (((uint64_t)1 << xlo) - 1)) | ((xf >> xlo) << (xlo + G::XB));
+      for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
+        const uint32_t eb = elem_base<G>(RL, 0, tid);
+        for (int j = 0; j < G::E; ++j) {
+          const uint32_t e = eb | elem_reg<G>(RL, 0, j);
+          const uint64_t x = xfix | ((uint64_t)((e >> G::DB) & XM) << xlo);
+          const uint64_t d = (td << G::DB) | (e & DM);
+          ck.rd(layout_addr<INL>(x, d, n, db));
+          ck.wr(layout_addr<OUTL>(x, d, n, db));
+        }
+      }
     }
   }
   return ck.ok ? TPD_SUCCESS : TPD_ERROR_INTERNAL;
@@ -607,7 +641,17 @@ extern "C" tpd_status_t tpd_debug_emulate_partial(const void* A, int n, void* co
       groups[g >> 5] |= 1u << (g & 31);
       tiles[t >> 5] |= 1u << (t & 31);
     }
-    const std::vector<uint32_t> requested = tiles;
+    // work lists as the device builds them (the order does not matter)
+    auto to_list = [](const std::vector<uint32_t>& bits, std::vector<uint32_t>* list) {
+      list->clear();
+      for (uint64_t w = 0; w < bits.size(); ++w)
+        for (int b = 0; b < 32; ++b)
+          if ((bits[w] >> b) & 1u) list->push_back((uint32_t)(w * 32 + b));
+    };
+    std::vector<uint32_t> glist, tlist;
+    static const uint32_t kNone = 0;  // an empty list is still a list (never read)
+    const bool group_list = !sw[0].herm;
+    to_list(groups, &glist);
     for (int i = 0; i < 2; ++i) {
       SweepArgs a{};
       a.in = i == 0 ? A : coeffs;
@@ -616,24 +660,40 @@ extern "C" tpd_status_t tpd_debug_emulate_partial(const void* A, int n, void* co
       a.xlo = sw[i].xlo;
       a.db = db;
       a.nfix_d = n - db;
-      a.bitmap = i == 0 ? live.data() : tiles.data();
-      a.bitmap_mode = sw[i].bitmap_mode;
       a.bm_xbits = n1;
       a.herm = sw[i].herm;
-      a.req = i == 0 ? groups.data() : nullptr;
       a.ntiles = sw[i].ntiles;
+      uint32_t lcount = 0;
+      if (i == 0) {
+        a.bitmap = live.data();
+        a.bitmap_mode = sw[i].bitmap_mode;
+        if (group_list) {
+          lcount = (uint32_t)glist.size();
+          a.list = glist.empty() ? &kNone : glist.data();
+          a.list_count = &lcount;
+          a.list_shift = sw[i].xlo;
+        } else {
+          a.req = groups.data();
+        }
+      } else {
+        if (prune)
+          for (uint64_t w = 0; w < words; ++w) tiles[w] &= live[w];
+        to_list(tiles, &tlist);
+        lcount = (uint32_t)tlist.size();
+        a.bitmap = nullptr;
+        a.bitmap_mode = 0;
+        a.list = tlist.empty() ? &kNone : tlist.data();
+        a.list_count = &lcount;
+        a.list_shift = 0;
+      }
       Checker ck(elems);
-      ck.live = live.data();
-      ck.requested = requested.data();
-      ck.zero_check = prune != 0;
+      ck.zero_check = false;
       if (dtype == TPD_C128)
         st = emulate_shape<double>(sw[i], (const Cx<double>*)a.in, (Cx<double>*)a.out, a, a.bitmap, ck);
       else
         st = emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, a.bitmap, ck);
       if (st) return st;
       if (!ck.complete()) return TPD_ERROR_INTERNAL;
-      if (i == 0 && prune)
-        for (uint64_t w = 0; w < words; ++w) tiles[w] &= live[w];
     }
   }
   for (uint64_t i = 0; i < count; ++i) {

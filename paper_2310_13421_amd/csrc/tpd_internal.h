@@ -37,7 +37,15 @@ struct SweepArgs {
   int bm_xbits;      // x bits of the first sweep (bit index = (td << bm_xbits) | x_hi)
   int herm;          // 1: Hermitian input, two-sweep schedule
   const uint32_t* req;  // partial decomposition: bit per d-group td, tiles of unset groups are skipped (null: all)
-  uint64_t ntiles;
+  // partial decomposition, work list instead of all tiles (null: all):
+  // list_shift > 0: list[g] are d-groups, tile t is (xf = t / count, group
+  // t mod count), count << list_shift tiles; list_shift = 0: list[t] are
+  // second-sweep tiles as bitmap bits (td << bm_xbits) | xf.  count =
+  // list_count[0], written by an earlier kernel.
+  const uint32_t* list;
+  const uint32_t* list_count;
+  int list_shift;
+  uint64_t ntiles;  // with a list: the most tiles it can hold
 };
 
 // Batched work item: `nmat` matrices of the same n starting at `mat0`
@@ -71,6 +79,8 @@ hipError_t launch_popcount(const uint32_t* p, uint64_t words, unsigned long long
 hipError_t launch_mark_requests(const uint64_t* req, uint64_t count, int n, int n1, int db, uint32_t* req_groups,
                                 uint32_t* req_tiles, hipStream_t st);
 hipError_t launch_and_u32(uint32_t* dst, const uint32_t* src, uint64_t words, hipStream_t st);
+hipError_t launch_bits_to_list(const uint32_t* bits, uint64_t words, uint32_t* list, uint32_t* count,
+                               hipStream_t st);
 hipError_t launch_gather(Dtype dt, const void* coeffs, int n, bool matrix_layout, const uint64_t* req,
                          uint64_t count, void* values, hipStream_t st);
 constexpr uint32_t kCompactChunk = 4096;  // elements per compaction workgroup (256 threads x 16)

@@ -33,6 +33,23 @@ __global__ void k_and_u32(uint32_t* __restrict__ dst, const uint32_t* __restrict
     dst[i] &= src[i];
 }
 
+// indices of the set bits of a bitmap, appended in any order; count must
+// start at zero
+__global__ void k_bits_to_list(const uint32_t* __restrict__ bits, uint64_t words, uint32_t* __restrict__ list,
+                               uint32_t* count) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t w = bits[i];
+    if (!w) continue;
+    uint32_t pos = atomicAdd(count, (uint32_t)__popc(w));
+    while (w) {
+      const int b = __builtin_ctz(w);
+      list[pos++] = (uint32_t)(i * 32 + b);
+      w &= w - 1;
+    }
+  }
+}
+
 template <class S>
 __global__ void k_gather(const Cx<S>* __restrict__ c, int n, int matrix_layout, const uint64_t* __restrict__ req,
                          uint64_t count, Cx<S>* __restrict__ values) {
@@ -68,6 +85,13 @@ hipError_t launch_mark_requests(const uint64_t* req, uint64_t count, int n, int 
 hipError_t launch_and_u32(uint32_t* dst, const uint32_t* src, uint64_t words, hipStream_t st) {
   if (words == 0) return hipSuccess;
   hipLaunchKernelGGL(k_and_u32, dim3(grid_for(words, 256, 4096)), dim3(256), 0, st, dst, src, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_bits_to_list(const uint32_t* bits, uint64_t words, uint32_t* list, uint32_t* count,
+                               hipStream_t st) {
+  if (words == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bits_to_list, dim3(grid_for(words, 256, 4096)), dim3(256), 0, st, bits, words, list, count);
   return hipGetLastError();
 }
 

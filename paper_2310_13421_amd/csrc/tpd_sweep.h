@@ -68,8 +68,18 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   struct Tile {
     uint64_t td, xf, xfix, hm;
   };
+  // tiles of this launch: all, or the entries of a work list
+  const uint64_t lcount = a.list ? (uint64_t)uniform_word(a.list_count, 0) : 0;
+  const uint64_t ntiles = a.list ? lcount << a.list_shift : a.ntiles;
   auto decode = [&](uint64_t tile, Tile& t) -> bool {
-    if (a.herm && xlo) {
+    if (a.list && a.list_shift) {
+      t.xf = tile / lcount;
+      t.td = uniform_word(a.list, tile - t.xf * lcount);
+    } else if (a.list) {  // second-sweep bitmap bit (td << bm_xbits) | xf
+      const uint64_t lt = uniform_word(a.list, tile);
+      t.td = lt >> a.bm_xbits;
+      t.xf = lt & (((uint64_t)1 << a.bm_xbits) - 1);
+    } else if (a.herm && xlo) {
       herm_first_tile(tile, xlo, G::DB, a.nfix_d, &t.xf, &t.td);
     } else {
       t.td = tile & tdmask;
@@ -96,7 +106,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
     return true;
   };
   auto next_tile = [&](uint64_t tile, Tile& t) -> uint64_t {
-    while (tile < a.ntiles && !decode(tile, t)) tile += gridDim.x;
+    while (tile < ntiles && !decode(tile, t)) tile += gridDim.x;
     return tile;
   };
   auto load = [&](const Tile& t, Cx<S>* v) {
@@ -216,23 +226,23 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   if constexpr (PF) {
     Tile cur, nxt;
     const uint64_t first = next_tile(blockIdx.x, cur);
-    if (first >= a.ntiles) return;
+    if (first >= ntiles) return;
     Cx<S> v[G::E], pf[G::E];
     load(cur, v);
     uint64_t next = next_tile(first + gridDim.x, nxt);
-    if (next < a.ntiles) load(nxt, pf);
+    if (next < ntiles) load(nxt, pf);
     process(cur, v);
-    while (next < a.ntiles) {
+    while (next < ntiles) {
 #pragma unroll
       for (int j = 0; j < G::E; ++j) v[j] = pf[j];
       cur = nxt;
       next = next_tile(next + gridDim.x, nxt);
-      if (next < a.ntiles) load(nxt, pf);
+      if (next < ntiles) load(nxt, pf);
       process(cur, v);
     }
   } else {
     Tile cur;
-    for (uint64_t tile = next_tile(blockIdx.x, cur); tile < a.ntiles; tile = next_tile(tile + gridDim.x, cur)) {
+    for (uint64_t tile = next_tile(blockIdx.x, cur); tile < ntiles; tile = next_tile(tile + gridDim.x, cur)) {
       Cx<S> v[G::E];
       load(cur, v);
       process(cur, v);
