@@ -179,48 +179,54 @@ __global__ void __launch_bounds__(kCT) k_compact_write(const Cx<S>* __restrict__
                                                        uint64_t* __restrict__ q_out, Cx<S>* __restrict__ w_out) {
   __shared__ uint32_t cnt[kCJ * (kCT / 64)];
   __shared__ uint32_t excl[kCJ * (kCT / 64)];
-  const uint64_t chunk = blockIdx.x;
-  if (counts[chunk] == 0) return;  // uniform per workgroup
-  const uint64_t off0 = offsets[chunk];
-  if (off0 >= capacity) return;
-  const uint64_t base = chunk * kCompactChunk;
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   constexpr int NW = kCT / 64;
+  const uint64_t nchunks = (elems + kCompactChunk - 1) / kCompactChunk;
+  // persistent grid over the chunks: chunks without kept elements cost one
+  // scalar read each, not a workgroup launch.  LDS reuse across iterations is
+  // ordered by the two barriers of each iteration (cnt is rewritten only after
+  // wave 0 has read it, excl only after every wave has read it).
+  for (uint64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    if (counts[chunk] == 0) continue;  // uniform per workgroup
+    const uint64_t off0 = offsets[chunk];
+    if (off0 >= capacity) continue;
+    const uint64_t base = chunk * kCompactChunk;
 
-  Cx<S> v[kCJ];
-  uint64_t m[kCJ];
+    Cx<S> v[kCJ];
+    uint64_t m[kCJ];
 #pragma unroll
-  for (int j = 0; j < kCJ; ++j) {
-    const uint64_t i = base + (uint64_t)j * kCT + tid;
-    bool k = false;
-    if (i < elems) {
-      v[j] = c[i];
-      k = keep_coeff<S>(v[j].re, v[j].im, tol);
+    for (int j = 0; j < kCJ; ++j) {
+      const uint64_t i = base + (uint64_t)j * kCT + tid;
+      bool k = false;
+      if (i < elems) {
+        v[j] = c[i];
+        k = keep_coeff<S>(v[j].re, v[j].im, tol);
+      }
+      m[j] = __ballot(k);
+      if (lane == 0) cnt[j * NW + wave] = (uint32_t)__popcll(m[j]);
     }
-    m[j] = __ballot(k);
-    if (lane == 0) cnt[j * NW + wave] = (uint32_t)__popcll(m[j]);
-  }
-  __syncthreads();
-  if (wave == 0) {
-    // exclusive scan of the kCJ * NW = 64 (j, wave) counts in storage order
-    const uint32_t x = cnt[lane];
-    uint32_t inc = x;
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(inc, o);
-      if ((int)lane >= o) inc += y;
+    __syncthreads();
+    if (wave == 0) {
+      // exclusive scan of the kCJ * NW = 64 (j, wave) counts in storage order
+      const uint32_t x = cnt[lane];
+      uint32_t inc = x;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if ((int)lane >= o) inc += y;
+      }
+      excl[lane] = inc - x;
     }
-    excl[lane] = inc - x;
-  }
-  __syncthreads();
-  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    __syncthreads();
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
 #pragma unroll
-  for (int j = 0; j < kCJ; ++j) {
-    if (!((m[j] >> lane) & 1ull)) continue;
-    const uint64_t pos = off0 + excl[j * NW + wave] + (uint64_t)__popcll(m[j] & below);
-    if (pos >= capacity) continue;
-    const uint64_t i = base + (uint64_t)j * kCT + tid;
-    q_out[pos] = q_of_storage(i, n, matrix_layout != 0);
-    w_out[pos] = v[j];
+    for (int j = 0; j < kCJ; ++j) {
+      if (!((m[j] >> lane) & 1ull)) continue;
+      const uint64_t pos = off0 + excl[j * NW + wave] + (uint64_t)__popcll(m[j] & below);
+      if (pos >= capacity) continue;
+      const uint64_t i = base + (uint64_t)j * kCT + tid;
+      q_out[pos] = q_of_storage(i, n, matrix_layout != 0);
+      w_out[pos] = v[j];
+    }
   }
 }
 
@@ -249,12 +255,15 @@ hipError_t launch_compact_write(Dtype dt, const void* coeffs, int n, bool matrix
   const uint64_t elems = (uint64_t)1 << (2 * n);
   const uint64_t nchunks = (elems + kCompactChunk - 1) / kCompactChunk;
   if (capacity == 0 || nchunks == 0) return hipSuccess;
+  // a few workgroups per CU loop over the chunks (most are empty for sparse
+  // spectra); 2048 covers 256 CUs with eight each
+  const unsigned grid = (unsigned)std::min<uint64_t>(nchunks, 2048);
   if (dt == DT_C128)
-    hipLaunchKernelGGL(k_compact_write<double>, dim3((unsigned)nchunks), dim3(kCT), 0, st,
+    hipLaunchKernelGGL(k_compact_write<double>, dim3(grid), dim3(kCT), 0, st,
                        (const Cx<double>*)coeffs, elems, n, (int)matrix_layout, tol, counts, offsets, capacity,
                        q_out, (Cx<double>*)w_out);
   else
-    hipLaunchKernelGGL(k_compact_write<float>, dim3((unsigned)nchunks), dim3(kCT), 0, st,
+    hipLaunchKernelGGL(k_compact_write<float>, dim3(grid), dim3(kCT), 0, st,
                        (const Cx<float>*)coeffs, elems, n, (int)matrix_layout, (float)tol, counts, offsets,
                        capacity, q_out, (Cx<float>*)w_out);
   return hipGetLastError();
