@@ -369,6 +369,42 @@ def test_config4_n16_sampled_strings_parseval_both_precisions():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("dtype,dbs", [(torch.complex128, (3, 4, 5)), (torch.complex64, (4, 5, 6))])
+def test_n16_in_place_every_tuning_candidate(dtype, dbs):
+    # the headline launch configuration at full size: n = 16 Hermitian, in
+    # place with the matrix layout, pruning on, for every schedule the
+    # autotuner may choose (tile width x persistent grid), in the general
+    # and the Hermitian mode; sampled positions against the definition, and
+    # every candidate bitwise equal to the default schedule there
+    n = 16
+    torch.cuda.empty_cache()
+    A = W.gaussian_device(n, seed=5, dtype=dtype, hermitian=True)
+    a_max = float(torch.view_as_real(A).abs().max())
+    qs = W.sampled_strings(n, 2000, seed=16)
+    bf = sampled_oracle(A, n, qs)
+    h, l = deinterleave(qs.astype(np.int64))
+    hb = torch.from_numpy(h).to(DEV)
+    lb = torch.from_numpy(l).to(DEV)
+    tol = n * U64 * a_max if dtype == torch.complex128 else (n + 1) * U32 * a_max
+    B = torch.empty_like(A)
+    B.copy_(A)
+    tpd.decompose(B, B.view(-1), layout="matrix")
+    ref = B[hb, lb].cpu().numpy()
+    assert cerr(ref, bf) <= tol
+    for herm in (False, True):
+        for db in dbs:
+            for g in (0, 1, 2, 4):
+                B.copy_(A)
+                tpd.decompose_tuned(B, B.view(-1), db=db, grid_per_cu=g, layout="matrix", hermitian=herm)
+                got = B[hb, lb].cpu().numpy()
+                if herm:
+                    assert np.array_equal(got.real, ref.real) and np.all(got.imag == 0), (db, g)
+                else:
+                    assert same_bits(got, ref), (db, g)
+    del A, B
+    torch.cuda.empty_cache()
+
+
 # ----------------------------------------------------------------------------
 # edge cases, determinism, poison fill, errors
 # ----------------------------------------------------------------------------
