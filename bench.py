@@ -282,7 +282,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=16)
-    ap.add_argument("--extras", default="synth,partial,hermitian,outofplace,fp32,n14dense,n14,batched",
+    ap.add_argument("--extras", default="synth,partial,hermitian,outofplace,real,fp32,n14dense,n14,batched",
                     help="comma list of synth,partial,hermitian,outofplace,fp32,n14dense,n14,batched, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -487,6 +487,19 @@ def main():
         r, o = single_matrix_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16)
         result["out_of_place_canonical_c128"] = r
         del o
+        torch.cuda.empty_cache()
+    if "real" in extras:
+        log("extra: real input (float64, real-coded weights): Re A, a real-symmetric matrix, in place")
+        Ar = A.real.contiguous()
+        d = {}
+        for name, herm in (("general", False), ("symmetric_mode", True)):
+            r, B = inplace_run(tpd, torch, Ar, n, tpd.TPD_R64, args.steps, args.warmup, 8, hermitian=herm)
+            r["speedup_vs_c128_general"] = main_res["ms_per_step"] / r["ms_per_step"]
+            d[name] = r
+            del B
+            torch.cuda.empty_cache()
+        result["real_r64"] = d
+        del Ar
         torch.cuda.empty_cache()
     if "fp32" in extras:
         log("extra: complex64 (round-to-nearest copy of the same matrix), in place")

@@ -45,7 +45,8 @@ void logf(const char* fmt, ...) {
   va_end(ap);
 }
 
-size_t elem_bytes(Dtype dt) { return dt == DT_C128 ? 16 : 8; }
+size_t elem_bytes(Dtype dt) { return dt == DT_C128 ? 16 : 8; }  // C64 and R64: 8
+const char* dtype_name(Dtype dt) { return dt == DT_C128 ? "c128" : dt == DT_C64 ? "c64" : "r64"; }
 
 // ---------------------------------------------------------------------------
 // schedule
@@ -89,7 +90,7 @@ std::map<TuneKey, Tuned> g_tuned;  // n = -1: batched kernel grid per dtype
 bool g_tune_loaded = false;
 std::atomic<int> g_cus{0};
 
-int default_db(Dtype dt, int n2) { return (dt == DT_C64 && n2 >= 5) ? 5 : 4; }
+int default_db(Dtype dt, int n2) { return (dt != DT_C128 && n2 >= 5) ? 5 : 4; }  // 8-byte elements: 5
 
 void load_tune_cache();
 
@@ -307,7 +308,7 @@ std::string describe(const Schedule& s) {
   std::snprintf(buf, sizeof buf,
                 "{\"n\":%d,\"dtype\":\"%s\",\"layout\":\"%s\",\"in_place\":%s,\"prune\":%s,"
                 "\"hermitian\":%s,\"elements\":%llu,\"algorithmic_bytes\":%llu,\"bitmap_words\":%llu,\"sweeps\":[",
-                s.n, s.dt == DT_C128 ? "c128" : "c64", s.matrix_layout ? "matrix" : "canonical",
+                s.n, dtype_name(s.dt), s.matrix_layout ? "matrix" : "canonical",
                 s.in_place ? "true" : "false", s.prune ? "true" : "false",
                 (s.nsweep == 2 && s.sw[0].herm) ? "true" : "false", (unsigned long long)count,
                 (unsigned long long)(2 * count * eb), (unsigned long long)s.bitmap_words);
@@ -339,10 +340,18 @@ tpd_status_t copy_out(const std::string& s, char* buf, size_t len) {
 // ---------------------------------------------------------------------------
 // validation helpers
 // ---------------------------------------------------------------------------
+// complex dtypes only (the entry points without a real-input path)
 tpd_status_t check_dtype_flags(int dtype, unsigned flags) {
+  if (dtype == TPD_R64) return TPD_ERROR_UNSUPPORTED;
   if (dtype != TPD_C128 && dtype != TPD_C64) return TPD_ERROR_INVALID_VALUE;
   if (flags & ~TPD_FLAGS_ALL) return TPD_ERROR_INVALID_VALUE;
   return TPD_SUCCESS;
+}
+
+// single-matrix decomposition: complex dtypes and the real input
+tpd_status_t check_dtype_flags_single(int dtype, unsigned flags) {
+  if (dtype == TPD_R64) return (flags & ~TPD_FLAGS_ALL) ? TPD_ERROR_INVALID_VALUE : TPD_SUCCESS;
+  return check_dtype_flags(dtype, flags);
 }
 
 tpd_status_t check_buffers(const void* A, void* C, int n, Dtype dt) {
@@ -745,7 +754,7 @@ struct tpd_plan_s {
 extern "C" {
 
 int tpd_max_qubits(tpd_dtype_t dtype) {
-  if (dtype != TPD_C128 && dtype != TPD_C64) return -1;
+  if (dtype != TPD_C128 && dtype != TPD_C64 && dtype != TPD_R64) return -1;
   return kMaxQubits;
 }
 
@@ -790,7 +799,7 @@ int tpd_string_from_index(uint64_t q, int n, char* buf, size_t len) {
 }
 
 tpd_status_t tpd_schedule_describe(int n, tpd_dtype_t dtype, unsigned flags, int in_place, char* buf, size_t len) {
-  tpd_status_t st = check_dtype_flags(dtype, flags);
+  tpd_status_t st = check_dtype_flags_single(dtype, flags);
   if (st) return st;
   Schedule s;
   st = make_schedule(n, (Dtype)dtype, flags, in_place != 0, &s);
@@ -800,7 +809,7 @@ tpd_status_t tpd_schedule_describe(int n, tpd_dtype_t dtype, unsigned flags, int
 
 tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                               tpd_stream_t stream) {
-  tpd_status_t st = check_dtype_flags(dtype, flags);
+  tpd_status_t st = check_dtype_flags_single(dtype, flags);
   if (st) return st;
   if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
   const Dtype dt = (Dtype)dtype;
@@ -955,7 +964,7 @@ tpd_status_t tpd_release_workspace(void) {
 tpd_status_t tpd_plan_create(int n, tpd_dtype_t dtype, unsigned flags, int in_place, tpd_plan_t* plan) {
   if (!plan) return TPD_ERROR_INVALID_VALUE;
   *plan = nullptr;
-  tpd_status_t st = check_dtype_flags(dtype, flags);
+  tpd_status_t st = check_dtype_flags_single(dtype, flags);
   if (st) return st;
   Schedule s;
   st = make_schedule(n, (Dtype)dtype, flags, in_place != 0, &s);
@@ -1261,7 +1270,7 @@ double median3(std::vector<float>& v) {
 extern "C" tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype,
                                                   unsigned flags, int db, int r, int grid_per_cu,
                                                   tpd_stream_t stream) {
-  tpd_status_t st = check_dtype_flags(dtype, flags);
+  tpd_status_t st = check_dtype_flags_single(dtype, flags);
   if (st) return st;
   if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
   if (grid_per_cu < 0 || grid_per_cu > 64) return TPD_ERROR_INVALID_VALUE;
@@ -1292,7 +1301,7 @@ extern "C" tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* co
 
 extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                                      tpd_stream_t stream, char* report, size_t len) {
-  tpd_status_t st = check_dtype_flags(dtype, flags);
+  tpd_status_t st = check_dtype_flags_single(dtype, flags);
   if (st) return st;
   if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
   const Dtype dt = (Dtype)dtype;
@@ -1348,7 +1357,7 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
   }
   double best = 1e300;
   Tuned best_t = cands[0];
-  rep = "{\"tuned\":true,\"n\":" + std::to_string(n) + ",\"dtype\":\"" + (dt == DT_C128 ? "c128" : "c64") +
+  rep = "{\"tuned\":true,\"n\":" + std::to_string(n) + ",\"dtype\":\"" + dtype_name(dt) +
         "\",\"candidates\":[";
   bool first = true;
   for (const Tuned& t : cands) {

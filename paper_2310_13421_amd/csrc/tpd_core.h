@@ -225,6 +225,50 @@ TPD_HD void butterfly(Cx<S>& u, Cx<S>& v, bool tw) {
   v.im = tw ? dr : di;
 }
 
+// Real input.  Every value the transform produces from a real matrix is a
+// real number times i^k, k = the number of Y letters among the levels done
+// so far (a Y output is i times a difference; all other outputs keep the
+// phase of their pair, and both members of a pair share it).  A real-coded
+// element holds that real factor, so a level is (u, v) -> ((u+v)/2, (u-v)/2)
+// on 8 or 4 bytes per element, with the same roundings as the complex
+// butterfly applied to the nonzero component.
+template <class S>
+struct alignas(sizeof(S)) Rl {
+  S re;
+};
+template <class S>
+TPD_HD void butterfly(Rl<S>& u, Rl<S>& v, bool) {
+  const S half = (S)0.5;
+  const S s = (u.re + v.re) * half, d = (u.re - v.re) * half;
+  u.re = s;
+  v.re = d;
+}
+
+// Element type of a kernel instantiation: Cx<S> for complex data, Rl<S> for
+// the tag Real<S> (real input, real-coded output).
+template <class S>
+struct Real {};
+template <class S>
+struct Elem {
+  using type = Cx<S>;
+  using scalar = S;
+  static constexpr bool real = false;
+};
+template <class S>
+struct Elem<Real<S>> {
+  using type = Rl<S>;
+  using scalar = S;
+  static constexpr bool real = true;
+};
+template <class S>
+TPD_HD bool nonzero(const Cx<S>& z) {
+  return z.re != (S)0 || z.im != (S)0;  // NaN counts as nonzero
+}
+template <class S>
+TPD_HD bool nonzero(const Rl<S>& z) {
+  return z.re != (S)0;
+}
+
 // inverse of butterfly(): (s, t) -> (s + t*conj(w), s - t*conj(w)), w = tw ? i : 1
 // (synthesis A = sum_t w_t sigma^t, no scaling)
 template <class S>
@@ -241,8 +285,8 @@ TPD_HD void butterfly_inv(Cx<S>& u, Cx<S>& v, bool tw) {
 // d coordinate of register 0 (twiddle bits); x bit of transform slot s is
 // xlo + (reg bit - DB).  Registers whose d differs (dl passengers) take
 // their own twiddle bit.
-template <class G, class S, bool INV = false>
-TPD_HD void phase_butterflies(const Roles& r, int p, Cx<S>* v, uint64_t d_thread, int xlo) {
+template <class G, class S, bool INV = false, class E>
+TPD_HD void phase_butterflies(const Roles& r, int p, E* v, uint64_t d_thread, int xlo) {
   for (int s = 0; s < r.nxf[p]; ++s) {
     const int xbit = xlo + (r.reg[p][s] - G::DB);
 #pragma unroll

@@ -8,7 +8,7 @@
 
 namespace tpd {
 
-enum Dtype : int { DT_C128 = 0, DT_C64 = 1 };
+enum Dtype : int { DT_C128 = 0, DT_C64 = 1, DT_R64 = 2, DT_R32 = 3 };
 
 // One HBM sweep over a single matrix: transform x bits [xlo, xlo+xb) for
 // every d, tiles of 2^(xb+db) elements.
@@ -179,7 +179,7 @@ __host__ __device__ inline bool keep_coeff(S re, S im, S tol) {
 // workgroup; gfx950 gives a workgroup up to 160 KiB, tiles use <= 128 KiB
 template <class S>
 constexpr bool shape_fits(int xb, int db) {
-  return ((size_t)sizeof(Cx<S>) << (xb + db)) <= 131072;
+  return ((size_t)sizeof(typename Elem<S>::type) << (xb + db)) <= 131072;
 }
 
 // Batched tile geometry (shared with the host emulator and planner): tiles

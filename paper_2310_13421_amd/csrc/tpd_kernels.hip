@@ -171,20 +171,33 @@ hipError_t launch_batched_perm(Dtype dt, const void* const* in_ptrs, void* const
 }
 
 // ---------------------------------------------------------------------------
-// sweep dispatch (instantiations live in tpd_sweep_c128.hip / tpd_sweep_c64.hip)
+// sweep dispatch (instantiations live in tpd_sweep_c128.hip, tpd_sweep_c64.hip
+// and tpd_sweep_r64.hip)
 // ---------------------------------------------------------------------------
 bool sweep_supported_c128(const SweepDesc& s);
 bool sweep_supported_c64(const SweepDesc& s);
+bool sweep_supported_r64(const SweepDesc& s);
 hipError_t launch_sweep_c128(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
 hipError_t launch_sweep_c64(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
+hipError_t launch_sweep_r64(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
 
 bool sweep_supported(Dtype dt, const SweepDesc& s) {
-  return dt == DT_C128 ? sweep_supported_c128(s) : sweep_supported_c64(s);
+  switch (dt) {
+    case DT_C128: return sweep_supported_c128(s);
+    case DT_C64: return sweep_supported_c64(s);
+    case DT_R64: return sweep_supported_r64(s);
+    default: return false;
+  }
 }
 
 hipError_t launch_sweep(Dtype dt, const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
   if (a.ntiles == 0) return hipSuccess;
-  return dt == DT_C128 ? launch_sweep_c128(s, a, st) : launch_sweep_c64(s, a, st);
+  switch (dt) {
+    case DT_C128: return launch_sweep_c128(s, a, st);
+    case DT_C64: return launch_sweep_c64(s, a, st);
+    case DT_R64: return launch_sweep_r64(s, a, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace tpd

@@ -28,18 +28,20 @@ __device__ inline uint32_t uniform_word(const uint32_t* p, uint64_t w) {
 
 template <class S, class G, int INL, int OUTL, bool INV = false>
 __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
+  using E = typename Elem<S>::type;  // Cx<double|float>, or Rl<..> for real input
+  constexpr bool REAL = Elem<S>::real;
   static constexpr Roles RL = make_roles<G>();
   constexpr int P = G::NPH;
   constexpr int LAST = P - 1;
   constexpr uint32_t DM = (1u << G::DB) - 1;
   constexpr uint32_t XM = (1u << G::XB) - 1;
   constexpr int NBW = (1 << G::XB) >= 32 ? (1 << G::XB) / 32 : 1;
-  __shared__ Cx<S> lds[1 << G::B];
+  __shared__ E lds[1 << G::B];
   __shared__ uint32_t bits[NBW];
 
   const uint32_t tid = threadIdx.x;
-  const Cx<S>* __restrict__ in = (const Cx<S>*)a.in;
-  Cx<S>* __restrict__ out = (Cx<S>*)a.out;
+  const E* __restrict__ in = (const E*)a.in;
+  E* __restrict__ out = (E*)a.out;
   const int n = a.n, xlo = a.xlo, db = a.db;
   const uint64_t tdmask = ((uint64_t)1 << a.nfix_d) - 1;
 
@@ -109,7 +111,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
     while (tile < ntiles && !decode(tile, t)) tile += gridDim.x;
     return tile;
   };
-  auto load = [&](const Tile& t, Cx<S>* v) {
+  auto load = [&](const Tile& t, E* v) {
     const uint64_t x = t.xfix | ((uint64_t)((eb0 >> G::DB) & XM) << xlo);
     const uint64_t d = (t.td << G::DB) | (eb0 & DM);
     const uint64_t base = layout_addr<INL>(x, d, n, db);
@@ -120,13 +122,13 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
       for (int s = 0; s < G::R; ++s)
         if ((j >> s) & 1) ad ^= din[s];
       const uint32_t e = eb0 | elem_reg<G>(RL, 0, j);
-      if (t.hm && !xlo && (((uint64_t)((e >> G::DB) & XM)) & t.hm)) v[j] = Cx<S>{(S)0, (S)0};
+      if (t.hm && !xlo && (((uint64_t)((e >> G::DB) & XM)) & t.hm)) v[j] = E{};
       else v[j] = in[ad];
     }
   };
 
   // Transform one loaded tile and store it.
-  auto process = [&](const Tile& t, Cx<S>* v) {
+  auto process = [&](const Tile& t, E* v) {
     const uint64_t td = t.td, hm = t.hm, xfix = t.xfix;
     if (a.bitmap_mode == 1 && tid < NBW) bits[tid] = 0;
 
@@ -140,7 +142,15 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
         if (((uint64_t)((e >> G::DB) & XM)) & hm) continue;
         const uint32_t dlo = (uint32_t)(dlo_hi | (e & DM));
         lds[e] = v[j];
-        lds[e ^ (dlo << G::DB)] = Cx<S>{v[j].re, -v[j].im};
+        if constexpr (REAL) {
+          // conj(i^k r) = i^k (-1)^k r, k = the Y letters of the first
+          // sweep's levels (x and d bits from XB up), the same at both rows
+          const uint64_t x = xfix | ((e >> G::DB) & XM), d = (td << G::DB) | (e & DM);
+          const bool neg = __popcll((x & d) >> G::XB) & 1;
+          lds[e ^ (dlo << G::DB)] = E{neg ? -v[j].re : v[j].re};
+        } else {
+          lds[e ^ (dlo << G::DB)] = Cx<S>{v[j].re, -v[j].im};
+        }
       }
       __syncthreads();
 #pragma unroll
@@ -171,7 +181,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
       if (P == 1) __syncthreads();
 #pragma unroll
       for (int j = 0; j < G::E; ++j) {
-        const bool nz = (v[j].re != (S)0) || (v[j].im != (S)0);
+        const bool nz = nonzero(v[j]);
         const uint64_t m = __ballot(nz);
         if ((lane & (gsz - 1)) == 0 && ((m >> lane) & gmask)) {
           const uint32_t xl = ((ebl | elem_reg<G>(RL, LAST, j)) >> G::DB) & XM;
@@ -209,7 +219,18 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
 #pragma unroll
         for (int s = 0; s < G::R; ++s)
           if ((j >> s) & 1) ad ^= dout[s];
-        if (real_out) v[j].im = (S)0;
+        if constexpr (REAL) {
+          // last sweep: the weight is i^y r (y = Y letters = popcount(x & d));
+          // store its nonzero component, Re w for even y and Im w for odd y,
+          // i.e. r negated when y mod 4 is 2 or 3
+          if (!xlo) {
+            const uint32_t e = REMAP ? (ebo | elem_reg_st<G>(RL, j)) : (ebl | elem_reg<G>(RL, LAST, j));
+            const uint64_t xe = xfix | ((uint64_t)((e >> G::DB) & XM)), de = (td << G::DB) | (e & DM);
+            if ((__popcll(xe & de) >> 1) & 1) v[j].re = -v[j].re;
+          }
+        } else {
+          if (real_out) v[j].im = (typename Elem<S>::scalar)0;
+        }
         out[ad] = v[j];
       }
     }
@@ -227,7 +248,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
     Tile cur, nxt;
     const uint64_t first = next_tile(blockIdx.x, cur);
     if (first >= ntiles) return;
-    Cx<S> v[G::E], pf[G::E];
+    E v[G::E], pf[G::E];
     load(cur, v);
     uint64_t next = next_tile(first + gridDim.x, nxt);
     if (next < ntiles) load(nxt, pf);
@@ -243,7 +264,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   } else {
     Tile cur;
     for (uint64_t tile = next_tile(blockIdx.x, cur); tile < ntiles; tile = next_tile(tile + gridDim.x, cur)) {
-      Cx<S> v[G::E];
+      E v[G::E];
       load(cur, v);
       process(cur, v);
     }

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libtpd.so")
 
 TPD_C128 = 0
 TPD_C64 = 1
+TPD_R64 = 2
 FLAG_NO_PRUNE = 0x1
 FLAG_LAYOUT_MATRIX = 0x2
 FLAG_TIMING = 0x4
@@ -143,6 +144,8 @@ def schedule(n: int, dtype: int = TPD_C128, flags: int = 0, in_place: bool = Fal
 
 
 def _np_dtype(dtype: int):
+    if dtype not in (TPD_C128, TPD_C64):
+        raise TPDError(2, "the host replays cover the complex dtypes only")
     return np.complex128 if dtype == TPD_C128 else np.complex64
 
 
@@ -234,6 +237,8 @@ def _dtype_code(t) -> int:
         return TPD_C128
     if t.dtype == torch.complex64:
         return TPD_C64
+    if t.dtype == torch.float64:
+        return TPD_R64
     raise TypeError(f"unsupported dtype {t.dtype}")
 
 
@@ -268,11 +273,14 @@ def _check_matrix(A):
 
 def decompose(A, out=None, *, layout: str = "canonical", prune: bool = True, order_bottom: bool = False,
               hermitian: bool = False, stream=None):
-    """Pauli coefficients of A (2^n x 2^n complex64/complex128 CUDA tensor).
+    """Pauli coefficients of A (2^n x 2^n complex64/complex128 CUDA tensor,
+    or float64 for a real matrix).
 
     Returns a 1-D tensor of 4^n coefficients (canonical order: index
     q = sum_k t_k 4^(n-k)), or the 2^n x 2^n matrix-layout array.  `out` may
-    be A itself for an in-place call (see include/tpd.h)."""
+    be A itself for an in-place call (see include/tpd.h).  For float64 input
+    the values are real-coded: w_t = r_t for an even number of Y letters,
+    i r_t for an odd number."""
     torch = _torch()
     n = _check_matrix(A)
     dt = _dtype_code(A)

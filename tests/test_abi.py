@@ -34,6 +34,7 @@ def test_status_strings_and_limits():
         assert tpd.lib.tpd_status_string(code).decode() == name
     assert tpd.max_qubits(tpd.TPD_C128) == 16
     assert tpd.max_qubits(tpd.TPD_C64) == 16
+    assert tpd.max_qubits(tpd.TPD_R64) == 16
     assert tpd.lib.tpd_max_qubits(7) == -1
 
 
@@ -66,6 +67,10 @@ FAKE = 0x100000  # never dereferenced: validation fails or the device check stop
     ((FAKE, 4, FAKE + 16, 0, 0), 1),       # partial overlap
     ((FAKE, 17, FAKE * 64, 0, 0), 2),      # n too large
     ((FAKE, -1, FAKE * 4, 0, 0), 2),       # n negative
+    ((FAKE, 4, FAKE * 4 + 4, 2, 0), 1),    # misaligned real float64
+    ((FAKE, 4, FAKE + 8, 2, 0), 1),        # partial overlap, real (8-byte elements)
+    ((FAKE, 17, FAKE * 64, 2, 0), 2),      # n too large, real
+    ((FAKE, 10, FAKE, 2, 0), 2),           # real, in place canonical
     ((FAKE, 4, FAKE * 4, 5, 0), 1),        # bad dtype
     ((FAKE, 4, FAKE * 4, 0, 0x100), 1),    # unknown flag
     ((FAKE, 8, FAKE, 0, 0), 2),            # in place, canonical, n > 6
@@ -94,6 +99,20 @@ def test_partial_and_compact_validation():
     assert C(FAKE, 17, 0, 0, 0.0, FAKE * 2, FAKE * 4, 8, FAKE * 8, None) == 2           # n too large
 
 
+def test_real_input_only_where_supported():
+    # the real-input dtype has no batched, partial, compaction or synthesis path
+    ns = (ctypes.c_int * 2)(3, 8)
+    ptrs = (ctypes.c_void_p * 2)(FAKE, FAKE * 2)
+    outs = (ctypes.c_void_p * 2)(FAKE * 4, FAKE * 8)
+    R = tpd.TPD_R64
+    assert tpd.lib.tpd_decompose_batched(ptrs, ns, 2, outs, R, 0, None) == 2
+    assert tpd.lib.tpd_decompose_partial(FAKE, 4, FAKE * 4, FAKE * 8, 5, FAKE * 16, R, 0, None) == 2
+    assert tpd.lib.tpd_compact(FAKE, 4, R, 0, 0.0, FAKE * 2, FAKE * 4, 8, FAKE * 8, None) == 2
+    assert tpd.lib.tpd_synthesize_ex(FAKE, 4, FAKE * 4, R, 0, None) == 2
+    h = ctypes.c_void_p()
+    assert tpd.lib.tpd_plan_create_batched(ns, 2, R, 0, 0, ctypes.byref(h)) == 2
+
+
 def test_batched_validation():
     ns = (ctypes.c_int * 2)(3, 10)
     ptrs = (ctypes.c_void_p * 2)(FAKE, FAKE * 2)
@@ -119,7 +138,7 @@ def test_plan_validation():
 
 @pytest.mark.parametrize("n", range(0, 17))
 def test_schedule_shapes(n):
-    for dt in (tpd.TPD_C128, tpd.TPD_C64):
+    for dt in (tpd.TPD_C128, tpd.TPD_C64, tpd.TPD_R64):
         s = tpd.schedule(n, dt)
         es = 16 if dt == tpd.TPD_C128 else 8
         assert s["elements"] == 4 ** n

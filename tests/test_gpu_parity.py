@@ -406,6 +406,118 @@ def test_n16_in_place_every_tuning_candidate(dtype, dbs):
 
 
 # ----------------------------------------------------------------------------
+# real input (real-coded weights): w_t = r_t for even #Y, i r_t for odd #Y
+# ----------------------------------------------------------------------------
+def y_odd(q):
+    """True where the canonical index q has an odd number of Y (= 2) digits."""
+    q = np.asarray(q, np.int64)
+    par = np.zeros(q.shape, bool)
+    for b in range(20):
+        par ^= ((q >> (2 * b)) & 3) == 2
+    return par
+
+
+def real_coded(w, q):
+    """(nonzero component, the other component) of complex weights w at q."""
+    odd = y_odd(q)
+    return np.where(odd, w.imag, w.real), np.where(odd, w.real, w.imag)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 5, 7, 8, 9, 11, 12])
+def test_real_input_vs_algorithm_1(n):
+    A = W.real_gaussian(n, seed=2200 + n) if n else np.array([[1.25]])
+    ref = O.tpd_recursive(A.astype(np.complex128))
+    exp, other = real_coded(ref, np.arange(4 ** n))
+    assert np.all(other == 0)  # a real matrix: each weight real or imaginary
+    Ad = torch.from_numpy(A).to(DEV)
+    got = tpd.decompose(Ad)
+    assert got.dtype == torch.float64
+    # the complex path's nonzero component, value for value (== ignores the sign of zero)
+    assert np.array_equal(got.cpu().numpy(), exp)
+    assert np.array_equal(tpd.decompose(Ad, prune=False).cpu().numpy(), exp)
+    # matrix layout, in place
+    B = Ad.clone()
+    tpd.decompose(B, B.view(-1), layout="matrix")
+    assert np.array_equal(matrix_to_canonical(B.cpu().numpy().ravel(), n), exp)
+    if n >= 9:
+        out = torch.empty_like(got)
+        for db in [b for b in (4, 5, 6) if b <= n // 2]:  # tiles fit the second sweep's x bits
+            for g in (0, 1, 4):
+                out.fill_(float("nan"))
+                tpd.decompose_tuned(Ad, out, db=db, grid_per_cu=g)
+                assert np.array_equal(out.cpu().numpy(), exp), (db, g)
+
+
+@pytest.mark.parametrize("n", [9, 12, 13])
+def test_real_symmetric_hermitian_mode(n):
+    A = W.real_gaussian(n, seed=2300 + n, symmetric=True)
+    ref = O.tpd_recursive(A.astype(np.complex128))
+    q = np.arange(4 ** n)
+    exp, _ = real_coded(ref, q)
+    assert np.all(exp[y_odd(q)] == 0)  # odd-Y strings vanish for real-symmetric input
+    Ad = torch.from_numpy(A).to(DEV)
+    for layout in ("canonical", "matrix"):
+        got = tpd.decompose(Ad, hermitian=True, layout=layout).cpu().numpy().ravel()
+        if layout == "matrix":
+            got = matrix_to_canonical(got, n)
+        assert np.array_equal(got, exp), layout
+    B = Ad.clone()
+    tpd.decompose(B, B.view(-1), layout="matrix", hermitian=True)
+    assert np.array_equal(matrix_to_canonical(B.cpu().numpy().ravel(), n), exp)
+
+
+def test_real_tfim_pruning_and_exact_terms():
+    # the transverse-field Ising chain is real symmetric: 2k+1 live CMWs,
+    # and exactly its 2n-1 terms survive with their coefficients
+    n = 12
+    H = W.dense_from_terms_device(W.tfim_terms(n, 1.0, 0.5), n).real.contiguous()
+    plan = tpd.Plan(n, tpd.TPD_R64)
+    out = torch.empty(4 ** n, dtype=torch.float64, device=DEV)
+    plan.execute(H, out)
+    st = plan.prune_stats()
+    assert st["live_prefixes"] == 2 * st["prefix_level"] + 1
+    plan.close()
+    got = out.cpu().numpy()
+    expect = {}
+    for s_, c in W.tfim_terms(n, 1.0, 0.5):
+        expect[W.string_index(s_)] = c
+    nz = np.flatnonzero(got)
+    assert sorted(expect) == nz.tolist()
+    assert all(got[k] == v.real for k, v in expect.items())
+
+
+@pytest.mark.parametrize("hermitian", [False, True])
+def test_n16_real_in_place_every_tuning_candidate(hermitian):
+    # the real path at full size: n = 16 real symmetric float64 in place,
+    # every tile width and grid the autotuner may choose, sampled strings
+    # against the definition
+    n = 16
+    torch.cuda.empty_cache()
+    A = W.gaussian_device(n, seed=6, dtype=torch.float64, hermitian=True)
+    a_max = float(A.abs().max())
+    qs = W.sampled_strings(n, 2000, seed=26)
+    bf = sampled_oracle(A, n, qs)
+    exp, other = real_coded(bf, qs)
+    assert np.max(np.abs(other)) <= n * U64 * a_max
+    h, l = deinterleave(qs.astype(np.int64))
+    hb = torch.from_numpy(h).to(DEV)
+    lb = torch.from_numpy(l).to(DEV)
+    B = torch.empty_like(A)
+    B.copy_(A)
+    tpd.decompose(B, B.view(-1), layout="matrix")
+    ref = B[hb, lb].cpu().numpy()
+    assert np.max(np.abs(ref - exp)) <= n * U64 * a_max
+    assert np.all(ref[y_odd(qs)] == 0)
+    for db in (4, 5, 6):
+        for g in (0, 1, 2, 4):
+            B.copy_(A)
+            tpd.decompose_tuned(B, B.view(-1), db=db, grid_per_cu=g, layout="matrix", hermitian=hermitian)
+            assert np.array_equal(B[hb, lb].cpu().numpy(), ref), (db, g)
+    del A, B
+    torch.cuda.empty_cache()
+
+
+# ----------------------------------------------------------------------------
 # edge cases, determinism, poison fill, errors
 # ----------------------------------------------------------------------------
 def test_edge_cases():

@@ -42,6 +42,16 @@ _FLIPS = {"I": 0, "X": 1, "Y": 1, "Z": 0}
 # ----------------------------------------------------------------------------
 # dense random matrices (host)
 # ----------------------------------------------------------------------------
+def real_gaussian(n: int, seed: int, symmetric: bool = False) -> np.ndarray:
+    """Real matrix with N(0,1) entries; optionally A = (G + G^T)/2."""
+    rng = np.random.default_rng(seed)
+    d = 1 << n
+    G = rng.standard_normal((d, d))
+    if symmetric:
+        G = (G + G.T) / 2
+    return np.ascontiguousarray(G)
+
+
 def gaussian(n: int, seed: int, hermitian: bool = False) -> np.ndarray:
     """re, im i.i.d. N(0,1); optionally A = (G + G^H)/2."""
     rng = np.random.default_rng(seed)
@@ -222,7 +232,8 @@ def gaussian_device(n: int, seed: int, dtype=None, hermitian: bool = False, devi
                     block: int = 4096):
     """Complex Gaussian matrix (re, im ~ N(0,1)) generated on the GPU from a
     seeded torch generator, optionally made Hermitian in place blockwise as
-    (G + G^H)/2.  Memory: one matrix plus one block pair of scratch."""
+    (G + G^H)/2.  A real dtype gives a real N(0,1) matrix (symmetric when
+    hermitian=True).  Memory: one matrix plus one block pair of scratch."""
     import torch
 
     dtype = dtype or torch.complex128
@@ -230,7 +241,7 @@ def gaussian_device(n: int, seed: int, dtype=None, hermitian: bool = False, devi
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
     A = torch.empty((d, d), dtype=dtype, device=device)
-    Ar = torch.view_as_real(A)
+    Ar = torch.view_as_real(A) if A.is_complex() else A
     rows = max(1, min(d, (1 << 28) // max(1, d)))
     for r0 in range(0, d, rows):
         Ar[r0:r0 + rows].normal_(0.0, 1.0, generator=gen)
