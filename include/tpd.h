@@ -29,7 +29,7 @@
  * Memory, ownership, aliasing
  *   - All matrix and coefficient pointers are DEVICE pointers owned by the
  *     caller, on the current HIP device.  Alignment: 16 bytes (C128) or 8
- *     bytes (C64, R64); otherwise TPD_ERROR_INVALID_VALUE.
+ *     bytes (C64, R64) or 4 bytes (R32); otherwise TPD_ERROR_INVALID_VALUE.
  *   - Out of place (coeffs != A, no overlap): A is read and not modified.
  *   - In place (coeffs == A): supported with TPD_FLAG_LAYOUT_MATRIX for every
  *     n, and in the canonical layout only for n <= 6.  Partial overlap is
@@ -63,25 +63,26 @@ typedef void* tpd_stream_t; /* a hipStream_t; NULL = default stream */
 typedef enum {
   TPD_C128 = 0, /* interleaved binary64 pairs */
   TPD_C64 = 1,  /* interleaved binary32 pairs */
-  TPD_R64 = 2   /* real input: binary64 entries, real-coded weights (below) */
+  TPD_R64 = 2,  /* real input: binary64 entries, real-coded weights (below) */
+  TPD_R32 = 3   /* real input: binary32 entries, real-coded weights (below) */
 } tpd_dtype_t;
 
-/* TPD_R64: A is a real 2^n x 2^n matrix of binary64 (8 bytes per entry).
- * Each level of a real matrix yields values that are real numbers times a
- * power of i (only the Y output multiplies by i), so the transform runs in
- * real arithmetic on 8 bytes per element, half the traffic of TPD_C128.
- * The weight of a string with y Y letters is real for even y and imaginary
- * for odd y (sigma^t is real or imaginary as y is even or odd, and
- * w_t = 2^-n tr(sigma^t A)); coeffs holds 4^n binary64 values r_t with
+/* TPD_R64 / TPD_R32: A is a real 2^n x 2^n matrix of binary64 / binary32
+ * (8 / 4 bytes per entry).  Each level of a real matrix yields values that
+ * are real numbers times a power of i (only the Y output multiplies by i),
+ * so the transform runs in real arithmetic, half the traffic of TPD_C128 /
+ * TPD_C64.  The weight of a string with y Y letters is real for even y and
+ * imaginary for odd y (sigma^t is real or imaginary as y is even or odd, and
+ * w_t = 2^-n tr(sigma^t A)); coeffs holds 4^n values r_t of A's type with
  *     w_t = r_t (y even),    w_t = i r_t (y odd),
  * i.e. the weight's nonzero component, in the canonical or matrix layout.
  * Each r_t equals, up to the sign of zero, that component of the TPD_C128
- * result for the same matrix.  With TPD_FLAG_HERMITIAN (A real symmetric;
- * its odd-y weights vanish, as the footnote on real-symmetric input in
- * section "Existing algorithms" notes) the first sweep reads half the input.
- * Supported by tpd_decompose_ex, tpd_plan_create / tpd_plan_execute and
- * tpd_autotune; the batched, partial, compaction and synthesis entry points
- * return TPD_ERROR_UNSUPPORTED for it.                                   */
+ * (TPD_C64) result for the same matrix.  With TPD_FLAG_HERMITIAN (A real
+ * symmetric; its odd-y weights vanish, as the footnote on real-symmetric
+ * input in section "Existing algorithms" notes) the first sweep reads half
+ * the input.  Supported by tpd_decompose_ex, tpd_plan_create /
+ * tpd_plan_execute and tpd_autotune; the batched, partial, compaction and
+ * synthesis entry points return TPD_ERROR_UNSUPPORTED for it.            */
 
 typedef enum {
   TPD_SUCCESS = 0,
@@ -123,7 +124,7 @@ int tpd_max_qubits(tpd_dtype_t dtype);
  *   stream [in]  hipStream_t or NULL                                     */
 tpd_status_t tpd_decompose(const void* A, int n, void* coeffs, tpd_stream_t stream);
 
-/* Same, with the dtype (TPD_C128, TPD_C64, TPD_R64) and flags
+/* Same, with the dtype (TPD_C128, TPD_C64, TPD_R64, TPD_R32) and flags
  * (TPD_FLAG_NO_PRUNE, TPD_FLAG_LAYOUT_MATRIX, TPD_FLAG_ORDER_BOTTOM,
  * TPD_FLAG_HERMITIAN) chosen by the caller.  coeffs may equal A (in place)
  * for any n with TPD_FLAG_LAYOUT_MATRIX and for n <= 6 in the canonical

@@ -17,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libtpd.so")
 SOURCES = ["tpd_sweep_c128_db3.hip", "tpd_sweep_c128_db4.hip", "tpd_sweep_c128_db5.hip", "tpd_sweep_c64_db4.hip",
            "tpd_sweep_c64_db5.hip", "tpd_sweep_c64_db6.hip", "tpd_sweep_r64_db4.hip", "tpd_sweep_r64_db5.hip",
-           "tpd_sweep_r64_db6.hip", "tpd_sweep_c128.hip", "tpd_sweep_c64.hip", "tpd_sweep_r64.hip",
+           "tpd_sweep_r64_db6.hip", "tpd_sweep_r32_db4.hip", "tpd_sweep_r32_db5.hip", "tpd_sweep_r32_db6.hip",
+           "tpd_sweep_c128.hip", "tpd_sweep_c64.hip", "tpd_sweep_r64.hip", "tpd_sweep_r32.hip",
            "tpd_kernels.hip", "tpd_select.hip", "tpd_emulate.cpp", "tpd_api.cpp"]
 HEADERS = ["tpd_core.h", "tpd_internal.h", "tpd_sweep.h"]
 

@@ -45,8 +45,10 @@ void logf(const char* fmt, ...) {
   va_end(ap);
 }
 
-size_t elem_bytes(Dtype dt) { return dt == DT_C128 ? 16 : 8; }  // C64 and R64: 8
-const char* dtype_name(Dtype dt) { return dt == DT_C128 ? "c128" : dt == DT_C64 ? "c64" : "r64"; }
+size_t elem_bytes(Dtype dt) { return dt == DT_C128 ? 16 : dt == DT_R32 ? 4 : 8; }  // C64 and R64: 8
+const char* dtype_name(Dtype dt) {
+  return dt == DT_C128 ? "c128" : dt == DT_C64 ? "c64" : dt == DT_R64 ? "r64" : "r32";
+}
 
 // ---------------------------------------------------------------------------
 // schedule
@@ -90,7 +92,11 @@ std::map<TuneKey, Tuned> g_tuned;  // n = -1: batched kernel grid per dtype
 bool g_tune_loaded = false;
 std::atomic<int> g_cus{0};
 
-int default_db(Dtype dt, int n2) { return (dt != DT_C128 && n2 >= 5) ? 5 : 4; }  // 8-byte elements: 5
+// default tile width: runs of 256 B where the second sweep's x bits allow
+int default_db(Dtype dt, int n2) {
+  const int want = dt == DT_C128 ? 4 : dt == DT_R32 ? 6 : 5;
+  return want < n2 ? want : (n2 > 4 ? n2 : 4);
+}
 
 void load_tune_cache();
 
@@ -281,7 +287,7 @@ void load_tune_cache() {
     if (!(is >> tag >> arch >> cus >> dt >> n >> mat >> inp >> herm >> db >> r >> grid)) continue;
     if (tag != "tpd-tune-v2" || arch != "gfx950") continue;
     if (g_cus > 0 && cus != g_cus) continue;
-    if (dt < 0 || dt > 1 || n < -1 || n > kMaxQubits || r != 4 || grid < 0 || grid > 64) continue;
+    if (dt < 0 || dt > 3 || n < -1 || n > kMaxQubits || r != 4 || grid < 0 || grid > 64) continue;
     Tuned t;
     t.db = db;
     t.r = r;
@@ -342,7 +348,7 @@ tpd_status_t copy_out(const std::string& s, char* buf, size_t len) {
 // ---------------------------------------------------------------------------
 // complex dtypes only (the entry points without a real-input path)
 tpd_status_t check_dtype_flags(int dtype, unsigned flags) {
-  if (dtype == TPD_R64) return TPD_ERROR_UNSUPPORTED;
+  if (dtype == TPD_R64 || dtype == TPD_R32) return TPD_ERROR_UNSUPPORTED;
   if (dtype != TPD_C128 && dtype != TPD_C64) return TPD_ERROR_INVALID_VALUE;
   if (flags & ~TPD_FLAGS_ALL) return TPD_ERROR_INVALID_VALUE;
   return TPD_SUCCESS;
@@ -350,7 +356,7 @@ tpd_status_t check_dtype_flags(int dtype, unsigned flags) {
 
 // single-matrix decomposition: complex dtypes and the real input
 tpd_status_t check_dtype_flags_single(int dtype, unsigned flags) {
-  if (dtype == TPD_R64) return (flags & ~TPD_FLAGS_ALL) ? TPD_ERROR_INVALID_VALUE : TPD_SUCCESS;
+  if (dtype == TPD_R64 || dtype == TPD_R32) return (flags & ~TPD_FLAGS_ALL) ? TPD_ERROR_INVALID_VALUE : TPD_SUCCESS;
   return check_dtype_flags(dtype, flags);
 }
 
@@ -754,7 +760,7 @@ struct tpd_plan_s {
 extern "C" {
 
 int tpd_max_qubits(tpd_dtype_t dtype) {
-  if (dtype != TPD_C128 && dtype != TPD_C64 && dtype != TPD_R64) return -1;
+  if (dtype != TPD_C128 && dtype != TPD_C64 && dtype != TPD_R64 && dtype != TPD_R32) return -1;
   return kMaxQubits;
 }
 

@@ -171,21 +171,24 @@ hipError_t launch_batched_perm(Dtype dt, const void* const* in_ptrs, void* const
 }
 
 // ---------------------------------------------------------------------------
-// sweep dispatch (instantiations live in tpd_sweep_c128.hip, tpd_sweep_c64.hip
-// and tpd_sweep_r64.hip)
+// sweep dispatch (instantiations live in tpd_sweep_c128.hip, tpd_sweep_c64.hip,
+// tpd_sweep_r64.hip and tpd_sweep_r32.hip)
 // ---------------------------------------------------------------------------
 bool sweep_supported_c128(const SweepDesc& s);
 bool sweep_supported_c64(const SweepDesc& s);
 bool sweep_supported_r64(const SweepDesc& s);
+bool sweep_supported_r32(const SweepDesc& s);
 hipError_t launch_sweep_c128(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
 hipError_t launch_sweep_c64(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
 hipError_t launch_sweep_r64(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
+hipError_t launch_sweep_r32(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
 
 bool sweep_supported(Dtype dt, const SweepDesc& s) {
   switch (dt) {
     case DT_C128: return sweep_supported_c128(s);
     case DT_C64: return sweep_supported_c64(s);
     case DT_R64: return sweep_supported_r64(s);
+    case DT_R32: return sweep_supported_r32(s);
     default: return false;
   }
 }
@@ -196,6 +199,7 @@ hipError_t launch_sweep(Dtype dt, const SweepDesc& s, const SweepArgs& a, hipStr
     case DT_C128: return launch_sweep_c128(s, a, st);
     case DT_C64: return launch_sweep_c64(s, a, st);
     case DT_R64: return launch_sweep_r64(s, a, st);
+    case DT_R32: return launch_sweep_r32(s, a, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libtpd.so")
 TPD_C128 = 0
 TPD_C64 = 1
 TPD_R64 = 2
+TPD_R32 = 3
 FLAG_NO_PRUNE = 0x1
 FLAG_LAYOUT_MATRIX = 0x2
 FLAG_TIMING = 0x4
@@ -239,6 +240,8 @@ def _dtype_code(t) -> int:
         return TPD_C64
     if t.dtype == torch.float64:
         return TPD_R64
+    if t.dtype == torch.float32:
+        return TPD_R32
     raise TypeError(f"unsupported dtype {t.dtype}")
 
 
@@ -274,11 +277,11 @@ def _check_matrix(A):
 def decompose(A, out=None, *, layout: str = "canonical", prune: bool = True, order_bottom: bool = False,
               hermitian: bool = False, stream=None):
     """Pauli coefficients of A (2^n x 2^n complex64/complex128 CUDA tensor,
-    or float64 for a real matrix).
+    or float64/float32 for a real matrix).
 
     Returns a 1-D tensor of 4^n coefficients (canonical order: index
     q = sum_k t_k 4^(n-k)), or the 2^n x 2^n matrix-layout array.  `out` may
-    be A itself for an in-place call (see include/tpd.h).  For float64 input
+    be A itself for an in-place call (see include/tpd.h).  For real input
     the values are real-coded: w_t = r_t for an even number of Y letters,
     i r_t for an odd number."""
     torch = _torch()

@@ -35,6 +35,7 @@ def test_status_strings_and_limits():
     assert tpd.max_qubits(tpd.TPD_C128) == 16
     assert tpd.max_qubits(tpd.TPD_C64) == 16
     assert tpd.max_qubits(tpd.TPD_R64) == 16
+    assert tpd.max_qubits(tpd.TPD_R32) == 16
     assert tpd.lib.tpd_max_qubits(7) == -1
 
 
@@ -71,6 +72,8 @@ FAKE = 0x100000  # never dereferenced: validation fails or the device check stop
     ((FAKE, 4, FAKE + 8, 2, 0), 1),        # partial overlap, real (8-byte elements)
     ((FAKE, 17, FAKE * 64, 2, 0), 2),      # n too large, real
     ((FAKE, 10, FAKE, 2, 0), 2),           # real, in place canonical
+    ((FAKE, 4, FAKE * 4 + 2, 3, 0), 1),    # misaligned real float32
+    ((FAKE, 4, FAKE + 4, 3, 0), 1),        # partial overlap, real float32 (4-byte elements)
     ((FAKE, 4, FAKE * 4, 5, 0), 1),        # bad dtype
     ((FAKE, 4, FAKE * 4, 0, 0x100), 1),    # unknown flag
     ((FAKE, 8, FAKE, 0, 0), 2),            # in place, canonical, n > 6
@@ -104,13 +107,13 @@ def test_real_input_only_where_supported():
     ns = (ctypes.c_int * 2)(3, 8)
     ptrs = (ctypes.c_void_p * 2)(FAKE, FAKE * 2)
     outs = (ctypes.c_void_p * 2)(FAKE * 4, FAKE * 8)
-    R = tpd.TPD_R64
-    assert tpd.lib.tpd_decompose_batched(ptrs, ns, 2, outs, R, 0, None) == 2
-    assert tpd.lib.tpd_decompose_partial(FAKE, 4, FAKE * 4, FAKE * 8, 5, FAKE * 16, R, 0, None) == 2
-    assert tpd.lib.tpd_compact(FAKE, 4, R, 0, 0.0, FAKE * 2, FAKE * 4, 8, FAKE * 8, None) == 2
-    assert tpd.lib.tpd_synthesize_ex(FAKE, 4, FAKE * 4, R, 0, None) == 2
-    h = ctypes.c_void_p()
-    assert tpd.lib.tpd_plan_create_batched(ns, 2, R, 0, 0, ctypes.byref(h)) == 2
+    for R in (tpd.TPD_R64, tpd.TPD_R32):
+        assert tpd.lib.tpd_decompose_batched(ptrs, ns, 2, outs, R, 0, None) == 2
+        assert tpd.lib.tpd_decompose_partial(FAKE, 4, FAKE * 4, FAKE * 8, 5, FAKE * 16, R, 0, None) == 2
+        assert tpd.lib.tpd_compact(FAKE, 4, R, 0, 0.0, FAKE * 2, FAKE * 4, 8, FAKE * 8, None) == 2
+        assert tpd.lib.tpd_synthesize_ex(FAKE, 4, FAKE * 4, R, 0, None) == 2
+        h = ctypes.c_void_p()
+        assert tpd.lib.tpd_plan_create_batched(ns, 2, R, 0, 0, ctypes.byref(h)) == 2
 
 
 def test_batched_validation():
@@ -123,7 +126,7 @@ def test_batched_validation():
     assert tpd.lib.tpd_decompose_batched(ptrs, ns2, -1, outs, 0, 0, None) == 1
     assert tpd.lib.tpd_decompose_batched(None, ns2, 2, outs, 0, 0, None) == 1
     assert tpd.lib.tpd_decompose_batched(ptrs, ns2, 0, outs, 0, 0, None) == 0  # empty batch is a no-op
-    assert tpd.lib.tpd_decompose_batched(ptrs, ns2, 2, outs, 3, 0, None) == 1
+    assert tpd.lib.tpd_decompose_batched(ptrs, ns2, 2, outs, 7, 0, None) == 1  # unknown dtype
 
 
 def test_plan_validation():
@@ -138,9 +141,9 @@ def test_plan_validation():
 
 @pytest.mark.parametrize("n", range(0, 17))
 def test_schedule_shapes(n):
-    for dt in (tpd.TPD_C128, tpd.TPD_C64, tpd.TPD_R64):
+    for dt in (tpd.TPD_C128, tpd.TPD_C64, tpd.TPD_R64, tpd.TPD_R32):
         s = tpd.schedule(n, dt)
-        es = 16 if dt == tpd.TPD_C128 else 8
+        es = {tpd.TPD_C128: 16, tpd.TPD_R32: 4}.get(dt, 8)
         assert s["elements"] == 4 ** n
         assert s["algorithmic_bytes"] == 2 * 4 ** n * es
         if n == 0:
@@ -158,8 +161,9 @@ def test_schedule_shapes(n):
         if n >= 9:
             assert sw[0]["bitmap"] == "set" and sw[1]["bitmap"] == "check"
             assert sw[0]["out"] == "MID" and sw[1]["in"] == "MID" and sw[1]["out"] == "CAN"
-            # coalescing: every run of the first sweep's reads is 2^db elements >= 128 B
-            assert (1 << sw[0]["db"]) * es >= 128
+            # coalescing: every run of the first sweep's reads is 2^db elements,
+            # >= 128 B (>= 64 B for 4-byte elements when n = 9 caps db at 4)
+            assert (1 << sw[0]["db"]) * es >= (128 if es >= 8 or n >= 10 else 64)
 
 
 def test_schedule_flags():

@@ -448,6 +448,40 @@ def test_real_input_vs_algorithm_1(n):
                 assert np.array_equal(out.cpu().numpy(), exp), (db, g)
 
 
+@pytest.mark.parametrize("n", [0, 1, 3, 8, 9, 12])
+def test_real_float32_input(n):
+    # float32 real input: the complex64 path's nonzero component, value for
+    # value (the same roundings), and within (n+1) 2^-24 max|a| of the oracle
+    A = W.real_gaussian(n, seed=2400 + n) if n else np.array([[1.25]])
+    A32 = A.astype(np.float32)
+    ref = O.tpd_recursive(A32.astype(np.complex128))
+    q = np.arange(4 ** n)
+    exp, _ = real_coded(ref, q)
+    Ad = torch.from_numpy(A32).to(DEV)
+    got = tpd.decompose(Ad)
+    assert got.dtype == torch.float32
+    g = got.cpu().numpy()
+    c64 = tpd.decompose(Ad.to(torch.complex64)).cpu().numpy()
+    e64, o64 = real_coded(c64, q)
+    assert np.all(o64 == 0) and np.array_equal(g, e64)
+    a_max = float(np.max(np.abs(A32))) if n else 1.25
+    assert np.max(np.abs(g.astype(np.float64) - exp)) <= (n + 1) * U32 * a_max
+    B = Ad.clone()
+    tpd.decompose(B, B.view(-1), layout="matrix")
+    assert np.array_equal(matrix_to_canonical(B.cpu().numpy().ravel(), n), g)
+    if n >= 9:
+        S = torch.from_numpy(((A + A.T) / 2).astype(np.float32)).to(DEV)
+        full = tpd.decompose(S).cpu().numpy()
+        herm = tpd.decompose(S, hermitian=True).cpu().numpy()
+        assert np.array_equal(full, herm) and np.all(herm[y_odd(q)] == 0)
+        out = torch.empty_like(got)
+        for db in [b for b in (4, 5, 6) if b <= n // 2]:
+            for gp in (0, 1, 4):
+                out.fill_(float("nan"))
+                tpd.decompose_tuned(Ad, out, db=db, grid_per_cu=gp)
+                assert np.array_equal(out.cpu().numpy(), g), (db, gp)
+
+
 @pytest.mark.parametrize("n", [9, 12, 13])
 def test_real_symmetric_hermitian_mode(n):
     A = W.real_gaussian(n, seed=2300 + n, symmetric=True)
@@ -486,19 +520,21 @@ def test_real_tfim_pruning_and_exact_terms():
     assert all(got[k] == v.real for k, v in expect.items())
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("hermitian", [False, True])
-def test_n16_real_in_place_every_tuning_candidate(hermitian):
-    # the real path at full size: n = 16 real symmetric float64 in place,
+def test_n16_real_in_place_every_tuning_candidate(hermitian, dtype):
+    # the real path at full size: n = 16 real symmetric matrix in place,
     # every tile width and grid the autotuner may choose, sampled strings
     # against the definition
     n = 16
     torch.cuda.empty_cache()
-    A = W.gaussian_device(n, seed=6, dtype=torch.float64, hermitian=True)
+    A = W.gaussian_device(n, seed=6, dtype=dtype, hermitian=True)
     a_max = float(A.abs().max())
     qs = W.sampled_strings(n, 2000, seed=26)
     bf = sampled_oracle(A, n, qs)
     exp, other = real_coded(bf, qs)
     assert np.max(np.abs(other)) <= n * U64 * a_max
+    tol = n * U64 * a_max if dtype == torch.float64 else (n + 1) * U32 * a_max
     h, l = deinterleave(qs.astype(np.int64))
     hb = torch.from_numpy(h).to(DEV)
     lb = torch.from_numpy(l).to(DEV)
@@ -506,7 +542,7 @@ def test_n16_real_in_place_every_tuning_candidate(hermitian):
     B.copy_(A)
     tpd.decompose(B, B.view(-1), layout="matrix")
     ref = B[hb, lb].cpu().numpy()
-    assert np.max(np.abs(ref - exp)) <= n * U64 * a_max
+    assert np.max(np.abs(ref.astype(np.float64) - exp)) <= tol
     assert np.all(ref[y_odd(qs)] == 0)
     for db in (4, 5, 6):
         for g in (0, 1, 2, 4):
