@@ -81,8 +81,9 @@ typedef enum {
  * symmetric; its odd-y weights vanish, as the footnote on real-symmetric
  * input in section "Existing algorithms" notes) the first sweep reads half
  * the input.  Supported by tpd_decompose_ex, tpd_plan_create /
- * tpd_plan_execute and tpd_autotune; the batched, partial, compaction and
- * synthesis entry points return TPD_ERROR_UNSUPPORTED for it.            */
+ * tpd_plan_execute, tpd_autotune, tpd_decompose_partial (real-coded values,
+ * NaN for out-of-range requests) and tpd_compact (keeps |r_t| > tol); the
+ * batched and synthesis entry points return TPD_ERROR_UNSUPPORTED for it. */
 
 typedef enum {
   TPD_SUCCESS = 0,
@@ -165,7 +166,8 @@ tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t d
  *   req    [in]  device array[count] of canonical indices q, any order,
  *                repeats allowed; q >= 4^n yields NaN + NaN i
  *   count  [in]  number of requests (0: nothing is enqueued)
- *   values [out] device array[count] of complex dtype, values[s] = w_req[s]
+ *   values [out] device array[count] of the dtype, values[s] = w_req[s]
+ *                (real-coded for TPD_R64 / TPD_R32; NaN for q >= 4^n)
  *   flags  TPD_FLAG_NO_PRUNE, TPD_FLAG_LAYOUT_MATRIX, TPD_FLAG_HERMITIAN,
  *          TPD_FLAG_ORDER_BOTTOM; TPD_FLAG_TIMING is TPD_ERROR_INVALID_VALUE
  * Workspace: two request bitmaps (2^(n-db) and 2^(n1+n-db) bits) and two
@@ -177,15 +179,15 @@ tpd_status_t tpd_decompose_partial(const void* A, int n, void* coeffs, const uin
 /* Sparse-list output: the nonzero weights as (q, w) pairs, the list L that
  * Algorithms 1 and 2 return (section "Methods").  Ordered stream
  * compaction of a coefficient array: an element is kept unless both |re|
- * and |im| are <= tol (compared in the dtype's precision, tol rounded to
- * it; NaN is kept).  Pairs appear in storage order: ascending q for the
+ * and |im| are <= tol (real-coded dtypes: unless |r| <= tol), compared in
+ * the dtype's precision, tol rounded to it; NaN is kept.  Pairs appear in storage order: ascending q for the
  * canonical layout, ascending (row h, column l) for the matrix layout.
  *   coeffs   [in]  device, 4^n coefficients (canonical, or matrix layout
  *                  with TPD_FLAG_LAYOUT_MATRIX; no other flag)
  *   tol      [in]  >= 0 (0: exact nonzeros); negative or NaN is
  *                  TPD_ERROR_INVALID_VALUE
  *   q_out    [out] device array[capacity] of canonical indices
- *   w_out    [out] device array[capacity] of complex dtype
+ *   w_out    [out] device array[capacity] of the dtype
  *   capacity [in]  entries available; only the first `capacity` pairs are
  *                  written (q_out and w_out may be NULL when it is 0)
  *   count    [out] device, one uint64: the total number of kept pairs

@@ -354,7 +354,8 @@ tpd_status_t check_dtype_flags(int dtype, unsigned flags) {
   return TPD_SUCCESS;
 }
 
-// single-matrix decomposition: complex dtypes and the real input
+// single-matrix entry points (decomposition, partial, compaction): complex
+// dtypes and the real input
 tpd_status_t check_dtype_flags_single(int dtype, unsigned flags) {
   if (dtype == TPD_R64 || dtype == TPD_R32) return (flags & ~TPD_FLAGS_ALL) ? TPD_ERROR_INVALID_VALUE : TPD_SUCCESS;
   return check_dtype_flags(dtype, flags);
@@ -860,7 +861,7 @@ tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t d
 
 tpd_status_t tpd_decompose_partial(const void* A, int n, void* coeffs, const uint64_t* req, uint64_t count,
                                    void* values, tpd_dtype_t dtype, unsigned flags, tpd_stream_t stream) {
-  tpd_status_t st = check_dtype_flags(dtype, flags);
+  tpd_status_t st = check_dtype_flags_single(dtype, flags);
   if (st) return st;
   if (flags & TPD_FLAG_TIMING) return TPD_ERROR_INVALID_VALUE;
   if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
@@ -910,7 +911,7 @@ tpd_status_t tpd_decompose_partial(const void* A, int n, void* coeffs, const uin
 
 tpd_status_t tpd_compact(const void* coeffs, int n, tpd_dtype_t dtype, unsigned flags, double tol, uint64_t* q_out,
                          void* w_out, uint64_t capacity, uint64_t* count, tpd_stream_t stream) {
-  tpd_status_t st = check_dtype_flags(dtype, flags);
+  tpd_status_t st = check_dtype_flags_single(dtype, flags);
   if (st) return st;
   if (flags & ~TPD_FLAG_LAYOUT_MATRIX) return TPD_ERROR_INVALID_VALUE;
   if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;

@@ -4,8 +4,8 @@
 // sparse (q, w) list (the list L that Algorithms 1 and 2 return).
 //
 // All of them are memory-bound and simple: grid-stride loops over 64-bit
-// element indices, coalesced 8/16-byte loads, integer atomics only on
-// request bitmaps.
+// element indices, coalesced 4- to 16-byte loads (complex or real-coded
+// elements), integer atomics only on request bitmaps.
 #include "tpd_internal.h"
 
 namespace tpd {
@@ -50,20 +50,38 @@ __global__ void k_bits_to_list(const uint32_t* __restrict__ bits, uint64_t words
   }
 }
 
+// element helpers for complex (Cx) and real-coded (Rl) values
 template <class S>
-__global__ void k_gather(const Cx<S>* __restrict__ c, int n, int matrix_layout, const uint64_t* __restrict__ req,
-                         uint64_t count, Cx<S>* __restrict__ values) {
+__device__ inline void set_nan(Cx<S>& v) {
+  v.re = __builtin_nan("");
+  v.im = __builtin_nan("");
+}
+template <class S>
+__device__ inline void set_nan(Rl<S>& v) {
+  v.re = __builtin_nan("");
+}
+template <class S>
+__device__ inline bool keep_elem(const Cx<S>& v, S tol) {
+  return keep_coeff<S>(v.re, v.im, tol);
+}
+template <class S>
+__device__ inline bool keep_elem(const Rl<S>& v, S tol) {
+  return keep_coeff<S>(v.re, (S)0, tol);
+}
+
+// T: double / float (complex elements) or Real<double> / Real<float>
+template <class T>
+__global__ void k_gather(const typename Elem<T>::type* __restrict__ c, int n, int matrix_layout,
+                         const uint64_t* __restrict__ req, uint64_t count, typename Elem<T>::type* __restrict__ values) {
   const uint64_t lim = (uint64_t)1 << (2 * n);
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t q = req[i];
-    Cx<S> v;
-    if (q < lim) {
+    typename Elem<T>::type v;
+    if (q < lim)
       v = c[storage_of_q(q, n, matrix_layout != 0)];
-    } else {
-      v.re = __builtin_nan("");
-      v.im = __builtin_nan("");
-    }
+    else
+      set_nan(v);
     values[i] = v;
   }
 }
@@ -95,16 +113,25 @@ hipError_t launch_bits_to_list(const uint32_t* bits, uint64_t words, uint32_t* l
   return hipGetLastError();
 }
 
+template <class T>
+static void gather_t(const void* coeffs, int n, bool matrix_layout, const uint64_t* req, uint64_t count,
+                     void* values, unsigned g, hipStream_t st) {
+  using E = typename Elem<T>::type;
+  hipLaunchKernelGGL(k_gather<T>, dim3(g), dim3(256), 0, st, (const E*)coeffs, n, (int)matrix_layout, req, count,
+                     (E*)values);
+}
+
 hipError_t launch_gather(Dtype dt, const void* coeffs, int n, bool matrix_layout, const uint64_t* req,
                          uint64_t count, void* values, hipStream_t st) {
   if (count == 0) return hipSuccess;
   const unsigned g = grid_for(count, 256, 16384);
-  if (dt == DT_C128)
-    hipLaunchKernelGGL(k_gather<double>, dim3(g), dim3(256), 0, st, (const Cx<double>*)coeffs, n,
-                       (int)matrix_layout, req, count, (Cx<double>*)values);
-  else
-    hipLaunchKernelGGL(k_gather<float>, dim3(g), dim3(256), 0, st, (const Cx<float>*)coeffs, n,
-                       (int)matrix_layout, req, count, (Cx<float>*)values);
+  switch (dt) {
+    case DT_C128: gather_t<double>(coeffs, n, matrix_layout, req, count, values, g, st); break;
+    case DT_C64: gather_t<float>(coeffs, n, matrix_layout, req, count, values, g, st); break;
+    case DT_R64: gather_t<Real<double>>(coeffs, n, matrix_layout, req, count, values, g, st); break;
+    case DT_R32: gather_t<Real<float>>(coeffs, n, matrix_layout, req, count, values, g, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -118,9 +145,9 @@ hipError_t launch_gather(Dtype dt, const void* coeffs, int n, bool matrix_layout
 constexpr int kCT = 256;
 constexpr int kCJ = (int)(kCompactChunk / kCT);  // 16
 
-template <class S>
-__global__ void __launch_bounds__(kCT) k_compact_count(const Cx<S>* __restrict__ c, uint64_t elems, S tol,
-                                                       uint32_t* __restrict__ counts) {
+template <class T, class S = typename Elem<T>::scalar>
+__global__ void __launch_bounds__(kCT) k_compact_count(const typename Elem<T>::type* __restrict__ c, uint64_t elems,
+                                                       S tol, uint32_t* __restrict__ counts) {
   __shared__ uint32_t wsum[kCT / 64];
   const uint64_t base = (uint64_t)blockIdx.x * kCompactChunk;
   const uint32_t tid = threadIdx.x;
@@ -129,10 +156,7 @@ __global__ void __launch_bounds__(kCT) k_compact_count(const Cx<S>* __restrict__
   for (int j = 0; j < kCJ; ++j) {
     const uint64_t i = base + (uint64_t)j * kCT + tid;
     bool k = false;
-    if (i < elems) {
-      const Cx<S> v = c[i];
-      k = keep_coeff<S>(v.re, v.im, tol);
-    }
+    if (i < elems) k = keep_elem(c[i], tol);
     cnt += (uint32_t)__popcll(__ballot(k));
   }
   if ((tid & 63) == 0) wsum[tid >> 6] = cnt;
@@ -171,12 +195,12 @@ __global__ void __launch_bounds__(1024) k_compact_scan(const uint32_t* __restric
   if (tid == 1023) *total = part[1023];
 }
 
-template <class S>
-__global__ void __launch_bounds__(kCT) k_compact_write(const Cx<S>* __restrict__ c, uint64_t elems, int n,
-                                                       int matrix_layout, S tol,
-                                                       const uint32_t* __restrict__ counts,
-                                                       const uint64_t* __restrict__ offsets, uint64_t capacity,
-                                                       uint64_t* __restrict__ q_out, Cx<S>* __restrict__ w_out) {
+template <class T, class S = typename Elem<T>::scalar>
+__global__ void __launch_bounds__(kCT)
+    k_compact_write(const typename Elem<T>::type* __restrict__ c, uint64_t elems, int n, int matrix_layout, S tol,
+                    const uint32_t* __restrict__ counts, const uint64_t* __restrict__ offsets, uint64_t capacity,
+                    uint64_t* __restrict__ q_out, typename Elem<T>::type* __restrict__ w_out) {
+  using E = typename Elem<T>::type;
   __shared__ uint32_t cnt[kCJ * (kCT / 64)];
   __shared__ uint32_t excl[kCJ * (kCT / 64)];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
@@ -192,7 +216,7 @@ __global__ void __launch_bounds__(kCT) k_compact_write(const Cx<S>* __restrict__
     if (off0 >= capacity) continue;
     const uint64_t base = chunk * kCompactChunk;
 
-    Cx<S> v[kCJ];
+    E v[kCJ];
     uint64_t m[kCJ];
 #pragma unroll
     for (int j = 0; j < kCJ; ++j) {
@@ -200,7 +224,7 @@ __global__ void __launch_bounds__(kCT) k_compact_write(const Cx<S>* __restrict__
       bool k = false;
       if (i < elems) {
         v[j] = c[i];
-        k = keep_coeff<S>(v[j].re, v[j].im, tol);
+        k = keep_elem(v[j], tol);
       }
       m[j] = __ballot(k);
       if (lane == 0) cnt[j * NW + wave] = (uint32_t)__popcll(m[j]);
@@ -230,16 +254,26 @@ __global__ void __launch_bounds__(kCT) k_compact_write(const Cx<S>* __restrict__
   }
 }
 
+template <class T>
+static void compact_count_t(const void* coeffs, uint64_t elems, double tol, uint32_t* counts, uint64_t nchunks,
+                            hipStream_t st) {
+  using E = typename Elem<T>::type;
+  using S = typename Elem<T>::scalar;
+  hipLaunchKernelGGL((k_compact_count<T>), dim3((unsigned)nchunks), dim3(kCT), 0, st, (const E*)coeffs, elems,
+                     (S)tol, counts);
+}
+
 hipError_t launch_compact_count(Dtype dt, const void* coeffs, uint64_t elems, double tol, uint32_t* counts,
                                 hipStream_t st) {
   const uint64_t nchunks = (elems + kCompactChunk - 1) / kCompactChunk;
   if (nchunks == 0) return hipSuccess;
-  if (dt == DT_C128)
-    hipLaunchKernelGGL(k_compact_count<double>, dim3((unsigned)nchunks), dim3(kCT), 0, st,
-                       (const Cx<double>*)coeffs, elems, tol, counts);
-  else
-    hipLaunchKernelGGL(k_compact_count<float>, dim3((unsigned)nchunks), dim3(kCT), 0, st,
-                       (const Cx<float>*)coeffs, elems, (float)tol, counts);
+  switch (dt) {
+    case DT_C128: compact_count_t<double>(coeffs, elems, tol, counts, nchunks, st); break;
+    case DT_C64: compact_count_t<float>(coeffs, elems, tol, counts, nchunks, st); break;
+    case DT_R64: compact_count_t<Real<double>>(coeffs, elems, tol, counts, nchunks, st); break;
+    case DT_R32: compact_count_t<Real<float>>(coeffs, elems, tol, counts, nchunks, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -247,6 +281,16 @@ hipError_t launch_compact_scan(const uint32_t* counts, uint64_t nchunks, uint64_
                                hipStream_t st) {
   hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, st, counts, nchunks, offsets, total);
   return hipGetLastError();
+}
+
+template <class T>
+static void compact_write_t(const void* coeffs, uint64_t elems, int n, bool matrix_layout, double tol,
+                            const uint32_t* counts, const uint64_t* offsets, uint64_t capacity, uint64_t* q_out,
+                            void* w_out, unsigned grid, hipStream_t st) {
+  using E = typename Elem<T>::type;
+  using S = typename Elem<T>::scalar;
+  hipLaunchKernelGGL((k_compact_write<T>), dim3(grid), dim3(kCT), 0, st, (const E*)coeffs, elems, n,
+                     (int)matrix_layout, (S)tol, counts, offsets, capacity, q_out, (E*)w_out);
 }
 
 hipError_t launch_compact_write(Dtype dt, const void* coeffs, int n, bool matrix_layout, double tol,
@@ -258,14 +302,23 @@ hipError_t launch_compact_write(Dtype dt, const void* coeffs, int n, bool matrix
   // a few workgroups per CU loop over the chunks (most are empty for sparse
   // spectra); 2048 covers 256 CUs with eight each
   const unsigned grid = (unsigned)std::min<uint64_t>(nchunks, 2048);
-  if (dt == DT_C128)
-    hipLaunchKernelGGL(k_compact_write<double>, dim3(grid), dim3(kCT), 0, st,
-                       (const Cx<double>*)coeffs, elems, n, (int)matrix_layout, tol, counts, offsets, capacity,
-                       q_out, (Cx<double>*)w_out);
-  else
-    hipLaunchKernelGGL(k_compact_write<float>, dim3(grid), dim3(kCT), 0, st,
-                       (const Cx<float>*)coeffs, elems, n, (int)matrix_layout, (float)tol, counts, offsets,
-                       capacity, q_out, (Cx<float>*)w_out);
+  switch (dt) {
+    case DT_C128:
+      compact_write_t<double>(coeffs, elems, n, matrix_layout, tol, counts, offsets, capacity, q_out, w_out, grid, st);
+      break;
+    case DT_C64:
+      compact_write_t<float>(coeffs, elems, n, matrix_layout, tol, counts, offsets, capacity, q_out, w_out, grid, st);
+      break;
+    case DT_R64:
+      compact_write_t<Real<double>>(coeffs, elems, n, matrix_layout, tol, counts, offsets, capacity, q_out, w_out,
+                                    grid, st);
+      break;
+    case DT_R32:
+      compact_write_t<Real<float>>(coeffs, elems, n, matrix_layout, tol, counts, offsets, capacity, q_out, w_out,
+                                   grid, st);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -351,7 +351,8 @@ def decompose_partial(A, req, values=None, work=None, *, layout: str = "canonica
     """Weights of the requested strings only (canonical indices `req`, a
     CUDA int64/uint64 tensor or a sequence).  `work` is the 4^n work array
     (allocated if None; may be A itself for an in-place call in the matrix
-    layout).  Returns `values`, one complex per request."""
+    layout).  Returns `values`, one value of A's dtype per request (NaN for
+    indices >= 4^n; real-coded for real input)."""
     torch = _torch()
     n = _check_matrix(A)
     dt = _dtype_code(A)

@@ -482,6 +482,41 @@ def test_real_float32_input(n):
                 assert np.array_equal(out.cpu().numpy(), g), (db, gp)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_real_partial_and_compaction(dtype):
+    # requested real-coded values are those of the full real decomposition
+    # (NaN past 4^n); the sparse list keeps |r| > tol in storage order
+    n = 12
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    A = W.real_gaussian(n, seed=2500, symmetric=True).astype(npdt)
+    Ad = torch.from_numpy(A).to(DEV)
+    full = tpd.decompose(Ad).cpu().numpy()
+    rng = np.random.default_rng(2501)
+    q = np.concatenate([rng.integers(0, 4 ** n, 500), [0, 4 ** n - 1, 4 ** n, 4 ** n + 9]]).astype(np.int64)
+    qd = torch.from_numpy(q).to(DEV)
+    for kw in ({}, {"hermitian": True}, {"prune": False}):
+        vals = tpd.decompose_partial(Ad, qd, **kw).cpu().numpy()
+        assert vals.dtype == npdt
+        assert np.array_equal(vals[:-2], full[q[:-2]]), kw
+        assert np.all(np.isnan(vals[-2:])), kw
+    B = Ad.clone()
+    vals = tpd.decompose_partial(B, qd, work=B.view(-1), layout="matrix").cpu().numpy()
+    assert np.array_equal(vals[:-2], full[q[:-2]])
+    fd = torch.from_numpy(full).to(DEV)
+    for tol in (0.0, 1e-3):
+        qs, ws, total = tpd.compact(fd, tol=tol)
+        keep = np.flatnonzero(~(np.abs(full) <= npdt(tol)))
+        assert total == keep.size
+        assert np.array_equal(qs.cpu().numpy(), keep) and np.array_equal(ws.cpu().numpy(), full[keep])
+    # the transverse-field Ising chain: the list is exactly its 2n - 1 terms
+    H = W.dense_from_terms_device(W.tfim_terms(n, 1.0, 0.5), n).real.to(dtype).contiguous()
+    qs, ws, total = tpd.compact(tpd.decompose(H))
+    expect = sorted((W.string_index(s_), c) for s_, c in W.tfim_terms(n, 1.0, 0.5))
+    assert total == len(expect) == 2 * n - 1
+    assert qs.cpu().numpy().tolist() == [k for k, _ in expect]
+    assert np.array_equal(ws.cpu().numpy(), np.array([c.real for _, c in expect], npdt))
+
+
 @pytest.mark.parametrize("n", [9, 12, 13])
 def test_real_symmetric_hermitian_mode(n):
     A = W.real_gaussian(n, seed=2300 + n, symmetric=True)
