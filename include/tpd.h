@@ -82,8 +82,9 @@ typedef enum {
  * input in section "Existing algorithms" notes) the first sweep reads half
  * the input.  Supported by tpd_decompose_ex, tpd_plan_create /
  * tpd_plan_execute, tpd_autotune, tpd_decompose_partial (real-coded values,
- * NaN for out-of-range requests) and tpd_compact (keeps |r_t| > tol); the
- * batched and synthesis entry points return TPD_ERROR_UNSUPPORTED for it. */
+ * NaN for out-of-range requests), tpd_compact (keeps |r_t| > tol) and
+ * tpd_synthesize_ex (real-coded weights in, the real matrix out); the
+ * batched entry points return TPD_ERROR_UNSUPPORTED for it.              */
 
 typedef enum {
   TPD_SUCCESS = 0,

@@ -249,7 +249,8 @@ tpd_status_t make_synth_schedule(int n, Dtype dt, unsigned flags, bool in_place,
     s->nsweep = 2;
     s->n1 = (n + 1) / 2;
     s->n2 = n / 2;
-    const int db = default_db(dt, s->n2);
+    const int dd = default_db(dt, s->n2);
+    const int db = dd < 5 ? dd : 5;  // the inverse kernels come in tile widths 2^4 and 2^5
     SweepDesc& a = s->sw[0];
     base(a);
     a.xlo = 0;
@@ -843,7 +844,7 @@ tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dt
 
 tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,
                                tpd_stream_t stream) {
-  tpd_status_t st = check_dtype_flags(dtype, flags);
+  tpd_status_t st = check_dtype_flags_single(dtype, flags);
   if (st) return st;
   if (flags & ~(TPD_FLAG_LAYOUT_MATRIX | TPD_FLAG_NO_PRUNE)) return TPD_ERROR_INVALID_VALUE;
   if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;

@@ -244,6 +244,16 @@ TPD_HD void butterfly(Rl<S>& u, Rl<S>& v, bool) {
   v.re = d;
 }
 
+// inverse of the real-coded butterfly: (s, t) -> (s + t, s - t).  With
+// w = i on X/Y diagonals, t conj(w) = -i t, and t carries one more factor i
+// than s (its Y letter), so both outputs keep s's phase: no twiddle.
+template <class S>
+TPD_HD void butterfly_inv(Rl<S>& u, Rl<S>& v, bool) {
+  const S s = u.re, t = v.re;
+  u.re = s + t;
+  v.re = s - t;
+}
+
 // Element type of a kernel instantiation: Cx<S> for complex data, Rl<S> for
 // the tag Real<S> (real input, real-coded output).
 template <class S>

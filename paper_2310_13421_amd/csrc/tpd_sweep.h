@@ -124,6 +124,14 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
       const uint32_t e = eb0 | elem_reg<G>(RL, 0, j);
       if (t.hm && !xlo && (((uint64_t)((e >> G::DB) & XM)) & t.hm)) v[j] = E{};
       else v[j] = in[ad];
+      if constexpr (REAL && INV) {
+        // synthesis from real-coded weights: back to the raw factor of
+        // i^y (the inverse of the forward transform's last store)
+        if (!xlo) {
+          const uint64_t xe = t.xfix | ((uint64_t)((e >> G::DB) & XM)), de = (t.td << G::DB) | (e & DM);
+          if ((__popcll(xe & de) >> 1) & 1) v[j].re = -v[j].re;
+        }
+      }
     }
   };
 
@@ -219,7 +227,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
 #pragma unroll
         for (int s = 0; s < G::R; ++s)
           if ((j >> s) & 1) ad ^= dout[s];
-        if constexpr (REAL) {
+        if constexpr (REAL && !INV) {
           // last sweep: the weight is i^y r (y = Y letters = popcount(x & d));
           // store its nonzero component, Re w for even y and Im w for odd y,
           // i.e. r negated when y mod 4 is 2 or 3
@@ -228,7 +236,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
             const uint64_t xe = xfix | ((uint64_t)((e >> G::DB) & XM)), de = (td << G::DB) | (e & DM);
             if ((__popcll(xe & de) >> 1) & 1) v[j].re = -v[j].re;
           }
-        } else {
+        } else if constexpr (!REAL) {
           if (real_out) v[j].im = (typename Elem<S>::scalar)0;
         }
         out[ad] = v[j];

@@ -1,7 +1,7 @@
 // tpd_sweep_r64.hip -- real-input float64 instantiations of the sweep kernel
 // (8-byte real-coded elements: the same tile shapes as complex64).
 // Two-sweep tile widths: 2^4, 2^5 (default) or 2^6 diagonals (128, 256 or
-// 512 B runs).  Forward transform only.
+// 512 B runs); the inverse transform with 2^4 or 2^5.
 #include "tpd_sweep.h"
 
 namespace tpd {
@@ -11,7 +11,15 @@ hipError_t launch_two_r64_db5(const SweepDesc& s, const SweepArgs& a, hipStream_
 hipError_t launch_two_r64_db6(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
 
 bool sweep_supported_r64(const SweepDesc& s) {
-  if (s.inv) return false;
+  if (s.inv) {
+    if (s.out_layout != L_MAT || (s.in_layout != L_CAN && s.in_layout != L_MAT)) return false;
+    if (s.is_one)
+      return (s.xb == 1 && s.db == 1) || (s.xb == 2 && s.db == 2) || (s.xb == 3 && s.db == 3) ||
+             (s.xb == 4 && s.db == 4) || (s.xb == 5 && s.db == 5) || (s.xb == 6 && s.db == 6) ||
+             (s.xb == 7 && s.db == 5) || (s.xb == 8 && s.db == 4);
+    return s.xb >= 4 && s.xb <= 8 && (s.db == 4 || s.db == 5) && s.r == 4 && s.order == 0 &&
+           shape_fits<Real<double>>(s.xb, s.db);
+  }
   const bool one = s.in_layout == L_MAT && s.xlo == 0 && s.out_layout != L_MID && s.bitmap_mode == 0 &&
                    ((s.xb == 1 && s.db == 1) || (s.xb == 2 && s.db == 2) || (s.xb == 3 && s.db == 3) ||
                     (s.xb == 4 && s.db == 4) || (s.xb == 5 && s.db == 5) || (s.xb == 6 && s.db == 6) ||
@@ -24,7 +32,7 @@ bool sweep_supported_r64(const SweepDesc& s) {
 }
 
 hipError_t launch_sweep_r64(const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
-  if (s.inv) return hipErrorInvalidValue;
+  if (s.inv) return dispatch_inv<Real<double>>(s, a, st);
   if (s.is_one) return dispatch_one<Real<double>>(s, a, st);
   switch (s.db) {
     case 4: return launch_two_r64_db4(s, a, st);

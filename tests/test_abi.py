@@ -103,7 +103,7 @@ def test_partial_and_compact_validation():
 
 
 def test_real_input_only_where_supported():
-    # the real-input dtypes have no batched or synthesis path
+    # the real-input dtypes have no batched path
     ns = (ctypes.c_int * 2)(3, 8)
     ptrs = (ctypes.c_void_p * 2)(FAKE, FAKE * 2)
     outs = (ctypes.c_void_p * 2)(FAKE * 4, FAKE * 8)
@@ -112,7 +112,7 @@ def test_real_input_only_where_supported():
         # partial and compaction validate real dtypes like the complex ones
         assert tpd.lib.tpd_decompose_partial(FAKE, 4, FAKE * 4, None, 5, FAKE * 16, R, 0, None) == 1
         assert tpd.lib.tpd_compact(FAKE, 4, R, 0, -1.0, FAKE * 2, FAKE * 4, 8, FAKE * 8, None) == 1
-        assert tpd.lib.tpd_synthesize_ex(FAKE, 4, FAKE * 4, R, 0, None) == 2
+        assert tpd.lib.tpd_synthesize_ex(FAKE, 4, FAKE * 4, R, 0x4, None) == 1  # flag check as for complex
         h = ctypes.c_void_p()
         assert tpd.lib.tpd_plan_create_batched(ns, 2, R, 0, 0, ctypes.byref(h)) == 2
 

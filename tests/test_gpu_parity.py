@@ -517,6 +517,33 @@ def test_real_partial_and_compaction(dtype):
     assert np.array_equal(ws.cpu().numpy(), np.array([c.real for _, c in expect], npdt))
 
 
+@pytest.mark.parametrize("n", [0, 1, 3, 8, 9, 12])
+def test_real_synthesis(n):
+    # real-coded weights back to the real matrix: the complex path's result
+    # (which is real) value for value, integer weights exactly, and the
+    # round trip through the real decomposition exact
+    rng = np.random.default_rng(2600 + n)
+    q = np.arange(4 ** n)
+    odd = y_odd(q)
+    r = rng.integers(-8, 9, 4 ** n).astype(np.float64)
+    w = np.where(odd, 1j * r, r + 0j)  # the complex weights the real-coded r stand for
+    ref = O.synthesize(w, n) if n <= 10 else None  # the oracle's sum costs 8^n
+    assert ref is None or np.all(ref.imag == 0)  # such weights give a real matrix
+    for dtype, cdtype in ((torch.float64, torch.complex128), (torch.float32, torch.complex64)):
+        rd = torch.from_numpy(r).to(DEV).to(dtype)
+        A = tpd.synthesize(rd)
+        assert A.dtype == dtype and A.shape == (1 << n, 1 << n)
+        Ac = tpd.synthesize(to_dev(w, cdtype)).cpu().numpy()
+        assert np.array_equal(A.cpu().numpy(), Ac.real)
+        if ref is not None:
+            assert np.array_equal(A.cpu().numpy().astype(np.float64), ref.real)
+        assert np.array_equal(tpd.decompose(A).cpu().numpy(), r.astype(A.cpu().numpy().dtype))
+        # matrix layout, in place
+        T = torch.from_numpy(canonical_to_matrix(r, n)).to(DEV).to(dtype).contiguous()
+        tpd.synthesize(T, T.view(1 << n, 1 << n), layout="matrix")
+        assert np.array_equal(T.view(1 << n, 1 << n).cpu().numpy(), A.cpu().numpy())
+
+
 @pytest.mark.parametrize("n", [9, 12, 13])
 def test_real_symmetric_hermitian_mode(n):
     A = W.real_gaussian(n, seed=2300 + n, symmetric=True)
@@ -741,7 +768,7 @@ def canonical_to_matrix(w, n):
     return np.asarray(w).reshape(-1)[q.ravel()].copy()
 
 
-@pytest.mark.parametrize("n", [0, 1, 4, 8, 9, 12])
+@pytest.mark.parametrize("n", [0, 1, 4, 8, 9, 10])  # the oracle's sum costs 8^n: n = 12 takes minutes
 def test_synthesize_vs_oracle(n):
     rng = np.random.default_rng(1200 + n)
     w = rng.standard_normal(4 ** n) + 1j * rng.standard_normal(4 ** n)
