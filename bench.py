@@ -108,14 +108,19 @@ def ingest_pair(fetch_csv, write_csv):
 
     fetch, write = per_kernel(fetch_csv), per_kernel(write_csv)
 
-    def calib(agg):
-        vals = [v for name, vs in agg.items() if "copyBuffer" in name for v in vs]
-        vals = [v for v in vals if 0.25 * copy_bytes < v < 4 * copy_bytes]
-        if not vals:
-            raise SystemExit("no plain-copy dispatch of 2^32 bytes in " + str(agg.keys()))
-        return (sum(vals) / len(vals)) / copy_bytes
-
-    fscale, wscale = calib(fetch), calib(write)
+    # The calibration copy is the copy dispatch that writes 2^32 bytes (the
+    # write counter reads a plain copy exactly); the input restores of the
+    # in-place legs are copies of other sizes.  Both runs dispatch the same
+    # kernels in the same order, so the fetch run's copies pair up by index.
+    fc = [v for name, vs in fetch.items() if "copyBuffer" in name for v in vs]
+    wc = [v for name, vs in write.items() if "copyBuffer" in name for v in vs]
+    if len(fc) != len(wc):
+        raise SystemExit("copy dispatches differ between the FETCH_SIZE and WRITE_SIZE runs")
+    sel = [i for i, w in enumerate(wc) if abs(w / copy_bytes - 1.0) < 0.02]
+    if not sel:
+        raise SystemExit("no plain-copy dispatch of 2^32 bytes in the WRITE_SIZE run")
+    fscale = sum(fc[i] for i in sel) / len(sel) / copy_bytes
+    wscale = sum(wc[i] for i in sel) / len(sel) / copy_bytes
     kernels = {}
     for name in fetch:
         if "tpd::k_sweep" not in name or name not in write:
@@ -140,6 +145,7 @@ def ingest_pair(fetch_csv, write_csv):
         full = [i for i, r in enumerate(fr) if r >= 0.75]
         reduced = [i for i in range(len(fr)) if i not in full] if len(fr) == len(wr) and full else []
         use = full if reduced else list(range(len(fr)))
+        only_reduced = not full
         fb = sum(fr[i] for i in use) / len(use) * alg
         wb = sum(wr[i] for i in (use if len(wr) == len(fr) else range(len(wr)))) / (
             len(use) if len(wr) == len(fr) else len(wr)) * alg
@@ -148,6 +154,8 @@ def ingest_pair(fetch_csv, write_csv):
             "fetch_bytes": fb, "write_bytes": wb, "total_bytes": fb + wb,
             "algorithmic_bytes": 2 * alg, "fetch_over_algorithmic": fb / alg, "write_over_algorithmic": wb / alg,
         }
+        if only_reduced:
+            kernels[name]["only_reduced_mode_dispatches"] = True  # Hermitian / real-symmetric mode only
         if reduced:
             kernels[name]["reduced_mode_dispatches"] = {
                 "count": len(reduced),

@@ -80,11 +80,11 @@ typedef enum {
  * (TPD_C64) result for the same matrix.  With TPD_FLAG_HERMITIAN (A real
  * symmetric; its odd-y weights vanish, as the footnote on real-symmetric
  * input in section "Existing algorithms" notes) the first sweep reads half
- * the input.  Supported by tpd_decompose_ex, tpd_plan_create /
- * tpd_plan_execute, tpd_autotune, tpd_decompose_partial (real-coded values,
- * NaN for out-of-range requests), tpd_compact (keeps |r_t| > tol) and
- * tpd_synthesize_ex (real-coded weights in, the real matrix out); the
- * batched entry points return TPD_ERROR_UNSUPPORTED for it.              */
+ * the input.  Every entry point takes them: tpd_decompose_partial returns
+ * real-coded values (NaN for out-of-range requests), tpd_compact keeps
+ * |r_t| > tol, tpd_synthesize_ex turns real-coded weights into the real
+ * matrix, and the batched entry points decompose real matrices of mixed
+ * sizes (2^13-element tiles for both real types).                        */
 
 typedef enum {
   TPD_SUCCESS = 0,

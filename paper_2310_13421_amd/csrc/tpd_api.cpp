@@ -347,19 +347,18 @@ tpd_status_t copy_out(const std::string& s, char* buf, size_t len) {
 // ---------------------------------------------------------------------------
 // validation helpers
 // ---------------------------------------------------------------------------
-// complex dtypes only (the entry points without a real-input path)
-tpd_status_t check_dtype_flags(int dtype, unsigned flags) {
+// complex dtypes only: the host replays (test aids) cover no real input
+tpd_status_t check_dtype_flags_complex(int dtype, unsigned flags) {
   if (dtype == TPD_R64 || dtype == TPD_R32) return TPD_ERROR_UNSUPPORTED;
   if (dtype != TPD_C128 && dtype != TPD_C64) return TPD_ERROR_INVALID_VALUE;
   if (flags & ~TPD_FLAGS_ALL) return TPD_ERROR_INVALID_VALUE;
   return TPD_SUCCESS;
 }
 
-// single-matrix entry points (decomposition, partial, compaction): complex
-// dtypes and the real input
-tpd_status_t check_dtype_flags_single(int dtype, unsigned flags) {
+// every device entry point: the complex dtypes and the real input
+tpd_status_t check_dtype_flags(int dtype, unsigned flags) {
   if (dtype == TPD_R64 || dtype == TPD_R32) return (flags & ~TPD_FLAGS_ALL) ? TPD_ERROR_INVALID_VALUE : TPD_SUCCESS;
-  return check_dtype_flags(dtype, flags);
+  return check_dtype_flags_complex(dtype, flags);
 }
 
 tpd_status_t check_buffers(const void* A, void* C, int n, Dtype dt) {
@@ -807,7 +806,7 @@ int tpd_string_from_index(uint64_t q, int n, char* buf, size_t len) {
 }
 
 tpd_status_t tpd_schedule_describe(int n, tpd_dtype_t dtype, unsigned flags, int in_place, char* buf, size_t len) {
-  tpd_status_t st = check_dtype_flags_single(dtype, flags);
+  tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   Schedule s;
   st = make_schedule(n, (Dtype)dtype, flags, in_place != 0, &s);
@@ -817,7 +816,7 @@ tpd_status_t tpd_schedule_describe(int n, tpd_dtype_t dtype, unsigned flags, int
 
 tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                               tpd_stream_t stream) {
-  tpd_status_t st = check_dtype_flags_single(dtype, flags);
+  tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
   const Dtype dt = (Dtype)dtype;
@@ -844,7 +843,7 @@ tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dt
 
 tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,
                                tpd_stream_t stream) {
-  tpd_status_t st = check_dtype_flags_single(dtype, flags);
+  tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (flags & ~(TPD_FLAG_LAYOUT_MATRIX | TPD_FLAG_NO_PRUNE)) return TPD_ERROR_INVALID_VALUE;
   if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
@@ -862,7 +861,7 @@ tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t d
 
 tpd_status_t tpd_decompose_partial(const void* A, int n, void* coeffs, const uint64_t* req, uint64_t count,
                                    void* values, tpd_dtype_t dtype, unsigned flags, tpd_stream_t stream) {
-  tpd_status_t st = check_dtype_flags_single(dtype, flags);
+  tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (flags & TPD_FLAG_TIMING) return TPD_ERROR_INVALID_VALUE;
   if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
@@ -912,7 +911,7 @@ tpd_status_t tpd_decompose_partial(const void* A, int n, void* coeffs, const uin
 
 tpd_status_t tpd_compact(const void* coeffs, int n, tpd_dtype_t dtype, unsigned flags, double tol, uint64_t* q_out,
                          void* w_out, uint64_t capacity, uint64_t* count, tpd_stream_t stream) {
-  tpd_status_t st = check_dtype_flags_single(dtype, flags);
+  tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (flags & ~TPD_FLAG_LAYOUT_MATRIX) return TPD_ERROR_INVALID_VALUE;
   if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
@@ -972,7 +971,7 @@ tpd_status_t tpd_release_workspace(void) {
 tpd_status_t tpd_plan_create(int n, tpd_dtype_t dtype, unsigned flags, int in_place, tpd_plan_t* plan) {
   if (!plan) return TPD_ERROR_INVALID_VALUE;
   *plan = nullptr;
-  tpd_status_t st = check_dtype_flags_single(dtype, flags);
+  tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   Schedule s;
   st = make_schedule(n, (Dtype)dtype, flags, in_place != 0, &s);
@@ -1148,7 +1147,7 @@ tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len) {
   if (!plan->batched) return copy_out(describe(plan->sched), buf, len);
   char tmp[256];
   std::snprintf(tmp, sizeof tmp, "{\"batched\":true,\"count\":%d,\"items\":%u,\"grid\":%d,\"dtype\":\"%s\"}",
-                plan->count, plan->nitems, plan->grid, plan->dt == DT_C128 ? "c128" : "c64");
+                plan->count, plan->nitems, plan->grid, dtype_name(plan->dt));
   return copy_out(tmp, buf, len);
 }
 
@@ -1207,7 +1206,7 @@ tpd_status_t tpd_decompose_batched(const void* const* ptrs, const int* ns, int c
 namespace tpd {
 tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, const int* tune, SweepDesc* sw,
                            int* nsweep, int* n1, uint64_t* bitmap_words) {
-  tpd_status_t st = check_dtype_flags(dtype, flags);
+  tpd_status_t st = check_dtype_flags_complex(dtype, flags);
   if (st) return st;
   Schedule s;
   Tuned t;
@@ -1227,7 +1226,7 @@ tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, cons
 
 tpd_status_t host_partial_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep,
                                    int* n1, uint64_t* bitmap_words, int* prune) {
-  tpd_status_t st = check_dtype_flags(dtype, flags);
+  tpd_status_t st = check_dtype_flags_complex(dtype, flags);
   if (st) return st;
   if (flags & TPD_FLAG_TIMING) return TPD_ERROR_INVALID_VALUE;
   Schedule s;
@@ -1242,7 +1241,7 @@ tpd_status_t host_partial_schedule(int n, int dtype, unsigned flags, bool in_pla
 }
 
 tpd_status_t host_synth_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep) {
-  tpd_status_t st = check_dtype_flags(dtype, flags);
+  tpd_status_t st = check_dtype_flags_complex(dtype, flags);
   if (st) return st;
   Schedule s;
   st = make_synth_schedule(n, (Dtype)dtype, flags, in_place, &s);
@@ -1254,7 +1253,7 @@ tpd_status_t host_synth_schedule(int n, int dtype, unsigned flags, bool in_place
 
 tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, int dtype,
                                std::vector<uint32_t>* perm, std::vector<BatchItem>* items) {
-  tpd_status_t st = check_dtype_flags(dtype, flags);
+  tpd_status_t st = check_dtype_flags_complex(dtype, flags);
   if (st) return st;
   BatchTables bt;
   st = build_batch(ns, count, in_place, flags, (Dtype)dtype, &bt);
@@ -1278,7 +1277,7 @@ double median3(std::vector<float>& v) {
 extern "C" tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype,
                                                   unsigned flags, int db, int r, int grid_per_cu,
                                                   tpd_stream_t stream) {
-  tpd_status_t st = check_dtype_flags_single(dtype, flags);
+  tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
   if (grid_per_cu < 0 || grid_per_cu > 64) return TPD_ERROR_INVALID_VALUE;
@@ -1309,7 +1308,7 @@ extern "C" tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* co
 
 extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                                      tpd_stream_t stream, char* report, size_t len) {
-  tpd_status_t st = check_dtype_flags_single(dtype, flags);
+  tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
   const Dtype dt = (Dtype)dtype;

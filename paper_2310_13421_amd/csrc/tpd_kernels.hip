@@ -30,8 +30,11 @@ namespace tpd {
 // batched persistent kernel: one work item = packed whole matrices (n <= 6)
 // or one d-group tile of one matrix (n = 7..9); every item is a single sweep.
 // ---------------------------------------------------------------------------
+// S: double / float (complex), or Real<double> / Real<float> (real input,
+// real-coded weights: the store writes each weight's nonzero component).
 template <class S, class G, int OUTL>
-__device__ __noinline__ void batched_item(const BatchArgs& a, const BatchItem& it, Cx<S>* lds) {
+__device__ __noinline__ void batched_item(const BatchArgs& a, const BatchItem& it, typename Elem<S>::type* lds) {
+  using E = typename Elem<S>::type;
   static constexpr Roles RL = make_roles<G>();
   constexpr int P = G::NPH;
   constexpr int LAST = P - 1;
@@ -41,12 +44,12 @@ __device__ __noinline__ void batched_item(const BatchArgs& a, const BatchItem& i
   const uint32_t tid = threadIdx.x;
   const uint64_t td = it.tile;
 
-  Cx<S> v[G::E];
+  E v[G::E];
   {
     const uint32_t e = elem_base<G>(RL, 0, tid);
     const uint32_t ml = e >> (G::DB + G::XB);
     if (ml < it.nmat) {
-      const Cx<S>* __restrict__ in = (const Cx<S>*)a.in_ptrs[a.perm[it.mat0 + ml]];
+      const E* __restrict__ in = (const E*)a.in_ptrs[a.perm[it.mat0 + ml]];
       const uint64_t base = layout_addr<L_MAT>((e >> G::DB) & XM, (td << G::DB) | (e & DM), N, G::DB);
 #pragma unroll
       for (int j = 0; j < G::E; ++j) {
@@ -55,7 +58,7 @@ __device__ __noinline__ void batched_item(const BatchArgs& a, const BatchItem& i
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < G::E; ++j) v[j] = Cx<S>{(S)0, (S)0};
+      for (int j = 0; j < G::E; ++j) v[j] = E{};
     }
   }
 #pragma unroll
@@ -78,11 +81,18 @@ __device__ __noinline__ void batched_item(const BatchArgs& a, const BatchItem& i
     const uint32_t e = elem_base<G>(RL, LAST, tid);
     const uint32_t ml = e >> (G::DB + G::XB);
     if (ml < it.nmat) {
-      Cx<S>* __restrict__ out = (Cx<S>*)a.out_ptrs[a.perm[it.mat0 + ml]];
+      E* __restrict__ out = (E*)a.out_ptrs[a.perm[it.mat0 + ml]];
       const uint64_t base = layout_addr<OUTL>((e >> G::DB) & XM, (td << G::DB) | (e & DM), N, G::DB);
 #pragma unroll
       for (int j = 0; j < G::E; ++j) {
         const uint32_t er = elem_reg<G>(RL, LAST, j);
+        if constexpr (Elem<S>::real) {
+          // the weight is i^y r, y = popcount(x & d): store its nonzero
+          // component (r negated for y mod 4 = 2, 3)
+          const uint32_t ee = e | er;
+          const uint64_t x = (ee >> G::DB) & XM, d = (td << G::DB) | (ee & DM);
+          if ((__popcll(x & d) >> 1) & 1) v[j].re = -v[j].re;
+        }
         out[base ^ layout_addr<OUTL>((er >> G::DB) & XM, er & DM, N, G::DB)] = v[j];
       }
     }
@@ -90,7 +100,8 @@ __device__ __noinline__ void batched_item(const BatchArgs& a, const BatchItem& i
 }
 
 template <class S, int OUTL, int BT>
-__device__ __forceinline__ void batched_dispatch(const BatchArgs& a, const BatchItem& it, Cx<S>* lds) {
+__device__ __forceinline__ void batched_dispatch(const BatchArgs& a, const BatchItem& it,
+                                                 typename Elem<S>::type* lds) {
   switch (it.n) {
     case 0: batched_item<S, typename BatchShape<0, BT>::G, OUTL>(a, it, lds); break;
     case 1: batched_item<S, typename BatchShape<1, BT>::G, OUTL>(a, it, lds); break;
@@ -108,7 +119,7 @@ __device__ __forceinline__ void batched_dispatch(const BatchArgs& a, const Batch
 
 template <class S, int OUTL, int BT>
 __global__ void __launch_bounds__(1 << (BT - 4)) k_batched(BatchArgs a) {
-  __shared__ Cx<S> lds[1 << BT];
+  __shared__ typename Elem<S>::type lds[1 << BT];
   for (uint32_t i = blockIdx.x; i < a.nitems; i += gridDim.x) {
     const BatchItem it = a.items[i];
     batched_dispatch<S, OUTL, BT>(a, it, lds);
@@ -150,22 +161,25 @@ hipError_t launch_popcount(const uint32_t* p, uint64_t words, unsigned long long
   return hipGetLastError();
 }
 
+template <class S, int BT>
+static void batched_launch(const BatchArgs& a, int layout, int grid, hipStream_t st) {
+  if (layout == L_CAN)
+    hipLaunchKernelGGL((k_batched<S, L_CAN, BT>), dim3(grid), dim3(1 << (BT - 4)), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_batched<S, L_MAT, BT>), dim3(grid), dim3(1 << (BT - 4)), 0, st, a);
+}
+
 hipError_t launch_batched_perm(Dtype dt, const void* const* in_ptrs, void* const* out_ptrs, const uint32_t* perm,
                                const BatchItem* items, uint32_t nitems, int layout, int grid, hipStream_t st) {
   BatchArgs a{in_ptrs, out_ptrs, perm, items, nitems, layout};
   if (a.nitems == 0) return hipSuccess;
   if (grid <= 0 || (uint32_t)grid > a.nitems) grid = (int)a.nitems;
-  constexpr int B128 = batch_tile_bits(DT_C128), B64 = batch_tile_bits(DT_C64);
-  if (dt == DT_C128) {
-    if (layout == L_CAN)
-      hipLaunchKernelGGL((k_batched<double, L_CAN, B128>), dim3(grid), dim3(1 << (B128 - 4)), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_batched<double, L_MAT, B128>), dim3(grid), dim3(1 << (B128 - 4)), 0, st, a);
-  } else {
-    if (layout == L_CAN)
-      hipLaunchKernelGGL((k_batched<float, L_CAN, B64>), dim3(grid), dim3(1 << (B64 - 4)), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_batched<float, L_MAT, B64>), dim3(grid), dim3(1 << (B64 - 4)), 0, st, a);
+  switch (dt) {
+    case DT_C128: batched_launch<double, batch_tile_bits(DT_C128)>(a, layout, grid, st); break;
+    case DT_C64: batched_launch<float, batch_tile_bits(DT_C64)>(a, layout, grid, st); break;
+    case DT_R64: batched_launch<Real<double>, batch_tile_bits(DT_R64)>(a, layout, grid, st); break;
+    case DT_R32: batched_launch<Real<float>, batch_tile_bits(DT_R32)>(a, layout, grid, st); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -2,6 +2,8 @@
 function include/tpd.h declares, validates arguments before touching a
 device, and its host helpers and schedule planner behave as documented."""
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -102,19 +104,22 @@ def test_partial_and_compact_validation():
     assert C(FAKE, 17, 0, 0, 0.0, FAKE * 2, FAKE * 4, 8, FAKE * 8, None) == 2           # n too large
 
 
-def test_real_input_only_where_supported():
-    # the real-input dtypes have no batched path
-    ns = (ctypes.c_int * 2)(3, 8)
+def test_real_input_validation():
+    # the real dtypes go through the same host validation as the complex ones
+    ns = (ctypes.c_int * 2)(3, 10)
     ptrs = (ctypes.c_void_p * 2)(FAKE, FAKE * 2)
     outs = (ctypes.c_void_p * 2)(FAKE * 4, FAKE * 8)
     for R in (tpd.TPD_R64, tpd.TPD_R32):
-        assert tpd.lib.tpd_decompose_batched(ptrs, ns, 2, outs, R, 0, None) == 2
-        # partial and compaction validate real dtypes like the complex ones
+        assert tpd.lib.tpd_decompose_batched(ptrs, ns, 2, outs, R, 0, None) == 2  # n > 9
+        assert tpd.lib.tpd_decompose_batched(ptrs, ns, -1, outs, R, 0, None) == 1
         assert tpd.lib.tpd_decompose_partial(FAKE, 4, FAKE * 4, None, 5, FAKE * 16, R, 0, None) == 1
         assert tpd.lib.tpd_compact(FAKE, 4, R, 0, -1.0, FAKE * 2, FAKE * 4, 8, FAKE * 8, None) == 1
-        assert tpd.lib.tpd_synthesize_ex(FAKE, 4, FAKE * 4, R, 0x4, None) == 1  # flag check as for complex
+        assert tpd.lib.tpd_synthesize_ex(FAKE, 4, FAKE * 4, R, 0x4, None) == 1
         h = ctypes.c_void_p()
         assert tpd.lib.tpd_plan_create_batched(ns, 2, R, 0, 0, ctypes.byref(h)) == 2
+    # the host replays cover the complex dtypes only
+    with pytest.raises(tpd.TPDError):
+        tpd.emulate(np.zeros((4, 4)), dtype=tpd.TPD_R64)
 
 
 def test_batched_validation():

@@ -544,6 +544,46 @@ def test_real_synthesis(n):
         assert np.array_equal(T.view(1 << n, 1 << n).cpu().numpy(), A.cpu().numpy())
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_real_batched(dtype):
+    # real matrices of mixed sizes in one persistent launch: each output is
+    # the single-matrix real decomposition's, value for value; graph replay
+    ns = [int(v) for v in W.batched_qubits(300, seed=27)]
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    mats = [W.real_gaussian(n, seed=2700 + k, symmetric=(k % 2 == 1)).astype(npdt) for k, n in enumerate(ns)]
+    dm = [torch.from_numpy(m).to(DEV) for m in mats]
+    refs = [tpd.decompose(m).cpu().numpy() for m in dm]
+    outs = tpd.decompose_batched(dm)
+    for k, (o, r) in enumerate(zip(outs, refs)):
+        assert o.dtype == dtype and np.array_equal(o.cpu().numpy(), r), k
+    code = tpd.TPD_R64 if dtype == torch.float64 else tpd.TPD_R32
+    plan = tpd.BatchedPlan(ns, code)
+    dp, do = tpd.BatchedPlan.pointer_table(dm), tpd.BatchedPlan.pointer_table(outs)
+    s_ = torch.cuda.Stream()
+    s_.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s_):
+        plan.execute(dp, do)  # warm up on the capture stream
+    torch.cuda.current_stream().wait_stream(s_)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.execute(dp, do)
+    for rep in range(2):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, (o, r) in enumerate(zip(outs, refs)):
+            assert np.array_equal(o.cpu().numpy(), r), (rep, k)
+    plan.close()
+    # in place, matrix layout
+    dm2 = [m.clone() for m in dm]
+    tpd.decompose_batched(dm2, "inplace", layout="matrix")
+    for k, (m, n) in enumerate(zip(dm2, ns)):
+        assert np.array_equal(matrix_to_canonical(m.cpu().numpy().ravel(), n), refs[k]), k
+
+
 @pytest.mark.parametrize("n", [9, 12, 13])
 def test_real_symmetric_hermitian_mode(n):
     A = W.real_gaussian(n, seed=2300 + n, symmetric=True)
