@@ -55,6 +55,30 @@ def test_ingest_scales_by_the_copy_and_keys_by_symbol(tmp_path, monkeypatch):
     assert bench.load_traffic(K2, 16) is None
 
 
+def test_ingest_calibrates_on_the_2_32_byte_copy_and_splits_reduced_modes(tmp_path):
+    # restores of other sizes (in-place legs) must not enter the calibration,
+    # and Hermitian / real-symmetric dispatches of a shared symbol are kept
+    # apart from the full ones
+    copy = 1 << 32
+    kr = "void tpd::k_sweep<tpd::Real<float>, tpd::Geom<8, 6, 0, 4, 0>, 0, 0, false>(tpd::SweepArgs)"
+    alg = 4 ** 16 * 4  # real float32 sweep bytes read (or written)
+    fetch = [(COPY, 0.5 * 4 * copy / 1024), (COPY, 0.5 * copy / 1024), (COPY, 0.5 * 8 * copy / 1024),
+             (kr, 0.5 * alg / 1024), (kr, 0.5 * alg / 1024), (kr, 0.5 * 0.5 * alg / 1024), (kr, 0.5 * 0.6 * alg / 1024)]
+    write = [(COPY, 4 * copy / 1024), (COPY, copy / 1024), (COPY, 8 * copy / 1024),
+             (kr, alg / 1024), (kr, alg / 1024), (kr, 0.5 * alg / 1024), (kr, alg / 1024)]
+    f1, w1 = tmp_path / "f.csv", tmp_path / "w.csv"
+    write_csv(f1, fetch)
+    write_csv(w1, write)
+    doc = bench.ingest_pmc([(str(f1), str(w1))], str(tmp_path / "t.json"))
+    assert abs(doc["scales"][0]["fetch_scale"] - 0.5) < 1e-12 and doc["scales"][0]["write_scale"] == 1.0
+    k = doc["kernels"][kr]
+    assert k["dtype"] == "r32" and k["dispatches"] == 2
+    assert abs(k["fetch_over_algorithmic"] - 1.0) < 1e-12 and abs(k["write_over_algorithmic"] - 1.0) < 1e-12
+    red = k["reduced_mode_dispatches"]
+    assert red["count"] == 2 and abs(red["fetch_over_algorithmic"] - 0.55) < 1e-12
+    assert abs(red["write_over_algorithmic"] - 0.75) < 1e-12
+
+
 def test_ingest_needs_the_copy_calibration(tmp_path):
     f1, w1 = tmp_path / "f.csv", tmp_path / "w.csv"
     write_csv(f1, [(K1, 1.0)])
