@@ -17,7 +17,9 @@
  *   - Complex numbers are interleaved (re, im): TPD_C128 = two IEEE binary64
  *     (16 bytes), TPD_C64 = two IEEE binary32 (8 bytes).
  *   - A is row-major with leading dimension 2^n.
- *   - Coefficients, canonical layout (default): 4^n complex values, the
+ *   - Real input (TPD_R64, TPD_R32): plain binary64 / binary32 entries, and
+ *     real-coded coefficients (see TPD_R64 below).
+ *   - Coefficients, canonical layout (default): 4^n values, the
  *     weight of string t_1..t_n at index q = sum_k t_k 4^(n-k), t_1 being the
  *     first (outermost) tensor factor.
  *   - Coefficients, matrix layout (TPD_FLAG_LAYOUT_MATRIX): the weight of t
@@ -262,9 +264,10 @@ tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len);
  * every later call and plan with the same key uses on this process (and,
  * if the environment variable TPD_AUTOTUNE_CACHE names a file, appended
  * there and reloaded by later processes).  Candidates: tile widths of
- * 2^3..2^5 (complex128) or 2^4..2^6 (complex64) XOR-diagonals, one
- * workgroup per tile or a persistent grid of 1, 2 or 4 workgroups per CU
- * (which load the next tile while transforming the current one).
+ * 2^3..2^5 (complex128) or 2^4..2^6 (complex64 and the real dtypes)
+ * XOR-diagonals, one workgroup per tile or a persistent grid of 1, 2 or 4
+ * workgroups per CU (which load the next tile while transforming the
+ * current one).
  * The choice never changes results (same operations in the same order).
  * Arguments as tpd_decompose_ex; `coeffs` is overwritten; with
  * A == coeffs the matrix is transformed repeatedly (destroyed).  Allocates
