@@ -116,8 +116,10 @@ typedef enum {
  * The real parts are bitwise those of the general schedule.  Results are
  * undefined if A is not Hermitian.  n <= 8 runs the general schedule.     */
 
-/* Largest supported n: 16 for every dtype (the two-sweep tile schedule and
- * 288 GB of HBM for an out-of-place n = 16 C128 pair). */
+/* Largest supported n: 16 for TPD_C128, 17 for TPD_C64, TPD_R64 and
+ * TPD_R32 (288 GB of HBM: an n = 17 complex128 matrix alone takes 256 GiB;
+ * n = 17 runs a first sweep of 9 levels with tiles of at most 2^5
+ * XOR-diagonals).  -1 for an unknown dtype. */
 int tpd_max_qubits(tpd_dtype_t dtype);
 
 /* Decompose one matrix, complex128, canonical layout, pruning on.

@@ -25,7 +25,7 @@ using namespace tpd;
 
 namespace {
 
-constexpr int kMaxQubits = 16;
+constexpr int kMaxQubits = 17;  // the largest n of any dtype (see max_qubits)
 constexpr int kMaxBatchQubits = 9;
 
 bool log_on() {
@@ -46,6 +46,10 @@ void logf(const char* fmt, ...) {
 }
 
 size_t elem_bytes(Dtype dt) { return dt == DT_C128 ? 16 : dt == DT_R32 ? 4 : 8; }  // C64 and R64: 8
+// Largest n: the two-sweep schedule covers n <= 17 (a first sweep of 9
+// levels); complex128 stops at 16, where one n = 17 matrix would take 256 GiB.
+int max_qubits(Dtype dt) { return dt == DT_C128 ? 16 : kMaxQubits; }
+
 const char* dtype_name(Dtype dt) {
   return dt == DT_C128 ? "c128" : dt == DT_C64 ? "c64" : dt == DT_R64 ? "r64" : "r32";
 }
@@ -101,7 +105,7 @@ int default_db(Dtype dt, int n2) {
 void load_tune_cache();
 
 tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, const Tuned* force, Schedule* s) {
-  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  if (n < 0 || n > max_qubits(dt)) return TPD_ERROR_UNSUPPORTED;
   *s = Schedule{};
   s->n = n;
   s->dt = dt;
@@ -144,6 +148,10 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
                                    (flags & TPD_FLAG_HERMITIAN) ? 1 : 0});
     if (it != g_tuned.end()) t = it->second;
   }
+  // tiles of 2^(n1 + db) elements: at most 1024 threads of 16 elements and
+  // 128 KiB of LDS (n = 17 has a first sweep of 9 levels)
+  const int max_tile_bits = dt == DT_C128 ? 13 : 14;
+  if (!force && s->n1 + t.db > max_tile_bits) t.db = max_tile_bits - s->n1;
   if (t.db > s->n2) return TPD_ERROR_INVALID_VALUE;  // MID needs the low db x bits in sweep 2
   const int db = t.db;
   s->prune = (flags & TPD_FLAG_NO_PRUNE) == 0;
@@ -216,7 +224,7 @@ uint64_t group_words_of(const Schedule& s) {
 // closed 16-run sets, writing 2^db-column runs of A), then the high n1 levels
 // in place on A.
 tpd_status_t make_synth_schedule(int n, Dtype dt, unsigned flags, bool in_place, Schedule* s) {
-  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  if (n < 0 || n > max_qubits(dt)) return TPD_ERROR_UNSUPPORTED;
   *s = Schedule{};
   s->n = n;
   s->dt = dt;
@@ -762,7 +770,7 @@ extern "C" {
 
 int tpd_max_qubits(tpd_dtype_t dtype) {
   if (dtype != TPD_C128 && dtype != TPD_C64 && dtype != TPD_R64 && dtype != TPD_R32) return -1;
-  return kMaxQubits;
+  return max_qubits((Dtype)dtype);
 }
 
 const char* tpd_status_string(tpd_status_t s) {
@@ -818,7 +826,7 @@ tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dt
                               tpd_stream_t stream) {
   tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
-  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  if (n < 0 || n > max_qubits((Dtype)dtype)) return TPD_ERROR_UNSUPPORTED;
   const Dtype dt = (Dtype)dtype;
   st = check_buffers(A, coeffs, n, dt);
   if (st) return st;
@@ -846,7 +854,7 @@ tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t d
   tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (flags & ~(TPD_FLAG_LAYOUT_MATRIX | TPD_FLAG_NO_PRUNE)) return TPD_ERROR_INVALID_VALUE;
-  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  if (n < 0 || n > max_qubits((Dtype)dtype)) return TPD_ERROR_UNSUPPORTED;
   const Dtype dt = (Dtype)dtype;
   st = check_buffers(coeffs, A, n, dt);
   if (st) return st;
@@ -864,7 +872,7 @@ tpd_status_t tpd_decompose_partial(const void* A, int n, void* coeffs, const uin
   tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (flags & TPD_FLAG_TIMING) return TPD_ERROR_INVALID_VALUE;
-  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  if (n < 0 || n > max_qubits((Dtype)dtype)) return TPD_ERROR_UNSUPPORTED;
   const Dtype dt = (Dtype)dtype;
   st = check_buffers(A, coeffs, n, dt);
   if (st) return st;
@@ -914,7 +922,7 @@ tpd_status_t tpd_compact(const void* coeffs, int n, tpd_dtype_t dtype, unsigned 
   tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (flags & ~TPD_FLAG_LAYOUT_MATRIX) return TPD_ERROR_INVALID_VALUE;
-  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  if (n < 0 || n > max_qubits((Dtype)dtype)) return TPD_ERROR_UNSUPPORTED;
   const Dtype dt = (Dtype)dtype;
   if (!coeffs || !count || ((uintptr_t)coeffs % elem_bytes(dt)) || ((uintptr_t)count % 8))
     return TPD_ERROR_INVALID_VALUE;
@@ -1279,7 +1287,7 @@ extern "C" tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* co
                                                   tpd_stream_t stream) {
   tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
-  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  if (n < 0 || n > max_qubits((Dtype)dtype)) return TPD_ERROR_UNSUPPORTED;
   if (grid_per_cu < 0 || grid_per_cu > 64) return TPD_ERROR_INVALID_VALUE;
   const Dtype dt = (Dtype)dtype;
   st = check_buffers(A, coeffs, n, dt);
@@ -1310,7 +1318,7 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
                                      tpd_stream_t stream, char* report, size_t len) {
   tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
-  if (n < 0 || n > kMaxQubits) return TPD_ERROR_UNSUPPORTED;
+  if (n < 0 || n > max_qubits((Dtype)dtype)) return TPD_ERROR_UNSUPPORTED;
   const Dtype dt = (Dtype)dtype;
   st = check_buffers(A, coeffs, n, dt);
   if (st) return st;

@@ -288,7 +288,7 @@ hipError_t launch_one(const SweepArgs& a, int grid_req, hipStream_t st) {
   constexpr int R1 = (XB + DB - 10) > RR ? (XB + DB - 10) : RR;
   constexpr int R = (XB + DB) < R1 ? (XB + DB) : R1;
   using G = Geom<XB, DB, 0, R, ORDER>;
-  if constexpr (!shape_fits<S>(XB, DB)) {
+  if constexpr (!shape_fits<S>(XB, DB) || XB + DB > 14) {  // <= 1024 threads of 16 elements
     return hipErrorInvalidValue;
   } else {
     // one workgroup per tile, or a persistent grid that loops over tiles;
@@ -317,7 +317,7 @@ hipError_t dispatch_one(const SweepDesc& s, const SweepArgs& a, hipStream_t st) 
   return hipErrorInvalidValue;
 }
 
-// two-sweep halves: XB in 4..8 for the tile widths DB of one dtype, 16
+// two-sweep halves: XB in 4..9 for the tile widths DB of one dtype, 16
 // elements per thread; the bottom-first phase order only for the default
 // tile width
 template <class S, int XB, int DB, int RR>
@@ -346,6 +346,7 @@ hipError_t dispatch_two_xb(const SweepDesc& s, const SweepArgs& a, hipStream_t s
     case 6: return dispatch_two_r<S, 6, DB>(s, a, st);
     case 7: return dispatch_two_r<S, 7, DB>(s, a, st);
     case 8: return dispatch_two_r<S, 8, DB>(s, a, st);
+    case 9: return dispatch_two_r<S, 9, DB>(s, a, st);  // n = 17, first sweep
   }
   return hipErrorInvalidValue;
 }
@@ -368,6 +369,7 @@ hipError_t dispatch_inv_two(const SweepDesc& s, const SweepArgs& a, hipStream_t 
     case 6: return dispatch_inv_layouts<S, 6, DB>(s, a, st);
     case 7: return dispatch_inv_layouts<S, 7, DB>(s, a, st);
     case 8: return dispatch_inv_layouts<S, 8, DB>(s, a, st);
+    case 9: return dispatch_inv_layouts<S, 9, DB>(s, a, st);  // n = 17, second synthesis sweep
   }
   return hipErrorInvalidValue;
 }

@@ -34,10 +34,12 @@ def test_every_declared_symbol_is_exported():
 def test_status_strings_and_limits():
     for code, name in tpd.STATUS.items():
         assert tpd.lib.tpd_status_string(code).decode() == name
+    # complex128 stops at 16 (one n = 17 matrix would take 256 GiB); the
+    # 8- and 4-byte dtypes reach 17
     assert tpd.max_qubits(tpd.TPD_C128) == 16
-    assert tpd.max_qubits(tpd.TPD_C64) == 16
-    assert tpd.max_qubits(tpd.TPD_R64) == 16
-    assert tpd.max_qubits(tpd.TPD_R32) == 16
+    assert tpd.max_qubits(tpd.TPD_C64) == 17
+    assert tpd.max_qubits(tpd.TPD_R64) == 17
+    assert tpd.max_qubits(tpd.TPD_R32) == 17
     assert tpd.lib.tpd_max_qubits(7) == -1
 
 
@@ -72,7 +74,8 @@ FAKE = 0x100000  # never dereferenced: validation fails or the device check stop
     ((FAKE, -1, FAKE * 4, 0, 0), 2),       # n negative
     ((FAKE, 4, FAKE * 4 + 4, 2, 0), 1),    # misaligned real float64
     ((FAKE, 4, FAKE + 8, 2, 0), 1),        # partial overlap, real (8-byte elements)
-    ((FAKE, 17, FAKE * 64, 2, 0), 2),      # n too large, real
+    ((FAKE, 18, FAKE * 64, 2, 0), 2),      # n too large, real
+    ((FAKE, 18, FAKE * 64, 1, 0), 2),      # n too large, complex64
     ((FAKE, 10, FAKE, 2, 0), 2),           # real, in place canonical
     ((FAKE, 4, FAKE * 4 + 2, 3, 0), 1),    # misaligned real float32
     ((FAKE, 4, FAKE + 4, 3, 0), 1),        # partial overlap, real float32 (4-byte elements)
@@ -145,9 +148,13 @@ def test_plan_validation():
     assert tpd.lib.tpd_plan_num_kernels(None) == -1
 
 
-@pytest.mark.parametrize("n", range(0, 17))
+@pytest.mark.parametrize("n", range(0, 18))
 def test_schedule_shapes(n):
     for dt in (tpd.TPD_C128, tpd.TPD_C64, tpd.TPD_R64, tpd.TPD_R32):
+        if n > tpd.max_qubits(dt):
+            with pytest.raises(tpd.TPDError):
+                tpd.schedule(n, dt)
+            continue
         s = tpd.schedule(n, dt)
         es = {tpd.TPD_C128: 16, tpd.TPD_R32: 4}.get(dt, 8)
         assert s["elements"] == 4 ** n
@@ -162,7 +169,7 @@ def test_schedule_shapes(n):
         assert bits == list(range(n))
         for w in sw:
             assert w["tiles"] * w["tile_elems"] == 4 ** n
-            assert w["tile_elems"] * es <= 65536  # one workgroup's LDS
+            assert w["tile_elems"] * es <= 131072  # one workgroup's LDS tile
             assert w["threads"] <= 1024
         if n >= 9:
             assert sw[0]["bitmap"] == "set" and sw[1]["bitmap"] == "check"

@@ -656,6 +656,74 @@ def test_n16_real_in_place_every_tuning_candidate(hermitian, dtype):
 
 
 # ----------------------------------------------------------------------------
+# n = 17 (complex64 and the real dtypes): a first sweep of 9 levels
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.float32, torch.float64])
+def test_n17_in_place_sampled_strings(dtype):
+    n = 17
+    torch.cuda.empty_cache()
+    A = W.gaussian_device(n, seed=17, dtype=dtype, hermitian=True)
+    real = not A.is_complex()
+    a_max = 0.0  # by row blocks: a full-size temporary would not fit beside A
+    for r0 in range(0, 1 << n, 4096):
+        blk = A[r0:r0 + 4096]
+        a_max = max(a_max, float((blk.abs() if real else torch.view_as_real(blk).abs()).max()))
+    qs = W.sampled_strings(n, 1000, seed=17)
+    bf = sampled_oracle(A, n, qs)  # read before the in-place transform
+    exp = real_coded(bf, qs)[0] if real else bf
+    tol = n * U64 * a_max if dtype == torch.float64 else (n + 1) * U32 * a_max
+    h, l = deinterleave(qs.astype(np.int64))
+    hb = torch.from_numpy(h).to(DEV)
+    lb = torch.from_numpy(l).to(DEV)
+    pristine = A.clone() if dtype == torch.float32 else None  # 64 GiB: room for a copy
+    tpd.decompose(A, A.view(-1), layout="matrix")
+    ref = A[hb, lb].cpu().numpy()
+    assert cerr(ref, exp) <= tol
+    if real:
+        assert np.all(ref[y_odd(qs)] == 0)  # real symmetric: no odd-Y weight
+    if pristine is not None:
+        for herm in (False, True):
+            for db in (4, 5):
+                for g in (0, 4):
+                    A.copy_(pristine)
+                    tpd.decompose_tuned(A, A.view(-1), db=db, grid_per_cu=g, layout="matrix", hermitian=herm)
+                    assert np.array_equal(A[hb, lb].cpu().numpy(), ref), (herm, db, g)
+    del A, pristine
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.float32])
+def test_n17_round_trip_in_place_integer_exact(dtype):
+    # integer weights synthesized in place into the 131072 x 131072 matrix
+    # and decomposed back in place: exact
+    n = 17
+    m = 4 ** n
+    torch.cuda.empty_cache()
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(1717)
+    T = torch.empty(m, dtype=dtype, device=DEV)
+    Tr = torch.view_as_real(T) if T.is_complex() else T.view(-1, 1)
+    step = 1 << 28
+    for c in range(0, m, step):
+        for k in range(Tr.shape[1]):
+            Tr[c:c + step, k].copy_(torch.randint(-8, 9, (min(step, m - c),), generator=gen, device=DEV))
+    probe = torch.randint(0, m, (4096,), generator=gen, device=DEV)
+    before = T[probe].cpu().numpy()
+    def total(t):  # exact for these integers; by chunks to stay small
+        v = torch.view_as_real(t).reshape(-1) if t.is_complex() else t
+        return sum(float(v[c:c + step].double().sum()) for c in range(0, v.numel(), step))
+
+    checksum = total(T)
+    M = T.view(1 << n, 1 << n)
+    tpd.synthesize(T, M, layout="matrix")
+    tpd.decompose(M, T, layout="matrix")
+    assert np.array_equal(T[probe].cpu().numpy(), before)
+    assert total(T) == checksum
+    del T, M
+    torch.cuda.empty_cache()
+
+
+# ----------------------------------------------------------------------------
 # edge cases, determinism, poison fill, errors
 # ----------------------------------------------------------------------------
 def test_edge_cases():
