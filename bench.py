@@ -310,7 +310,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=16)
-    ap.add_argument("--extras", default="synth,partial,hermitian,outofplace,real,fp32,n14dense,n14,batched",
+    ap.add_argument("--extras", default="synth,partial,hermitian,outofplace,real,fp32,n14dense,n14,batched,n17",
                     help="comma list of synth,partial,hermitian,outofplace,fp32,n14dense,n14,batched, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -663,6 +663,35 @@ def main():
             del mats, outs, g
             torch.cuda.empty_cache()
         result["batched"] = bres
+
+    if "n17" in extras:
+        log("extra: n=17 (131072 x 131072): real float32 in place with restores, complex64 in place once")
+        n17 = 17
+        d17 = {}
+        R = W.gaussian_device(n17, seed=17, dtype=torch.float32, hermitian=True)  # 64 GiB, real symmetric
+        r, B = inplace_run(tpd, torch, R, n17, tpd.TPD_R32, args.steps, args.warmup, 4)
+        d17["r32"] = r
+        del B, R
+        torch.cuda.empty_cache()
+        # complex64: 128 GiB, no room for a pristine copy; one decomposition
+        # of a freshly generated input, timed by the plan's events
+        C = W.gaussian_device(n17, seed=17, dtype=torch.complex64, hermitian=True)
+        plan = tpd.Plan(n17, tpd.TPD_C64, timing=True, in_place=True, layout="matrix")
+        torch.cuda.synchronize()
+        plan.execute(C, C.view(-1))
+        torch.cuda.synchronize()
+        kav, _ = kernel_avgs(plan)
+        desc = plan.describe()
+        plan.close()
+        ms = sum(kav)
+        d17["c64_single"] = {
+            "ms": ms, "kernel_ms": kav, "coeffs_per_s": 4 ** n17 / (ms / 1e3),
+            "sweep_GBps": [2 * 4 ** n17 * 8 / (k / 1e3) / 1e9 for k in kav],
+            "schedule": [{k: w[k] for k in ("xb", "db", "r", "grid", "tile_elems", "threads")} for w in desc["sweeps"]],
+        }
+        del C
+        torch.cuda.empty_cache()
+        result["n17"] = d17
 
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")

@@ -249,9 +249,11 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   // so that the loop is entered with the same operations in flight as on
   // its back edge (next loads, then current stores): the copy of the
   // prefetched data then waits for those loads only, never for the stores.
-  // Workgroups of 1024 threads have 128 registers per thread and no room
-  // for a second copy of the tile: they load at the top of each iteration.
-  constexpr bool PF = G::NT < 1024;
+  // Workgroups of 1024 threads have 128 registers per thread: a second copy
+  // of the tile fits only for 4-byte elements, and not beside the canonical
+  // store's extra LDS pass (those spill); the others load at the top of
+  // each iteration.
+  constexpr bool PF = G::NT < 1024 || (sizeof(E) <= 4 && OUTL != L_CAN && !INV);
   if constexpr (PF) {
     Tile cur, nxt;
     const uint64_t first = next_tile(blockIdx.x, cur);

@@ -1093,6 +1093,32 @@ def test_n15_every_schedule_same_bits(dtype, dbs):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_n15_real_out_of_place_every_schedule(dtype):
+    # real input at n = 15, canonical order out of place: 2^14-element tiles
+    # (float32 ones prefetch the next tile at 1024 threads in the first
+    # sweep); every tile width and grid gives the same values, which match
+    # the definition on sampled strings
+    n = 15
+    torch.cuda.empty_cache()
+    A = W.gaussian_device(n, seed=151, dtype=dtype, hermitian=False)
+    ref = tpd.decompose(A)
+    qs = W.sampled_strings(n, 600, seed=152)
+    qd = torch.from_numpy(qs.astype(np.int64)).to(DEV)
+    exp = real_coded(sampled_oracle(A, n, qs), qs)[0]
+    a_max = float(A.abs().max())
+    tol = n * U64 * a_max if dtype == torch.float64 else (n + 1) * U32 * a_max
+    assert np.max(np.abs(ref[qd].cpu().numpy().astype(np.float64) - exp)) <= tol
+    out = torch.empty_like(ref)
+    for db in (4, 5, 6):
+        for g in (0, 1, 4):
+            out.fill_(float("nan"))
+            tpd.decompose_tuned(A, out, db=db, grid_per_cu=g)
+            assert torch.equal(out, ref), (db, g)
+    del A, ref, out
+    torch.cuda.empty_cache()
+
+
 def test_partial_with_hermitian_flag_and_in_place():
     n = 12
     A = W.gaussian(n, seed=1600, hermitian=True)
