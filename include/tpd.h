@@ -104,7 +104,8 @@ typedef enum {
 #define TPD_FLAG_TIMING 0x4u        /* plans only: record per-kernel HIP events */
 #define TPD_FLAG_ORDER_BOTTOM 0x8u  /* register phases bottom level first (tuning) */
 #define TPD_FLAG_HERMITIAN 0x10u    /* caller promises A = A^H (see below) */
-#define TPD_FLAGS_ALL 0x1Fu
+#define TPD_FLAG_ROTATE_TILES 0x20u /* second sweep: row blocks rotate every 8 tile columns (tuning) */
+#define TPD_FLAGS_ALL 0x3Fu
 
 /* TPD_FLAG_HERMITIAN: for a Hermitian A every weight is real (section
  * "Results" discusses the real-symmetric promise; Hermitian => real follows
@@ -132,7 +133,7 @@ tpd_status_t tpd_decompose(const void* A, int n, void* coeffs, tpd_stream_t stre
 
 /* Same, with the dtype (TPD_C128, TPD_C64, TPD_R64, TPD_R32) and flags
  * (TPD_FLAG_NO_PRUNE, TPD_FLAG_LAYOUT_MATRIX, TPD_FLAG_ORDER_BOTTOM,
- * TPD_FLAG_HERMITIAN) chosen by the caller.  coeffs may equal A (in place)
+ * TPD_FLAG_HERMITIAN, TPD_FLAG_ROTATE_TILES) chosen by the caller.  coeffs may equal A (in place)
  * for any n with TPD_FLAG_LAYOUT_MATRIX and for n <= 6 in the canonical
  * order; otherwise TPD_ERROR_UNSUPPORTED.                                 */
 tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
@@ -269,7 +270,10 @@ tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len);
  * 2^3..2^5 (complex128) or 2^4..2^6 (complex64 and the real dtypes)
  * XOR-diagonals, one workgroup per tile or a persistent grid of 1, 2 or 4
  * workgroups per CU (which load the next tile while transforming the
- * current one).
+ * current one); then the fastest of these once more with the second
+ * sweep's rotated tile order (TPD_FLAG_ROTATE_TILES: which tiles run side by
+ * side, hence how their rows meet the memory channels, depends on where the
+ * buffer sits in physical memory).
  * The choice never changes results (same operations in the same order).
  * Arguments as tpd_decompose_ex; `coeffs` is overwritten; with
  * A == coeffs the matrix is transformed repeatedly (destroyed).  Allocates

@@ -22,6 +22,7 @@ struct SweepDesc {
   bool is_one;      // the single sweep of an n <= 8 schedule
   int herm;         // 1: the input is Hermitian (read representatives only)
   bool inv;         // inverse butterflies (synthesis)
+  int tile_order;   // 1: row blocks rotate every 8 d-groups (second sweep, tuning)
   uint64_t ntiles;
 };
 
@@ -46,6 +47,7 @@ struct SweepArgs {
   const uint32_t* list_count;
   int list_shift;
   uint64_t ntiles;  // with a list: the most tiles it can hold
+  int tile_order;   // 1: rotated tile order (see SweepDesc)
 };
 
 // Batched work item: `nmat` matrices of the same n starting at `mat0`

@@ -86,6 +86,13 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
     } else {
       t.td = tile & tdmask;
       t.xf = tile >> a.nfix_d;
+      if (a.tile_order) {
+        // rotated order: the row block index advances with every 8 d-groups,
+        // so workgroups running at the same time spread over row blocks (a
+        // bijection of the tile index: the tile count is a power of two)
+        const uint64_t xmask = (ntiles >> a.nfix_d) - 1;
+        t.xf = (t.xf ^ (t.td >> 3)) & xmask;
+      }
     }
     t.xfix = (t.xf & (((uint64_t)1 << xlo) - 1)) | ((t.xf >> xlo) << (xlo + G::XB));
     if (a.req && !((uniform_word(a.req, t.td >> 5) >> (t.td & 31)) & 1u)) return false;

@@ -26,6 +26,7 @@ FLAG_LAYOUT_MATRIX = 0x2
 FLAG_TIMING = 0x4
 FLAG_ORDER_BOTTOM = 0x8
 FLAG_HERMITIAN = 0x10
+FLAG_ROTATE_TILES = 0x20
 
 STATUS = {
     0: "TPD_SUCCESS",
@@ -297,8 +298,9 @@ def decompose(A, out=None, *, layout: str = "canonical", prune: bool = True, ord
 
 
 def decompose_tuned(A, out=None, *, db: int, grid_per_cu: int = 0, r: int = 4, layout: str = "canonical",
-                    prune: bool = True, hermitian: bool = False, stream=None):
-    """decompose() with a forced two-sweep schedule (test aid)."""
+                    prune: bool = True, hermitian: bool = False, rotate: bool = False, stream=None):
+    """decompose() with a forced two-sweep schedule (test aid); rotate=True
+    selects the second sweep's rotated tile order."""
     torch = _torch()
     n = _check_matrix(A)
     if out is None:
@@ -306,8 +308,8 @@ def decompose_tuned(A, out=None, *, db: int, grid_per_cu: int = 0, r: int = 4, l
     if out.dtype != A.dtype or not out.is_cuda or not out.is_contiguous() or out.numel() != 4 ** n:
         raise ValueError("out must be a contiguous CUDA tensor of 4^n elements of A's dtype")
     _check(lib.tpd_debug_decompose_tuned(A.data_ptr(), n, out.data_ptr(), _dtype_code(A),
-                                         _flags(layout, prune, False, hermitian), db, r, grid_per_cu,
-                                         _stream(stream)), "tpd_debug_decompose_tuned")
+                                         _flags(layout, prune, False, hermitian) | (FLAG_ROTATE_TILES if rotate else 0),
+                                         db, r, grid_per_cu, _stream(stream)), "tpd_debug_decompose_tuned")
     return out
 
 

@@ -2,11 +2,13 @@
 function include/tpd.h declares, validates arguments before touching a
 device, and its host helpers and schedule planner behave as documented."""
 import ctypes
-
-import numpy as np
+import json
 import os
 import re
+import subprocess
+import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -187,6 +189,30 @@ def test_schedule_flags():
     assert not s["prune"] and all(w["bitmap"] == "none" for w in s["sweeps"])
     with pytest.raises(tpd.TPDError):
         tpd.schedule(12, tpd.TPD_C128, 0, in_place=True)
+
+
+def test_tune_cache_lines_with_and_without_tile_order(tmp_path):
+    # the autotune cache's optional last field selects the second sweep's
+    # rotated tile order; older lines without it keep the plain order
+    cache = tmp_path / "tune.txt"
+    cache.write_text("tpd-tune-v2 gfx950 0 0 16 1 1 0 4 4 2 1\n"
+                     "tpd-tune-v2 gfx950 0 1 16 1 1 0 6 4 4\n"
+                     "tpd-tune-v2 gfx950 0 0 14 0 0 0 3 4 0 1\n"
+                     "garbage line\n")
+    code = ("import json; from paper_2310_13421_amd import tpd\n"
+            "a = tpd.schedule(16, tpd.TPD_C128, tpd.FLAG_LAYOUT_MATRIX, in_place=True)['sweeps']\n"
+            "b = tpd.schedule(16, tpd.TPD_C64, tpd.FLAG_LAYOUT_MATRIX, in_place=True)['sweeps']\n"
+            "c = tpd.schedule(14, tpd.TPD_C128)['sweeps']\n"
+            "d = tpd.schedule(14, tpd.TPD_C128, tpd.FLAG_ROTATE_TILES | tpd.FLAG_NO_PRUNE)['sweeps']\n"
+            "print(json.dumps([[(w['db'], w['tile_order']) for w in x] for x in (a, b, c, d)]))\n")
+    env = dict(os.environ, TPD_AUTOTUNE_CACHE=str(cache))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT, timeout=300)
+    assert r.returncode == 0, r.stderr
+    a, b, c, d = json.loads(r.stdout.strip().splitlines()[-1])
+    assert a == [[4, 0], [4, 1]]  # only the second sweep rotates
+    assert b == [[6, 0], [6, 0]]
+    assert c == [[3, 0], [3, 1]]
+    assert d[1][1] == 1
 
 
 def test_single_hip_runtime_in_process():

@@ -395,7 +395,8 @@ def test_n16_in_place_every_tuning_candidate(dtype, dbs):
         for db in dbs:
             for g in (0, 1, 2, 4):
                 B.copy_(A)
-                tpd.decompose_tuned(B, B.view(-1), db=db, grid_per_cu=g, layout="matrix", hermitian=herm)
+                tpd.decompose_tuned(B, B.view(-1), db=db, grid_per_cu=g, layout="matrix", hermitian=herm,
+                                    rotate=(g == 4))
                 got = B[hb, lb].cpu().numpy()
                 if herm:
                     assert np.array_equal(got.real, ref.real) and np.all(got.imag == 0), (db, g)
@@ -1084,9 +1085,10 @@ def test_n15_every_schedule_same_bits(dtype, dbs):
     out = torch.empty_like(ref)
     for db in dbs:
         for g in (0, 1, 4):
-            out.fill_(float("nan"))
-            tpd.decompose_tuned(A, out, db=db, grid_per_cu=g)
-            assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref)), (db, g)
+            for rot in (False, True):
+                out.fill_(float("nan"))
+                tpd.decompose_tuned(A, out, db=db, grid_per_cu=g, rotate=rot)
+                assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref)), (db, g, rot)
     with pytest.raises(tpd.TPDError):
         tpd.decompose_tuned(A, out, db=9)
     del A, ref, out
