@@ -433,11 +433,13 @@ class Plan:
     graph-capturable.  timing=True records HIP events around each kernel."""
 
     def __init__(self, n: int, dtype: int = TPD_C128, *, layout: str = "canonical", prune: bool = True,
-                 in_place: bool = False, timing: bool = False, order_bottom: bool = False, hermitian: bool = False):
+                 in_place: bool = False, timing: bool = False, order_bottom: bool = False, hermitian: bool = False,
+                 rotate: bool = False):
         self.n = n
         self.dtype = dtype
         self.in_place = in_place
         f = _flags(layout, prune, order_bottom, hermitian) | (FLAG_TIMING if timing else 0)
+        f |= FLAG_ROTATE_TILES if rotate else 0
         h = ctypes.c_void_p()
         _check(lib.tpd_plan_create(n, dtype, f, int(in_place), ctypes.byref(h)), "tpd_plan_create")
         self._h = h

@@ -812,6 +812,36 @@ def test_single_plan_graph_capture_and_timing():
     plan.close()
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_real_plan_graph_capture(dtype):
+    # a real-input plan (pruning bitmap, rotated second-sweep order) captured
+    # once and replayed, with eager work between the replays
+    n = 12
+    A = W.real_gaussian(n, seed=1212, symmetric=True).astype(np.float64 if dtype == torch.float64 else np.float32)
+    Ad = torch.from_numpy(A).to(DEV)
+    ref = tpd.decompose(Ad).cpu().numpy()
+    code = tpd.TPD_R64 if dtype == torch.float64 else tpd.TPD_R32
+    out = torch.empty(4 ** n, dtype=dtype, device=DEV)
+    for flags in ({}, {"hermitian": True, "rotate": True}):
+        plan = tpd.Plan(n, code, **flags)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            plan.execute(Ad, out)  # warm up on the capture stream
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plan.execute(Ad, out)
+        for _ in range(3):
+            out.fill_(float("nan"))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), ref), flags
+        plan.close()
+
+
 def test_autotune_keeps_results_bitwise():
     for n, dtype in ((11, torch.complex128), (12, torch.complex64)):
         A = to_dev(W.gaussian(n, seed=90 + n), dtype)
