@@ -159,12 +159,25 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
     if (it != g_tuned.end()) t = it->second;
   }
   // tiles of 2^(levels + db) elements: at most 1024 threads of 16 elements
-  // and 128 KiB of LDS (n = 17 has a sweep of 9 levels)
+  // and 128 KiB of LDS (n = 17 has a sweep of 9 levels).  In the matrix
+  // layout without the Hermitian mode each sweep takes the requested width
+  // up to its own cap (n = 17: 2^6 in the 8-level sweep, 2^5 in the 9-level
+  // one; the pruning bits follow the second sweep's d-groups); otherwise
+  // both sweeps share one width (MID order, Hermitian representatives).
   const int max_tile_bits = dt == DT_C128 ? 13 : 14;
-  const int nmax = s->n1 > s->n2 ? s->n1 : s->n2;
-  if (!force && nmax + t.db > max_tile_bits) t.db = max_tile_bits - nmax;
-  if (t.db > s->n2) return TPD_ERROR_INVALID_VALUE;  // MID needs the low db x bits in sweep 2
-  const int db = t.db;
+  const int cap1 = max_tile_bits - s->n1, cap2 = max_tile_bits - s->n2;
+  const bool split_db = s->matrix_layout && !(flags & TPD_FLAG_HERMITIAN) && s->n1 >= 5;
+  int db1 = t.db, db2 = t.db;
+  if (split_db) {
+    if (!force && db1 > cap1) db1 = cap1;
+    if (db2 > cap2) db2 = cap2;
+    if (db1 > db2 + 1) db1 = db2 + 1;
+  } else if (!force) {
+    const int cap = cap1 < cap2 ? cap1 : cap2;
+    if (db1 > cap) db1 = db2 = cap;
+  }
+  if (db2 > s->n2) return TPD_ERROR_INVALID_VALUE;  // MID needs the low db x bits in sweep 2
+  const int db = db1;
   s->prune = (flags & TPD_FLAG_NO_PRUNE) == 0;
   const int cus = g_cus > 0 ? (int)g_cus : 256;
   SweepDesc& a = s->sw[0];
@@ -185,7 +198,7 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
   SweepDesc& b = s->sw[1];
   b.xlo = 0;
   b.xb = s->n2;
-  b.db = db;
+  b.db = db2;
   b.in_layout = s->matrix_layout ? L_MAT : L_MID;
   b.out_layout = out_l;
   b.bitmap_mode = s->prune ? 2 : 0;
@@ -195,9 +208,9 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
   b.is_one = false;
   b.herm = a.herm;
   b.inv = false;
-  b.ntiles = ((uint64_t)1 << s->n1) << (n - db);
+  b.ntiles = ((uint64_t)1 << s->n1) << (n - db2);
   b.tile_order = ((flags & TPD_FLAG_ROTATE_TILES) || t.order2) ? 1 : 0;
-  const uint64_t bits = ((uint64_t)1 << s->n1) << (n - db);
+  const uint64_t bits = ((uint64_t)1 << s->n1) << (n - db2);
   s->bitmap_words = (bits + 31) / 32;
   for (int i = 0; i < 2; ++i)
     if (!sweep_supported(dt, s->sw[i])) return force ? TPD_ERROR_INVALID_VALUE : TPD_ERROR_INTERNAL;
@@ -588,6 +601,7 @@ tpd_status_t launch_sweep_i(const Schedule& s, int i, const void* A, void* C, ui
   a.bitmap = bitmap;
   a.bitmap_mode = w.bitmap_mode;
   a.bm_xbits = s.n1;
+  a.bm_db = s.nsweep == 2 ? s.sw[1].db : w.db;
   a.herm = w.herm;
   a.req = req;
   a.ntiles = w.ntiles;
@@ -657,6 +671,7 @@ tpd_status_t run_partial(const Schedule& s, const void* A, void* C, const uint64
       a.db = w.db;
       a.nfix_d = s.n - w.db;
       a.bm_xbits = s.n1;
+      a.bm_db = s.sw[1].db;
       a.herm = w.herm;
       if (i == 0) {
         a.bitmap = live;

@@ -36,6 +36,7 @@ struct SweepArgs {
   uint32_t* bitmap;  // 32-bit words, one bit per second-sweep tile
   int bitmap_mode;
   int bm_xbits;      // x bits of the first sweep (bit index = (td << bm_xbits) | x_hi)
+  int bm_db;         // the second sweep's tile width (bitmap d-groups); 0 or db: this sweep's own
   int herm;          // 1: Hermitian input, two-sweep schedule
   const uint32_t* req;  // partial decomposition: bit per d-group td, tiles of unset groups are skipped (null: all)
   // partial decomposition, work list instead of all tiles (null: all):

@@ -683,14 +683,37 @@ def test_n17_in_place_sampled_strings(dtype):
     if real:
         assert np.all(ref[y_odd(qs)] == 0)  # real symmetric: no odd-Y weight
     if pristine is not None:
-        for herm in (False, True):
-            for db in (4, 5):
+        # db 6 in the general mode: 2^6-diagonal tiles in the 8-level sweep,
+        # 2^5 in the 9-level one (pruning bits per narrower d-group)
+        for herm, dbs in ((False, (4, 5, 6)), (True, (4, 5))):
+            for db in dbs:
                 for g in (0, 4):
                     A.copy_(pristine)
                     tpd.decompose_tuned(A, A.view(-1), db=db, grid_per_cu=g, layout="matrix", hermitian=herm)
                     assert np.array_equal(A[hb, lb].cpu().numpy(), ref), (herm, db, g)
     del A, pristine
     torch.cuda.empty_cache()
+
+
+def test_n17_real_tfim_pruning_with_split_tile_widths():
+    # the transverse-field Ising chain at n = 17 (real float32, 64 GiB): its
+    # X_i terms sit on single diagonals 2^i, so second-sweep d-groups of 2^5
+    # inside first-sweep tiles of 2^6 diagonals are live or dead on their
+    # own; the pruned result must still be exactly the 2n - 1 terms
+    n = 17
+    torch.cuda.empty_cache()
+    terms = W.tfim_terms(n, 1.0, 0.5)
+    H = W.dense_from_terms_device(terms, n, dtype=torch.float32)
+    sched = tpd.schedule(n, tpd.TPD_R32, tpd.FLAG_LAYOUT_MATRIX, in_place=True)
+    tpd.decompose_tuned(H, H.view(-1), db=6, grid_per_cu=4, layout="matrix")
+    # the nonzero weights through the library's compaction (64-bit counts)
+    qs, ws, total = tpd.compact(H.view(-1), layout="matrix")
+    got = dict(zip(qs.cpu().numpy().tolist(), ws.cpu().numpy().tolist()))
+    expect = {W.string_index(s_): float(np.real(c)) for s_, c in terms}
+    assert total == 2 * n - 1 and got == expect
+    del H
+    torch.cuda.empty_cache()
+    assert sched["sweeps"][0]["db"] in (5, 6)
 
 
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.float32])

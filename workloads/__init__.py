@@ -220,7 +220,12 @@ def dense_from_terms_device(terms: Sequence[Term], n: int, dtype=None, device="c
     rows = torch.arange(d, dtype=torch.int64, device=device)
     for s, c in terms:
         x, val = _row_values(s, rows_h)
-        v = torch.from_numpy(c * val).to(device=device, dtype=dtype)
+        cv = c * val
+        if not A.is_complex():  # a real matrix: the terms must be real
+            if np.any(np.imag(cv) != 0):
+                raise ValueError("a term with imaginary entries in a real matrix")
+            cv = np.real(cv)
+        v = torch.from_numpy(np.ascontiguousarray(cv)).to(device=device, dtype=dtype)
         flat.index_add_(0, rows * d + (rows ^ x), v)
     return A
 
