@@ -37,7 +37,10 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   constexpr uint32_t XM = (1u << G::XB) - 1;
   constexpr int NBW = (1 << G::XB) >= 32 ? (1 << G::XB) / 32 : 1;
   __shared__ E lds[1 << G::B];
-  __shared__ uint32_t bits[2 * NBW];  // x 2: second-sweep d-groups half as wide as this tile
+  // split pruning groups (see sub_bits below): only the 8-level, 2^6-wide
+  // first sweep of 4-byte elements in the matrix layout takes them
+  constexpr bool SPLIT = sizeof(E) <= 4 && INL == L_MAT && OUTL == L_MAT && !INV && G::XB == 8 && G::DB == 6;
+  __shared__ uint32_t bits[(SPLIT ? 2 : 1) * NBW];
 
   const uint32_t tid = threadIdx.x;
   const E* __restrict__ in = (const E*)a.in;
@@ -142,17 +145,24 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
     }
   };
 
-  // Pruning bits are per second-sweep tile; with the matrix layout that
-  // sweep may use d-groups of half this tile's width (sub_bits = 1; the host
-  // allows it only for tiles of >= 32 rows, so every bitmap word belongs to
-  // one sub-group).  Lane bit b holds d bit b of the tile in the last phase.
-  const int sub_bits = (G::XB >= 5 && a.bm_db == G::DB - 1) ? 1 : 0;
+  // Pruning bits are per second-sweep tile; with the matrix layout and
+  // 4-byte elements that sweep may use d-groups of half this tile's width
+  // (sub_bits = 1; only for tiles of >= 32 rows, so every bitmap word belongs
+  // to one sub-group).  Lane bit b holds d bit b of the tile in the last
+  // phase.  Wider elements keep the plain epilogue: the split's extra
+  // per-lane values made the 1024-thread 8-byte kernels spill.
+  int sub_bits = 0;
+  if constexpr (SPLIT) sub_bits = (G::XB >= 5 && a.bm_db == G::DB - 1) ? 1 : 0;
   const int nbw = NBW << sub_bits;
 
   // Transform one loaded tile and store it.
   auto process = [&](const Tile& t, E* v) {
     const uint64_t td = t.td, hm = t.hm, xfix = t.xfix;
-    if (a.bitmap_mode == 1 && (int)tid < nbw) bits[tid] = 0;
+    if constexpr (SPLIT) {
+      if (a.bitmap_mode == 1 && (int)tid < nbw) bits[tid] = 0;
+    } else {
+      if (a.bitmap_mode == 1 && tid < NBW) bits[tid] = 0;
+    }
 
     if (hm && !xlo) {
       // second sweep: rebuild the non-representative rows by conjugation
@@ -194,7 +204,32 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
       }
     }
 
-    if (a.bitmap_mode == 1) {
+    if (a.bitmap_mode == 1 && !SPLIT) {
+      // OR "any nonzero" over the 2^DB diagonals (lanes [0, DB)) of each row
+      // block; one bit per second-sweep tile (td, x_hi).  NaN counts as nonzero.
+      const uint32_t lane = tid & 63u;
+      constexpr uint32_t gsz = 1u << G::DB;
+      constexpr uint64_t gmask = gsz >= 64 ? ~0ull : ((1ull << gsz) - 1);
+      if (P == 1) __syncthreads();
+#pragma unroll
+      for (int j = 0; j < G::E; ++j) {
+        const bool nz = nonzero(v[j]);
+        const uint64_t m = __ballot(nz);
+        if ((lane & (gsz - 1)) == 0 && ((m >> lane) & gmask)) {
+          const uint32_t xl = ((ebl | elem_reg<G>(RL, LAST, j)) >> G::DB) & XM;
+          atomicOr(&bits[xl >> 5], 1u << (xl & 31));
+        }
+      }
+      __syncthreads();
+      if (tid < NBW) {
+        const uint32_t w = bits[tid];
+        if (w) {
+          const uint64_t b0 = (td << a.bm_xbits) + 32ull * tid;
+          atomicOr(&a.bitmap[b0 >> 5], w << (b0 & 31));
+        }
+      }
+    }
+    if (a.bitmap_mode == 1 && SPLIT) {
       // OR "any nonzero" over the diagonals of each second-sweep d-group
       // (2^(DB - sub_bits) consecutive lanes) of each row block; one bit per
       // second-sweep tile (td << sub_bits | sub, x_hi).  NaN counts as nonzero.
