@@ -79,6 +79,25 @@ def test_ingest_calibrates_on_the_2_32_byte_copy_and_splits_reduced_modes(tmp_pa
     assert abs(red["write_over_algorithmic"] - 0.75) < 1e-12
 
 
+def test_ingest_splits_reduced_modes_of_tiles_that_fetch_whole_lines(tmp_path):
+    # runs shorter than a line: the full mode fetches twice the algorithmic
+    # bytes and the reduced mode a little over them; the reduced dispatches
+    # are still told apart (they read about half of what the full ones read)
+    copy = 1 << 32
+    kr = "void tpd::k_sweep<tpd::Real<float>, tpd::Geom<8, 4, 0, 4, 0>, 0, 0, false>(tpd::SweepArgs)"
+    alg = 4 ** 16 * 4
+    fetch = [(COPY, 0.5 * copy / 1024)] + [(kr, 0.5 * r * alg / 1024) for r in (2.0, 2.0, 1.063, 1.063)]
+    write = [(COPY, copy / 1024)] + [(kr, r * alg / 1024) for r in (1.0, 1.0, 0.531, 1.0)]
+    f1, w1 = tmp_path / "f.csv", tmp_path / "w.csv"
+    write_csv(f1, fetch)
+    write_csv(w1, write)
+    k = bench.ingest_pmc([(str(f1), str(w1))], str(tmp_path / "t.json"))["kernels"][kr]
+    assert k["dispatches"] == 2 and abs(k["fetch_over_algorithmic"] - 2.0) < 1e-12
+    assert abs(k["write_over_algorithmic"] - 1.0) < 1e-12
+    red = k["reduced_mode_dispatches"]
+    assert red["count"] == 2 and abs(red["fetch_over_algorithmic"] - 1.063) < 1e-12
+
+
 def test_ingest_needs_the_copy_calibration(tmp_path):
     f1, w1 = tmp_path / "f.csv", tmp_path / "w.csv"
     write_csv(f1, [(K1, 1.0)])
