@@ -18,6 +18,7 @@ per-matrix launches), and the CPU oracle timed on the host.
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -59,9 +60,23 @@ def load_traffic(kernel_name, n):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha") != kernel_source_hash() or t.get("n") != n:
+    if t.get("kernel_source_sha") != kernel_source_hash():
         return None
-    return t.get("kernels", {}).get(kernel_name)
+    k = t.get("kernels", {}).get(kernel_name)
+    return k if k and k.get("n") == n else None
+
+
+def leg_traffic(dt, res, n):
+    """Measured HBM bytes per launch of each sweep of a two-sweep leg
+    (None where no PMC figures were taken on the current sources)."""
+    sched = res.get("schedule") or []
+    if len(sched) != 2:
+        return None
+    out = []
+    for w in (1, 2):
+        k = load_traffic(sweep_kernel_name(dt, sched, w), n)
+        out.append(k["total_bytes"] if k else None)
+    return out
 
 
 LAYOUT_CODE = {"MAT": 0, "CAN": 1, "MID": 2}
@@ -86,7 +101,7 @@ def ingest_pmc(pairs, out_path):
         ks, fs, ws = ingest_pair(fetch_csv, write_csv)
         kernels.update(ks)
         scales.append({"fetch_scale": fs, "write_scale": ws})
-    doc = {"kernel_source_sha": kernel_source_hash(), "n": 16, "scales": scales,
+    doc = {"kernel_source_sha": kernel_source_hash(), "scales": scales,
            "calibration": "plain device copy of 2^32 bytes (__amd_rocclr_copyBuffer via torch copy_)",
            "kernels": kernels}
     with open(out_path, "w") as f:
@@ -137,7 +152,13 @@ def ingest_pair(fetch_csv, write_csv):
             next((k for k in (", 0, 2, false>", ", 2, 1, false>", ", 0, 0, false>") if k in name), ""), 0)
         if not which:
             continue  # 12: matrix layout in place, both sweeps share the symbol
-        alg = 4 ** 16 * es
+        # the profiled legs split an even n into two sweeps of n/2 levels,
+        # each with tiles of 2^(n/2) rows: n = 2 x the tile's row bits
+        m = re.search(r"Geom<(\d+),", name)
+        if not m:
+            continue
+        n = 2 * int(m.group(1))
+        alg = 4 ** n * es
         fr = [v / fscale / alg for v in fetch[name]]
         wr = [v / wscale / alg for v in write[name]]
         # Hermitian / real-symmetric mode shares the kernel symbol and reads
@@ -153,7 +174,7 @@ def ingest_pair(fetch_csv, write_csv):
         wb = sum(wr[i] for i in (use if len(wr) == len(fr) else range(len(wr)))) / (
             len(use) if len(wr) == len(fr) else len(wr)) * alg
         kernels[name] = {
-            "sweep": which, "dtype": dt, "dispatches": len(use),
+            "n": n, "sweep": which, "dtype": dt, "dispatches": len(use),
             "fetch_bytes": fb, "write_bytes": wb, "total_bytes": fb + wb,
             "algorithmic_bytes": 2 * alg, "fetch_over_algorithmic": fb / alg, "write_over_algorithmic": wb / alg,
         }
@@ -700,6 +721,18 @@ def main():
         del C
         torch.cuda.empty_cache()
         result["n17"] = d17
+
+    # PMC-measured HBM bytes per launch of each sweep, for the general-mode
+    # two-sweep legs whose kernels were profiled on the current sources
+    legs = [(result.get("out_of_place_canonical_c128"), "double", n), (result.get("fp32"), "float", n),
+            (result.get("fp32_out_of_place_canonical"), "float", n),
+            ((result.get("real_r64") or {}).get("general"), "tpd::Real<double>", n),
+            ((result.get("real_r32") or {}).get("general"), "tpd::Real<float>", n)]
+    legs += [((result.get("n14_dense") or {}).get(k), dt, 14)
+             for k, dt in (("c128", "double"), ("c128_in_place", "double"), ("c64", "float"), ("c64_in_place", "float"))]
+    for r, dt, nn in legs:
+        if r is not None:
+            r["traffic_bytes"] = leg_traffic(dt, r, nn)
 
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")

@@ -98,6 +98,27 @@ def test_ingest_splits_reduced_modes_of_tiles_that_fetch_whole_lines(tmp_path):
     assert red["count"] == 2 and abs(red["fetch_over_algorithmic"] - 1.063) < 1e-12
 
 
+def test_ingest_takes_n_from_the_tile_rows_and_legs_look_it_up(tmp_path, monkeypatch):
+    # an n = 14 leg: tiles of 2^7 rows, 4^14 elements per sweep
+    copy = 1 << 32
+    k14 = "void tpd::k_sweep<double, tpd::Geom<7, 3, 0, 4, 0>, 0, 0, false>(tpd::SweepArgs)"
+    alg = 4 ** 14 * 16
+    f1, w1 = tmp_path / "f.csv", tmp_path / "w.csv"
+    write_csv(f1, [(COPY, 0.5 * copy / 1024), (k14, 0.5 * alg / 1024), (k14, 0.5 * alg / 1024)])
+    write_csv(w1, [(COPY, copy / 1024), (k14, 1.001 * alg / 1024), (k14, 1.001 * alg / 1024)])
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "profiles")
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "x")
+    doc = bench.ingest_pmc([(str(f1), str(w1))], str(tmp_path / "profiles" / "traffic.json"))
+    k = doc["kernels"][k14]
+    assert k["n"] == 14 and abs(k["fetch_over_algorithmic"] - 1.0) < 1e-12
+    assert abs(k["write_over_algorithmic"] - 1.001) < 1e-12
+    sched = [{"xb": 7, "db": 3, "r": 4, "in": "MAT", "out": "MAT"}] * 2
+    assert bench.leg_traffic("double", {"schedule": sched}, 14) == [k["total_bytes"]] * 2
+    assert bench.leg_traffic("double", {"schedule": sched}, 16) == [None, None]
+    assert bench.leg_traffic("float", {"schedule": sched}, 14) == [None, None]
+
+
 def test_ingest_needs_the_copy_calibration(tmp_path):
     f1, w1 = tmp_path / "f.csv", tmp_path / "w.csv"
     write_csv(f1, [(K1, 1.0)])
