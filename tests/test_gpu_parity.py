@@ -406,6 +406,44 @@ def test_n16_in_place_every_tuning_candidate(dtype, dbs):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("dtype,dbs", [(torch.complex128, (3, 4, 5)), (torch.complex64, (4, 5, 6))])
+def test_n14_dense_every_tuning_candidate(dtype, dbs):
+    # the n = 14 dense legs at full size: Hermitian input, in place with the
+    # matrix layout and out of place in canonical order, pruning on, for
+    # every tile width x persistent grid the autotuner may choose, each also
+    # with the second sweep's rotated tile order; every candidate gives the
+    # default schedule's bits, which match the definition on sampled strings
+    n = 14
+    torch.cuda.empty_cache()
+    A = W.gaussian_device(n, seed=14, dtype=dtype, hermitian=True)
+    a_max = float(torch.view_as_real(A).abs().max())
+    qs = W.sampled_strings(n, 1500, seed=141)
+    bf = sampled_oracle(A, n, qs)
+    tol = n * U64 * a_max if dtype == torch.complex128 else (n + 1) * U32 * a_max
+    qd = torch.from_numpy(qs.astype(np.int64)).to(DEV)
+    h, l = deinterleave(qs.astype(np.int64))
+    hb = torch.from_numpy(h).to(DEV)
+    lb = torch.from_numpy(l).to(DEV)
+    ref_can = tpd.decompose(A)
+    assert cerr(ref_can[qd].cpu().numpy(), bf) <= tol
+    B = A.clone()
+    tpd.decompose(B, B.view(-1), layout="matrix")
+    ref_mat = B.clone()
+    assert cerr(ref_mat[hb, lb].cpu().numpy(), bf) <= tol
+    out = torch.empty_like(ref_can)
+    for db in dbs:
+        for g in (0, 1, 2, 4):
+            for rot in (False, True):
+                out.fill_(float("nan"))
+                tpd.decompose_tuned(A, out, db=db, grid_per_cu=g, rotate=rot)
+                assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref_can)), ("canonical", db, g, rot)
+                B.copy_(A)
+                tpd.decompose_tuned(B, B.view(-1), db=db, grid_per_cu=g, layout="matrix", rotate=rot)
+                assert torch.equal(torch.view_as_real(B), torch.view_as_real(ref_mat)), ("matrix", db, g, rot)
+    del A, B, ref_can, ref_mat, out
+    torch.cuda.empty_cache()
+
+
 # ----------------------------------------------------------------------------
 # real input (real-coded weights): w_t = r_t for even #Y, i r_t for odd #Y
 # ----------------------------------------------------------------------------
