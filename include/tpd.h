@@ -275,6 +275,9 @@ tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len);
  * side, hence how their rows meet the memory channels, depends on where the
  * buffer sits in physical memory).
  * The choice never changes results (same operations in the same order).
+ * Timed runs include the first sweep's pruning epilogue unless
+ * TPD_FLAG_NO_PRUNE is given; in place, where each run transforms the
+ * previous result, the second sweep skips no tiles while timing.
  * Arguments as tpd_decompose_ex; `coeffs` is overwritten; with
  * A == coeffs the matrix is transformed repeatedly (destroyed).  Allocates
  * a bitmap, synchronises `stream`.  report/len (optional): JSON of the

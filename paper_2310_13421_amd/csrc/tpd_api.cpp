@@ -1367,9 +1367,10 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
     return report ? copy_out(rep, report, len) : TPD_SUCCESS;
   }
   hipStream_t hs = (hipStream_t)stream;
-  // in place every run transforms the previous result; pruning is switched
-  // off while timing so that vanishing values cannot skip work
-  const unsigned tflags = (flags & ~TPD_FLAG_ORDER_BOTTOM) | (in_place ? TPD_FLAG_NO_PRUNE : 0u);
+  // in place every run transforms the previous result, whose values shrink
+  // towards zero: while timing, the second sweep skips no tiles, and the
+  // first still sets the pruning bitmap (its epilogue is part of the cost)
+  const unsigned tflags = flags & ~TPD_FLAG_ORDER_BOTTOM;
   const int dbs128[3] = {3, 4, 5}, dbs64[3] = {4, 5, 6};
   const int* dbs = dt == DT_C128 ? dbs128 : dbs64;
   const int rs[1] = {4};
@@ -1412,6 +1413,7 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
   auto time_candidate = [&](const Tuned& t, double* med) -> bool {
     Schedule sc;
     if (make_schedule_with(n, dt, tflags, in_place, &t, &sc) != TPD_SUCCESS) return false;
+    if (in_place && sc.prune && sc.nsweep == 2) sc.sw[1].bitmap_mode = 0;
     st = run_schedule(sc, A, coeffs, bm, hs, nullptr);  // warm-up
     if (st) return false;
     std::vector<float> ms;
