@@ -153,6 +153,13 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   // per-lane values made the 1024-thread 8-byte kernels spill.
   int sub_bits = 0;
   if constexpr (SPLIT) sub_bits = (G::XB >= 5 && a.bm_db == G::DB - 1) ? 1 : 0;
+  // rows held by the last phase's register slots (x offsets of the slots)
+  constexpr uint32_t SLOT_ROWS = [] {
+    uint32_t r = 0;
+    for (int j = 0; j < G::E; ++j) r |= (elem_reg<G>(make_roles<G>(), G::NPH - 1, j) >> G::DB) & ((1u << G::XB) - 1);
+    return r;
+  }();
+  constexpr bool ROWS_IN_WORD = G::XB >= 5 && SLOT_ROWS < 32;
   const int nbw = NBW << sub_bits;
 
   // Transform one loaded tile and store it.
@@ -204,7 +211,28 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
       }
     }
 
-    if (a.bitmap_mode == 1 && !SPLIT) {
+    if (a.bitmap_mode == 1 && !SPLIT && ROWS_IN_WORD) {
+      // OR "any nonzero" over the 2^DB diagonals (lanes [0, DB)) of each row
+      // block; one bit per second-sweep tile (td, x_hi).  NaN counts as nonzero.
+      // The register slots of the last phase hold rows that differ only in
+      // their low 5 bits, so each lane group's rows share one bitmap word:
+      // its leader ORs them in with one global atomic (no LDS pass, and no
+      // barrier between the transform and the stores).
+      const uint32_t lane = tid & 63u;
+      constexpr uint32_t gsz = 1u << G::DB;
+      constexpr uint64_t gmask = gsz >= 64 ? ~0ull : ((1ull << gsz) - 1);
+      uint32_t wbits = 0;
+#pragma unroll
+      for (int j = 0; j < G::E; ++j) {
+        const uint64_t m = __ballot(nonzero(v[j]));
+        if ((m >> (lane & ~(gsz - 1))) & gmask) wbits |= 1u << ((elem_reg<G>(RL, LAST, j) >> G::DB) & XM);
+      }
+      if ((lane & (gsz - 1)) == 0 && wbits) {
+        const uint64_t b0 = (td << a.bm_xbits) + ((ebl >> G::DB) & XM);
+        atomicOr(&a.bitmap[b0 >> 5], wbits << (b0 & 31));
+      }
+    }
+    if (a.bitmap_mode == 1 && !SPLIT && !ROWS_IN_WORD) {
       // OR "any nonzero" over the 2^DB diagonals (lanes [0, DB)) of each row
       // block; one bit per second-sweep tile (td, x_hi).  NaN counts as nonzero.
       const uint32_t lane = tid & 63u;
