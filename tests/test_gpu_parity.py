@@ -754,6 +754,34 @@ def test_n17_real_tfim_pruning_with_split_tile_widths():
     assert sched["sweeps"][0]["db"] in (5, 6)
 
 
+@pytest.mark.parametrize("dtype,code", [(torch.complex128, tpd.TPD_C128), (torch.complex64, tpd.TPD_C64),
+                                        (torch.float64, tpd.TPD_R64)])
+def test_n16_tfim_pruning_lane_group_bits(dtype, code):
+    # n = 16: the first sweep transforms 8 levels, and each lane group ORs
+    # its rows' pruning bits into one bitmap word; the transverse-field Ising
+    # chain's live prefixes follow the closed form 2k + 1, and the result is
+    # exactly its 2n - 1 terms, out of place (canonical) and in place (matrix)
+    n = 16
+    torch.cuda.empty_cache()
+    terms = W.tfim_terms(n, 1.0, 0.5)
+    expect = {W.string_index(s_): complex(c) for s_, c in terms}
+    H = W.dense_from_terms_device(terms, n, dtype=dtype)
+    out = torch.empty(4 ** n, dtype=dtype, device=DEV)
+    for layout, in_place in (("canonical", False), ("matrix", True)):
+        plan = tpd.Plan(n, code, layout=layout, in_place=in_place)
+        dst = H.view(-1) if in_place else out
+        plan.execute(H, dst)
+        st = plan.prune_stats()
+        plan.close()
+        assert st["live_prefixes"] == 2 * st["prefix_level"] + 1, (layout, st)
+        assert 0 < st["live_tiles"] < st["total_tiles"], (layout, st)
+        qs, ws, total = tpd.compact(dst, layout=layout)
+        got = {int(q): complex(w) for q, w in zip(qs.cpu().numpy(), ws.cpu().numpy())}
+        assert total == 2 * n - 1 and got == expect, layout
+    del H, out
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.float32])
 def test_n17_round_trip_in_place_integer_exact(dtype):
     # integer weights synthesized in place into the 131072 x 131072 matrix
