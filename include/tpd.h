@@ -268,8 +268,8 @@ tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len);
  * if the environment variable TPD_AUTOTUNE_CACHE names a file, appended
  * there and reloaded by later processes).  Candidates: tile widths of
  * 2^3..2^5 (complex128) or 2^4..2^6 (complex64 and the real dtypes)
- * XOR-diagonals, one workgroup per tile or a persistent grid of 1, 2 or 4
- * workgroups per CU (which load the next tile while transforming the
+ * XOR-diagonals, one workgroup per tile or a persistent grid of 1, 2, 4 or
+ * 8 workgroups per CU (which load the next tile while transforming the
  * current one); then the fastest of these once more with the second
  * sweep's rotated tile order (TPD_FLAG_ROTATE_TILES: which tiles run side by
  * side, hence how their rows meet the memory channels, depends on where the

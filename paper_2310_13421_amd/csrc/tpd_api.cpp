@@ -1374,7 +1374,7 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
   const int dbs128[3] = {3, 4, 5}, dbs64[3] = {4, 5, 6};
   const int* dbs = dt == DT_C128 ? dbs128 : dbs64;
   const int rs[1] = {4};
-  const int grids[4] = {0, 1, 2, 4};
+  const int grids[5] = {0, 1, 2, 4, 8};
   std::vector<Tuned> cands;
   uint64_t max_words = 0;
   for (int i = 0; i < 3; ++i)

@@ -393,7 +393,7 @@ def test_n16_in_place_every_tuning_candidate(dtype, dbs):
     assert cerr(ref, bf) <= tol
     for herm in (False, True):
         for db in dbs:
-            for g in (0, 1, 2, 4):
+            for g in (0, 1, 2, 4, 8):
                 B.copy_(A)
                 tpd.decompose_tuned(B, B.view(-1), db=db, grid_per_cu=g, layout="matrix", hermitian=herm,
                                     rotate=(g == 4))
@@ -432,7 +432,7 @@ def test_n14_dense_every_tuning_candidate(dtype, dbs):
     assert cerr(ref_mat[hb, lb].cpu().numpy(), bf) <= tol
     out = torch.empty_like(ref_can)
     for db in dbs:
-        for g in (0, 1, 2, 4):
+        for g in (0, 1, 2, 4, 8):
             for rot in (False, True):
                 out.fill_(float("nan"))
                 tpd.decompose_tuned(A, out, db=db, grid_per_cu=g, rotate=rot)
@@ -686,7 +686,7 @@ def test_n16_real_in_place_every_tuning_candidate(hermitian, dtype):
     assert np.max(np.abs(ref.astype(np.float64) - exp)) <= tol
     assert np.all(ref[y_odd(qs)] == 0)
     for db in (4, 5, 6):
-        for g in (0, 1, 2, 4):
+        for g in (0, 1, 2, 4, 8):
             B.copy_(A)
             tpd.decompose_tuned(B, B.view(-1), db=db, grid_per_cu=g, layout="matrix", hermitian=hermitian)
             assert np.array_equal(B[hb, lb].cpu().numpy(), ref), (db, g)
