@@ -319,18 +319,23 @@ tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tpd_dtype_t d
                                int in_place);
 
 /* As tpd_debug_emulate with a forced two-sweep tile width 2^db (db = 0:
- * the default schedule); r must be 0 or 4 (elements per thread = 16).    */
+ * the default schedule); r must be 0 or 4 (elements per thread = 16);
+ * chunk_bits > 0 (with db > 0) runs the chunked order of
+ * tpd_debug_decompose_tuned.                                              */
 tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
-                                     int in_place, int db, int r);
+                                     int in_place, int db, int r, int chunk_bits);
 
 /* One decomposition on the device with a forced two-sweep schedule: tile
  * width 2^db, 2^r elements per thread (r = 4), grid_per_cu workgroups per
- * CU (0 = one per tile).  For tests that every tunable schedule gives the
- * same bits; arguments and errors otherwise as tpd_decompose_ex, and
- * TPD_ERROR_INVALID_VALUE for a schedule that does not exist.  n <= 8
- * ignores the schedule arguments.                                         */
+ * CU (0 = one per tile), and chunk_bits: 0 runs each sweep over the whole
+ * matrix, k > 0 runs sweep 1 then sweep 2 over 2^k first-sweep d-groups
+ * (XOR-diagonal strips of 2^db) at a time, 2^(n-db-k) chunks (needs
+ * k < n - db, not with TPD_FLAG_HERMITIAN).  For tests that every tunable
+ * schedule gives the same bits; arguments and errors otherwise as
+ * tpd_decompose_ex, and TPD_ERROR_INVALID_VALUE for a schedule that does
+ * not exist.  n <= 8 ignores the schedule arguments.                      */
 tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
-                                       int db, int r, int grid_per_cu, tpd_stream_t stream);
+                                       int db, int r, int grid_per_cu, int chunk_bits, tpd_stream_t stream);
 
 /* Host replays of the partial decomposition (request marking, tile skips,
  * gather) and of the compaction (same chunks, order and clipping); HOST

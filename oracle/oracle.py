@@ -1,7 +1,8 @@
 """CPU FP64 oracle for the Tensorized Pauli Decomposition -- TEST INFRASTRUCTURE.
 
-Thin ctypes front end to ``tpd_oracle.c`` (plain single-threaded C, binary64,
-no FMA contraction).  Only the test-suite, the package smoke check and the
+Thin ctypes front end to ``tpd_oracle.c`` (plain C, binary64, no FMA
+contraction; single-threaded except the OpenMP form of Algorithm 2 used to
+time the CPU baseline).  Only the test-suite, the package smoke check and the
 CPU-baseline leg of the benchmark may import this module; the product path
 never does.  It shares no code with the HIP library.
 
@@ -15,6 +16,7 @@ Every function follows a passage of Hantzko, Binkowski, Gupta,
 * ``weight_from_diagonal`` -- as ``weight_sparse`` given only the entries it reads.
 * ``tpd_recursive``    -- Fig. 1, Algorithm 1, with live-CMW counts per level.
 * ``tpd_iterative``    -- Fig. 1, Algorithm 2 (n expansions, see its C comment).
+* ``tpd_iterative_mt`` -- the same on several OpenMP threads (CPU baseline timing).
 * ``tpd_partial``      -- Fig. 2, Algorithm 3.
 * ``synthesize``       -- eq. (PauliDecomposition) read as a sum of strings.
 
@@ -36,7 +38,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-_CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+_CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
 
 
 def build(force: bool = False) -> str:
@@ -61,10 +63,11 @@ def _bind(lib):
     lib.oracle_xy_mask.restype = U
     lib.oracle_tpd_recursive.argtypes = [P, I, P, P, P]
     lib.oracle_tpd_iterative.argtypes = [P, I, P, P]
+    lib.oracle_tpd_iterative_mt.argtypes = [P, I, P, P, I]
     lib.oracle_tpd_partial.argtypes = [P, I, P, S, P]
     lib.oracle_synthesize.argtypes = [P, I, P]
     for name in ("oracle_weight_dense", "oracle_weight_sparse", "oracle_weight_from_diagonal",
-                 "oracle_tpd_recursive", "oracle_tpd_iterative", "oracle_tpd_partial",
+                 "oracle_tpd_recursive", "oracle_tpd_iterative", "oracle_tpd_iterative_mt", "oracle_tpd_partial",
                  "oracle_synthesize"):
         getattr(lib, name).restype = I
     return lib
@@ -180,6 +183,49 @@ def weight_from_diagonal(v: np.ndarray, n: int, x: int, qs) -> np.ndarray:
     return out
 
 
+def sampled_weights(fetch_diagonals, n: int, qs, threads: int = 0, masks_per_fetch: int = 256) -> np.ndarray:
+    """omega_q for sampled strings of a matrix too large to copy whole, from
+    the definition (weight_from_diagonal).  Strings are grouped by X/Y mask x
+    (all strings of one mask read the same 2^n entries v[i] = A[i ^ x][i]);
+    fetch_diagonals(xs) must return an array [len(xs), 2^n] of those entries
+    (e.g. gathered from a device copy of A).  The per-mask sums run on
+    `threads` host threads (0: os.cpu_count()); each call is the
+    single-threaded C definition, which releases the GIL."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    q = _qs(qs)
+    masks = np.array([xy_mask(int(v), n) for v in q], np.int64) if q.size < 4096 else _xy_masks(q, n)
+    out = np.empty(q.size, np.complex128)
+    order = np.argsort(masks, kind="stable")
+    ms = masks[order]
+    uniq, starts = np.unique(ms, return_index=True)
+    ends = np.append(starts[1:], ms.size)
+    nth = threads if threads > 0 else (os.cpu_count() or 1)
+
+    def one(args):
+        v, x, sel = args
+        out[sel] = weight_from_diagonal(v, n, int(x), q[sel])
+
+    with ThreadPoolExecutor(nth) as ex:
+        for c0 in range(0, uniq.size, masks_per_fetch):
+            xs = uniq[c0:c0 + masks_per_fetch]
+            V = np.asarray(fetch_diagonals(xs))
+            jobs = [(V[k], x, order[starts[c0 + k]:ends[c0 + k]]) for k, x in enumerate(xs)]
+            list(ex.map(one, jobs))
+    return out
+
+
+def _xy_masks(q: np.ndarray, n: int) -> np.ndarray:
+    """X/Y masks of many canonical indices at once (bit n-k set iff letter
+    t_k is X or Y, i.e. the digit's two bits differ)."""
+    q = q.astype(np.uint64)
+    x = np.zeros(q.size, np.int64)
+    for k in range(1, n + 1):
+        d = (q >> np.uint64(2 * (n - k))) & np.uint64(3)
+        x |= ((d == 1) | (d == 2)).astype(np.int64) << (n - k)
+    return x
+
+
 def tpd_recursive(A: np.ndarray, with_stats: bool = False):
     """Algorithm 1.  Returns the 4^n weights (canonical order); with_stats adds
     (live CMW counts per level 0..n, complex entries computed)."""
@@ -200,6 +246,18 @@ def tpd_iterative(A: np.ndarray, with_stats: bool = False):
     out = np.empty(1 << (2 * n), np.complex128)
     live = np.zeros(n + 1, np.uint64)
     _check(_cur().oracle_tpd_iterative(_ptr(A), n, _ptr(out), _ptr(live)), "tpd_iterative")
+    if with_stats:
+        return out, live.astype(np.int64)
+    return out
+
+
+def tpd_iterative_mt(A: np.ndarray, threads: int = 0, with_stats: bool = False):
+    """Algorithm 2 on `threads` OpenMP threads (0: all); bitwise equal to
+    tpd_iterative.  For timing the CPU baseline."""
+    A, n = _mat(A)
+    out = np.empty(1 << (2 * n), np.complex128)
+    live = np.zeros(n + 1, np.uint64)
+    _check(_cur().oracle_tpd_iterative_mt(_ptr(A), n, _ptr(out), _ptr(live), int(threads)), "tpd_iterative_mt")
     if with_stats:
         return out, live.astype(np.int64)
     return out

@@ -25,10 +25,13 @@
  * Kronecker products built with a library routine, closed forms such as the
  * transverse-field Ising Hamiltonian, and invariants).
  *
- * Build: gcc -O2 -std=c99 -ffp-contract=off -fno-fast-math -shared -fPIC
- * (no FMA contraction, no flush-to-zero).
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -fno-fast-math -fopenmp -shared
+ * -fPIC (no FMA contraction, no flush-to-zero).  OpenMP is used by one
+ * function only, the multithreaded form of Algorithm 2 (7), for timing the
+ * CPU baseline; every other function runs on one thread.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -211,10 +214,12 @@ int oracle_weight_from_diagonal(const double* v, int n, uint64_t x, const uint64
 /* Returns 1 iff the produced block has a nonzero entry (exact comparison,    */
 /* a NaN counts as nonzero).                                                  */
 /* ------------------------------------------------------------------------ */
-static int cmw(const double* M, int m, int t, double* C) {
+/* rows [r0, r1) of the CMW only (used directly by the multithreaded form
+ * of Algorithm 2, which splits one CMW over threads) */
+static int cmw_rows(const double* M, int m, int t, double* C, uint64_t r0, uint64_t r1) {
   const uint64_t dim = (uint64_t)1 << m, h = dim >> 1;
   int nonzero = 0;
-  for (uint64_t r = 0; r < h; ++r) {
+  for (uint64_t r = r0; r < r1; ++r) {
     for (uint64_t c = 0; c < h; ++c) {
       const double* a11 = M + 2 * (r * dim + c);
       const double* a12 = M + 2 * (r * dim + c + h);
@@ -239,6 +244,10 @@ static int cmw(const double* M, int m, int t, double* C) {
     }
   }
   return nonzero;
+}
+
+static int cmw(const double* M, int m, int t, double* C) {
+  return cmw_rows(M, m, t, C, 0, ((uint64_t)1 << m) >> 1);
 }
 
 static int block_nonzero(const double* M, uint64_t count) {
@@ -361,6 +370,97 @@ int oracle_tpd_iterative(const double* A, int n, double* out, uint64_t* live) {
   }
   free(pre);
   free(blocks);
+  return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* (7) Algorithm 2 on several threads (OpenMP), for the CPU baseline only.   */
+/* The same level loop and the same CMW arithmetic as (4); within a level    */
+/* the children of all frontier blocks (4 per block, each split into row     */
+/* ranges so that the first levels also spread over the threads) are         */
+/* computed independently into their own slots, then the nonzero ones are    */
+/* kept in (block, letter) order.  Each entry sees the same operations as    */
+/* in (4), so the weights are bitwise those of (4) for any thread count.     */
+/* Two buffers of 4^n entries, allocated once and first touched by the       */
+/* threads, take turns holding the parents and the children (a level's      */
+/* children never need more room than its parents).                          */
+/* threads <= 0: the OpenMP default.                                         */
+/* ------------------------------------------------------------------------ */
+int oracle_tpd_iterative_mt(const double* A, int n, double* out, uint64_t* live, int threads) {
+  if (n < 0 || n > 16 || !A || !out) return ORACLE_EINVAL;
+  const int nth = threads > 0 ? threads : omp_get_max_threads();
+  const int64_t count = (int64_t)1 << (2 * n);
+#pragma omp parallel for schedule(static) num_threads(nth)
+  for (int64_t k = 0; k < 2 * count; ++k) out[k] = 0.0;
+  if (live) memset(live, 0, sizeof(uint64_t) * (size_t)(n + 1));
+  if (!block_nonzero(A, (uint64_t)count)) return ORACLE_OK;
+  if (live) live[0] = 1;
+
+  uint64_t nf = 1;
+  uint64_t* pre = (uint64_t*)malloc(sizeof(uint64_t));
+  double* blocks = (double*)malloc(sizeof(double) * 2 * (size_t)count);
+  double* all = (double*)malloc(sizeof(double) * 2 * (size_t)count);
+  if (!pre || !blocks || !all) { free(pre); free(blocks); free(all); return ORACLE_ENOMEM; }
+  pre[0] = 0;
+#pragma omp parallel for schedule(static) num_threads(nth)
+  for (int64_t k = 0; k < 2 * count; ++k) {
+    blocks[k] = A[k];
+    all[k] = 0.0;
+  }
+
+  for (int i = 1; i <= n; ++i) {
+    const int m = n - i + 1;
+    const uint64_t psize = (uint64_t)1 << (2 * m), csize = psize >> 2, h = (uint64_t)1 << (m - 1);
+    const uint64_t kids = 4 * nf;
+    /* jobs: runs of whole children when there are many, else row ranges of
+     * one child, so that every thread has work at every level */
+    const uint64_t want = 32 * (uint64_t)nth;
+    uint64_t split = 1, per = 1;
+    while (kids * split < want && split < h) split *= 2;
+    while (kids / (per * 2) >= want && kids % (per * 2) == 0) per *= 2;
+    const int64_t jobs = (int64_t)(kids / per * split);
+    unsigned char* nz = (unsigned char*)calloc(kids, 1);
+    uint64_t* npre = (uint64_t*)malloc(sizeof(uint64_t) * kids);
+    if (!nz || !npre) {
+      free(nz); free(npre); free(pre); free(blocks); free(all);
+      return ORACLE_ENOMEM;
+    }
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
+    for (int64_t j = 0; j < jobs; ++j) {
+      const uint64_t k0 = (uint64_t)j / split * per, part = (uint64_t)j % split;
+      const uint64_t r0 = h * part / split, r1 = h * (part + 1) / split;
+      for (uint64_t k = k0; k < k0 + per; ++k) {
+        if (cmw_rows(blocks + 2 * psize * (k / 4), m, (int)(k % 4), all + 2 * csize * k, r0, r1)) {
+#pragma omp atomic write
+          nz[k] = 1;
+        }
+      }
+    }
+    /* keep the nonzero children in order (blocks move only towards the
+     * front, each after every earlier one: a sequential compaction) */
+    uint64_t nn = 0;
+    for (uint64_t k = 0; k < kids; ++k) {
+      if (!nz[k]) continue;
+      if (nn != k) memmove(all + 2 * csize * nn, all + 2 * csize * k, sizeof(double) * 2 * csize);
+      npre[nn++] = pre[k / 4] * 4 + (k % 4);
+    }
+    free(nz);
+    if (live) live[i] = nn;
+    free(pre);
+    pre = npre;
+    double* tmp = blocks;
+    blocks = all;
+    all = tmp;
+    nf = nn;
+    if (nf == 0) break;
+  }
+  for (uint64_t f = 0; f < nf; ++f) {
+    out[2 * pre[f]] = blocks[2 * f];
+    out[2 * pre[f] + 1] = blocks[2 * f + 1];
+  }
+  free(pre);
+  free(blocks);
+  free(all);
   return ORACLE_OK;
 }
 

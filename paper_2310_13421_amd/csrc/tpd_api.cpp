@@ -67,6 +67,11 @@ struct Schedule {
   SweepDesc sw[2];
   int n1 = 0, n2 = 0;
   uint64_t bitmap_words = 0;
+  // chunked order (general two-sweep schedules): > 0 runs sweep 1 then
+  // sweep 2 over 2^chunk_bits first-sweep d-groups at a time, so a chunk's
+  // intermediate can still sit in the memory-side cache when sweep 2 reads
+  // it; 0: each sweep over the whole matrix
+  int chunk_bits = 0;
 };
 
 int single_db(int n) {
@@ -81,6 +86,7 @@ int single_db(int n) {
 struct Tuned {
   int db = 0, r = 4, grid = 0;
   int order2 = 0;  // second sweep's tile order (SweepDesc::tile_order)
+  int chunk = 0;   // Schedule::chunk_bits
 };
 struct TuneKey {
   int n, dt, matrix, in_place, herm;
@@ -179,6 +185,14 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
   }
   if (db2 > s->n2) return TPD_ERROR_INVALID_VALUE;  // MID needs the low db x bits in sweep 2
   const int db = db1;
+  // chunks of first-sweep d-groups: at least two chunks; not with the
+  // Hermitian mode, whose first sweep enumerates representative tiles over
+  // the whole matrix
+  if (t.chunk > 0) {
+    const bool ok = !(flags & TPD_FLAG_HERMITIAN) && t.chunk < n - db1;
+    if (!ok && force) return TPD_ERROR_INVALID_VALUE;
+    s->chunk_bits = ok ? t.chunk : 0;
+  }
   s->prune = (flags & TPD_FLAG_NO_PRUNE) == 0;
   const int cus = g_cus > 0 ? (int)g_cus : 256;
   SweepDesc& a = s->sw[0];
@@ -306,7 +320,7 @@ tpd_status_t make_synth_schedule(int n, Dtype dt, unsigned flags, bool in_place,
 }
 
 // Autotune cache: TPD_AUTOTUNE_CACHE names a text file of lines
-//   tpd-tune-v2 <arch> <cus> <dtype> <n> <matrix> <in_place> <hermitian> <db> <r> <grid> [<order2>]
+//   tpd-tune-v2 <arch> <cus> <dtype> <n> <matrix> <in_place> <hermitian> <db> <r> <grid> [<order2> [<chunk>]]
 // Unreadable or foreign lines are ignored (the built-in defaults apply).
 void load_tune_cache() {
   g_tune_loaded = true;
@@ -317,9 +331,10 @@ void load_tune_cache() {
   while (std::getline(f, line)) {
     std::istringstream is(line);
     std::string tag, arch;
-    int cus, dt, n, mat, inp, herm, db, r, grid, order2 = 0;
+    int cus, dt, n, mat, inp, herm, db, r, grid, order2 = 0, chunk = 0;
     if (!(is >> tag >> arch >> cus >> dt >> n >> mat >> inp >> herm >> db >> r >> grid)) continue;
     if (!(is >> order2)) order2 = 0;  // optional field: the second sweep's tile order
+    else if (!(is >> chunk) || chunk < 0 || chunk > 16) chunk = 0;  // optional field: chunked order
     if (tag != "tpd-tune-v2" || arch != "gfx950") continue;
     if (g_cus > 0 && cus != g_cus) continue;
     if (dt < 0 || dt > 3 || n < -1 || n > kMaxQubits || r != 4 || grid < 0 || grid > 64) continue;
@@ -328,6 +343,7 @@ void load_tune_cache() {
     t.r = r;
     t.grid = grid;
     t.order2 = order2 ? 1 : 0;
+    t.chunk = chunk;
     g_tuned[TuneKey{n, dt, mat, inp, herm}] = t;
   }
 }
@@ -337,7 +353,8 @@ void save_tune_entry(const TuneKey& k, const Tuned& t) {
   if (!path || !path[0]) return;
   std::ofstream f(path, std::ios::app);
   f << "tpd-tune-v2 gfx950 " << (g_cus > 0 ? (int)g_cus : 0) << " " << k.dt << " " << k.n << " " << k.matrix << " "
-    << k.in_place << " " << k.herm << " " << t.db << " " << t.r << " " << t.grid << " " << t.order2 << "\n";
+    << k.in_place << " " << k.herm << " " << t.db << " " << t.r << " " << t.grid << " " << t.order2 << " "
+    << t.chunk << "\n";
 }
 
 const char* layout_name(int l) { return l == L_MAT ? "MAT" : (l == L_CAN ? "CAN" : "MID"); }
@@ -349,11 +366,12 @@ std::string describe(const Schedule& s) {
   std::string j;
   std::snprintf(buf, sizeof buf,
                 "{\"n\":%d,\"dtype\":\"%s\",\"layout\":\"%s\",\"in_place\":%s,\"prune\":%s,"
-                "\"hermitian\":%s,\"elements\":%llu,\"algorithmic_bytes\":%llu,\"bitmap_words\":%llu,\"sweeps\":[",
+                "\"hermitian\":%s,\"elements\":%llu,\"algorithmic_bytes\":%llu,\"bitmap_words\":%llu,"
+                "\"chunk_bits\":%d,\"sweeps\":[",
                 s.n, dtype_name(s.dt), s.matrix_layout ? "matrix" : "canonical",
                 s.in_place ? "true" : "false", s.prune ? "true" : "false",
                 (s.nsweep == 2 && s.sw[0].herm) ? "true" : "false", (unsigned long long)count,
-                (unsigned long long)(2 * count * eb), (unsigned long long)s.bitmap_words);
+                (unsigned long long)(2 * count * eb), (unsigned long long)s.bitmap_words, s.chunk_bits);
   j += buf;
   for (int i = 0; i < s.nsweep; ++i) {
     const SweepDesc& w = s.sw[i];
@@ -590,7 +608,7 @@ struct Timing {
 // single-matrix execution
 // ---------------------------------------------------------------------------
 tpd_status_t launch_sweep_i(const Schedule& s, int i, const void* A, void* C, uint32_t* bitmap,
-                            const uint32_t* req, hipStream_t st) {
+                            const uint32_t* req, hipStream_t st, int64_t chunk = -1) {
   const SweepDesc& w = s.sw[i];
   SweepArgs a{};
   a.in = (i == 0) ? A : C;
@@ -607,6 +625,13 @@ tpd_status_t launch_sweep_i(const Schedule& s, int i, const void* A, void* C, ui
   a.req = req;
   a.ntiles = w.ntiles;
   a.tile_order = w.tile_order;
+  if (chunk >= 0) {
+    // chunk `chunk` of 2^chunk_bits first-sweep d-groups; in d-groups of
+    // this sweep's width (the second sweep's may be half as wide)
+    a.chunk_bits = s.chunk_bits + s.sw[0].db - w.db;
+    a.td_base = (uint64_t)chunk << a.chunk_bits;
+    a.ntiles = ((uint64_t)1 << (s.n - w.xb)) << a.chunk_bits;
+  }
   const hipError_t e = launch_sweep(s.dt, w, a, st);
   if (e != hipSuccess) {
     logf("sweep %d launch failed: %s", i, hipGetErrorString(e));
@@ -624,6 +649,18 @@ tpd_status_t run_schedule(const Schedule& s, const void* A, void* C, uint32_t* b
   }
   if (s.prune && s.nsweep == 2) {
     if (launch_fill_u32(bitmap, s.bitmap_words, 0u, st) != hipSuccess) return TPD_ERROR_LAUNCH;
+  }
+  if (s.nsweep == 2 && s.chunk_bits > 0) {
+    // sweep 1 then sweep 2 over one chunk of d-groups at a time (the
+    // sweeps' tiles never cross a d-group, so each chunk is closed); timing
+    // records the whole loop as kernel 0
+    const uint64_t nchunks = (uint64_t)1 << (s.n - s.sw[0].db - s.chunk_bits);
+    const int slot = tm ? tm->begin(0, st) : -1;
+    tpd_status_t e = TPD_SUCCESS;
+    for (uint64_t c = 0; c < nchunks && !e; ++c)
+      for (int i = 0; i < 2 && !e; ++i) e = launch_sweep_i(s, i, A, C, bitmap, nullptr, st, (int64_t)c);
+    if (tm) tm->end(0, slot, st);
+    return e;
   }
   for (int i = 0; i < s.nsweep; ++i) {
     const int slot = tm ? tm->begin(i, st) : -1;
@@ -655,7 +692,7 @@ tpd_status_t run_partial(const Schedule& s, const void* A, void* C, const uint64
     const int cus = g_cus > 0 ? (int)g_cus : 256;
     if (launch_fill_u32(groups, group_words + s.bitmap_words, 0u, st) != hipSuccess) return TPD_ERROR_LAUNCH;
     if (launch_fill_u32(pl.counts, 2, 0u, st) != hipSuccess) return TPD_ERROR_LAUNCH;
-    if (launch_mark_requests(req, count, s.n, s.n1, s.sw[0].db, groups, tiles, st) != hipSuccess)
+    if (launch_mark_requests(req, count, s.n, s.n1, s.sw[0].db, s.sw[1].db, groups, tiles, st) != hipSuccess)
       return TPD_ERROR_LAUNCH;
     const bool group_list = !s.sw[0].herm;
     if (group_list && launch_bits_to_list(groups, group_words, pl.groups, &pl.counts[0], st) != hipSuccess)
@@ -685,11 +722,16 @@ tpd_status_t run_partial(const Schedule& s, const void* A, void* C, const uint64
           a.req = groups;
         }
       } else {
-        if (s.prune && launch_and_u32(tiles, live, s.bitmap_words, st) != hipSuccess) return TPD_ERROR_LAUNCH;
+        // Hermitian mode: requested zero tiles stay in the list and the
+        // kernel stores their mirrored rows, which the first sweep never
+        // wrote; otherwise the list holds requested and live tiles only
+        const bool herm_zero = s.prune && w.herm;
+        if (s.prune && !herm_zero && launch_and_u32(tiles, live, s.bitmap_words, st) != hipSuccess)
+          return TPD_ERROR_LAUNCH;
         if (launch_bits_to_list(tiles, s.bitmap_words, pl.tiles, &pl.counts[1], st) != hipSuccess)
           return TPD_ERROR_LAUNCH;
-        a.bitmap = nullptr;
-        a.bitmap_mode = 0;  // the list holds requested (and live) tiles only
+        a.bitmap = herm_zero ? live : nullptr;
+        a.bitmap_mode = herm_zero ? 2 : 0;
         a.list = pl.tiles;
         a.list_count = &pl.counts[1];
         a.list_shift = 0;
@@ -870,8 +912,12 @@ tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dt
   if (st) return st;
   hipStream_t hs = (hipStream_t)stream;
   uint32_t* bm = nullptr;
+  // the lock is held until the kernels are enqueued: another thread on the
+  // same stream could otherwise grow (free and reallocate) the workspace
+  // between this thread taking its pointer and launching on it
+  std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
   if (s.prune && s.nsweep == 2) {
-    std::lock_guard<std::mutex> lk(g_mu);
+    lk.lock();
     Workspace& w = g_ws[{dev, hs}];
     st = ensure_bitmap(w, s.bitmap_words);
     if (st) return st;
@@ -927,8 +973,9 @@ tpd_status_t tpd_decompose_partial(const void* A, int n, void* coeffs, const uin
     return launch_gather(dt, coeffs, 0, s.matrix_layout, req, count, values, hs) == hipSuccess ? TPD_SUCCESS
                                                                                               : TPD_ERROR_LAUNCH;
   }
+  std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);  // held until the kernels are enqueued
   if (s.nsweep == 2) {
-    std::lock_guard<std::mutex> lk(g_mu);
+    lk.lock();
     Workspace& w = g_ws[{dev, hs}];
     if (s.prune) {
       st = ensure_bitmap(w, s.bitmap_words);
@@ -969,8 +1016,8 @@ tpd_status_t tpd_compact(const void* coeffs, int n, tpd_dtype_t dtype, unsigned 
   const uint64_t nchunks = (elems + kCompactChunk - 1) / kCompactChunk;
   uint32_t* counts;
   uint64_t* offsets;
+  std::lock_guard<std::mutex> lk(g_mu);  // held until the kernels are enqueued
   {
-    std::lock_guard<std::mutex> lk(g_mu);
     Workspace& w = g_ws[{dev, hs}];
     const size_t cbytes = ((nchunks * 4 + 255) / 256) * 256;
     st = ensure_sel(w, cbytes + nchunks * 8);
@@ -1163,8 +1210,9 @@ tpd_status_t tpd_plan_prune_stats(tpd_plan_t plan, uint64_t* live_tiles, uint64_
   *live_tiles = c;
   *total_tiles = s.sw[1].ntiles;
   // a level-n1 CMW is the set of tiles sharing x_hi and the top n1 d bits;
-  // bit index = (td << n1) | x_hi, td = d >> db
-  const int db = s.sw[0].db;
+  // bit index = (td << n1) | x_hi, td = d >> db2 (the bitmap has one bit per
+  // second-sweep tile, whose width may differ from the first sweep's)
+  const int db = s.sw[1].db;
   const int lowd = s.n2 - db;  // d bits [db, n2) vary inside one CMW
   std::vector<uint8_t> live(((size_t)1 << (2 * s.n1)), 0);
   const uint64_t nb = s.sw[1].ntiles;
@@ -1245,7 +1293,7 @@ tpd_status_t tpd_decompose_batched(const void* const* ptrs, const int* ns, int c
 // ---------------------------------------------------------------------------
 namespace tpd {
 tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, const int* tune, SweepDesc* sw,
-                           int* nsweep, int* n1, uint64_t* bitmap_words) {
+                           int* nsweep, int* n1, uint64_t* bitmap_words, int* chunk_bits) {
   tpd_status_t st = check_dtype_flags_complex(dtype, flags);
   if (st) return st;
   Schedule s;
@@ -1254,6 +1302,7 @@ tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, cons
     t.db = tune[0];
     t.r = tune[1];
     t.grid = tune[2];
+    t.chunk = tune[3];
   }
   st = make_schedule_with(n, (Dtype)dtype, flags, in_place, tune && n > 8 ? &t : nullptr, &s);
   if (st) return st;
@@ -1261,6 +1310,7 @@ tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, cons
   *nsweep = s.nsweep;
   *n1 = s.n1;
   *bitmap_words = s.bitmap_words;
+  *chunk_bits = s.chunk_bits;
   return TPD_SUCCESS;
 }
 
@@ -1315,12 +1365,12 @@ double median3(std::vector<float>& v) {
 }  // namespace
 
 extern "C" tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype,
-                                                  unsigned flags, int db, int r, int grid_per_cu,
+                                                  unsigned flags, int db, int r, int grid_per_cu, int chunk_bits,
                                                   tpd_stream_t stream) {
   tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (n < 0 || n > max_qubits((Dtype)dtype)) return TPD_ERROR_UNSUPPORTED;
-  if (grid_per_cu < 0 || grid_per_cu > 64) return TPD_ERROR_INVALID_VALUE;
+  if (grid_per_cu < 0 || grid_per_cu > 64 || chunk_bits < 0) return TPD_ERROR_INVALID_VALUE;
   const Dtype dt = (Dtype)dtype;
   st = check_buffers(A, coeffs, n, dt);
   if (st) return st;
@@ -1331,13 +1381,18 @@ extern "C" tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* co
   t.db = db;
   t.r = r;
   t.grid = grid_per_cu;
+  t.chunk = chunk_bits;
   Schedule s;
   st = make_schedule_with(n, dt, flags, A == coeffs, n > 8 ? &t : nullptr, &s);
   if (st) return st;
   hipStream_t hs = (hipStream_t)stream;
   uint32_t* bm = nullptr;
+  // the lock is held until the kernels are enqueued: another thread on the
+  // same stream could otherwise grow (free and reallocate) the workspace
+  // between this thread taking its pointer and launching on it
+  std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
   if (s.prune && s.nsweep == 2) {
-    std::lock_guard<std::mutex> lk(g_mu);
+    lk.lock();
     Workspace& w = g_ws[{dev, hs}];
     st = ensure_bitmap(w, s.bitmap_words);
     if (st) return st;
@@ -1429,8 +1484,9 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
     if (st) return false;
     *med = median3(ms);
     char buf[192];
-    std::snprintf(buf, sizeof buf, "%s{\"db\":%d,\"r\":%d,\"grid_per_cu\":%d,\"order2\":%d,\"ms\":%.4f}",
-                  first ? "" : ",", t.db, t.r, t.grid, t.order2, *med);
+    std::snprintf(buf, sizeof buf,
+                  "%s{\"db\":%d,\"r\":%d,\"grid_per_cu\":%d,\"order2\":%d,\"chunk_bits\":%d,\"ms\":%.4f}",
+                  first ? "" : ",", t.db, t.r, t.grid, t.order2, t.chunk, *med);
     rep += buf;
     first = false;
     return true;
@@ -1457,6 +1513,28 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
       best_t = t;
     }
   }
+  // then the winner in the chunked order, sweep 1 and sweep 2 over 32-256 MB
+  // of d-groups at a time (whether the second sweep then reads the chunk
+  // from the memory-side cache depends on the device; measured here)
+  if (!st && best < 1e300 && !(flags & TPD_FLAG_HERMITIAN)) {
+    const Tuned base_t = best_t;
+    Schedule sc;
+    if (make_schedule_with(n, dt, tflags, in_place, &base_t, &sc) == TPD_SUCCESS && sc.nsweep == 2) {
+      const uint64_t group_bytes = ((uint64_t)elem_bytes(dt) << n) << sc.sw[0].db;
+      for (uint64_t mb = 32; mb <= 256 && !st; mb *= 2) {
+        int cb = 0;
+        while ((group_bytes << (cb + 1)) <= (mb << 20)) ++cb;
+        if (cb < 1 || cb >= n - sc.sw[0].db || (group_bytes << cb) != (mb << 20)) continue;
+        Tuned t = base_t;
+        t.chunk = cb;
+        double med;
+        if (time_candidate(t, &med) && med < best) {
+          best = med;
+          best_t = t;
+        }
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(hs);
@@ -1470,9 +1548,11 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
     g_tuned[key] = best_t;
     save_tune_entry(key, best_t);
   }
-  char buf[160];
-  std::snprintf(buf, sizeof buf, "],\"chosen\":{\"db\":%d,\"r\":%d,\"grid_per_cu\":%d,\"order2\":%d,\"ms\":%.4f}}",
-                best_t.db, best_t.r, best_t.grid, best_t.order2, best);
+  char buf[256];
+  std::snprintf(buf, sizeof buf,
+                "],\"chosen\":{\"db\":%d,\"r\":%d,\"grid_per_cu\":%d,\"order2\":%d,\"chunk_bits\":%d,"
+                "\"ms\":%.4f}}",
+                best_t.db, best_t.r, best_t.grid, best_t.order2, best_t.chunk, best);
   rep += buf;
   logf("autotune %s", rep.c_str());
   return report ? copy_out(rep, report, len) : TPD_SUCCESS;

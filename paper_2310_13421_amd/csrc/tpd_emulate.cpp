@@ -60,6 +60,7 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
   constexpr int NBW = (1 << G::XB) >= 32 ? (1 << G::XB) / 32 : 1;
   const int n = a.n, xlo = a.xlo, db = a.db;
   const uint64_t tdmask = ((uint64_t)1 << a.nfix_d) - 1;
+  const int tdb = a.chunk_bits > 0 ? a.chunk_bits : a.nfix_d;  // d-group bits of the tile index
   const bool in_place = (const void*)in == (const void*)out;
   std::vector<Cx<S>> v((size_t)G::NT * G::E), lds((size_t)1 << G::B);
   std::vector<uint64_t> rset, wset;
@@ -108,8 +109,8 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
     } else if (a.herm && xlo) {
       herm_first_tile(tile, xlo, G::DB, a.nfix_d, &xf, &td);
     } else {
-      td = tile & tdmask;
-      xf = tile >> a.nfix_d;
+      td = a.td_base + (tile & (((uint64_t)1 << tdb) - 1));
+      xf = tile >> tdb;
     }
     if (a.list) {
       if (td > tdmask || xf >= ((uint64_t)1 << xfbits)) return TPD_ERROR_INTERNAL;
@@ -155,10 +156,14 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
             const uint64_t ao = layout_addr<OUTL>(x, d, n, db);
             ck.rd(ai);
             ck.wr(ao);
-            if (must_be_zero && ai < ck.count && !(((uint64_t)((e >> G::DB) & XM)) & hskip)) {
+            const bool mirrored = (((uint64_t)((e >> G::DB) & XM)) & hskip) != 0;
+            if (must_be_zero && ai < ck.count && !mirrored) {
               const Cx<S> z = in[ai];
               if (z.re != (S)0 || z.im != (S)0) return TPD_ERROR_INTERNAL;  // bit must have been set
             }
+            // the kernel stores zeros on the mirrored rows of a Hermitian
+            // zero tile (the first sweep never wrote them)
+            if (mirrored && ao < ck.count) out[ao] = Cx<S>{(S)0, (S)0};
           }
         }
         continue;
@@ -494,7 +499,7 @@ tpd_status_t emulate_item_n(const void* const* ptrs, void* const* outs, const ui
 namespace tpd {
 // defined in tpd_api.cpp
 tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, const int* tune, SweepDesc* sw,
-                           int* nsweep, int* n1, uint64_t* bitmap_words);
+                           int* nsweep, int* n1, uint64_t* bitmap_words, int* chunk_bits);
 tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, int dtype,
                                std::vector<uint32_t>* perm, std::vector<BatchItem>* items);
 tpd_status_t host_synth_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep);
@@ -541,15 +546,17 @@ extern "C" tpd_status_t tpd_debug_emulate_synth(const void* coeffs, int n, void*
 }
 
 extern "C" tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype,
-                                                unsigned flags, int in_place, int db, int r) {
+                                                unsigned flags, int in_place, int db, int r, int chunk_bits) {
   if (!A || !coeffs) return TPD_ERROR_INVALID_VALUE;
   if (n < 0 || n > 12) return TPD_ERROR_UNSUPPORTED;  // host replay is for small n
   if (in_place && A != coeffs) return TPD_ERROR_INVALID_VALUE;
+  if (chunk_bits < 0 || (chunk_bits > 0 && db <= 0)) return TPD_ERROR_INVALID_VALUE;
   SweepDesc sw[2];
-  int nsweep = 0, n1 = 0;
+  int nsweep = 0, n1 = 0, chunk = 0;
   uint64_t words = 0;
-  const int tune[3] = {db, r, 0};
-  tpd_status_t st = host_schedule(n, dtype, flags, in_place != 0, db > 0 ? tune : nullptr, sw, &nsweep, &n1, &words);
+  const int tune[4] = {db, r, 0, chunk_bits};
+  tpd_status_t st =
+      host_schedule(n, dtype, flags, in_place != 0, db > 0 ? tune : nullptr, sw, &nsweep, &n1, &words, &chunk);
   if (st) return st;
   const uint64_t count = (uint64_t)1 << (2 * n);
   const size_t eb = dtype == TPD_C128 ? 16 : 8;
@@ -558,33 +565,45 @@ extern "C" tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coef
     return TPD_SUCCESS;
   }
   std::vector<uint32_t> bitmap(words ? words : 1, 0u);
-  for (int i = 0; i < nsweep; ++i) {
-    SweepArgs a{};
-    a.in = i == 0 ? A : coeffs;
-    a.out = coeffs;
-    a.n = n;
-    a.xlo = sw[i].xlo;
-    a.db = sw[i].db;
-    a.nfix_d = n - sw[i].db;
-    a.bitmap = bitmap.data();
-    a.bitmap_mode = sw[i].bitmap_mode;
-    a.bm_xbits = n1;
-    a.herm = sw[i].herm;
-    a.ntiles = sw[i].ntiles;
-    Checker ck(count);
-    if (dtype == TPD_C128)
-      st = emulate_shape<double>(sw[i], (const Cx<double>*)a.in, (Cx<double>*)a.out, a, bitmap.data(), ck);
-    else
-      st = emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, bitmap.data(), ck);
-    if (st) return st;
-    if (!ck.complete()) return TPD_ERROR_INTERNAL;
+  // chunked order: sweep 1 then sweep 2 per chunk of d-groups; each sweep's
+  // checker accumulates over the chunks, so completeness covers the union
+  const uint64_t nchunks = (nsweep == 2 && chunk > 0) ? ((uint64_t)1 << (n - sw[0].db - chunk)) : 1;
+  Checker ck0(count), ck1(count);
+  Checker* cks[2] = {&ck0, &ck1};
+  for (uint64_t c = 0; c < nchunks; ++c) {
+    for (int i = 0; i < nsweep; ++i) {
+      SweepArgs a{};
+      a.in = i == 0 ? A : coeffs;
+      a.out = coeffs;
+      a.n = n;
+      a.xlo = sw[i].xlo;
+      a.db = sw[i].db;
+      a.nfix_d = n - sw[i].db;
+      a.bitmap = bitmap.data();
+      a.bitmap_mode = sw[i].bitmap_mode;
+      a.bm_xbits = n1;
+      a.herm = sw[i].herm;
+      a.ntiles = sw[i].ntiles;
+      if (nchunks > 1) {
+        a.chunk_bits = chunk + sw[0].db - sw[i].db;
+        a.td_base = c << a.chunk_bits;
+        a.ntiles = ((uint64_t)1 << (n - sw[i].xb)) << a.chunk_bits;
+      }
+      if (dtype == TPD_C128)
+        st = emulate_shape<double>(sw[i], (const Cx<double>*)a.in, (Cx<double>*)a.out, a, bitmap.data(), *cks[i]);
+      else
+        st = emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, bitmap.data(), *cks[i]);
+      if (st) return st;
+    }
   }
+  for (int i = 0; i < nsweep; ++i)
+    if (!cks[i]->complete()) return TPD_ERROR_INTERNAL;
   return TPD_SUCCESS;
 }
 
 extern "C" tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                                           int in_place) {
-  return tpd_debug_emulate_tuned(A, n, coeffs, dtype, flags, in_place, 0, 0);
+  return tpd_debug_emulate_tuned(A, n, coeffs, dtype, flags, in_place, 0, 0, 0);
 }
 
 extern "C" tpd_status_t tpd_debug_emulate_batched(const void* const* ptrs, const int* ns, int count,
@@ -628,7 +647,7 @@ extern "C" tpd_status_t tpd_debug_emulate_partial(const void* A, int n, void* co
   if (n == 0) {
     if (A != coeffs) std::memcpy(coeffs, A, eb);
   } else if (nsweep == 1) {
-    st = tpd_debug_emulate_tuned(A, n, coeffs, dtype, flags, in_place, 0, 0);
+    st = tpd_debug_emulate_tuned(A, n, coeffs, dtype, flags, in_place, 0, 0, 0);
     if (st) return st;
   } else {
     const int db = sw[0].db;
@@ -637,7 +656,7 @@ extern "C" tpd_status_t tpd_debug_emulate_partial(const void* A, int n, void* co
     for (uint64_t i = 0; i < count; ++i) {
       if (req[i] >= elems) continue;
       uint64_t g, t;
-      request_bits(req[i], n, n1, db, &g, &t);
+      request_bits(req[i], n, n1, db, sw[1].db, &g, &t);
       groups[g >> 5] |= 1u << (g & 31);
       tiles[t >> 5] |= 1u << (t & 31);
     }
@@ -676,12 +695,15 @@ extern "C" tpd_status_t tpd_debug_emulate_partial(const void* A, int n, void* co
           a.req = groups.data();
         }
       } else {
-        if (prune)
+        // Hermitian mode: requested zero tiles stay in the list, the kernel
+        // stores their mirrored rows (the first sweep never wrote them)
+        const bool herm_zero = prune && sw[i].herm;
+        if (prune && !herm_zero)
           for (uint64_t w = 0; w < words; ++w) tiles[w] &= live[w];
         to_list(tiles, &tlist);
         lcount = (uint32_t)tlist.size();
-        a.bitmap = nullptr;
-        a.bitmap_mode = 0;
+        a.bitmap = herm_zero ? live.data() : nullptr;
+        a.bitmap_mode = herm_zero ? 2 : 0;
         a.list = tlist.empty() ? &kNone : tlist.data();
         a.list_count = &lcount;
         a.list_shift = 0;

@@ -49,6 +49,11 @@ struct SweepArgs {
   int list_shift;
   uint64_t ntiles;  // with a list: the most tiles it can hold
   int tile_order;   // 1: rotated tile order (see SweepDesc)
+  // chunked two-sweep order: chunk_bits > 0 restricts the launch to the
+  // 2^chunk_bits consecutive d-groups starting at td_base (tile t is
+  // (xf = t >> chunk_bits, td = td_base + t mod 2^chunk_bits)); 0: every group
+  int chunk_bits;
+  uint64_t td_base;
 };
 
 // Batched work item: `nmat` matrices of the same n starting at `mat0`
@@ -79,7 +84,7 @@ hipError_t launch_batched_perm(Dtype dt, const void* const* in_ptrs, void* const
 hipError_t launch_popcount(const uint32_t* p, uint64_t words, unsigned long long* out, hipStream_t st);
 
 // selection kernels (tpd_select.hip)
-hipError_t launch_mark_requests(const uint64_t* req, uint64_t count, int n, int n1, int db, uint32_t* req_groups,
+hipError_t launch_mark_requests(const uint64_t* req, uint64_t count, int n, int n1, int db1, int db2, uint32_t* req_groups,
                                 uint32_t* req_tiles, hipStream_t st);
 hipError_t launch_and_u32(uint32_t* dst, const uint32_t* src, uint64_t words, hipStream_t st);
 hipError_t launch_bits_to_list(const uint32_t* bits, uint64_t words, uint32_t* list, uint32_t* count,
@@ -129,13 +134,14 @@ __host__ __device__ inline uint64_t q_of_storage(uint64_t a, int n, bool matrix_
   return (spread_bits(a >> n) << 1) | spread_bits(lo);
 }
 // the two request bits of canonical string q in a two-sweep schedule: its
-// d-group td = (row ^ col) >> db (first sweep) and its second-sweep tile
-// (td << n1) | (row >> (n - n1))
-__host__ __device__ inline void request_bits(uint64_t q, int n, int n1, int db, uint64_t* group, uint64_t* tile) {
+// first-sweep d-group (row ^ col) >> db1 and its second-sweep tile
+// (((row ^ col) >> db2) << n1) | (row >> (n - n1)); db1 and db2 are the
+// two sweeps' tile widths (they differ only for split widths)
+__host__ __device__ inline void request_bits(uint64_t q, int n, int n1, int db1, int db2, uint64_t* group,
+                                             uint64_t* tile) {
   const uint64_t row = pack_even_bits(q >> 1), col = pack_even_bits(q);
-  const uint64_t td = (row ^ col) >> db;
-  *group = td;
-  *tile = (td << n1) | (row >> (n - n1));
+  *group = (row ^ col) >> db1;
+  *tile = (((row ^ col) >> db2) << n1) | (row >> (n - n1));
 }
 // Hermitian first sweep: the tiles (fixed low x bits xf, d-group td) whose
 // row block holds representatives, enumerated without gaps so that every

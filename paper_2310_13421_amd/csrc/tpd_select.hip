@@ -13,7 +13,7 @@ namespace tpd {
 // ---------------------------------------------------------------------------
 // partial decomposition: request bitmaps and gather
 // ---------------------------------------------------------------------------
-__global__ void k_mark_requests(const uint64_t* __restrict__ req, uint64_t count, int n, int n1, int db,
+__global__ void k_mark_requests(const uint64_t* __restrict__ req, uint64_t count, int n, int n1, int db1, int db2,
                                 uint32_t* groups, uint32_t* tiles) {
   const uint64_t lim = (uint64_t)1 << (2 * n);
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
@@ -21,7 +21,7 @@ __global__ void k_mark_requests(const uint64_t* __restrict__ req, uint64_t count
     const uint64_t q = req[i];
     if (q >= lim) continue;  // answered with NaN by the gather
     uint64_t g, t;
-    request_bits(q, n, n1, db, &g, &t);
+    request_bits(q, n, n1, db1, db2, &g, &t);
     atomicOr(&groups[g >> 5], 1u << (g & 31));
     atomicOr(&tiles[t >> 5], 1u << (t & 31));
   }
@@ -92,11 +92,11 @@ static unsigned grid_for(uint64_t items, unsigned block, unsigned cap) {
   return g ? (unsigned)g : 1u;
 }
 
-hipError_t launch_mark_requests(const uint64_t* req, uint64_t count, int n, int n1, int db, uint32_t* groups,
-                                uint32_t* tiles, hipStream_t st) {
+hipError_t launch_mark_requests(const uint64_t* req, uint64_t count, int n, int n1, int db1, int db2,
+                                uint32_t* groups, uint32_t* tiles, hipStream_t st) {
   if (count == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mark_requests, dim3(grid_for(count, 256, 8192)), dim3(256), 0, st, req, count, n, n1, db,
-                     groups, tiles);
+  hipLaunchKernelGGL(k_mark_requests, dim3(grid_for(count, 256, 8192)), dim3(256), 0, st, req, count, n, n1, db1,
+                     db2, groups, tiles);
   return hipGetLastError();
 }
 

@@ -46,7 +46,8 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   const E* __restrict__ in = (const E*)a.in;
   E* __restrict__ out = (E*)a.out;
   const int n = a.n, xlo = a.xlo, db = a.db;
-  const uint64_t tdmask = ((uint64_t)1 << a.nfix_d) - 1;
+  const int tdb = a.chunk_bits > 0 ? a.chunk_bits : a.nfix_d;  // d-group bits of the tile index
+  const uint64_t tdmask = ((uint64_t)1 << tdb) - 1;
 
   // Canonical-order output: the tile is passed once more through LDS so that
   // each store instruction writes 64 consecutive coefficients (whole cache
@@ -72,6 +73,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   // input when its row block holds no representatives.
   struct Tile {
     uint64_t td, xf, xfix, hm;
+    bool zero;  // Hermitian second sweep, zero tile: only its mirrored rows are stored (zeros)
   };
   // tiles of this launch: all, or the entries of a work list
   const uint64_t lcount = a.list ? (uint64_t)uniform_word(a.list_count, 0) : 0;
@@ -87,33 +89,40 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
     } else if (a.herm && xlo) {
       herm_first_tile(tile, xlo, G::DB, a.nfix_d, &t.xf, &t.td);
     } else {
-      t.td = tile & tdmask;
-      t.xf = tile >> a.nfix_d;
+      t.td = a.td_base + (tile & tdmask);
+      t.xf = tile >> tdb;
       if (a.tile_order) {
         // rotated order: the row block index advances with every 8 d-groups,
         // so workgroups running at the same time spread over row blocks (a
         // bijection of the tile index: the tile count is a power of two)
-        const uint64_t xmask = (ntiles >> a.nfix_d) - 1;
+        const uint64_t xmask = (ntiles >> tdb) - 1;
         t.xf = (t.xf ^ (t.td >> 3)) & xmask;
       }
     }
     t.xfix = (t.xf & (((uint64_t)1 << xlo) - 1)) | ((t.xf >> xlo) << (xlo + G::XB));
     if (a.req && !((uniform_word(a.req, t.td >> 5) >> (t.td & 31)) & 1u)) return false;
-    if (a.bitmap_mode == 2) {
-      const uint64_t bit = (t.td << a.bm_xbits) | t.xf;
-      if (!((uniform_word(a.bitmap, bit >> 5) >> (bit & 31)) & 1u)) return false;  // zero subtree
-    }
     // Hermitian input: entry (x, d) is the conjugate of (x ^ d, d), and so
     // is every intermediate value inside one cumulative matrix weight.  With
     // dlh = the d bits of this tile above the diagonal group, below n2, and
     // m the top set bit of d's low n2 bits, only rows with x bit m = 0 are
     // needed ("representatives"); the others follow by conjugation.
     t.hm = 0;  // 1 << m when representatives can be used, else 0
+    t.zero = false;
     if (a.herm) {
       const int n2 = xlo ? xlo : G::XB;
       const uint64_t dlh = t.td & (((uint64_t)1 << (n2 - G::DB)) - 1);
       if (dlh) t.hm = (uint64_t)1 << (63 - __builtin_clzll(dlh) + G::DB);
       if (xlo && (t.xf & t.hm)) return false;  // first sweep: never enumerated (herm_first_tile)
+    }
+    if (a.bitmap_mode == 2) {
+      const uint64_t bit = (t.td << a.bm_xbits) | t.xf;
+      if (!((uniform_word(a.bitmap, bit >> 5) >> (bit & 31)) & 1u)) {
+        // zero subtree: the first sweep already stored its zeros, except, in
+        // the Hermitian mode, on the mirrored rows it never visits; those are
+        // written here (stores only, nothing is read)
+        if (!(a.herm && !xlo && t.hm)) return false;
+        t.zero = true;
+      }
     }
     return true;
   };
@@ -122,6 +131,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
     return tile;
   };
   auto load = [&](const Tile& t, E* v) {
+    if (t.zero) return;
     const uint64_t x = t.xfix | ((uint64_t)((eb0 >> G::DB) & XM) << xlo);
     const uint64_t d = (t.td << G::DB) | (eb0 & DM);
     const uint64_t base = layout_addr<INL>(x, d, n, db);
@@ -165,6 +175,26 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   // Transform one loaded tile and store it.
   auto process = [&](const Tile& t, E* v) {
     const uint64_t td = t.td, hm = t.hm, xfix = t.xfix;
+    if (t.zero) {
+      // Hermitian zero tile: zeros on the rows with x bit m set (the
+      // representatives already hold the first sweep's zeros).  Row bit m
+      // of an element is the same in every layout, so these are exactly the
+      // addresses the first sweep left unwritten.
+      const uint64_t x = xfix | ((uint64_t)((ebo >> G::DB) & XM) << xlo);
+      const uint64_t d = (td << G::DB) | (ebo & DM);
+      const uint64_t base = layout_addr<OUTL>(x, d, n, db);
+#pragma unroll
+      for (int j = 0; j < G::E; ++j) {
+        const uint32_t e = REMAP ? (ebo | elem_reg_st<G>(RL, j)) : (ebl | elem_reg<G>(RL, LAST, j));
+        if (!(((uint64_t)((e >> G::DB) & XM)) & hm)) continue;
+        uint64_t ad = base;
+#pragma unroll
+        for (int s = 0; s < G::R; ++s)
+          if ((j >> s) & 1) ad ^= dout[s];
+        out[ad] = E{};
+      }
+      return;
+    }
     if constexpr (SPLIT) {
       if (a.bitmap_mode == 1 && (int)tid < nbw) bits[tid] = 0;
     } else {

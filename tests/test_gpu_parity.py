@@ -88,24 +88,22 @@ def run(A_host, dtype=torch.complex128, **kw):
     return out.cpu().numpy()
 
 
+HOST_THREADS = 16  # the GPU machine's host share
+
+
 def sampled_oracle(A_dev, n, qs, chunk_masks=256):
     """omega_q for sampled q from the definition, reading only the entries
-    A[i ^ x][i] each string needs (gathered from the device input)."""
-    qs = np.asarray(qs, np.uint64)
-    masks = np.array([O.xy_mask(int(q), n) for q in qs], np.int64)
-    out = np.empty(qs.size, np.complex128)
+    A[i ^ x][i] each string needs (gathered from the device input), the
+    per-mask sums on host threads."""
     flat = A_dev.view(-1)
     i = torch.arange(1 << n, device=A_dev.device, dtype=torch.int64)
-    uniq = np.unique(masks)
-    for c0 in range(0, uniq.size, chunk_masks):
-        ms = uniq[c0:c0 + chunk_masks]
-        xs = torch.from_numpy(ms).to(A_dev.device)
+
+    def fetch(ms):
+        xs = torch.from_numpy(np.asarray(ms, np.int64)).to(A_dev.device)
         idx = ((i[None, :] ^ xs[:, None]) << n) + i[None, :]
-        v = flat[idx.reshape(-1)].to(torch.complex128).reshape(len(ms), -1).cpu().numpy()
-        for k, x in enumerate(ms):
-            sel = np.flatnonzero(masks == x)
-            out[sel] = O.weight_from_diagonal(v[k], n, int(x), qs[sel])
-    return out
+        return flat[idx.reshape(-1)].to(torch.complex128).reshape(len(ms), -1).cpu().numpy()
+
+    return O.sampled_weights(fetch, n, qs, threads=HOST_THREADS, masks_per_fetch=chunk_masks)
 
 
 # ----------------------------------------------------------------------------
@@ -316,12 +314,14 @@ def test_batched_plan_graph_capture_and_layouts():
 # configuration 4: n = 16 Hermitian, complex128 and complex64, sampled strings
 # ----------------------------------------------------------------------------
 def test_config4_n16_sampled_strings_parseval_both_precisions():
+    # 10^6 strings uniform over the 4^16 plus the forced ones (I..I, X..X,
+    # Y..Y, Z..Z, 4^16 - 1), each against the definition in binary64
     n = 16
     torch.cuda.empty_cache()
     A = W.gaussian_device(n, seed=5, hermitian=True)
     a_max = float(torch.view_as_real(A).abs().max())
     fro = float(torch.view_as_real(A).double().square().sum())
-    qs = W.sampled_strings(n, 4000, seed=5)
+    qs = W.sampled_strings(n, 10 ** 6, seed=5)
     bf = sampled_oracle(A, n, qs)
     qd = torch.from_numpy(qs.astype(np.int64)).to(DEV)
 
@@ -754,6 +754,42 @@ def test_n17_real_tfim_pruning_with_split_tile_widths():
     assert sched["sweeps"][0]["db"] in (5, 6)
 
 
+def test_n17_real_split_widths_prune_stats_and_partial():
+    # real float32, matrix layout, n = 17: the default schedule gives the two
+    # sweeps different tile widths (2^6 and 2^5 diagonals).  The pruning
+    # bitmap has one bit per second-sweep tile, so the live level-8 CMWs of
+    # the Ising chain (2k + 1 = 17, section "Results") and the partial
+    # decomposition's request tiles must be counted at the second sweep's width.
+    n = 17
+    torch.cuda.empty_cache()
+    terms = W.tfim_terms(n, 1.0, 0.5)
+    expect = {W.string_index(s_): float(np.real(c)) for s_, c in terms}
+    H = W.dense_from_terms_device(terms, n, dtype=torch.float32)
+    plan = tpd.Plan(n, tpd.TPD_R32, layout="matrix", in_place=True)
+    sw = plan.describe()["sweeps"]
+    plan.execute(H, H.view(-1))
+    st = plan.prune_stats()
+    plan.close()
+    assert st["prefix_level"] == 8 and st["live_prefixes"] == 2 * 8 + 1, (sw, st)
+    qs, ws, total = tpd.compact(H.view(-1), layout="matrix")
+    assert total == 2 * n - 1
+    assert dict(zip(qs.cpu().numpy().tolist(), ws.cpu().numpy().tolist())) == expect
+    del H
+    torch.cuda.empty_cache()
+    # partial, bottom-first order (default widths, split like the plan above)
+    H = W.dense_from_terms_device(terms, n, dtype=torch.float32)
+    rng = np.random.default_rng(1717)
+    req = np.concatenate([np.array(sorted(expect), np.int64), two_local(n),
+                          rng.integers(0, 4 ** n, 2000, dtype=np.int64)])
+    vals = tpd.decompose_partial(H, torch.from_numpy(req).to(DEV), work=H.view(-1), layout="matrix",
+                                 order_bottom=True).cpu().numpy()
+    want = np.array([expect.get(int(q), 0.0) for q in req], np.float32)
+    assert np.array_equal(vals, want)
+    del H
+    torch.cuda.empty_cache()
+    assert sw[0]["db"] == 6 and sw[1]["db"] == 5, sw
+
+
 @pytest.mark.parametrize("dtype,code", [(torch.complex128, tpd.TPD_C128), (torch.complex64, tpd.TPD_C64),
                                         (torch.float64, tpd.TPD_R64)])
 def test_n16_tfim_pruning_lane_group_bits(dtype, code):
@@ -985,6 +1021,108 @@ def test_hermitian_mode(n):
         assert np.array_equal(got.real, gen.cpu().numpy().real) and np.all(got.imag == 0)
 
 
+def _terms_dense_expect(terms, n, dtype):
+    """Dense expected weights on the device: the generating coefficients at
+    their canonical indices, zeros elsewhere."""
+    qs = torch.tensor([W.string_index(s) for s, _ in terms], dtype=torch.int64, device=DEV)
+    cs = torch.tensor(np.array([c for _, c in terms], np.complex128), device=DEV)
+    exp = torch.zeros(4 ** n, dtype=torch.complex128, device=DEV)
+    exp.index_put_((qs,), cs, accumulate=True)
+    return exp.to(dtype) if dtype.is_complex else exp.real.to(dtype).contiguous()
+
+
+def _dev_matrix_to_canonical(M, n):
+    """Matrix-layout weights (device) to canonical order (device)."""
+    d = 1 << n
+    h = torch.arange(d, device=DEV, dtype=torch.int64)
+    sp = torch.zeros_like(h)
+    for b in range(n):
+        sp |= ((h >> b) & 1) << (2 * b)
+    q = ((sp[:, None] << 1) | sp[None, :]).reshape(-1)
+    out = torch.empty(4 ** n, dtype=M.dtype, device=DEV)
+    out[q] = M.reshape(-1)
+    return out
+
+
+def _exactly(a, b):
+    """Same values everywhere (-0 == +0, NaN never equal)."""
+    if a.is_complex():
+        a, b = torch.view_as_real(a), torch.view_as_real(b)
+    return bool(torch.equal(a, b))
+
+
+@pytest.mark.parametrize("case", ["tfim10", "tfim12", "heisenberg14"])
+def test_hermitian_mode_structured_input_with_pruning(case):
+    # Hermitian mode with pruning on: the first sweep writes representative
+    # rows only, so a zero second-sweep tile must still store zeros on its
+    # mirrored rows.  Outputs start NaN-poisoned (out of place) or hold the
+    # input (in place); complex128 must give exactly the generating terms,
+    # complex64 the general path's real parts with imaginary parts 0.
+    if case.startswith("tfim"):
+        n = int(case[4:])
+        terms = W.tfim_terms(n, 1.0, 0.5)
+    else:
+        n = 14
+        terms = W.heisenberg_terms(n, seed=3, n_local=200, dyadic=True)
+    H = W.dense_from_terms_device(terms, n)
+    for dtype in (torch.complex128, torch.complex64):
+        Hd = H if dtype == torch.complex128 else H.to(dtype)
+        gen = tpd.decompose(Hd)
+        exp = _terms_dense_expect(terms, n, dtype) if dtype == torch.complex128 else torch.complex(
+            gen.real, torch.zeros_like(gen.real))
+        for layout in ("canonical", "matrix"):
+            out = torch.full((4 ** n,), float("nan"), dtype=dtype, device=DEV)
+            tpd.decompose(Hd, out, hermitian=True, layout=layout)
+            got = out if layout == "canonical" else _dev_matrix_to_canonical(out, n)
+            assert _exactly(got, exp), (case, dtype, layout)
+        T = Hd.clone()
+        tpd.decompose(T, T.view(-1), hermitian=True, layout="matrix")
+        assert _exactly(_dev_matrix_to_canonical(T.view(-1), n), exp), (case, dtype, "in place")
+        del Hd, gen, exp, T
+    del H
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_real_symmetric_mode_structured_input_with_pruning(dtype):
+    # the transverse-field Ising chain is real symmetric: real-coded weights
+    # in the real-symmetric (Hermitian) mode with zero tiles pruned, NaN-
+    # poisoned output and in place, equal the 2n - 1 generating terms
+    n = 12
+    terms = W.tfim_terms(n, 1.0, 0.5)
+    H = W.dense_from_terms_device(terms, n).real.to(dtype).contiguous()
+    exp = _terms_dense_expect(terms, n, dtype)
+    for layout in ("canonical", "matrix"):
+        out = torch.full((4 ** n,), float("nan"), dtype=dtype, device=DEV)
+        tpd.decompose(H, out, hermitian=True, layout=layout)
+        got = out if layout == "canonical" else _dev_matrix_to_canonical(out, n)
+        assert _exactly(got, exp), layout
+    T = H.clone()
+    tpd.decompose(T, T.view(-1), hermitian=True, layout="matrix")
+    assert _exactly(_dev_matrix_to_canonical(T.view(-1), n), exp)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_partial_hermitian_structured_every_string(dtype):
+    # every string requested from a structured Hermitian input: requests on
+    # the mirrored rows of zero tiles must read the zeros the second sweep
+    # stores there (work array NaN-poisoned; in place in the matrix layout)
+    n = 12
+    terms = W.heisenberg_terms(n, seed=12, n_local=60, dyadic=True)
+    H = W.dense_from_terms_device(terms, n).to(dtype)
+    full = tpd.decompose(H)
+    exp = torch.complex(full.real, torch.zeros_like(full.real))
+    q = torch.arange(4 ** n, dtype=torch.int64, device=DEV)
+    work = torch.full((4 ** n,), float("nan"), dtype=dtype, device=DEV)
+    vals = tpd.decompose_partial(H, q, work=work, hermitian=True)
+    assert _exactly(vals, exp)
+    T = H.clone()
+    vals = tpd.decompose_partial(T, q, work=T.view(-1), layout="matrix", hermitian=True)
+    assert _exactly(vals, exp)
+    if dtype == torch.complex128:
+        assert _exactly(full, _terms_dense_expect(terms, n, dtype))
+
+
 # ----------------------------------------------------------------------------
 # inverse transform (synthesis) and round trips
 # ----------------------------------------------------------------------------
@@ -1090,8 +1228,13 @@ def test_partial_vs_algorithm_3(n):
         T = Ad.clone()
         g3 = tpd.decompose_partial(T, qd, work=T.view(-1), layout="matrix").cpu().numpy()
         assert same_bits(g3, ref)
-        g64 = tpd.decompose_partial(to_dev(A, torch.complex64), qd).cpu().numpy()
-        assert cerr(g64, ref) <= (n + 1) * U32 * amax(A) * 1.5
+        # complex64: the requested values are bitwise the full decomposition's,
+        # which is within (n + 1) u max|a| (input rounding plus n levels)
+        A32 = to_dev(A, torch.complex64)
+        g64 = tpd.decompose_partial(A32, qd).cpu().numpy()
+        f64 = tpd.decompose(A32).cpu().numpy()
+        assert same_bits(g64, f64[q])
+        assert cerr(g64, ref) <= (n + 1) * U32 * amax(A)
 
 
 def test_config2_n14_partial_and_sparse_list():

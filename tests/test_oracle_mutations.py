@@ -3,7 +3,9 @@ and checks that the pin suite in test_oracle_pins.py rejects every one of
 them: a dropped block, a wrong sign, the factor -i instead of i, a missing
 1/2, a transposed block, the reversed digit order of the string index, the
 printed n-1 loop bound, the wrong Y matrix, a zero test that ignores the
-imaginary part or NaN, and transposed reads in the definition and synthesis.
+imaginary part or NaN, and transposed reads in the definition and synthesis,
+plus mistakes in the multithreaded form of Algorithm 2 (loop bound, a
+dropped row range).
 """
 import os
 
@@ -25,7 +27,14 @@ MUTANTS = {
                                "const double* a12 = M + 2 * ((r + h) * dim + c + h);"),
     "reversed_digit_order": ("tpd_rec(ctx, C, m - 1, prefix * 4 + (uint64_t)t);",
                              "tpd_rec(ctx, C, m - 1, prefix + ((uint64_t)t << (2 * (depth - 1))));"),
-    "printed_loop_bound_n_minus_1": ("for (int i = 1; i <= n; ++i) {", "for (int i = 1; i < n; ++i) {"),
+    "printed_loop_bound_n_minus_1": ("for (int i = 1; i <= n; ++i) {\n    const int m = n - i + 1; /* parent",
+                                     "for (int i = 1; i < n; ++i) {\n    const int m = n - i + 1; /* parent"),
+    "multithreaded_form_loop_bound_n_minus_1": (
+        "for (int i = 1; i <= n; ++i) {\n    const int m = n - i + 1;\n    const uint64_t psize",
+        "for (int i = 1; i < n; ++i) {\n    const int m = n - i + 1;\n    const uint64_t psize"),
+    "multithreaded_form_drops_last_row_range": ("const uint64_t r0 = h * part / split, r1 = h * (part + 1) / split;",
+                                                "const uint64_t r0 = h * part / split, r1 = h * part / split + "
+                                                "(h / split > 1 ? h / split - 1 : 1);"),
     "wrong_sign_of_Y": ("/* Y */ {{-1, 3}, {1, -1}},", "/* Y */ {{-1, 1}, {3, -1}},"),
     "zero_test_ignores_imag": ("if (re != 0.0 || im != 0.0 || re != re || im != im) nonzero = 1;",
                                "if (re != 0.0 || re != re) nonzero = 1;"),
@@ -59,6 +68,7 @@ def pin_checks(golden_dir):
         P.test_zero_and_nan_semantics,
         P.test_tensor_factorisation,
         P.test_purely_imaginary_cmw_is_live,
+        lambda: P.test_multithreaded_algorithm_2_is_the_serial_one(3),
     ]
 
 

@@ -216,6 +216,41 @@ def test_gaussian_recursion_vs_brute_force(n):
     assert same_bits(O.tpd_iterative(A), rec)
 
 
+@pytest.mark.parametrize("threads", [1, 2, 3, 8])
+def test_multithreaded_algorithm_2_is_the_serial_one(threads):
+    # the OpenMP form of Algorithm 2 (CPU baseline) performs the same per-entry
+    # operations: bitwise the serial weights and the same live-CMW counts, on
+    # dense, integer, structured (pruned), zero and NaN inputs
+    cases = [W.gaussian(n, seed=600 + n) for n in (1, 2, 4, 7, 9)]
+    cases.append(W.integer(8, seed=610))
+    cases.append(W.dense_from_terms(W.tfim_terms(9, 1.0, 0.5), 9))
+    cases.append(W.dense_from_terms(W.heisenberg_terms(10, seed=611, n_local=25, dyadic=True), 10))
+    cases.append(np.zeros((32, 32), np.complex128))
+    nan = np.zeros((64, 64), np.complex128)
+    nan[3, 40] = np.nan
+    cases.append(nan)
+    cases.append(np.array([[0.5 - 2j]]))
+    for A in cases:
+        w, live = O.tpd_iterative(A, with_stats=True)
+        wm, livem = O.tpd_iterative_mt(A, threads, with_stats=True)
+        # identical bit patterns (NaN payloads and signed zeros included)
+        assert np.array_equal(wm.view(np.uint64), w.view(np.uint64)) and np.array_equal(livem, live)
+
+
+def test_sampled_weights_grouped_by_mask_on_threads():
+    # the sampled-string evaluation used at full size (grouping by X/Y mask,
+    # host threads, entries fetched per mask) returns exactly the plain
+    # definition's values; the vectorised masks are the C function's
+    n = 8
+    A = W.gaussian(n, seed=650)
+    rng = np.random.default_rng(651)
+    qs = np.concatenate([rng.integers(0, 4 ** n, 6000), [0, 4 ** n - 1, 0x5555, 0xAAAA, 0xFFFF]])
+    i = np.arange(1 << n)
+    got = O.sampled_weights(lambda xs: np.stack([A[i ^ x, i] for x in xs]), n, qs, threads=3, masks_per_fetch=17)
+    assert same_bits(got, O.weight_sparse(A, qs))
+    assert np.array_equal(O._xy_masks(qs.astype(np.uint64), n), [O.xy_mask(int(q), n) for q in qs])
+
+
 def test_partial_tpd_matches_full():
     n = 6
     A = W.gaussian(n, seed=7)

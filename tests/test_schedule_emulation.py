@@ -193,6 +193,65 @@ def test_emulated_hermitian_mode_reads_half_and_matches(n):
         assert np.array_equal(got.real, gen.real) and np.all(got.imag == 0)
 
 
+@pytest.mark.parametrize("n", [9, 10])
+def test_chunked_order_is_bitwise_the_same(n):
+    # sweep 1 then sweep 2 over chunks of d-groups: every tile is still
+    # processed exactly once (the emulator checks completeness over the
+    # chunks), in place tiles stay closed, and results keep the oracle's bits;
+    # pruning bits of a chunk come from that chunk's first sweep
+    A = W.gaussian(n, seed=1200 + n)
+    ref = O.tpd_recursive(A)
+    H = W.dense_from_terms(W.heisenberg_terms(n, seed=1300 + n, n_local=20, dyadic=True), n)
+    href = O.tpd_recursive(H)
+    for db in (3, 4, 5):
+        if db > n // 2:
+            continue
+        # smallest and largest chunks (the largest: two chunks), and one between
+        for cb in sorted({1, (n - db) // 2, n - db - 1}):
+            assert same_bits(tpd.emulate(A, db=db, r=4, chunk_bits=cb), ref), (db, cb)
+            got = tpd.emulate(A, flags=tpd.FLAG_LAYOUT_MATRIX, in_place=True, db=db, r=4, chunk_bits=cb)
+            assert same_bits(matrix_to_canonical(got, n), ref), (db, cb)
+            assert same_bits(tpd.emulate(H, db=db, r=4, chunk_bits=cb), href), (db, cb)
+        with pytest.raises(tpd.TPDError):  # at least two chunks
+            tpd.emulate(A, db=db, r=4, chunk_bits=n - db)
+        with pytest.raises(tpd.TPDError):  # not with the Hermitian enumeration
+            tpd.emulate(A, flags=tpd.FLAG_HERMITIAN, db=db, r=4, chunk_bits=1)
+
+
+def _structured_cases():
+    # Hermitian inputs with zero cumulative matrix weights: the transverse-
+    # field Ising chain (section "Results") and a dyadic Heisenberg chain
+    # with 4-local strings
+    yield "tfim9", 9, W.tfim_terms(9, 1.0, 0.5)
+    yield "tfim10", 10, W.tfim_terms(10, 1.0, 0.5)
+    yield "tfim12", 12, W.tfim_terms(12, 1.0, 0.5)
+    yield "heis10", 10, W.heisenberg_terms(10, seed=5, n_local=30, dyadic=True)
+
+
+@pytest.mark.parametrize("case", [c[0] for c in _structured_cases()])
+def test_emulated_hermitian_mode_with_pruned_tiles(case):
+    # Hermitian mode + pruning: a zero second-sweep tile is skipped, but the
+    # first sweep never wrote its mirrored rows, so the kernel stores zeros
+    # there.  Out of place the output starts NaN-poisoned; in place it holds
+    # the input.  Both must come out exactly as the generating terms.
+    _, n, terms = next(c for c in _structured_cases() if c[0] == case)
+    H = W.dense_from_terms(terms, n)
+    expect = np.zeros(4 ** n, np.complex128)
+    for s, c in terms:
+        expect[W.string_index(s)] += c
+    for dt in (tpd.TPD_C128, tpd.TPD_C64):
+        got = tpd.emulate(H, dt, tpd.FLAG_HERMITIAN)
+        assert same_bits(got, expect.astype(got.dtype)), dt
+        got = tpd.emulate(H, dt, tpd.FLAG_HERMITIAN | tpd.FLAG_LAYOUT_MATRIX, in_place=True)
+        assert same_bits(matrix_to_canonical(got, n), expect.astype(got.dtype)), dt
+        for db in (3, 4, 5, 6):
+            try:
+                got = tpd.emulate(H, dt, tpd.FLAG_HERMITIAN, db=db)
+            except tpd.TPDError:
+                continue
+            assert same_bits(got, expect.astype(got.dtype)), (dt, db)
+
+
 def synth_bound(w, n, u):
     # each output component is a sum of 2^n weight components taken with
     # sign +-1: the level tree rounds <= n u 2^n max|w| and the oracle's

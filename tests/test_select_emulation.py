@@ -107,6 +107,23 @@ def test_partial_hermitian_and_complex64(n):
     assert np.array_equal(v32, tpd.emulate(A, dtype=tpd.TPD_C64)[q])
 
 
+@pytest.mark.parametrize("kind", ["tfim", "heisenberg"])
+def test_partial_hermitian_structured_requests_in_zero_tiles(kind):
+    # requests that fall on the mirrored rows of zero tiles: the first sweep
+    # never wrote those rows, so the second sweep must store their zeros
+    # (every string is requested; the work array starts NaN-poisoned)
+    n = 10
+    terms = W.tfim_terms(n, 1.0, 0.5) if kind == "tfim" else W.heisenberg_terms(n, seed=9, n_local=30, dyadic=True)
+    H = W.dense_from_terms(terms, n)
+    expect = np.zeros(4 ** n, np.complex128)
+    for s, c in terms:
+        expect[W.string_index(s)] += c
+    q = np.arange(4 ** n, dtype=np.int64)
+    for flags, in_place in ((tpd.FLAG_HERMITIAN, False), (tpd.FLAG_HERMITIAN | tpd.FLAG_LAYOUT_MATRIX, True)):
+        vals, _ = tpd.emulate_partial(H, q, flags=flags, in_place=in_place)
+        assert same_bits(vals, expect), flags
+
+
 def selection(c, tol, matrix=False, n=None):
     """Plain definition of the list: storage order, kept unless both parts
     are within tol (in the array's precision)."""
