@@ -139,6 +139,23 @@ tpd_status_t tpd_decompose(const void* A, int n, void* coeffs, tpd_stream_t stre
 tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                               tpd_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * decomposition as tpd_decompose_ex, with the same arguments, errors and
+ * results (bitwise), but the pruning bitmap lives in a static device array
+ * of 256 KiB that the library holds on each device it runs on until the
+ * process ends, instead of a workspace.  The call allocates and frees
+ * nothing.  The array's address on a device is looked up on the first call
+ * on that device (TPD_ERROR_LAUNCH if that fails).  Every call on a device
+ * shares that device's array and clears it (with a fill kernel) before use,
+ * so calls that overlap on one device, e.g. on two streams, race and give
+ * undefined results; calls ordered by one stream are fine.  A schedule
+ * whose bitmap exceeds the array is TPD_ERROR_UNSUPPORTED (none does:
+ * the largest, n = 16 at tile width 2^3 or n = 17 at 2^4, takes 2^21
+ * bits).  TPD_FLAG_TIMING is TPD_ERROR_INVALID_VALUE.                   */
+tpd_status_t tpd_decompose_noalloc(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
+                                   tpd_stream_t stream);
+
 /* Inverse transform (synthesis), eq. (PauliDecomposition) read left to
  * right: A = sum_t w_t sigma^t, by the same n levels with the inverse
  * slicing step (u, v) = (s + t conj(w), s - t conj(w)), w = i on X/Y

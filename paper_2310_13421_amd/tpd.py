@@ -48,6 +48,7 @@ _SIGS = {
     "tpd_max_qubits": (_I, [_I]),
     "tpd_decompose": (_I, [_P, _I, _P, _P]),
     "tpd_decompose_ex": (_I, [_P, _I, _P, _I, _U, _P]),
+    "tpd_decompose_noalloc": (_I, [_P, _I, _P, _I, _U, _P]),
     "tpd_decompose_batched": (_I, [_P, _P, _I, _P, _I, _U, _P]),
     "tpd_plan_create": (_I, [_I, _I, _U, _I, _P]),
     "tpd_plan_create_batched": (_I, [_P, _I, _I, _U, _I, _P]),
@@ -295,6 +296,20 @@ def decompose(A, out=None, *, layout: str = "canonical", prune: bool = True, ord
         raise ValueError("out must be a contiguous CUDA tensor of 4^n elements of A's dtype")
     _check(lib.tpd_decompose_ex(A.data_ptr(), n, out.data_ptr(), dt,
                                 _flags(layout, prune, order_bottom, hermitian), _stream(stream)), "tpd_decompose_ex")
+    return out
+
+
+def decompose_noalloc(A, out, *, layout: str = "canonical", prune: bool = True, hermitian: bool = False,
+                      stream=None):
+    """decompose() through tpd_decompose_noalloc: the library allocates
+    nothing (its pruning bitmap is a static device array shared by every
+    call on the device).  `out` is required."""
+    n = _check_matrix(A)
+    if out.dtype != A.dtype or not out.is_cuda or not out.is_contiguous() or out.numel() != 4 ** n:
+        raise ValueError("out must be a contiguous CUDA tensor of 4^n elements of A's dtype")
+    _check(lib.tpd_decompose_noalloc(A.data_ptr(), n, out.data_ptr(), _dtype_code(A),
+                                     _flags(layout, prune, False, hermitian), _stream(stream)),
+           "tpd_decompose_noalloc")
     return out
 
 

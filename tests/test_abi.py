@@ -89,6 +89,12 @@ FAKE = 0x100000  # never dereferenced: validation fails or the device check stop
 def test_decompose_validation_before_device(args, code):
     A, n, C, dt, fl = args
     assert tpd.lib.tpd_decompose_ex(A, n, C, dt, fl, None) == code
+    # the no-allocation entry point validates the same way
+    assert tpd.lib.tpd_decompose_noalloc(A, n, C, dt, fl, None) == code
+
+
+def test_noalloc_rejects_timing_flag():
+    assert tpd.lib.tpd_decompose_noalloc(FAKE, 4, FAKE * 4, 0, tpd.FLAG_TIMING, None) == 1
 
 
 def test_partial_and_compact_validation():
