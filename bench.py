@@ -1,17 +1,24 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the MI355X Tensorized Pauli Decomposition.
 
-Default workload (the largest single-GPU configuration): one dense Hermitian
+Headline (the largest single-GPU configuration): one dense Hermitian
 2^16 x 2^16 matrix, A = (G + G^H)/2 with complex N(0,1) G (seed 5),
-complex128, decomposed out of place into its 4^16 canonical Pauli
-coefficients.  A step is one full decomposition (bitmap clear + two HBM
-sweeps, pruning on).  Inputs are generated on the GPU and resident in HBM
-before the timed region.  Prints ONE JSON line.
+complex128, decomposed IN PLACE (coefficients in the matrix layout, the
+only in-place order for n > 6).  A step is one full decomposition (bitmap
+clear + two HBM sweeps, pruning on), timed with HIP events; the input is
+restored from a pristine device copy before every step, outside the timed
+region.  The K timed steps are spread over several successive allocations
+of the in-place buffer (where the driver places a 64 GiB buffer moves the
+rate by up to ~15 %): `value` is the median allocation's rate, and the
+allocations' figures are listed.  Inputs are generated on the GPU and
+resident in HBM before the timed region.  Prints ONE JSON line.
 
-Extras in the same line: the complex64 run of the same matrix, the same
-matrix in place (matrix layout), the n = 14 structured Hamiltonian with
-zero-block pruning, the 4096-matrix batched workload (graph replay vs
-per-matrix launches), and the CPU oracle timed on the host.
+Extras in the same line: the other configurations (n = 8 dense and
+integer, n = 12 Hermitian, n = 14 structured with pruning, the 4096-matrix
+batched set against a graph of per-matrix launches, n = 16 complex64), the
+error against the binary64 oracle for every configuration in both
+precisions, out-of-place / Hermitian-mode / real-input / synthesis /
+partial legs, and the CPU oracle timed on the host.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--extras ...]
 """
@@ -189,6 +196,7 @@ def ingest_pair(fetch_csv, write_csv):
     return kernels, fscale, wscale
 
 
+
 def timed_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -205,7 +213,28 @@ def kernel_avgs(plan):
     return [m / c if c else 0.0 for m, c in zip(ms, cnt)], cnt
 
 
+def event_ms(torch, fn, reps):
+    """Median over reps of fn's device time (events on the current stream)."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return sorted(ts)[len(ts) // 2]
+
+
 TUNE = True  # cleared by --no-autotune
+SCHED_KEYS = ("xb", "db", "r", "grid", "tile_elems", "threads", "in", "out")
+
+
+def _sched(desc):
+    return [{k: w[k] for k in SCHED_KEYS} for w in desc["sweeps"]]
 
 
 def single_matrix_run(tpd, torch, A, n, dtype_code, steps, warmup, esize, in_place=False, layout="canonical",
@@ -219,33 +248,33 @@ def single_matrix_run(tpd, torch, A, n, dtype_code, steps, warmup, esize, in_pla
     plan = tpd.Plan(n, dtype_code, timing=True, in_place=in_place, layout=layout, hermitian=hermitian, prune=prune)
     ms = timed_steps(lambda: plan.execute(A, out), steps, warmup, torch)
     avgs, cnt = kernel_avgs(plan)
-    plan.timing(reset=True)
     desc = plan.describe()
     plan.close()
-    sweep_bytes = 2 * 4 ** n * esize
+    alg = 2 * 4 ** n * esize
     res = {
         "ms_per_step": ms,
         "coeffs_per_s": 4 ** n / (ms / 1e3),
-        "algorithmic_GBps": sweep_bytes / (ms / 1e3) / 1e9,
+        "algorithmic_GBps": alg / (ms / 1e3) / 1e9,
         "kernel_ms": avgs,
         "kernel_launches": cnt,
-        "sweep_GBps": [sweep_bytes / (a / 1e3) / 1e9 if a else None for a in avgs],
         "sweeps": len(desc["sweeps"]),
-        "schedule": [{k: w[k] for k in ("xb", "db", "r", "grid", "tile_elems", "threads", "in", "out")}
-                     for w in desc["sweeps"]],
+        "chunk_bits": desc.get("chunk_bits", 0),
+        "schedule": _sched(desc),
         "autotuned": tuned,
     }
+    # per-sweep rate: achieved where every tile is read and written, an
+    # effective (bytes of the dense transform) rate where the Hermitian mode
+    # skips tiles (pruned legs rename it themselves)
+    res["effective_GBps" if hermitian else "sweep_GBps"] = [alg / (a / 1e3) / 1e9 if a else None for a in avgs]
     res["pct_peak_algorithmic"] = 100.0 * res["algorithmic_GBps"] / PEAK_HBM_GBPS
     return res, out
 
 
-def inplace_run(tpd, torch, A0, n, dtype_code, steps, warmup, esize, hermitian=False):
-    """In-place decomposition (matrix layout) of a copy of A0, the copy
-    restored from A0 before every step outside the timed region (repeated
-    in-place transforms would shrink the values towards zero, where pruning
-    and subnormals change the work).  Each step is timed with HIP events
-    around the decomposition alone."""
-    B = torch.empty_like(A0)
+def inplace_steps(tpd, torch, A0, B, n, dtype_code, steps, warmup, hermitian=False):
+    """Autotune on B (unless --no-autotune), then `steps` timed in-place
+    decompositions of B (matrix layout) after `warmup` untimed ones, B
+    restored from A0 before each (untimed).  Returns (per-step ms list,
+    kernel averages, launch counts, plan description, tuner choice)."""
     flat = B.view(-1)
     tuned = None
     if TUNE:
@@ -269,63 +298,180 @@ def inplace_run(tpd, torch, A0, n, dtype_code, steps, warmup, esize, hermitian=F
     avgs, cnt = kernel_avgs(plan)
     desc = plan.describe()
     plan.close()
+    return times, avgs, cnt, desc, tuned
+
+
+def inplace_run(tpd, torch, A0, n, dtype_code, steps, warmup, esize, hermitian=False):
+    """In-place decomposition (matrix layout) of a copy of A0 on one buffer;
+    returns (result dict, the buffer holding the last step's weights)."""
+    B = torch.empty_like(A0)
+    times, avgs, cnt, desc, tuned = inplace_steps(tpd, torch, A0, B, n, dtype_code, steps, warmup, hermitian)
     ms = sum(times) / len(times)
-    sweep_bytes = 2 * 4 ** n * esize
+    alg = 2 * 4 ** n * esize
     res = {
         "ms_per_step": ms,
         "ms_min": min(times),
         "coeffs_per_s": 4 ** n / (ms / 1e3),
-        "algorithmic_GBps": sweep_bytes / (ms / 1e3) / 1e9,
+        "algorithmic_GBps": alg / (ms / 1e3) / 1e9,
         "kernel_ms": avgs,
         "kernel_launches": cnt,
-        "sweep_GBps": [sweep_bytes / (a / 1e3) / 1e9 if a else None for a in avgs],
         "sweeps": len(desc["sweeps"]),
-        "schedule": [{k: w[k] for k in ("xb", "db", "r", "grid", "tile_elems", "threads", "in", "out")}
-                     for w in desc["sweeps"]],
+        "chunk_bits": desc.get("chunk_bits", 0),
+        "schedule": _sched(desc),
         "autotuned": tuned,
     }
+    # the Hermitian mode reads and writes fewer bytes than the dense
+    # transform: its per-sweep figure is an effective rate, not HBM traffic
+    res["effective_GBps" if hermitian else "sweep_GBps"] = [alg / (a / 1e3) / 1e9 if a else None for a in avgs]
     res["pct_peak_algorithmic"] = 100.0 * res["algorithmic_GBps"] / PEAK_HBM_GBPS
     return res, B
 
 
-def cpu_baseline(tpd, torch, n_sample=13, min_seconds=10.0):
-    """The oracle's Algorithm 1 (plain single-threaded C, binary64) on a
-    Hermitian matrix of the workload's distribution at n = n_sample; its
-    result also gives the GPU path's error on the same matrix."""
+def headline_run(tpd, torch, A0, n, steps, warmup, allocations):
+    """The headline: K = steps timed in-place steps spread over
+    `allocations` successive allocations of the in-place buffer (each freed
+    before the next is taken, so the driver may place it elsewhere in
+    physical memory); every allocation autotunes on its own buffer and runs
+    `warmup` untimed steps first.  Returns (per-allocation results, the last
+    buffer, holding the weights of A0)."""
+    per = [steps // allocations + (1 if k < steps % allocations else 0) for k in range(allocations)]
+    runs, B = [], None
+    for k in range(allocations):
+        if B is not None:
+            del B
+            torch.cuda.empty_cache()
+        B = torch.empty_like(A0)
+        times, avgs, cnt, desc, tuned = inplace_steps(tpd, torch, A0, B, n, tpd.TPD_C128, per[k], warmup)
+        runs.append({"steps": per[k], "ms_mean": sum(times) / len(times), "ms_min": min(times),
+                     "ms_max": max(times), "kernel_ms": avgs, "kernel_launches": cnt,
+                     "chunk_bits": desc.get("chunk_bits", 0), "schedule": _sched(desc), "autotuned": tuned,
+                     "buffer_address": int(B.data_ptr())})
+        log(f"main: allocation {k}: {runs[-1]['ms_mean']:.3f} ms/step over {per[k]} steps, kernels {avgs}")
+    return runs, B
+
+
+def rel_err(got, ref, a_max):
+    """max over components of |got - ref| / max|a_ij|."""
+    import numpy as np
+
+    d = np.asarray(got, np.complex128) - np.asarray(ref, np.complex128)
+    if d.size == 0:
+        return 0.0
+    return float(np.max(np.abs(np.concatenate([d.real.ravel(), d.imag.ravel()])))) / a_max
+
+
+def a_max_of(torch, A):
+    m = 0.0
+    rows = max(1, (1 << 26) // A.shape[1])
+    for r0 in range(0, A.shape[0], rows):
+        blk = A[r0:r0 + rows]
+        m = max(m, float((torch.view_as_real(blk) if blk.is_complex() else blk).abs().max()))
+    return m
+
+
+def deinterleave(q):
+    """canonical q -> (row h, column l) of the matrix layout"""
+    import numpy as np
+
+    q = np.asarray(q, np.int64)
+    h = np.zeros_like(q)
+    l = np.zeros_like(q)
+    for b in range(20):
+        l |= ((q >> (2 * b)) & 1) << b
+        h |= ((q >> (2 * b + 1)) & 1) << b
+    return h, l
+
+
+def sampled_reference(torch, A, n, qs, threads):
+    """The oracle's definition at sampled strings of a device matrix: the
+    entries each X/Y mask needs are gathered on the device, the per-mask
+    sums run on host threads."""
     import numpy as np
 
     from oracle import oracle as O
+
+    flat = A.view(-1)
+    i = torch.arange(1 << n, device=A.device, dtype=torch.int64)
+
+    def fetch(ms):
+        xs = torch.from_numpy(np.asarray(ms, np.int64)).to(A.device)
+        idx = ((i[None, :] ^ xs[:, None]) << n) + i[None, :]
+        return flat[idx.reshape(-1)].to(torch.complex128).reshape(len(ms), -1).cpu().numpy()
+
+    return O.sampled_weights(fetch, n, qs, threads=threads, masks_per_fetch=256)
+
+
+def host_threads():
+    try:
+        cpus = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cpus = os.cpu_count() or 1
+    return max(1, min(cpus, int(os.environ.get("OMP_NUM_THREADS", cpus))))
+
+
+def cpu_info():
+    import subprocess
+
+    info = {"nproc": None, "affinity_cpus": None, "lscpu": {}}
+    try:
+        info["nproc"] = int(subprocess.run(["nproc"], capture_output=True, text=True).stdout.strip())
+    except Exception:
+        pass
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)",
+                             "NUMA node(s)"):
+                info["lscpu"][k.strip()] = v.strip()
+    except Exception:
+        pass
+    return info
+
+
+def cpu_baseline(torch, budget_s=20.0):
+    """The oracle timed on the host: Algorithm 2 on all host threads (OpenMP,
+    bitwise the serial form) on an n = 14 sample of the headline's
+    distribution (dense Hermitian, complex Gaussian G), plus Algorithm 1 on
+    one thread and Algorithm 2 on all threads at n = 12.  Bounded: about
+    budget_s of CPU time in total."""
+    from oracle import oracle as O
     import workloads as W
 
-    A = W.gaussian(n_sample, seed=5, hermitian=True)
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        ref = O.tpd_recursive(A)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= min_seconds:
-            break
-    rate = reps * 4 ** n_sample / el
-    a_max = float(np.max(np.abs(np.concatenate([A.real.ravel(), A.imag.ravel()]))))
-    errs = {}
-    for name, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
-        got = tpd.decompose(torch.from_numpy(A).to("cuda").to(dt)).cpu().numpy().astype(np.complex128)
-        d = got - ref
-        errs[name] = float(np.max(np.abs(np.concatenate([d.real, d.imag])))) / a_max
-    errs["c128_bitwise"] = bool(errs["c128"] == 0.0)
-    del A, np
-    return {
-        "value": rate,
-        "unit": "coeffs/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"oracle Algorithm 1 recursion (single-threaded C, binary64) on a dense Hermitian "
-                   f"n={n_sample} matrix of the workload's distribution, {reps} run(s), {el:.1f} s; its cost per "
-                   f"coefficient grows with n, so the n=16 rate is about {n_sample}/16 of this"),
-        "seconds": el,
-        "gpu_max_abs_err_over_max_abs_a": errs,
+    th = host_threads()
+    res = {"kind": "oracle", "unit": "coeffs/s", "cores": th, "host": cpu_info()}
+
+    def rate(fn, n, min_s):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            fn()
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= min_s:
+                return reps * 4 ** n / el, reps, el
+
+    A12 = W.gaussian_device(12, seed=5, hermitian=True).cpu().numpy()
+    r1, k1, e1 = rate(lambda: O.tpd_recursive(A12), 12, 0.2 * budget_s)
+    r2, k2, e2 = rate(lambda: O.tpd_iterative_mt(A12, th), 12, 0.15 * budget_s)
+    del A12
+    A14 = W.gaussian_device(14, seed=5, hermitian=True).cpu().numpy()
+    r3, k3, e3 = rate(lambda: O.tpd_iterative_mt(A14, th), 14, 0.5 * budget_s)
+    del A14
+    res["value"] = r3
+    res["sample"] = (f"oracle Algorithm 2 (level-synchronous, OpenMP on {th} host threads, binary64) on a dense "
+                     f"Hermitian n=14 matrix of the headline's distribution, {k3} run(s) in {e3:.1f} s; no n=16 "
+                     f"figure is extrapolated")
+    res["legs"] = {
+        "alg1_recursive_1thread_n12": {"coeffs_per_s": r1, "runs": k1, "seconds": e1, "threads": 1},
+        "alg2_openmp_n12": {"coeffs_per_s": r2, "runs": k2, "seconds": e2, "threads": th},
+        "alg2_openmp_n14": {"coeffs_per_s": r3, "runs": k3, "seconds": e3, "threads": th,
+                            "level_sweep_GBps": 2 * 14 * 4 ** 14 * 16 / (e3 / k3) / 1e9},
     }
+    return res
 
 
 def main():
@@ -334,9 +480,18 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=16)
-    ap.add_argument("--extras", default="synth,partial,hermitian,outofplace,real,fp32,n14dense,n14,batched,n17",
-                    help="comma list of synth,partial,hermitian,outofplace,fp32,n14dense,n14,batched, or 'none'")
+    ap.add_argument("--allocations", type=int, default=3,
+                    help="successive allocations of the headline's in-place buffer the timed steps are spread over")
+    ap.add_argument("--samples", type=int, default=100000,
+                    help="sampled strings (plus the forced ones) checked against the oracle at n=16")
+    ap.add_argument("--extras", default="n8,n12,n14,batched,fp32,hermitian,outofplace,real,synth,partial,n14dense",
+                    help="comma list of n8,n12,n14,batched,fp32,hermitian,outofplace,real,synth,partial,n14dense,"
+                         "n17, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs-only", action="store_true",
+                    help="skip the n=16 headline and its legs (profiling runs of the other configurations)")
+    ap.add_argument("--no-batched-baseline", action="store_true",
+                    help="batched leg without the graph of 4096 per-matrix launches (profiling runs)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the schedules already chosen (TPD_AUTOTUNE_CACHE) instead of timing candidates")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -360,235 +515,306 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
+    from oracle import oracle as O
     from paper_2310_13421_amd import tpd
     import workloads as W
 
     extras = set() if args.extras == "none" else set(args.extras.split(","))
     torch.cuda.set_device(0)
+    threads = host_threads()
     n = args.n
-    log(f"generating n={n} Hermitian complex128 input on the GPU")
-    A = W.gaussian_device(n, seed=5, hermitian=True)
-    torch.cuda.synchronize()
-
-    if args.copy_calibration:
-        nbytes = 1 << 32
-        src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        src.fill_(1.0)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copy calibration: 3 copies of {nbytes} bytes")
-        del src, dst
-        torch.cuda.empty_cache()
-
-    log(f"main: n={n} complex128 in place (matrix layout), {args.warmup} warmup + {args.steps} timed steps, "
-        f"input restored before each")
-    main_res, B = inplace_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16)
-    log(f"main: {main_res['ms_per_step']:.3f} ms/step, {main_res['coeffs_per_s']:.3e} coeffs/s, "
-        f"kernels {main_res['kernel_ms']}")
-    del B
-    torch.cuda.empty_cache()
-
-    # attainable-bandwidth context on this device: a plain device-to-device
-    # copy of 4 GiB (torch copy_), median of 5, read + write bytes / time
-    csrc = torch.empty(1 << 29, dtype=torch.float64, device="cuda")
-    cdst = torch.empty_like(csrc)
-    csrc.fill_(1.0)
-    cdst.copy_(csrc)
-    ctimes = []
-    for _ in range(5):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        cdst.copy_(csrc)
-        e1.record()
-        torch.cuda.synchronize()
-        ctimes.append(e0.elapsed_time(e1))
-    copy_gbps = 2 * csrc.numel() * 8 / (sorted(ctimes)[2] / 1e3) / 1e9
-    del csrc, cdst
-    torch.cuda.empty_cache()
-    log(f"plain copy on this device: {copy_gbps:.0f} GB/s")
-
-    avgs = main_res["kernel_ms"]
-    k = max(range(len(avgs)), key=lambda i: avgs[i])
-    unit_bytes = 2 * 16  # one complex128 read + one write per coefficient
-    achieved = unit_bytes * 4 ** n / (avgs[k] / 1e3) / 1e9
-    kname = sweep_kernel_name("double", main_res["schedule"], k + 1)
-    tr_doc = load_traffic(kname, n)
-    tr = tr_doc["total_bytes"] if tr_doc else None
-    roofline = {
-        "bound": "hbm",
-        "kernel": f"k_sweep (sweep {k + 1} of 2): {kname}",
-        "achieved": achieved,
-        "peak": PEAK_HBM_GBPS,
-        "unit": "GB/s",
-        "frac": achieved / PEAK_HBM_GBPS,
-        "traffic": tr,
-    }
-
-    result = {
-        "metric": METRIC,
-        "value": main_res["coeffs_per_s"],
-        "unit": "coeffs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": main_res["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": f"dense Hermitian {2 ** n}x{2 ** n} complex128 (n={n}), A=(G+G^H)/2, G complex N(0,1) "
-                        f"seed 5; in place (coefficients in the matrix layout), input restored from a pristine "
-                        f"copy before each timed step (untimed), pruning on",
-            "n": n,
-            "precision": "complex128",
-            "layout": "matrix",
-            "placement": "in-place",
-        },
-        "hbm_GBps_algorithmic": main_res["algorithmic_GBps"],
-        "pct_peak_algorithmic": main_res["pct_peak_algorithmic"],
-        "sweeps": main_res["sweeps"],
-        "kernel_ms": main_res["kernel_ms"],
-        "sweep_GBps": main_res["sweep_GBps"],
-        "schedule": main_res["schedule"],
-        "autotuned": main_res["autotuned"],
-        "roofline": roofline,
-        "torch_copy_GBps_same_device": copy_gbps,
-        "frac_of_copy": achieved / copy_gbps,
-    }
-
     steps_x = max(3, min(args.steps, 10))
-
-    def event_ms(fn, reps):
-        """Median over reps of fn's device time (events on the current stream)."""
-        fn()
+    errors = {}
+    result = {"metric": METRIC, "legs_only": True}
+    if not args.legs_only:
+        log(f"generating n={n} Hermitian complex128 input on the GPU")
+        A = W.gaussian_device(n, seed=5, hermitian=True)
         torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            fn()
-            e1.record()
+
+        if args.copy_calibration:
+            nbytes = 1 << 32
+            src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            src.fill_(1.0)
             torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        return sorted(ts)[len(ts) // 2]
-
-    if extras & {"synth", "partial"}:
-        coeffs = tpd.decompose(A)
-        torch.cuda.synchronize()
-        if "synth" in extras:
-            log("extra: synthesis A = sum w_t sigma^t from the n=16 weights, complex128")
-            M = torch.empty((2 ** n, 2 ** n), dtype=A.dtype, device="cuda")
-            ms = event_ms(lambda: tpd.synthesize(coeffs, M), steps_x)
-            err_num, a_max = 0.0, 0.0
-            for r0 in range(0, 2 ** n, 2048):  # chunked: no full-size temporaries
-                err_num = max(err_num, float((M[r0:r0 + 2048] - A[r0:r0 + 2048]).abs().max()))
-                a_max = max(a_max, float(A[r0:r0 + 2048].abs().max()))
-            err = err_num / a_max
-            result["synthesis_c128"] = {
-                "ms_per_step": ms, "coeffs_per_s": 4 ** n / (ms / 1e3),
-                "algorithmic_GBps": 2 * 2 * 4 ** n * 16 / (ms / 1e3) / 1e9,
-                "round_trip_max_rel_err": err,
-            }
-            # compaction of the dense weights, count only (one read of 4^n values)
-            total = torch.zeros(1, dtype=torch.int64, device="cuda")
-            cms = event_ms(lambda: tpd.lib.tpd_compact(coeffs.data_ptr(), n, tpd.TPD_C128, 0, 0.0, None, None, 0,
-                                                       total.data_ptr(), None), steps_x)
-            result["compact_count_dense_c128"] = {
-                "ms": cms, "read_GBps": 4 ** n * 16 / (cms / 1e3) / 1e9, "kept": int(total.item()),
-            }
-            del M
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"copy calibration: 3 copies of {nbytes} bytes")
+            del src, dst
             torch.cuda.empty_cache()
-        if "partial" in extras:
-            log("extra: partial decomposition of the n=16 matrix, all 1- and 2-local strings")
-            qs = {0}
-            for i in range(n):
-                for a in (1, 2, 3):
-                    qs.add(a << (2 * (n - 1 - i)))
-                    for j in range(i + 1, n):
-                        for b in (1, 2, 3):
-                            qs.add((a << (2 * (n - 1 - i))) | (b << (2 * (n - 1 - j))))
-            req = torch.tensor(sorted(qs), dtype=torch.int64, device="cuda")
-            vals = torch.empty(req.numel(), dtype=A.dtype, device="cuda")
-            ms = event_ms(lambda: tpd.decompose_partial(A, req, vals, work=coeffs), steps_x)
-            full_ms = event_ms(lambda: tpd.decompose(A, coeffs), steps_x)
-            result["partial_2local_c128"] = {
-                "requests": int(req.numel()), "ms": ms, "full_out_of_place_ms": full_ms,
-                "speedup_vs_full": full_ms / ms,
-            }
-        del coeffs
-        torch.cuda.empty_cache()
 
-    if "hermitian" in extras:
-        log("extra: Hermitian mode (representatives only, real weights), complex128, in place")
-        r, B = inplace_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16, hermitian=True)
-        r["speedup_vs_general"] = main_res["ms_per_step"] / r["ms_per_step"]
-        result["hermitian_c128"] = r
+        # ---- headline -----------------------------------------------------------
+        log(f"main: n={n} complex128 in place (matrix layout), {args.steps} timed steps over {args.allocations} "
+            f"buffer allocations ({args.warmup} warmup each), input restored before each step")
+        runs, B = headline_run(tpd, torch, A, n, args.steps, args.warmup, max(1, args.allocations))
+        order = sorted(range(len(runs)), key=lambda k: runs[k]["ms_mean"])
+        med = runs[order[len(order) // 2]]
+        ms_step = med["ms_mean"]
+        alg_bytes = 2 * 4 ** n * 16  # one complex128 read + one write per coefficient
+        a_max = a_max_of(torch, A)
+
+        # config 4 check, complex128: sampled strings against the definition
+        qs = W.sampled_strings(n, args.samples, seed=5)
+        log(f"oracle: {qs.size} sampled strings of the n={n} matrix on {threads} host threads")
+        t0 = time.perf_counter()
+        bf = sampled_reference(torch, A, n, qs, threads)
+        oracle_s = time.perf_counter() - t0
+        h, l = deinterleave(qs.astype(np.int64))
+        hb, lb = torch.from_numpy(h).to("cuda"), torch.from_numpy(l).to("cuda")
+        got128 = B[hb, lb].cpu().numpy()
+        errors["config4_n16_hermitian"] = {
+            "samples": int(qs.size), "c128": rel_err(got128, bf, a_max),
+            "c128_bound_n_u": n * 2.0 ** -53, "oracle_seconds": oracle_s,
+            "what": "max |w_gpu - w_oracle| / max|a_ij| over uniformly sampled strings plus I..I, X..X, Y..Y, Z..Z, "
+                    "4^16-1; in place, matrix layout",
+        }
         del B
         torch.cuda.empty_cache()
-    if "outofplace" in extras:
-        log("extra: out of place, canonical order, complex128")
-        r, o = single_matrix_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16)
-        result["out_of_place_canonical_c128"] = r
-        del o
+
+        # attainable-bandwidth context on this device: a plain device-to-device
+        # copy of 4 GiB (torch copy_), median of 5, read + write bytes / time
+        csrc = torch.empty(1 << 29, dtype=torch.float64, device="cuda")
+        cdst = torch.empty_like(csrc)
+        csrc.fill_(1.0)
+        copy_ms = event_ms(torch, lambda: cdst.copy_(csrc), 5)
+        copy_gbps = 2 * csrc.numel() * 8 / (copy_ms / 1e3) / 1e9
+        del csrc, cdst
         torch.cuda.empty_cache()
-    if "real" in extras:
-        log("extra: real input (float64 and float32, real-coded weights): Re A, a real-symmetric matrix, in place")
-        Ar = A.real.contiguous()
-        d = {}
-        for name, herm in (("general", False), ("symmetric_mode", True)):
-            r, B = inplace_run(tpd, torch, Ar, n, tpd.TPD_R64, args.steps, args.warmup, 8, hermitian=herm)
-            r["speedup_vs_c128_general"] = main_res["ms_per_step"] / r["ms_per_step"]
-            d[name] = r
-            del B
-            torch.cuda.empty_cache()
-        result["real_r64"] = d
-        Ar32 = Ar.to(torch.float32)
-        del Ar
-        torch.cuda.empty_cache()
-        d = {}
-        for name, herm in (("general", False), ("symmetric_mode", True)):
-            r, B = inplace_run(tpd, torch, Ar32, n, tpd.TPD_R32, args.steps, args.warmup, 4, hermitian=herm)
-            r["speedup_vs_c128_general"] = main_res["ms_per_step"] / r["ms_per_step"]
-            d[name] = r
-            del B
-            torch.cuda.empty_cache()
-        result["real_r32"] = d
-        del Ar32
-        torch.cuda.empty_cache()
-    if "fp32" in extras:
-        log("extra: complex64 (round-to-nearest copy of the same matrix), in place")
-        A32 = A.to(torch.complex64)
-        del A
-        A = None
-        torch.cuda.empty_cache()
-        r, B32 = inplace_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8)
-        r["speedup_vs_c128"] = main_res["ms_per_step"] / r["ms_per_step"]
-        result["fp32"] = r
-        del B32
-        torch.cuda.empty_cache()
-        if "hermitian" in extras:
-            r, B32 = inplace_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8, hermitian=True)
-            r["speedup_vs_c128_general"] = main_res["ms_per_step"] / r["ms_per_step"]
-            result["hermitian_c64"] = r
+        log(f"plain copy on this device: {copy_gbps:.0f} GB/s")
+
+        avgs = med["kernel_ms"]
+        k = max(range(len(avgs)), key=lambda i: avgs[i])
+        chunked = med["chunk_bits"] > 0
+        # bytes per launch of the timed kernel: one sweep moves 2 * 4^n * 16 B
+        # (with the chunked order the plan times the whole chunk loop, both sweeps)
+        launch_bytes = alg_bytes * (2 if chunked else 1)
+        achieved = launch_bytes / (avgs[k] / 1e3) / 1e9
+        kname = sweep_kernel_name("double", med["schedule"], k + 1)
+        tr_doc = load_traffic(kname, n)
+        roofline = {
+            "bound": "hbm",
+            "kernel": (f"k_sweep (sweep {k + 1} of 2): {kname}" if not chunked else f"k_sweep chunk loop: {kname}"),
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBPS,
+            "traffic": tr_doc["total_bytes"] if tr_doc else None,
+            "kernel_ms_per_launch": avgs[k],
+            "algorithmic_bytes_per_launch": launch_bytes,
+            "method_achieved": alg_bytes / (ms_step / 1e3) / 1e9,
+            "method_frac": alg_bytes / (ms_step / 1e3) / 1e9 / PEAK_HBM_GBPS,
+            "method_note": "2 * 4^n * 16 B (one read and one write per coefficient) / ms_per_step / peak: the two "
+                           "sweeps move twice these bytes",
+        }
+
+        result = {
+            "metric": METRIC,
+            "value": 4 ** n / (ms_step / 1e3),
+            "unit": "coeffs/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": ms_step,
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f64",
+            "data": "synthetic",
+            "config": {
+                "workload": f"dense Hermitian {2 ** n}x{2 ** n} complex128 (n={n}), A=(G+G^H)/2, G complex N(0,1) "
+                            f"seed 5; in place (coefficients in the matrix layout), input restored from a pristine "
+                            f"copy before each timed step (untimed), pruning on; {args.steps} timed steps over "
+                            f"{len(runs)} successive buffer allocations, value = the median allocation",
+                "n": n,
+                "precision": "complex128",
+                "layout": "matrix",
+                "placement": "in-place",
+            },
+            "allocations": {
+                "ms_per_step": [r["ms_mean"] for r in runs],
+                "min": runs[order[0]]["ms_mean"], "median": ms_step, "max": runs[order[-1]]["ms_mean"],
+                "runs": runs,
+            },
+            "hbm_GBps_algorithmic": alg_bytes / (ms_step / 1e3) / 1e9,
+            "pct_peak_algorithmic": 100.0 * alg_bytes / (ms_step / 1e3) / 1e9 / PEAK_HBM_GBPS,
+            "sweeps": len(med["schedule"]),
+            "kernel_ms": avgs,
+            "sweep_GBps": [alg_bytes / (a / 1e3) / 1e9 if a else None for a in avgs] if not chunked else None,
+            "schedule": med["schedule"],
+            "autotuned": med["autotuned"],
+            "roofline": roofline,
+            "torch_copy_GBps_same_device": copy_gbps,
+            "frac_of_copy": achieved / copy_gbps,
+        }
+
+        # ---- n = 16 complex64 (config 4, FP32 path) ----------------------------
+        if "fp32" in extras:
+            log("extra: complex64 (round-to-nearest copy of the same matrix), in place")
+            A32 = A.to(torch.complex64)
+            r, B32 = inplace_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8)
+            r["speedup_vs_c128"] = ms_step / r["ms_per_step"]
+            got64 = B32[hb, lb].cpu().numpy()
+            e64 = rel_err(got64, bf, a_max)
+            errors["config4_n16_hermitian"]["c64"] = e64
+            errors["config4_n16_hermitian"]["c64_bound_n_plus_1_u"] = (n + 1) * 2.0 ** -24
+            r["max_abs_err_over_max_abs_a"] = e64
+            result["fp32"] = r
             del B32
             torch.cuda.empty_cache()
+            if "hermitian" in extras:
+                r, B32 = inplace_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8, hermitian=True)
+                r["speedup_vs_c128_general"] = ms_step / r["ms_per_step"]
+                result["hermitian_c64"] = r
+                del B32
+                torch.cuda.empty_cache()
+            if "outofplace" in extras:
+                r, o32 = single_matrix_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8)
+                result["fp32_out_of_place_canonical"] = r
+                del o32
+            del A32
+            torch.cuda.empty_cache()
+
+        if extras & {"synth", "partial"}:
+            coeffs = tpd.decompose(A)
+            torch.cuda.synchronize()
+            if "synth" in extras:
+                log("extra: synthesis A = sum w_t sigma^t from the n=16 weights, complex128")
+                M = torch.empty((2 ** n, 2 ** n), dtype=A.dtype, device="cuda")
+                ms = event_ms(torch, lambda: tpd.synthesize(coeffs, M), steps_x)
+                err_num = 0.0
+                for r0 in range(0, 2 ** n, 2048):  # chunked: no full-size temporaries
+                    err_num = max(err_num, float((M[r0:r0 + 2048] - A[r0:r0 + 2048]).abs().max()))
+                result["synthesis_c128"] = {
+                    "ms_per_step": ms, "coeffs_per_s": 4 ** n / (ms / 1e3),
+                    "algorithmic_GBps": 2 * 2 * 4 ** n * 16 / (ms / 1e3) / 1e9,
+                    "round_trip_max_abs_err_over_max_abs_a": err_num / a_max,
+                }
+                total = torch.zeros(1, dtype=torch.int64, device="cuda")
+                cms = event_ms(torch, lambda: tpd.lib.tpd_compact(coeffs.data_ptr(), n, tpd.TPD_C128, 0, 0.0, None, None,
+                                                                  0, total.data_ptr(), None), steps_x)
+                result["compact_count_dense_c128"] = {
+                    "ms": cms, "read_GBps": 4 ** n * 16 / (cms / 1e3) / 1e9, "kept": int(total.item()),
+                }
+                del M
+                torch.cuda.empty_cache()
+            if "partial" in extras:
+                log("extra: partial decomposition of the n=16 matrix, all 1- and 2-local strings")
+                qs2 = {0}
+                for i in range(n):
+                    for a in (1, 2, 3):
+                        qs2.add(a << (2 * (n - 1 - i)))
+                        for j in range(i + 1, n):
+                            for b in (1, 2, 3):
+                                qs2.add((a << (2 * (n - 1 - i))) | (b << (2 * (n - 1 - j))))
+                req = torch.tensor(sorted(qs2), dtype=torch.int64, device="cuda")
+                vals = torch.empty(req.numel(), dtype=A.dtype, device="cuda")
+                ms = event_ms(torch, lambda: tpd.decompose_partial(A, req, vals, work=coeffs), steps_x)
+                full_ms = event_ms(torch, lambda: tpd.decompose(A, coeffs), steps_x)
+                result["partial_2local_c128"] = {
+                    "requests": int(req.numel()), "ms": ms, "full_out_of_place_ms": full_ms,
+                    "speedup_vs_full": full_ms / ms,
+                }
+            del coeffs
+            torch.cuda.empty_cache()
+
+        if "hermitian" in extras:
+            log("extra: Hermitian mode (representatives only, real weights), complex128, in place")
+            r, B = inplace_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16, hermitian=True)
+            r["speedup_vs_general"] = ms_step / r["ms_per_step"]
+            result["hermitian_c128"] = r
+            del B
+            torch.cuda.empty_cache()
         if "outofplace" in extras:
-            r, o32 = single_matrix_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8)
-            result["fp32_out_of_place_canonical"] = r
-            del o32
-        del A32
-        torch.cuda.empty_cache()
-    if A is not None:
+            log("extra: out of place, canonical order, complex128")
+            r, o = single_matrix_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16)
+            result["out_of_place_canonical_c128"] = r
+            del o
+            torch.cuda.empty_cache()
+        if "real" in extras:
+            log("extra: real input (float64 and float32, real-coded weights): Re A, a real-symmetric matrix, in place")
+            Ar = A.real.contiguous()
+            d = {}
+            for name, herm in (("general", False), ("symmetric_mode", True)):
+                r, Bb = inplace_run(tpd, torch, Ar, n, tpd.TPD_R64, args.steps, args.warmup, 8, hermitian=herm)
+                r["speedup_vs_c128_general"] = ms_step / r["ms_per_step"]
+                d[name] = r
+                del Bb
+                torch.cuda.empty_cache()
+            result["real_r64"] = d
+            Ar32 = Ar.to(torch.float32)
+            del Ar
+            torch.cuda.empty_cache()
+            d = {}
+            for name, herm in (("general", False), ("symmetric_mode", True)):
+                r, Bb = inplace_run(tpd, torch, Ar32, n, tpd.TPD_R32, args.steps, args.warmup, 4, hermitian=herm)
+                r["speedup_vs_c128_general"] = ms_step / r["ms_per_step"]
+                d[name] = r
+                del Bb
+                torch.cuda.empty_cache()
+            result["real_r32"] = d
+            del Ar32
+            torch.cuda.empty_cache()
         del A
+        torch.cuda.empty_cache()
+
+    # ---- config 0: n = 8 dense Gaussian (and integer entries) --------------
+    if "n8" in extras:
+        log("extra: n=8 dense complex Gaussian (launch-latency bound), both precisions")
+        n8 = 8
+        A8 = W.gaussian(n8, seed=1)
+        ref8 = O.tpd_recursive(A8)
+        am8 = float(np.max(np.abs(np.concatenate([A8.real.ravel(), A8.imag.ravel()]))))
+        Z8 = W.integer(n8, seed=1)
+        refz = O.tpd_recursive(Z8)
+        d = {}
+        e = {}
+        for name, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
+            Ad = torch.from_numpy(A8).to("cuda").to(dt)
+            o = torch.empty(4 ** n8, dtype=dt, device="cuda")
+            ms = event_ms(torch, lambda: tpd.decompose(Ad, o), 50)
+            got = o.cpu().numpy()
+            e[name] = rel_err(got, ref8, am8)
+            if name == "c128":
+                e["c128_bitwise_vs_algorithm_1"] = bool(np.array_equal(got.real, ref8.real) and
+                                                        np.array_equal(got.imag, ref8.imag))
+            gz = tpd.decompose(torch.from_numpy(Z8).to("cuda").to(dt)).cpu().numpy().astype(np.complex128)
+            e[name + "_integer_bit_exact"] = bool(np.array_equal(gz, refz))
+            d[name] = {"ms": ms, "coeffs_per_s": 4 ** n8 / (ms / 1e3)}
+        e["strings"] = 4 ** n8
+        errors["config0_n8"] = e
+        result["n8"] = d
+    # ---- config 1: n = 12 dense Hermitian ----------------------------------
+    if "n12" in extras:
+        log("extra: n=12 dense Hermitian, both precisions (MALL-sized: GB/s indicative)")
+        n12 = 12
+        H = W.gaussian_device(n12, seed=2, hermitian=True)
+        Hh = H.cpu().numpy()
+        ref12 = O.tpd_iterative_mt(Hh, threads)
+        am12 = float(np.max(np.abs(np.concatenate([Hh.real.ravel(), Hh.imag.ravel()]))))
+        fro = float(np.sum(np.abs(Hh) ** 2))
+        d = {}
+        e = {"strings": 4 ** n12}
+        for name, dt, es in (("c128", torch.complex128, 16), ("c64", torch.complex64, 8)):
+            Hd = H if dt == torch.complex128 else H.to(dt)
+            o = torch.empty(4 ** n12, dtype=dt, device="cuda")
+            if TUNE:
+                tpd.autotune(Hd, o)
+            ms = event_ms(torch, lambda: tpd.decompose(Hd, o), 20)
+            got = o.cpu().numpy()
+            e[name] = rel_err(got, ref12, am12)
+            oh = tpd.decompose(Hd, hermitian=True).cpu().numpy()
+            e[name + "_hermitian_mode_imag_exactly_zero"] = bool(np.all(oh.imag == 0))
+            e[name + "_parseval_rel"] = abs(float(np.sum(np.abs(got.astype(np.complex128)) ** 2)) * 2 ** n12 - fro) / fro
+            d[name] = {"ms": ms, "coeffs_per_s": 4 ** n12 / (ms / 1e3),
+                       "algorithmic_GBps": 2 * 4 ** n12 * es / (ms / 1e3) / 1e9}
+        e["c128_bitwise_vs_algorithm_2"] = bool(e["c128"] == 0.0)
+        errors["config1_n12_hermitian"] = e
+        result["n12"] = d
+        del H, Hh
         torch.cuda.empty_cache()
 
     if "n14dense" in extras:
@@ -602,18 +828,27 @@ def main():
             r, o = single_matrix_run(tpd, torch, Hd, n14, code, args.steps, args.warmup, es)
             d[name] = r
             del o
-            r, B = inplace_run(tpd, torch, Hd, n14, code, args.steps, args.warmup, es)
+            r, Bb = inplace_run(tpd, torch, Hd, n14, code, args.steps, args.warmup, es)
             d[name + "_in_place"] = r
-            del B, Hd
+            del Bb, Hd
             torch.cuda.empty_cache()
+        d["fp32_speedup_in_place"] = d["c128_in_place"]["ms_per_step"] / d["c64_in_place"]["ms_per_step"]
         result["n14_dense"] = d
         del H
         torch.cuda.empty_cache()
+    # ---- config 2: n = 14 structured Hamiltonian ---------------------------
     if "n14" in extras:
-        log("extra: n=14 Heisenberg chain + 200 4-local strings, pruning")
+        log("extra: n=14 Heisenberg chain + 200 4-local strings, pruning, both precisions")
         n14 = 14
-        H = W.dense_from_terms_device(W.heisenberg_terms(n14, seed=3, n_local=200), n14)
+        terms = W.heisenberg_terms(n14, seed=3, n_local=200)
+        H = W.dense_from_terms_device(terms, n14)
+        amh = a_max_of(torch, H)
+        qsd = torch.tensor([W.string_index(s_) for s_, _ in terms], dtype=torch.int64, device="cuda")
+        exp = torch.zeros(4 ** n14, dtype=torch.complex128, device="cuda")
+        exp.index_put_((qsd,), torch.tensor(np.array([c for _, c in terms], np.complex128), device="cuda"),
+                       accumulate=True)
         r, o = single_matrix_run(tpd, torch, H, n14, tpd.TPD_C128, args.steps, args.warmup, 16)
+        r["effective_GBps"] = r.pop("sweep_GBps")  # pruned tiles move no bytes: an effective rate
         plan = tpd.Plan(n14)
         plan.execute(H, o)
         st = plan.prune_stats()
@@ -621,40 +856,49 @@ def main():
         r["live_tile_fraction"] = st["live_tiles"] / st["total_tiles"]
         r["live_prefixes_level"] = st["prefix_level"]
         r["live_prefixes"] = st["live_prefixes"]
+        e = {"strings": 4 ** n14, "what": "max |w_gpu - w_generating| / max|a_ij| over all 4^14 strings (zeros "
+                                          "where no term was generated)"}
+        e["c128"] = float(torch.view_as_real(o - exp).abs().max()) / amh
         rn, o2 = single_matrix_run(tpd, torch, H, n14, tpd.TPD_C128, steps_x, 1, 16, tune=False, prune=False)
         r["ms_per_step_no_prune"] = rn["ms_per_step"]
         r["speedup_from_pruning"] = rn["ms_per_step"] / r["ms_per_step"]
-        # sparse list of the weights (the paper's output form)
+        del o2
         q, w, total = tpd.compact(o)
         cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
-        cms = event_ms(lambda: tpd.lib.tpd_compact(o.data_ptr(), n14, tpd.TPD_C128, 0, 0.0, q.data_ptr(), w.data_ptr(),
-                                                   total, cnt.data_ptr(), None), steps_x)
-        assert int(cnt.item()) == total
+        cms = event_ms(torch, lambda: tpd.lib.tpd_compact(o.data_ptr(), n14, tpd.TPD_C128, 0, 0.0, q.data_ptr(),
+                                                          w.data_ptr(), total, cnt.data_ptr(), None), steps_x)
         _, _, total_tol = tpd.compact(o, tol=1e-12, capacity=0)
         r["sparse_list"] = {"pairs": total, "compact_ms": cms, "pairs_above_1e-12": total_tol}
+        del o, q, w
+        H32 = H.to(torch.complex64)
+        r32, o32 = single_matrix_run(tpd, torch, H32, n14, tpd.TPD_C64, args.steps, args.warmup, 8)
+        r32["effective_GBps"] = r32.pop("sweep_GBps")
+        e["c64"] = float(torch.view_as_real(o32.to(torch.complex128) - exp).abs().max()) / amh
+        r["c64"] = r32
+        errors["config2_n14_structured"] = e
         result["n14_structured"] = r
-        del H, o, o2
+        del H, H32, o32, exp
         torch.cuda.empty_cache()
 
+    # ---- config 3: batched -------------------------------------------------
     if "batched" in extras:
         log("extra: batched 4096 matrices, n in 2..9")
         ns = [int(v) for v in W.batched_qubits(4096, seed=4)]
         bres = {"count": len(ns), "elements": int(sum(4 ** v for v in ns))}
+        e = {}
+        check_idx = list(range(0, len(ns), 16))
+        refs = {}  # oracle weights of the complex128 matrices (the complex64 set is their rounding)
         for name, dt, code, es in (("c128", torch.complex128, tpd.TPD_C128, 16),
                                    ("c64", torch.complex64, tpd.TPD_C64, 8)):
-            mats = W.batched_matrices_device(ns, seed=4, dtype=dt)
+            buf, mats = W.batched_matrices_packed(ns, seed=4, dtype=dt)
             outs = [torch.empty(4 ** v, dtype=dt, device="cuda") for v in ns]
             plan = tpd.BatchedPlan(ns, code, timing=True)
             dp = tpd.BatchedPlan.pointer_table(mats)
             do = tpd.BatchedPlan.pointer_table(outs)
-            s = torch.cuda.Stream()
-            s.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(s):
-                plan.execute(dp, do)
-            torch.cuda.current_stream().wait_stream(s)
+            plan.execute(dp, do)
             torch.cuda.synchronize()
             plan.timing(reset=True)
-            btuned = plan.autotune(dp, do)["chosen"] if TUNE else None
+            btuned = plan.autotune(dp, do) if TUNE else None
             plan.timing(reset=True)
             ms_eager = timed_steps(lambda: plan.execute(dp, do), args.steps, args.warmup, torch)
             kavg, _ = kernel_avgs(plan)
@@ -663,12 +907,39 @@ def main():
             with torch.cuda.graph(g):
                 plan_g.execute(dp, do)
             ms_graph = timed_steps(lambda: g.replay(), args.steps, args.warmup, torch)
+            # baseline: the same 4096 decompositions as single-matrix calls,
+            # captured in one graph (per-matrix launches, no host overhead);
+            # the no-allocation entry point keeps the capture free of hipMalloc
+            ms_pm = ms_loop = None
+            same = None
+            outs2 = []
+            if not args.no_batched_baseline:
+                outs2 = [torch.empty(4 ** v, dtype=dt, device="cuda") for v in ns]
+                for m_, o_ in zip(mats, outs2):
+                    tpd.decompose_noalloc(m_, o_)
+                torch.cuda.synchronize()
+                g2 = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g2):
+                    for m_, o_ in zip(mats, outs2):
+                        tpd.decompose_noalloc(m_, o_)
+                ms_pm = timed_steps(lambda: g2.replay(), max(3, steps_x), 1, torch)
 
-            def loop():
-                for m, o in zip(mats, outs):
-                    tpd.decompose(m, o)
+                def loop():
+                    for m_, o_ in zip(mats, outs2):
+                        tpd.decompose(m_, o_)
 
-            ms_loop = timed_steps(loop, max(2, steps_x // 3), 1, torch)
+                ms_loop = timed_steps(loop, 2, 1, torch)
+                same = all(torch.equal(torch.view_as_real(a_), torch.view_as_real(b_)) for a_, b_ in zip(outs, outs2))
+                del g2
+            errs = []
+            for i in check_idx:
+                if i not in refs:
+                    Mh = mats[i].cpu().numpy().astype(np.complex128)
+                    refs[i] = (O.tpd_recursive(Mh),
+                               float(np.max(np.abs(np.concatenate([Mh.real.ravel(), Mh.imag.ravel()])))))
+                ref, am = refs[i]
+                errs.append(rel_err(outs[i].cpu().numpy(), ref, am))
+            e[name] = max(errs)
             bytes_ = 2 * bres["elements"] * es
             bres[name] = {
                 "graph_ms": ms_graph,
@@ -676,51 +947,31 @@ def main():
                 "eager_ms": ms_eager,
                 "kernel_ms": kavg[0],
                 "kernel_GBps": bytes_ / (kavg[0] / 1e3) / 1e9,
-                "per_matrix_launch_loop_ms": ms_loop,
-                "per_matrix_mats_per_s": len(ns) / (ms_loop / 1e3),
-                "speedup_vs_per_matrix": ms_loop / ms_graph,
+                "kernel_frac_of_peak": bytes_ / (kavg[0] / 1e3) / 1e9 / PEAK_HBM_GBPS,
+                "per_matrix_graph_ms": ms_pm,
+                "per_matrix_graph_mats_per_s": len(ns) / (ms_pm / 1e3) if ms_pm else None,
+                "speedup_vs_per_matrix_graph": ms_pm / ms_graph if ms_pm else None,
+                "per_matrix_python_loop_ms": ms_loop,
+                "batched_equals_per_matrix": same,
                 "autotuned": btuned,
                 "algorithmic_GBps": bytes_ / (ms_graph / 1e3) / 1e9,
             }
             plan.close()
             plan_g.close()
-            del mats, outs, g
+            del mats, outs, outs2, g, buf
             torch.cuda.empty_cache()
+        e["matrices_checked"] = len(check_idx)
+        e["what"] = "max over every 16th matrix of max |w_gpu - w_oracle| / max|a_ij| of that matrix"
+        errors["config3_batched"] = e
         result["batched"] = bres
 
     if "n17" in extras:
-        log("extra: n=17 (131072 x 131072): real float32 in place with restores, complex64 in place once")
-        n17 = 17
-        d17 = {}
-        R = W.gaussian_device(n17, seed=17, dtype=torch.float32, hermitian=True)  # 64 GiB, real symmetric
-        r, B = inplace_run(tpd, torch, R, n17, tpd.TPD_R32, args.steps, args.warmup, 4)
-        d17["r32"] = r
-        del B, R
+        log("extra: n=17 (131072 x 131072): real float32 in place with restores")
+        R = W.gaussian_device(17, seed=17, dtype=torch.float32, hermitian=True)  # 64 GiB, real symmetric
+        r, Bb = inplace_run(tpd, torch, R, 17, tpd.TPD_R32, args.steps, args.warmup, 4)
+        result["n17_r32"] = r
+        del Bb, R
         torch.cuda.empty_cache()
-        # complex64: 128 GiB, no room for a pristine copy.  The autotuner
-        # transforms the buffer repeatedly, so the input is generated again
-        # before the one timed decomposition (the plan's events).
-        C = W.gaussian_device(n17, seed=17, dtype=torch.complex64, hermitian=True)
-        tuned17 = tpd.autotune(C, C.view(-1), layout="matrix").get("chosen") if TUNE else None
-        del C
-        torch.cuda.empty_cache()
-        C = W.gaussian_device(n17, seed=17, dtype=torch.complex64, hermitian=True)
-        plan = tpd.Plan(n17, tpd.TPD_C64, timing=True, in_place=True, layout="matrix")
-        torch.cuda.synchronize()
-        plan.execute(C, C.view(-1))
-        torch.cuda.synchronize()
-        kav, _ = kernel_avgs(plan)
-        desc = plan.describe()
-        plan.close()
-        ms = sum(kav)
-        d17["c64_single"] = {
-            "ms": ms, "kernel_ms": kav, "coeffs_per_s": 4 ** n17 / (ms / 1e3), "autotuned": tuned17,
-            "sweep_GBps": [2 * 4 ** n17 * 8 / (k / 1e3) / 1e9 for k in kav],
-            "schedule": [{k: w[k] for k in ("xb", "db", "r", "grid", "tile_elems", "threads")} for w in desc["sweeps"]],
-        }
-        del C
-        torch.cuda.empty_cache()
-        result["n17"] = d17
 
     # PMC-measured HBM bytes per launch of each sweep, for the general-mode
     # two-sweep legs whose kernels were profiled on the current sources
@@ -733,10 +984,11 @@ def main():
     for r, dt, nn in legs:
         if r is not None:
             r["traffic_bytes"] = leg_traffic(dt, r, nn)
+    result["errors"] = errors
 
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")
-        result["cpu_baseline"] = cpu_baseline(tpd, torch)
+        result["cpu_baseline"] = cpu_baseline(torch)
     print(json.dumps(result), flush=True)
 
 

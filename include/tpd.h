@@ -290,7 +290,9 @@ tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len);
  * current one); then the fastest of these once more with the second
  * sweep's rotated tile order (TPD_FLAG_ROTATE_TILES: which tiles run side by
  * side, hence how their rows meet the memory channels, depends on where the
- * buffer sits in physical memory).
+ * buffer sits in physical memory); then, outside the Hermitian mode, the
+ * winner in the chunked order (sweep 1 then sweep 2 over 64, 128 or 256 MB
+ * of XOR-diagonal strips at a time, see tpd_debug_decompose_tuned).
  * The choice never changes results (same operations in the same order).
  * Timed runs include the first sweep's pruning epilogue unless
  * TPD_FLAG_NO_PRUNE is given; in place, where each run transforms the

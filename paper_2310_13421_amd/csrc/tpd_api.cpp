@@ -1564,15 +1564,17 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
       best_t = t;
     }
   }
-  // then the winner in the chunked order, sweep 1 and sweep 2 over 32-256 MB
-  // of d-groups at a time (whether the second sweep then reads the chunk
-  // from the memory-side cache depends on the device; measured here)
+  // then the winner in the chunked order, sweep 1 and sweep 2 over 64-256 MB
+  // of d-groups at a time: the second sweep may then read the chunk from the
+  // 256 MB memory-side cache, but each chunk is a strip of columns across
+  // all rows, so the sweeps lose row locality in HBM (measured: a few
+  // percent faster at n = 14, slower at n = 16)
   if (!st && best < 1e300 && !(flags & TPD_FLAG_HERMITIAN)) {
     const Tuned base_t = best_t;
     Schedule sc;
     if (make_schedule_with(n, dt, tflags, in_place, &base_t, &sc) == TPD_SUCCESS && sc.nsweep == 2) {
       const uint64_t group_bytes = ((uint64_t)elem_bytes(dt) << n) << sc.sw[0].db;
-      for (uint64_t mb = 32; mb <= 256 && !st; mb *= 2) {
+      for (uint64_t mb = 64; mb <= 256 && !st; mb *= 2) {
         int cb = 0;
         while ((group_bytes << (cb + 1)) <= (mb << 20)) ++cb;
         if (cb < 1 || cb >= n - sc.sw[0].db || (group_bytes << cb) != (mb << 20)) continue;

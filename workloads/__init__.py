@@ -308,6 +308,30 @@ def batched_matrices_device(ns: Sequence[int], seed: int = 4, dtype=None, device
     return mats
 
 
+def batched_matrices_packed(ns: Sequence[int], seed: int = 4, dtype=None, device="cuda"):
+    """Host-generated counterpart of ``batched_matrices`` packed into one
+    device buffer (one upload instead of thousands of small device
+    launches): returns (buffer, list of per-matrix 2-D views).  Same
+    distribution: complex N(0,1), every odd-indexed matrix (G + G^H)/2."""
+    import torch
+
+    dtype = dtype or torch.complex128
+    npdt = np.complex128 if dtype == torch.complex128 else np.complex64
+    sizes = [1 << (2 * int(n)) for n in ns]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    host = np.empty(int(offs[-1]), npdt)
+    rng = np.random.default_rng(seed + 2)
+    for k, n in enumerate(ns):
+        d = 1 << int(n)
+        G = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+        if k % 2 == 1:
+            G = (G + G.conj().T) / 2
+        host[offs[k]:offs[k + 1]] = G.reshape(-1)
+    buf = torch.from_numpy(host).to(device)
+    views = [buf[offs[k]:offs[k + 1]].view(1 << int(n), 1 << int(n)) for k, n in enumerate(ns)]
+    return buf, views
+
+
 # ----------------------------------------------------------------------------
 # sampled strings for very large n
 # ----------------------------------------------------------------------------
