@@ -19,7 +19,9 @@ SOURCES = ["tpd_sweep_c128_db3.hip", "tpd_sweep_c128_db4.hip", "tpd_sweep_c128_d
            "tpd_sweep_c64_db5.hip", "tpd_sweep_c64_db6.hip", "tpd_sweep_r64_db4.hip", "tpd_sweep_r64_db5.hip",
            "tpd_sweep_r64_db6.hip", "tpd_sweep_r32_db4.hip", "tpd_sweep_r32_db5.hip", "tpd_sweep_r32_db6.hip",
            "tpd_sweep_c128.hip", "tpd_sweep_c64.hip", "tpd_sweep_r64.hip", "tpd_sweep_r32.hip",
-           "tpd_kernels.hip", "tpd_select.hip", "tpd_emulate.cpp", "tpd_api.cpp"]
+           "tpd_kernels.hip", "tpd_select.hip", "tpd_scratch.hip", "tpd_shapes.cpp", "tpd_emulate.cpp",
+           "tpd_api.cpp"]
+HOST_SOURCES = ("tpd_emulate.cpp", "tpd_shapes.cpp")  # plain host C++ (g++)
 HEADERS = ["tpd_core.h", "tpd_internal.h", "tpd_sweep.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -60,9 +62,11 @@ def build(verbose: bool = True, jobs: int = 0) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
         objs.append(obj)
-        if src == "tpd_emulate.cpp":
-            # host replay used by the tests: plain host C++ (no device pass), -O1
-            cmd = ["g++", "-O1", "-std=c++20", "-fPIC", "-ffp-contract=off", "-D__HIP_PLATFORM_AMD__",
+        if src in HOST_SOURCES:
+            # host-only code (the schedule's shape table, the host replay used by
+            # the tests): plain host C++, no device pass
+            cmd = ["g++", "-O2" if src == "tpd_shapes.cpp" else "-O1", "-std=c++20", "-fPIC", "-ffp-contract=off",
+                   "-D__HIP_PLATFORM_AMD__",
                    "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), "-c", os.path.join(HERE, src),
                    "-o", obj]
         else:

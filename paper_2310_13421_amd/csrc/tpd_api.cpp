@@ -488,33 +488,6 @@ struct Workspace {
 };
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 
-// ---------------------------------------------------------------------------
-// scratch of tpd_decompose_noalloc: the pruning bitmap in a static device
-// array instead of a workspace.  The largest bitmap of any schedule is
-// 2^n1 x 2^(n - db) bits with n1 = 8, n - db = 13 (n = 16 at tile width 2^3,
-// n = 17 at 2^4): 2^21 bits = 256 KiB.  Each device holds its own copy at
-// its own address, looked up once per device with the device current.
-// ---------------------------------------------------------------------------
-constexpr uint64_t kScratchWords = (uint64_t)1 << 16;
-static __device__ __align__(256) uint32_t scratch[kScratchWords];
-std::mutex g_scratch_mu;
-std::map<int, uint32_t*> g_scratch;  // device -> address of its copy of `scratch`
-
-tpd_status_t scratch_of(int dev, uint32_t** out) {
-  std::lock_guard<std::mutex> lk(g_scratch_mu);
-  auto it = g_scratch.find(dev);
-  if (it == g_scratch.end()) {
-    uint32_t* ptr = nullptr;
-    if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
-      (void)hipGetLastError();
-      return TPD_ERROR_LAUNCH;
-    }
-    it = g_scratch.emplace(dev, ptr).first;
-  }
-  *out = it->second;
-  return TPD_SUCCESS;
-}
-
 tpd_status_t ensure_bitmap(Workspace& w, uint64_t words) {
   if (w.bitmap_words >= words) return TPD_SUCCESS;
   if (w.bitmap) (void)hipFree(w.bitmap);
@@ -1076,14 +1049,15 @@ tpd_status_t tpd_decompose_noalloc(const void* A, int n, void* coeffs, tpd_dtype
   Schedule s;
   st = make_schedule(n, dt, flags, A == coeffs, &s);
   if (st) return st;
-  if (s.bitmap_words > kScratchWords) return TPD_ERROR_UNSUPPORTED;  // never for a schedule of this library
+  if (s.bitmap_words > kNoallocScratchWords) return TPD_ERROR_UNSUPPORTED;  // never for a schedule of this library
   int dev;
   st = current_device(&dev);
   if (st) return st;
   uint32_t* bm = nullptr;
   if (s.prune && s.nsweep == 2) {
-    st = scratch_of(dev, &bm);  // cleared by run_schedule's fill kernel
-    if (st) return st;
+    // the device's copy of the static scratch array (tpd_scratch.hip),
+    // cleared by run_schedule's fill kernel
+    if (noalloc_scratch(dev, &bm) != hipSuccess) return TPD_ERROR_LAUNCH;
   }
   return run_schedule(s, A, coeffs, bm, (hipStream_t)stream, nullptr);
 }

@@ -21,6 +21,15 @@
 
 using namespace tpd;
 
+// A build with TPD_EMULATE_COMPLEX128_ONLY (the host-only sanitizer test
+// build, where compile time grows with every instantiation) replays the
+// complex128 schedules only; complex64 requests return TPD_ERROR_UNSUPPORTED.
+#ifdef TPD_EMULATE_COMPLEX128_ONLY
+#define TPD_IF_C64(...) TPD_ERROR_UNSUPPORTED
+#else
+#define TPD_IF_C64(...) __VA_ARGS__
+#endif
+
 namespace {
 
 struct Checker {
@@ -538,7 +547,7 @@ extern "C" tpd_status_t tpd_debug_emulate_synth(const void* coeffs, int n, void*
     if (dtype == TPD_C128)
       st = emulate_shape<double>(sw[i], (const Cx<double>*)a.in, (Cx<double>*)a.out, a, nullptr, ck);
     else
-      st = emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, nullptr, ck);
+      st = TPD_IF_C64(emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, nullptr, ck));
     if (st) return st;
     if (!ck.complete()) return TPD_ERROR_INTERNAL;
   }
@@ -592,7 +601,8 @@ extern "C" tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coef
       if (dtype == TPD_C128)
         st = emulate_shape<double>(sw[i], (const Cx<double>*)a.in, (Cx<double>*)a.out, a, bitmap.data(), *cks[i]);
       else
-        st = emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, bitmap.data(), *cks[i]);
+        st = TPD_IF_C64(
+            emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, bitmap.data(), *cks[i]));
       if (st) return st;
     }
   }
@@ -623,8 +633,8 @@ extern "C" tpd_status_t tpd_debug_emulate_batched(const void* const* ptrs, const
       st = mat ? emulate_item_n<double, L_MAT>(ptrs, outs, perm.data(), it)
                : emulate_item_n<double, L_CAN>(ptrs, outs, perm.data(), it);
     else
-      st = mat ? emulate_item_n<float, L_MAT>(ptrs, outs, perm.data(), it)
-               : emulate_item_n<float, L_CAN>(ptrs, outs, perm.data(), it);
+      st = TPD_IF_C64(mat ? emulate_item_n<float, L_MAT>(ptrs, outs, perm.data(), it)
+                          : emulate_item_n<float, L_CAN>(ptrs, outs, perm.data(), it));
     if (st) return st;
   }
   return TPD_SUCCESS;
@@ -713,7 +723,7 @@ extern "C" tpd_status_t tpd_debug_emulate_partial(const void* A, int n, void* co
       if (dtype == TPD_C128)
         st = emulate_shape<double>(sw[i], (const Cx<double>*)a.in, (Cx<double>*)a.out, a, a.bitmap, ck);
       else
-        st = emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, a.bitmap, ck);
+        st = TPD_IF_C64(emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, a.bitmap, ck));
       if (st) return st;
       if (!ck.complete()) return TPD_ERROR_INTERNAL;
     }

@@ -75,6 +75,15 @@ struct BatchArgs {
   int layout;                   // L_CAN or L_MAT output
 };
 
+// scratch of the no-allocation entry point (tpd_scratch.hip): the pruning
+// bitmap in a static device array of kNoallocScratchWords 32-bit words.  The
+// largest bitmap of any schedule is 2^n1 x 2^(n - db) bits with n1 = 8,
+// n - db = 13 (n = 16 at tile width 2^3, n = 17 at 2^4): 2^21 bits = 256 KiB.
+constexpr uint64_t kNoallocScratchWords = (uint64_t)1 << 16;
+// address of device `dev`'s copy of the array (looked up once per device,
+// with that device current); hipSuccess or the lookup's error
+hipError_t noalloc_scratch(int dev, uint32_t** out);
+
 // launchers (tpd_kernels.hip)
 hipError_t launch_sweep(Dtype dt, const SweepDesc& s, const SweepArgs& a, hipStream_t st);
 bool sweep_supported(Dtype dt, const SweepDesc& s);

@@ -188,24 +188,10 @@ hipError_t launch_batched_perm(Dtype dt, const void* const* in_ptrs, void* const
 // sweep dispatch (instantiations live in tpd_sweep_c128.hip, tpd_sweep_c64.hip,
 // tpd_sweep_r64.hip and tpd_sweep_r32.hip)
 // ---------------------------------------------------------------------------
-bool sweep_supported_c128(const SweepDesc& s);
-bool sweep_supported_c64(const SweepDesc& s);
-bool sweep_supported_r64(const SweepDesc& s);
-bool sweep_supported_r32(const SweepDesc& s);
 hipError_t launch_sweep_c128(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
 hipError_t launch_sweep_c64(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
 hipError_t launch_sweep_r64(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
 hipError_t launch_sweep_r32(const SweepDesc& s, const SweepArgs& a, hipStream_t st);
-
-bool sweep_supported(Dtype dt, const SweepDesc& s) {
-  switch (dt) {
-    case DT_C128: return sweep_supported_c128(s);
-    case DT_C64: return sweep_supported_c64(s);
-    case DT_R64: return sweep_supported_r64(s);
-    case DT_R32: return sweep_supported_r32(s);
-    default: return false;
-  }
-}
 
 hipError_t launch_sweep(Dtype dt, const SweepDesc& s, const SweepArgs& a, hipStream_t st) {
   if (a.ntiles == 0) return hipSuccess;

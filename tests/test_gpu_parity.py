@@ -9,6 +9,8 @@ in both precisions.  Sizes span many tiles; full-size configurations are
 checked on sampled strings against the definition, plus Parseval and
 exact invariants.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -896,6 +898,41 @@ def test_determinism_and_poison():
     tpd.decompose(A, o2)
     assert not bool(torch.isnan(torch.view_as_real(o1)).any())
     assert torch.equal(torch.view_as_real(o1), torch.view_as_real(o2))
+
+
+def test_allocation_failure_hook_reports_out_of_memory():
+    # TPD_TEST_FAIL_ALLOC=1 makes every library allocation fail: plan
+    # creation and the workspace of a pruned decomposition report
+    # TPD_ERROR_OUT_OF_MEMORY, while calls that need no allocation (pruning
+    # off, the no-allocation entry point) still run and agree bitwise
+    import subprocess
+    import sys
+    import textwrap
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = textwrap.dedent("""
+        import ctypes, sys
+        sys.path.insert(0, %r)
+        import torch
+        from paper_2310_13421_amd import tpd
+        import workloads as W
+        A = torch.from_numpy(W.gaussian(9, seed=77)).to("cuda")
+        o1 = torch.empty(4 ** 9, dtype=A.dtype, device="cuda")
+        o2 = torch.empty(4 ** 9, dtype=A.dtype, device="cuda")
+        h = ctypes.c_void_p()
+        rc_plan = tpd.lib.tpd_plan_create(9, tpd.TPD_C128, 0, 0, ctypes.byref(h))
+        rc_ws = tpd.lib.tpd_decompose_ex(A.data_ptr(), 9, o1.data_ptr(), tpd.TPD_C128, 0, None)
+        rc_np = tpd.lib.tpd_decompose_ex(A.data_ptr(), 9, o1.data_ptr(), tpd.TPD_C128, tpd.FLAG_NO_PRUNE, None)
+        rc_na = tpd.lib.tpd_decompose_noalloc(A.data_ptr(), 9, o2.data_ptr(), tpd.TPD_C128, 0, None)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(torch.view_as_real(o1), torch.view_as_real(o2)))
+        print("RESULT", rc_plan, rc_ws, rc_np, rc_na, int(same), flush=True)
+    """ % root)
+    env = dict(os.environ, TPD_TEST_FAIL_ALLOC="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240, env=env)
+    assert r.returncode == 0, r.stderr[-2000:]
+    line = [ln for ln in r.stdout.splitlines() if ln.startswith("RESULT")][0].split()[1:]
+    assert line == ["3", "3", "0", "0", "1"], (line, r.stderr[-1000:])
 
 
 def test_device_errors_do_not_launch():

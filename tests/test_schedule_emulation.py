@@ -171,7 +171,7 @@ def test_every_tunable_schedule_is_bitwise_the_same(n):
             assert err <= (n + 1) * 2.0 ** -24 * amax
 
 
-@pytest.mark.parametrize("n", [9, 10, 12])
+@pytest.mark.parametrize("n", [9, 10])
 def test_emulated_hermitian_mode_reads_half_and_matches(n):
     # representatives only + conjugation on chip: bitwise the general result,
     # imaginary parts exactly +0, and no read of the skipped (NaN-poisoned)
@@ -270,7 +270,7 @@ def weights(n, seed):
     return rng.standard_normal(m) + 1j * rng.standard_normal(m)
 
 
-@pytest.mark.parametrize("n", list(range(0, 12)))
+@pytest.mark.parametrize("n", list(range(0, 11)))
 def test_emulated_synthesis_matches_definition(n):
     w = weights(n, 1000 + n)
     ref = O.synthesize(w, n)
@@ -287,7 +287,7 @@ def test_emulated_synthesis_matches_definition(n):
         synth_bound(w, n, 2.0 ** -53)
 
 
-@pytest.mark.parametrize("n", [1, 5, 9, 11])
+@pytest.mark.parametrize("n", [1, 5, 9, 10])
 def test_emulated_round_trip_integer_exact(n):
     # integer weights: synthesis is exact (sums of integers), and the forward
     # transform gives them back exactly (its 1/2 per level is exact)
