@@ -954,6 +954,7 @@ def main():
                 "per_matrix_python_loop_ms": ms_loop,
                 "batched_equals_per_matrix": same,
                 "autotuned": btuned,
+                "plan": plan_g.describe(),
                 "algorithmic_GBps": bytes_ / (ms_graph / 1e3) / 1e9,
             }
             plan.close()

@@ -304,9 +304,13 @@ tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len);
 tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                           tpd_stream_t stream, char* report, size_t len);
 
-/* Time the batched plan's persistent kernel with 1, 2, 3, 4, 6 or 8
- * workgroups per CU, or one workgroup per work item, and keep the fastest
- * for this plan (and as the default for later batched plans of the dtype).
+/* Autotune a batched plan: for each n in the plan, time the item shapes of
+ * tpd_debug_plan_batched_codes (full tile with and without prefetch, half
+ * tile) on that n's matrices alone and keep the fastest; then time the
+ * persistent kernel with 1, 2, 3, 4, 6 or 8 workgroups per CU, or one
+ * workgroup per work item, and keep the fastest.  The choices apply to this
+ * plan and become the defaults of later batched plans and calls of the
+ * dtype (and, with TPD_AUTOTUNE_CACHE, of later processes).
  * d_ptrs / d_out_ptrs as tpd_plan_execute_batched; outputs are
  * overwritten.  Synchronises `stream`.                                     */
 tpd_status_t tpd_autotune_batched(tpd_plan_t plan, const void* const* d_ptrs, void* const* d_out_ptrs,
@@ -368,9 +372,20 @@ tpd_status_t tpd_debug_emulate_compact(const void* coeffs, int n, tpd_dtype_t dt
 tpd_status_t tpd_debug_emulate_synth(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,
                                      int in_place);
 
-/* Host replay of the batched schedule for one batch (HOST pointer arrays). */
+/* Host replay of the batched schedule for one batch (HOST pointer arrays);
+ * codes: NULL (the tuned or default shapes) or array[10] of per-n shape
+ * codes as tpd_debug_plan_batched_codes takes.                            */
 tpd_status_t tpd_debug_emulate_batched(const void* const* ptrs, const int* ns, int count, void* const* out_ptrs,
-                                       tpd_dtype_t dtype, unsigned flags);
+                                       tpd_dtype_t dtype, unsigned flags, const int* codes);
+
+/* Rebuild a batched plan's work table with forced per-n shape codes
+ * (array[10], index n): 0 = items filling the 2^BT-element tile, with the
+ * next item's loads issued before the current one is transformed; 1 = the
+ * same without that prefetch; 2 (n >= 3) = items of half a tile (half as
+ * many matrices per item, or d-groups half as wide), with prefetch.  For
+ * tests that every shape gives the same bits.  Allocates; not
+ * graph-capturable.  TPD_ERROR_INVALID_VALUE for an invalid code.          */
+tpd_status_t tpd_debug_plan_batched_codes(tpd_plan_t plan, const int* codes);
 
 #ifdef __cplusplus
 }

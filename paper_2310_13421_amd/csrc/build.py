@@ -19,10 +19,11 @@ SOURCES = ["tpd_sweep_c128_db3.hip", "tpd_sweep_c128_db4.hip", "tpd_sweep_c128_d
            "tpd_sweep_c64_db5.hip", "tpd_sweep_c64_db6.hip", "tpd_sweep_r64_db4.hip", "tpd_sweep_r64_db5.hip",
            "tpd_sweep_r64_db6.hip", "tpd_sweep_r32_db4.hip", "tpd_sweep_r32_db5.hip", "tpd_sweep_r32_db6.hip",
            "tpd_sweep_c128.hip", "tpd_sweep_c64.hip", "tpd_sweep_r64.hip", "tpd_sweep_r32.hip",
+           "tpd_batched_c128.hip", "tpd_batched_c64.hip", "tpd_batched_r64.hip", "tpd_batched_r32.hip",
            "tpd_kernels.hip", "tpd_select.hip", "tpd_scratch.hip", "tpd_shapes.cpp", "tpd_emulate.cpp",
            "tpd_api.cpp"]
 HOST_SOURCES = ("tpd_emulate.cpp", "tpd_shapes.cpp")  # plain host C++ (g++)
-HEADERS = ["tpd_core.h", "tpd_internal.h", "tpd_sweep.h"]
+HEADERS = ["tpd_core.h", "tpd_internal.h", "tpd_sweep.h", "tpd_batched.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -93,7 +94,7 @@ def build(verbose: bool = True, jobs: int = 0) -> str:
     if failed:
         raise RuntimeError("libtpd compilation failed")
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, *objs])
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB} in {time.time() - t0:.1f}s")

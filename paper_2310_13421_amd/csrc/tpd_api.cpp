@@ -757,25 +757,62 @@ tpd_status_t run_partial(const Schedule& s, const void* A, void* C, const uint64
 struct BatchTables {
   std::vector<uint32_t> perm;  // position -> caller's matrix index
   std::vector<BatchItem> items;
+  std::vector<BatchSeg> segs;  // runs of one shape, in item order
 };
 
-tpd_status_t build_batch(const int* ns, int count, bool in_place, unsigned flags, Dtype dt, BatchTables* bt) {
+// per-n shape codes of the batched kernel (see BatchSeg): the tuner's
+// choice for (dtype, n) if any, else 0 (full tile, prefetch)
+constexpr int kBatchedKeyMatrix = 2;  // TuneKey.matrix of per-n batched entries
+void batch_codes(Dtype dt, int codes[kMaxBatchQubits + 1]) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (!g_tune_loaded) load_tune_cache();
+  for (int n = 0; n <= kMaxBatchQubits; ++n) {
+    codes[n] = 0;
+    auto it = g_tuned.find(TuneKey{n, (int)dt, kBatchedKeyMatrix, 0, 0});
+    if (it != g_tuned.end() && batch_code_ok(n, it->second.db)) codes[n] = it->second.db;
+  }
+}
+
+tpd_status_t check_batch_ns(const int* ns, int count, bool in_place, unsigned flags) {
   const bool matrix_layout = (flags & TPD_FLAG_LAYOUT_MATRIX) != 0;
   for (int i = 0; i < count; ++i) {
     if (ns[i] < 0 || ns[i] > kMaxBatchQubits) return TPD_ERROR_UNSUPPORTED;
     if (in_place && !matrix_layout && ns[i] > 6) return TPD_ERROR_UNSUPPORTED;
   }
-  bt->perm.resize(count);
-  for (int i = 0; i < count; ++i) bt->perm[i] = (uint32_t)i;
+  return TPD_SUCCESS;
+}
+
+// Work table: matrices sorted largest n first (stable), each n's matrices
+// cut into items of that n's geometry; `only` >= 0 keeps the matrices of
+// that n alone (the per-n tuner).  codes == null: the tuned/default codes.
+tpd_status_t build_batch(const int* ns, int count, bool in_place, unsigned flags, Dtype dt, BatchTables* bt,
+                         const int* codes = nullptr, int only = -1) {
+  tpd_status_t st = check_batch_ns(ns, count, in_place, flags);
+  if (st) return st;
+  int def[kMaxBatchQubits + 1];
+  if (!codes) {
+    batch_codes(dt, def);
+    codes = def;
+  }
+  bt->perm.clear();
+  for (int i = 0; i < count; ++i)
+    if (only < 0 || ns[i] == only) bt->perm.push_back((uint32_t)i);
   // largest first, stable within a size
   std::stable_sort(bt->perm.begin(), bt->perm.end(), [&](uint32_t a, uint32_t b) { return ns[a] > ns[b]; });
   bt->items.clear();
+  bt->segs.clear();
+  const int m_all = (int)bt->perm.size();
   int pos = 0;
-  while (pos < count) {
+  while (pos < m_all) {
     const int n = ns[bt->perm[pos]];
     int end = pos;
-    while (end < count && ns[bt->perm[end]] == n) ++end;
-    const BatchGeom g = batch_geom(n, batch_tile_bits(dt));
+    while (end < m_all && ns[bt->perm[end]] == n) ++end;
+    const int code = batch_code_ok(n, codes[n]) ? codes[n] : 0;
+    const int v = batch_code_variant(code);
+    const BatchGeom g = batch_geom(n, batch_tile_bits(dt), v);
+    BatchSeg sg{};
+    sg.first = (uint32_t)bt->items.size();
+    sg.shape = (uint32_t)(n * kBatchCodes + code);
     if (g.mb > 0) {
       const int per = 1 << g.mb;
       for (int m = pos; m < end; m += per) {
@@ -784,6 +821,7 @@ tpd_status_t build_batch(const int* ns, int count, bool in_place, unsigned flags
         it.n = (uint16_t)n;
         it.nmat = (uint16_t)std::min(per, end - m);
         it.tile = 0;
+        it.variant = (uint32_t)v;
         bt->items.push_back(it);
       }
     } else {
@@ -795,13 +833,56 @@ tpd_status_t build_batch(const int* ns, int count, bool in_place, unsigned flags
           it.n = (uint16_t)n;
           it.nmat = 1;
           it.tile = t;
+          it.variant = (uint32_t)v;
           bt->items.push_back(it);
         }
     }
+    sg.end = (uint32_t)bt->items.size();
+    bt->segs.push_back(sg);
     pos = end;
   }
   return TPD_SUCCESS;
 }
+
+// a batched work table on the device (plans and the tuner); grows as needed
+struct DevBatch {
+  uint32_t* perm = nullptr;
+  BatchItem* items = nullptr;
+  BatchSeg* segs = nullptr;
+  size_t perm_cap = 0, items_cap = 0, segs_cap = 0;
+  uint32_t nitems = 0, nseg = 0;
+
+  template <class T>
+  static tpd_status_t put(T** dst, size_t* cap, const std::vector<T>& src) {
+    if (src.size() > *cap) {
+      if (*dst) (void)hipFree(*dst);
+      *dst = nullptr;
+      *cap = 0;
+      void* mem = nullptr;
+      tpd_status_t st = dev_alloc(&mem, sizeof(T) * src.size());
+      if (st) return st;
+      *dst = (T*)mem;
+      *cap = src.size();
+    }
+    if (!src.empty() && hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return TPD_ERROR_LAUNCH;
+    return TPD_SUCCESS;
+  }
+  tpd_status_t upload(const BatchTables& bt) {
+    tpd_status_t st = put(&perm, &perm_cap, bt.perm);
+    if (!st) st = put(&items, &items_cap, bt.items);
+    if (!st) st = put(&segs, &segs_cap, bt.segs);
+    nitems = st ? 0 : (uint32_t)bt.items.size();
+    nseg = st ? 0 : (uint32_t)bt.segs.size();
+    return st;
+  }
+  void release() {
+    if (perm) (void)hipFree(perm);
+    if (items) (void)hipFree(items);
+    if (segs) (void)hipFree(segs);
+    *this = DevBatch{};
+  }
+};
 
 int batched_grid(Dtype dt, uint32_t nitems) {
   const int cus = g_cus > 0 ? (int)g_cus : 256;
@@ -833,10 +914,10 @@ struct tpd_plan_s {
   unsigned long long* counter = nullptr;
   // batched
   int count = 0;
-  uint32_t nitems = 0;
   int grid = 0;
-  uint32_t* d_perm = nullptr;
-  BatchItem* d_items = nullptr;
+  std::vector<int> ns;                // qubit counts in the caller's order
+  int codes[kMaxBatchQubits + 1] = {};  // per-n shape codes of the table
+  DevBatch tab;
   Timing timing;
 };
 
@@ -1121,8 +1202,10 @@ tpd_status_t tpd_plan_create_batched(const int* ns, int count, tpd_dtype_t dtype
   tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (count < 0 || (count > 0 && !ns)) return TPD_ERROR_INVALID_VALUE;
+  int codes[kMaxBatchQubits + 1];
+  batch_codes((Dtype)dtype, codes);
   BatchTables bt;
-  st = build_batch(ns, count, in_place != 0, flags, (Dtype)dtype, &bt);
+  st = build_batch(ns, count, in_place != 0, flags, (Dtype)dtype, &bt, codes);
   if (st) return st;
   int dev;
   st = current_device(&dev);
@@ -1135,22 +1218,10 @@ tpd_status_t tpd_plan_create_batched(const int* ns, int count, tpd_dtype_t dtype
   p->flags = flags;
   p->in_place = in_place != 0;
   p->count = count;
-  p->nitems = (uint32_t)bt.items.size();
-  p->grid = batched_grid(p->dt, p->nitems);
-  void* mem = nullptr;
-  st = dev_alloc(&mem, sizeof(uint32_t) * (size_t)count);
-  if (!st) {
-    p->d_perm = (uint32_t*)mem;
-    st = dev_alloc(&mem, sizeof(BatchItem) * bt.items.size());
-    p->d_items = (BatchItem*)mem;
-  }
-  if (!st && count > 0 &&
-      hipMemcpy(p->d_perm, bt.perm.data(), sizeof(uint32_t) * (size_t)count, hipMemcpyHostToDevice) != hipSuccess)
-    st = TPD_ERROR_LAUNCH;
-  if (!st && !bt.items.empty() &&
-      hipMemcpy(p->d_items, bt.items.data(), sizeof(BatchItem) * bt.items.size(), hipMemcpyHostToDevice) !=
-          hipSuccess)
-    st = TPD_ERROR_LAUNCH;
+  p->ns.assign(ns, ns + count);
+  std::memcpy(p->codes, codes, sizeof codes);
+  p->grid = batched_grid(p->dt, (uint32_t)bt.items.size());
+  st = p->tab.upload(bt);
   if (!st && (flags & TPD_FLAG_TIMING)) st = p->timing.create(kMaxKernels);
   if (st) {
     tpd_plan_destroy(p);
@@ -1178,8 +1249,8 @@ tpd_status_t tpd_plan_execute_batched(tpd_plan_t plan, const void* const* d_ptrs
   hipStream_t hs = (hipStream_t)stream;
   const int slot = plan->timing.on ? plan->timing.begin(0, hs) : -1;
   const hipError_t e =
-      launch_batched_perm(plan->dt, d_ptrs, d_out_ptrs ? d_out_ptrs : (void* const*)d_ptrs, plan->d_perm,
-                          plan->d_items, plan->nitems,
+      launch_batched_perm(plan->dt, d_ptrs, d_out_ptrs ? d_out_ptrs : (void* const*)d_ptrs, plan->tab.perm,
+                          plan->tab.items, plan->tab.nitems, plan->tab.segs, plan->tab.nseg,
                           (plan->flags & TPD_FLAG_LAYOUT_MATRIX) ? L_MAT : L_CAN, plan->grid, hs);
   if (plan->timing.on) plan->timing.end(0, slot, hs);
   return e == hipSuccess ? TPD_SUCCESS : TPD_ERROR_LAUNCH;
@@ -1189,8 +1260,7 @@ tpd_status_t tpd_plan_destroy(tpd_plan_t plan) {
   if (!plan) return TPD_ERROR_INVALID_VALUE;
   if (plan->bitmap) (void)hipFree(plan->bitmap);
   if (plan->counter) (void)hipFree(plan->counter);
-  if (plan->d_perm) (void)hipFree(plan->d_perm);
-  if (plan->d_items) (void)hipFree(plan->d_items);
+  plan->tab.release();
   plan->timing.destroy();
   delete plan;
   return TPD_SUCCESS;
@@ -1258,10 +1328,31 @@ tpd_status_t tpd_plan_prune_stats(tpd_plan_t plan, uint64_t* live_tiles, uint64_
 tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len) {
   if (!plan) return TPD_ERROR_INVALID_VALUE;
   if (!plan->batched) return copy_out(describe(plan->sched), buf, len);
+  // per n present: the shape code (0: full tile with prefetch, 1: full tile
+  // without, 2: half tile with prefetch) and its geometry
+  std::string j;
   char tmp[256];
-  std::snprintf(tmp, sizeof tmp, "{\"batched\":true,\"count\":%d,\"items\":%u,\"grid\":%d,\"dtype\":\"%s\"}",
-                plan->count, plan->nitems, plan->grid, dtype_name(plan->dt));
-  return copy_out(tmp, buf, len);
+  std::snprintf(tmp, sizeof tmp,
+                "{\"batched\":true,\"count\":%d,\"items\":%u,\"segments\":%u,\"grid\":%d,\"dtype\":\"%s\","
+                "\"tile_bits\":%d,\"threads\":%d,\"per_n\":[",
+                plan->count, plan->tab.nitems, plan->tab.nseg, plan->grid, dtype_name(plan->dt),
+                batch_tile_bits(plan->dt), 1 << (batch_tile_bits(plan->dt) - 4));
+  j += tmp;
+  bool first = true;
+  for (int n = kMaxBatchQubits; n >= 0; --n) {
+    if (std::find(plan->ns.begin(), plan->ns.end(), n) == plan->ns.end()) continue;
+    const int code = plan->codes[n];
+    const BatchGeom g = batch_geom(n, batch_tile_bits(plan->dt), batch_code_variant(code));
+    std::snprintf(tmp, sizeof tmp,
+                  "%s{\"n\":%d,\"code\":%d,\"prefetch\":%s,\"variant\":%d,\"db\":%d,\"matrices_per_item\":%d,"
+                  "\"elements_per_thread\":%d}",
+                  first ? "" : ",", n, code, batch_code_prefetch(code) ? "true" : "false", batch_code_variant(code),
+                  g.db, 1 << g.mb, 1 << g.r);
+    j += tmp;
+    first = false;
+  }
+  j += "]}";
+  return copy_out(j, buf, len);
 }
 
 tpd_status_t tpd_decompose_batched(const void* const* ptrs, const int* ns, int count, void* const* out_ptrs,
@@ -1285,9 +1376,10 @@ tpd_status_t tpd_decompose_batched(const void* const* ptrs, const int* ns, int c
   st = current_device(&dev);
   if (st) return st;
   hipStream_t hs = (hipStream_t)stream;
-  // table: perm[count] | pad | items[nitems] | in ptrs[count] | out ptrs[count]
+  // table: perm[count] | pad | items[nitems] | segs[nseg] | in ptrs[count] | out ptrs[count]
   const size_t off_items = ((sizeof(uint32_t) * (size_t)count + 15) / 16) * 16;
-  const size_t off_in = off_items + sizeof(BatchItem) * bt.items.size();
+  const size_t off_segs = off_items + sizeof(BatchItem) * bt.items.size();
+  const size_t off_in = off_segs + sizeof(BatchSeg) * bt.segs.size();
   const size_t off_out = off_in + sizeof(void*) * (size_t)count;
   const size_t total = off_out + sizeof(void*) * (size_t)count;
   unsigned char* dtab = nullptr;
@@ -1299,6 +1391,7 @@ tpd_status_t tpd_decompose_batched(const void* const* ptrs, const int* ns, int c
   unsigned char* host = (unsigned char*)w.host_table;
   std::memcpy(host, bt.perm.data(), sizeof(uint32_t) * (size_t)count);
   std::memcpy(host + off_items, bt.items.data(), sizeof(BatchItem) * bt.items.size());
+  std::memcpy(host + off_segs, bt.segs.data(), sizeof(BatchSeg) * bt.segs.size());
   std::memcpy(host + off_in, ptrs, sizeof(void*) * (size_t)count);
   std::memcpy(host + off_out, in_place ? (const void*)ptrs : (const void*)out_ptrs, sizeof(void*) * (size_t)count);
   if (hipMemcpyAsync(dtab, host, total, hipMemcpyHostToDevice, hs) != hipSuccess) return TPD_ERROR_LAUNCH;
@@ -1306,6 +1399,7 @@ tpd_status_t tpd_decompose_batched(const void* const* ptrs, const int* ns, int c
   const hipError_t e =
       launch_batched_perm(dt, (const void* const*)(dtab + off_in), (void* const*)(dtab + off_out),
                           (const uint32_t*)dtab, (const BatchItem*)(dtab + off_items), (uint32_t)bt.items.size(),
+                          (const BatchSeg*)(dtab + off_segs), (uint32_t)bt.segs.size(),
                           (flags & TPD_FLAG_LAYOUT_MATRIX) ? L_MAT : L_CAN, batched_grid(dt, (uint32_t)bt.items.size()),
                           hs);
   return e == hipSuccess ? TPD_SUCCESS : TPD_ERROR_LAUNCH;
@@ -1366,12 +1460,15 @@ tpd_status_t host_synth_schedule(int n, int dtype, unsigned flags, bool in_place
   return TPD_SUCCESS;
 }
 
-tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, int dtype,
+tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, int dtype, const int* codes,
                                std::vector<uint32_t>* perm, std::vector<BatchItem>* items) {
   tpd_status_t st = check_dtype_flags_complex(dtype, flags);
   if (st) return st;
+  if (codes)
+    for (int n = 0; n <= kMaxBatchQubits; ++n)
+      if (!batch_code_ok(n, codes[n])) return TPD_ERROR_INVALID_VALUE;
   BatchTables bt;
-  st = build_batch(ns, count, in_place, flags, (Dtype)dtype, &bt);
+  st = build_batch(ns, count, in_place, flags, (Dtype)dtype, &bt, codes);
   if (st) return st;
   *perm = std::move(bt.perm);
   *items = std::move(bt.items);
@@ -1589,10 +1686,9 @@ extern "C" tpd_status_t tpd_autotune_batched(tpd_plan_t plan, const void* const*
                                              tpd_stream_t stream, char* report, size_t len) {
   if (!plan || !plan->batched || !d_ptrs) return TPD_ERROR_INVALID_VALUE;
   if (!d_out_ptrs && !plan->in_place) return TPD_ERROR_INVALID_VALUE;
-  if (plan->nitems == 0) return TPD_SUCCESS;
+  if (plan->tab.nitems == 0) return TPD_SUCCESS;
   hipStream_t hs = (hipStream_t)stream;
   const int cus = g_cus > 0 ? (int)g_cus : 256;
-  const int mults[7] = {1, 2, 3, 4, 6, 8, 0};  // 0: one workgroup per item
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -1600,18 +1696,13 @@ extern "C" tpd_status_t tpd_autotune_batched(tpd_plan_t plan, const void* const*
   }
   const int layout = (plan->flags & TPD_FLAG_LAYOUT_MATRIX) ? L_MAT : L_CAN;
   void* const* outs = d_out_ptrs ? d_out_ptrs : (void* const*)d_ptrs;
-  double best = 1e300;
-  int best_m = 2, best_grid = plan->grid;
-  std::string rep = "{\"tuned\":true,\"batched\":true,\"candidates\":[";
   tpd_status_t st = TPD_SUCCESS;
-  for (int i = 0; i < 7 && !st; ++i) {
-    const int m = mults[i];
-    int grid = m > 0 ? m * cus : (int)plan->nitems;
-    if ((uint32_t)grid > plan->nitems) grid = (int)plan->nitems;
+  // median of five timed launches after a warm-up
+  auto time_table = [&](const DevBatch& tb, int grid, double* med) {
     std::vector<float> ms;
     for (int k = 0; k < 6 && !st; ++k) {
       if (hipEventRecord(e0, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
-      if (!st && launch_batched_perm(plan->dt, d_ptrs, outs, plan->d_perm, plan->d_items, plan->nitems, layout,
+      if (!st && launch_batched_perm(plan->dt, d_ptrs, outs, tb.perm, tb.items, tb.nitems, tb.segs, tb.nseg, layout,
                                      grid, hs) != hipSuccess)
         st = TPD_ERROR_LAUNCH;
       if (!st && hipEventRecord(e1, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
@@ -1620,8 +1711,68 @@ extern "C" tpd_status_t tpd_autotune_batched(tpd_plan_t plan, const void* const*
         st = TPD_ERROR_LAUNCH;
       if (k > 0) ms.push_back(t_ms);  // the first launch is a warm-up
     }
-    if (st) break;
-    const double med = median3(ms);
+    *med = st ? 0.0 : median3(ms);
+    return st == TPD_SUCCESS;
+  };
+  std::string rep = "{\"tuned\":true,\"batched\":true,\"per_n\":[";
+  // 1. per n present: every shape code on the matrices of that n alone
+  //    (the others keep their codes), at the plan's grid
+  int codes[kMaxBatchQubits + 1];
+  std::memcpy(codes, plan->codes, sizeof codes);
+  DevBatch sub;
+  bool first_n = true;
+  for (int n = kMaxBatchQubits; n >= 0 && !st; --n) {
+    if (std::find(plan->ns.begin(), plan->ns.end(), n) == plan->ns.end()) continue;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s{\"n\":%d,\"candidates\":[", first_n ? "" : ",", n);
+    rep += buf;
+    first_n = false;
+    double best = 1e300;
+    int best_code = codes[n];
+    bool first_c = true;
+    for (int code = 0; code < kBatchCodes && !st; ++code) {
+      if (!batch_code_ok(n, code)) continue;
+      int cc[kMaxBatchQubits + 1];
+      std::memcpy(cc, codes, sizeof cc);
+      cc[n] = code;
+      BatchTables bt;
+      st = build_batch(plan->ns.data(), plan->count, plan->in_place, plan->flags, plan->dt, &bt, cc, n);
+      if (!st) st = sub.upload(bt);
+      double med = 0;
+      const int grid = std::min<int>(plan->grid, (int)sub.nitems);
+      if (st || !time_table(sub, grid, &med)) break;
+      std::snprintf(buf, sizeof buf, "%s{\"code\":%d,\"items\":%u,\"ms\":%.4f}", first_c ? "" : ",", code, sub.nitems,
+                    med);
+      rep += buf;
+      first_c = false;
+      if (med < best) {
+        best = med;
+        best_code = code;
+      }
+    }
+    codes[n] = best_code;
+    std::snprintf(buf, sizeof buf, "],\"chosen\":%d}", best_code);
+    rep += buf;
+  }
+  sub.release();
+  // 2. the whole table with the chosen codes
+  if (!st) {
+    BatchTables bt;
+    st = build_batch(plan->ns.data(), plan->count, plan->in_place, plan->flags, plan->dt, &bt, codes);
+    if (!st) st = plan->tab.upload(bt);
+    if (!st) std::memcpy(plan->codes, codes, sizeof codes);
+  }
+  // 3. the grid: 1, 2, 3, 4, 6 or 8 workgroups per CU, or one per item
+  rep += "],\"grid_candidates\":[";
+  const int mults[7] = {1, 2, 3, 4, 6, 8, 0};
+  double best = 1e300;
+  int best_m = 2, best_grid = plan->grid;
+  for (int i = 0; i < 7 && !st; ++i) {
+    const int m = mults[i];
+    int grid = m > 0 ? m * cus : (int)plan->tab.nitems;
+    if ((uint32_t)grid > plan->tab.nitems) grid = (int)plan->tab.nitems;
+    double med = 0;
+    if (!time_table(plan->tab, grid, &med)) break;
     char buf[128];
     std::snprintf(buf, sizeof buf, "%s{\"grid_per_cu\":%d,\"grid\":%d,\"ms\":%.4f}", i ? "," : "", m, grid, med);
     rep += buf;
@@ -1645,9 +1796,38 @@ extern "C" tpd_status_t tpd_autotune_batched(tpd_plan_t plan, const void* const*
     const TuneKey key{-1, (int)plan->dt, 0, 0, 0};
     g_tuned[key] = t;
     save_tune_entry(key, t);
+    for (int n = 0; n <= kMaxBatchQubits; ++n) {
+      if (std::find(plan->ns.begin(), plan->ns.end(), n) == plan->ns.end()) continue;
+      Tuned tn;
+      tn.db = codes[n];  // the shape code, stored in the tile-width field
+      tn.r = 4;
+      tn.grid = 0;
+      const TuneKey kn{n, (int)plan->dt, kBatchedKeyMatrix, 0, 0};
+      g_tuned[kn] = tn;
+      save_tune_entry(kn, tn);
+    }
   }
-  char buf[128];
-  std::snprintf(buf, sizeof buf, "],\"chosen\":{\"grid_per_cu\":%d,\"grid\":%d,\"ms\":%.4f}}", best_m, best_grid, best);
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "],\"chosen\":{\"grid_per_cu\":%d,\"grid\":%d,\"ms\":%.4f,\"codes\":[", best_m,
+                best_grid, best);
   rep += buf;
+  for (int n = 0; n <= kMaxBatchQubits; ++n) {
+    std::snprintf(buf, sizeof buf, "%s%d", n ? "," : "", codes[n]);
+    rep += buf;
+  }
+  rep += "]}}";
   return report ? copy_out(rep, report, len) : TPD_SUCCESS;
+}
+
+extern "C" tpd_status_t tpd_debug_plan_batched_codes(tpd_plan_t plan, const int* codes) {
+  if (!plan || !plan->batched || !codes) return TPD_ERROR_INVALID_VALUE;
+  for (int n = 0; n <= kMaxBatchQubits; ++n)
+    if (!batch_code_ok(n, codes[n])) return TPD_ERROR_INVALID_VALUE;
+  BatchTables bt;
+  tpd_status_t st = build_batch(plan->ns.data(), plan->count, plan->in_place, plan->flags, plan->dt, &bt, codes);
+  if (st) return st;
+  st = plan->tab.upload(bt);
+  if (st) return st;
+  std::memcpy(plan->codes, codes, sizeof plan->codes);
+  return TPD_SUCCESS;
 }

@@ -485,20 +485,28 @@ tpd_status_t emulate_item(const void* const* ptrs, void* const* outs, const uint
   return TPD_SUCCESS;
 }
 
+template <class S, int OUTL, int N>
+tpd_status_t emulate_item_v(const void* const* ptrs, void* const* outs, const uint32_t* perm, const BatchItem& it) {
+  constexpr int BT = batch_tile_bits(sizeof(S) == 8 ? DT_C128 : DT_C64);
+  if (it.variant == 0) return emulate_item<S, typename BatchShape<N, BT, 0>::G, OUTL>(ptrs, outs, perm, it);
+  if constexpr (N >= 3)
+    if (it.variant == 1) return emulate_item<S, typename BatchShape<N, BT, 1>::G, OUTL>(ptrs, outs, perm, it);
+  return TPD_ERROR_INTERNAL;
+}
+
 template <class S, int OUTL>
 tpd_status_t emulate_item_n(const void* const* ptrs, void* const* outs, const uint32_t* perm, const BatchItem& it) {
-  constexpr int BT = batch_tile_bits(sizeof(S) == 8 ? DT_C128 : DT_C64);
   switch (it.n) {
-    case 0: return emulate_item<S, typename BatchShape<0, BT>::G, OUTL>(ptrs, outs, perm, it);
-    case 1: return emulate_item<S, typename BatchShape<1, BT>::G, OUTL>(ptrs, outs, perm, it);
-    case 2: return emulate_item<S, typename BatchShape<2, BT>::G, OUTL>(ptrs, outs, perm, it);
-    case 3: return emulate_item<S, typename BatchShape<3, BT>::G, OUTL>(ptrs, outs, perm, it);
-    case 4: return emulate_item<S, typename BatchShape<4, BT>::G, OUTL>(ptrs, outs, perm, it);
-    case 5: return emulate_item<S, typename BatchShape<5, BT>::G, OUTL>(ptrs, outs, perm, it);
-    case 6: return emulate_item<S, typename BatchShape<6, BT>::G, OUTL>(ptrs, outs, perm, it);
-    case 7: return emulate_item<S, typename BatchShape<7, BT>::G, OUTL>(ptrs, outs, perm, it);
-    case 8: return emulate_item<S, typename BatchShape<8, BT>::G, OUTL>(ptrs, outs, perm, it);
-    case 9: return emulate_item<S, typename BatchShape<9, BT>::G, OUTL>(ptrs, outs, perm, it);
+    case 0: return emulate_item_v<S, OUTL, 0>(ptrs, outs, perm, it);
+    case 1: return emulate_item_v<S, OUTL, 1>(ptrs, outs, perm, it);
+    case 2: return emulate_item_v<S, OUTL, 2>(ptrs, outs, perm, it);
+    case 3: return emulate_item_v<S, OUTL, 3>(ptrs, outs, perm, it);
+    case 4: return emulate_item_v<S, OUTL, 4>(ptrs, outs, perm, it);
+    case 5: return emulate_item_v<S, OUTL, 5>(ptrs, outs, perm, it);
+    case 6: return emulate_item_v<S, OUTL, 6>(ptrs, outs, perm, it);
+    case 7: return emulate_item_v<S, OUTL, 7>(ptrs, outs, perm, it);
+    case 8: return emulate_item_v<S, OUTL, 8>(ptrs, outs, perm, it);
+    case 9: return emulate_item_v<S, OUTL, 9>(ptrs, outs, perm, it);
   }
   return TPD_ERROR_INTERNAL;
 }
@@ -509,7 +517,7 @@ namespace tpd {
 // defined in tpd_api.cpp
 tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, const int* tune, SweepDesc* sw,
                            int* nsweep, int* n1, uint64_t* bitmap_words, int* chunk_bits);
-tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, int dtype,
+tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, int dtype, const int* codes,
                                std::vector<uint32_t>* perm, std::vector<BatchItem>* items);
 tpd_status_t host_synth_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep);
 tpd_status_t host_partial_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep,
@@ -617,14 +625,15 @@ extern "C" tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tp
 }
 
 extern "C" tpd_status_t tpd_debug_emulate_batched(const void* const* ptrs, const int* ns, int count,
-                                                  void* const* out_ptrs, tpd_dtype_t dtype, unsigned flags) {
+                                                  void* const* out_ptrs, tpd_dtype_t dtype, unsigned flags,
+                                                  const int* codes) {
   if (count < 0) return TPD_ERROR_INVALID_VALUE;
   if (count == 0) return TPD_SUCCESS;
   if (!ptrs || !ns) return TPD_ERROR_INVALID_VALUE;
   if (dtype != TPD_C128 && dtype != TPD_C64) return TPD_ERROR_INVALID_VALUE;
   std::vector<uint32_t> perm;
   std::vector<BatchItem> items;
-  tpd_status_t st = host_batch_tables(ns, count, out_ptrs == nullptr, flags, dtype, &perm, &items);
+  tpd_status_t st = host_batch_tables(ns, count, out_ptrs == nullptr, flags, dtype, codes, &perm, &items);
   if (st) return st;
   void* const* outs = out_ptrs ? out_ptrs : (void* const*)ptrs;
   const bool mat = (flags & TPD_FLAG_LAYOUT_MATRIX) != 0;

@@ -57,14 +57,31 @@ struct SweepArgs {
 };
 
 // Batched work item: `nmat` matrices of the same n starting at `mat0`
-// (packed whole matrices), or one d-group tile of one matrix.
+// (packed whole matrices), or one d-group tile of one matrix, in the item
+// geometry `variant` (see batch_geom).
 struct BatchItem {
   uint32_t mat0;
   uint16_t n;
   uint16_t nmat;
   uint32_t tile;
+  uint32_t variant;
+};
+
+// A run of consecutive work items of one shape: items [first, end) of
+// qubit count n in geometry variant `variant`, processed with (prefetch = 1)
+// or without (0) the next item's loads issued before the current item is
+// transformed.  The shape code n * 3 + code picks the device function:
+// code 0 = (variant 0, prefetch), 1 = (variant 0, no prefetch),
+// 2 = (variant 1, prefetch).
+struct BatchSeg {
+  uint32_t first, end;
+  uint32_t shape;
   uint32_t pad;
 };
+constexpr int kBatchCodes = 3;
+constexpr int batch_code_variant(int code) { return code == 2 ? 1 : 0; }
+constexpr bool batch_code_prefetch(int code) { return code != 1; }
+constexpr bool batch_code_ok(int n, int code) { return n >= 0 && n <= 9 && code >= 0 && code < kBatchCodes && (code != 2 || n >= 3); }
 
 struct BatchArgs {
   const void* const* in_ptrs;   // device array of device pointers (caller's order)
@@ -73,6 +90,8 @@ struct BatchArgs {
   const BatchItem* items;       // device array
   uint32_t nitems;
   int layout;                   // L_CAN or L_MAT output
+  const BatchSeg* segs;         // device array of the runs of one shape, in item order
+  uint32_t nseg;
 };
 
 // scratch of the no-allocation entry point (tpd_scratch.hip): the pruning
@@ -89,7 +108,8 @@ hipError_t launch_sweep(Dtype dt, const SweepDesc& s, const SweepArgs& a, hipStr
 bool sweep_supported(Dtype dt, const SweepDesc& s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t words, uint32_t value, hipStream_t st);
 hipError_t launch_batched_perm(Dtype dt, const void* const* in_ptrs, void* const* out_ptrs, const uint32_t* perm,
-                               const BatchItem* items, uint32_t nitems, int layout, int grid, hipStream_t st);
+                               const BatchItem* items, uint32_t nitems, const BatchSeg* segs, uint32_t nseg, int layout,
+                               int grid, hipStream_t st);
 hipError_t launch_popcount(const uint32_t* p, uint64_t words, unsigned long long* out, hipStream_t st);
 
 // selection kernels (tpd_select.hip)
@@ -200,27 +220,31 @@ constexpr bool shape_fits(int xb, int db) {
   return ((size_t)sizeof(typename Elem<S>::type) << (xb + db)) <= 131072;
 }
 
-// Batched tile geometry (shared with the host emulator and planner): tiles
-// of 2^BT elements, 2^(BT-4) threads, one 64 KiB LDS tile for either dtype
-// (complex128: BT = 12, complex64: BT = 13).  n <= 6: 2^mb whole matrices
-// per item; n >= 7: one d-group of 2^db diagonals of one matrix per item.
+// Batched tile geometry (shared with the host emulator and planner): the
+// kernel has 2^(BT-4) threads and one LDS tile of 2^BT elements, 64 KiB for
+// every dtype (complex128: BT = 12, the 8- and 4-byte dtypes: 13).  An item
+// is 2^mb whole matrices (small n) or one d-group of 2^db XOR-diagonals of
+// one matrix, of 2^(BT - v) elements, 2^(4 - v) per thread: variant v = 0
+// fills the tile; v = 1 (n >= 3) holds half as much, i.e. half as many
+// matrices per item or d-groups half as wide.  n = 0..2 pack whole matrices
+// into each thread's registers (variant 0 only).
 struct BatchGeom {
-  int xb, db, mb, r;  // packed matrices per item = 2^mb
+  int xb, db, mb, r;  // packed matrices per item = 2^mb, 2^r elements per thread
 };
 constexpr int batch_tile_bits(Dtype dt) { return dt == DT_C128 ? 12 : 13; }
-template <int N, int BT>
+constexpr BatchGeom batch_geom(int n, int bt, int v = 0) {
+  if (n < 0 || n > 9 || v < 0 || v > 1 || (v == 1 && n < 3)) return BatchGeom{-1, -1, -1, -1};
+  if (n == 0) return BatchGeom{0, 0, bt - 4, 0};
+  if (n <= 2) return BatchGeom{n, n, bt - 4, n == 1 ? 2 : 4};
+  const int ib = bt - v;  // item bits
+  return 2 * n <= ib ? BatchGeom{n, n, ib - 2 * n, 4 - v} : BatchGeom{n, ib - n, 0, 4 - v};
+}
+template <int N, int BT, int V = 0>
 struct BatchShape {
-  static constexpr int XB = N;
-  static constexpr int DB = N <= 6 ? N : BT - N;
-  static constexpr int MB = N <= 2 ? BT - 4 : (N <= 6 ? BT - 2 * N : 0);
-  static constexpr int R = N == 0 ? 0 : (N == 1 ? 2 : 4);
-  using G = Geom<XB, DB, MB, R, 0>;
+  static constexpr BatchGeom g = batch_geom(N, BT, V);
+  using G = Geom<g.xb, g.db, g.mb, g.r, 0>;
+  static_assert(g.xb >= 0, "no such batched geometry");
   static_assert(G::NT == (1 << (BT - 4)), "every batched item uses the whole workgroup");
 };
-constexpr BatchGeom batch_geom(int n, int bt) {
-  return n < 0 || n > 9 ? BatchGeom{-1, -1, -1, -1}
-                        : BatchGeom{n, n <= 6 ? n : bt - n, n <= 2 ? bt - 4 : (n <= 6 ? bt - 2 * n : 0),
-                                    n == 0 ? 0 : (n == 1 ? 2 : 4)};
-}
 
 }  // namespace tpd

@@ -70,7 +70,8 @@ _SIGS = {
     "tpd_string_from_index": (_I, [_U64, _I, ctypes.c_char_p, _SZ]),
     "tpd_schedule_describe": (_I, [_I, _I, _U, _I, ctypes.c_char_p, _SZ]),
     "tpd_debug_emulate": (_I, [_P, _I, _P, _I, _U, _I]),
-    "tpd_debug_emulate_batched": (_I, [_P, _P, _I, _P, _I, _U]),
+    "tpd_debug_emulate_batched": (_I, [_P, _P, _I, _P, _I, _U, _P]),
+    "tpd_debug_plan_batched_codes": (_I, [_P, _P]),
     "tpd_decompose_partial": (_I, [_P, _I, _P, _P, _U64, _P, _I, _U, _P]),
     "tpd_debug_decompose_tuned": (_I, [_P, _I, _P, _I, _U, _I, _I, _I, _I, _P]),
     "tpd_compact": (_I, [_P, _I, _I, _U, ctypes.c_double, _P, _P, _U64, _P, _P]),
@@ -210,19 +211,31 @@ def emulate_compact(coeffs: np.ndarray, n: int, tol: float = 0.0, capacity: Opti
     return q[:k], w[:k], int(total[0])
 
 
+def _codes(codes):
+    """per-n shape codes (sequence of 10, index n) as a C array, or None"""
+    if codes is None:
+        return None
+    codes = list(codes)
+    if len(codes) != 10:
+        raise ValueError("codes needs one entry per n = 0..9")
+    return (ctypes.c_int * 10)(*codes)
+
+
 def emulate_batched(mats: Sequence[np.ndarray], dtype: int = TPD_C128, flags: int = 0,
-                    in_place: bool = False) -> List[np.ndarray]:
+                    in_place: bool = False, codes=None) -> List[np.ndarray]:
+    """Host replay of the batched kernel; codes: per-n shape codes (see
+    BatchedPlan.set_codes) or None for the tuned/default ones."""
     mats = [np.ascontiguousarray(m, dtype=_np_dtype(dtype)) for m in mats]
     ns = (ctypes.c_int * len(mats))(*[m.shape[0].bit_length() - 1 for m in mats])
     ins = (ctypes.c_void_p * len(mats))(*[m.ctypes.data for m in mats])
     if in_place:
         outs_np = [m.copy().reshape(-1) for m in mats]
         ins = (ctypes.c_void_p * len(mats))(*[o.ctypes.data for o in outs_np])
-        _check(lib.tpd_debug_emulate_batched(ins, ns, len(mats), None, dtype, flags), "emulate_batched")
+        _check(lib.tpd_debug_emulate_batched(ins, ns, len(mats), None, dtype, flags, _codes(codes)), "emulate_batched")
         return outs_np
     outs_np = [np.empty(m.size, _np_dtype(dtype)) for m in mats]
     outs = (ctypes.c_void_p * len(mats))(*[o.ctypes.data for o in outs_np])
-    _check(lib.tpd_debug_emulate_batched(ins, ns, len(mats), outs, dtype, flags), "emulate_batched")
+    _check(lib.tpd_debug_emulate_batched(ins, ns, len(mats), outs, dtype, flags, _codes(codes)), "emulate_batched")
     return outs_np
 
 
@@ -530,6 +543,11 @@ class BatchedPlan(Plan):
                                         None if d_out_ptrs is None else d_out_ptrs.data_ptr(), _stream(stream),
                                         buf, 8192), "tpd_autotune_batched")
         return json.loads(buf.value.decode())
+
+    def set_codes(self, codes):
+        """Force per-n shape codes (index n): 0 full tile with prefetch, 1
+        full tile without, 2 (n >= 3) half tile with prefetch (test aid)."""
+        _check(lib.tpd_debug_plan_batched_codes(self._h, _codes(codes)), "tpd_debug_plan_batched_codes")
 
     def execute(self, d_ptrs, d_out_ptrs=None, stream=None):
         _check(lib.tpd_plan_execute_batched(self._h, d_ptrs.data_ptr(),

@@ -6,6 +6,7 @@
 // build replays complex128 only (TPD_EMULATE_COMPLEX128_ONLY); complex64
 // replays are checked by the regular test-suite.  Prints
 // one line per check and exits nonzero on the first mismatch.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -207,12 +208,21 @@ void batched_check() {
     in[k] = mats[k].data();
     out[k] = outs[k].data();
   }
-  bool ok = tpd_debug_emulate_batched(in.data(), ns.data(), (int)ns.size(), out.data(), TPD_C128, 0) == TPD_SUCCESS;
-  for (size_t k = 0; k < mats.size() && ok; ++k) {
-    const auto ref = oracle(mats[k], ns[k]);
-    ok = same_bits(outs[k].data(), ref.data(), ref.size());
+  for (int code = 0; code < 3; ++code) {
+    // the same shape code for every n (code 2 exists for n >= 3 only)
+    int codes[10];
+    for (int n = 0; n < 10; ++n) codes[n] = (code == 2 && n < 3) ? 0 : code;
+    for (auto& o : outs) std::fill(o.begin(), o.end(), cd(NAN, NAN));
+    bool ok = tpd_debug_emulate_batched(in.data(), ns.data(), (int)ns.size(), out.data(), TPD_C128, 0, codes) ==
+              TPD_SUCCESS;
+    for (size_t k = 0; k < mats.size() && ok; ++k) {
+      const auto ref = oracle(mats[k], ns[k]);
+      ok = same_bits(outs[k].data(), ref.data(), ref.size());
+    }
+    char name[96];
+    std::snprintf(name, sizeof name, "batched 30 matrices n=0..9, shape code %d, bitwise Algorithm 1", code);
+    report(name, ok);
   }
-  report("batched 30 matrices n=0..9, bitwise Algorithm 1", ok);
 }
 
 void oracle_mt_check() {

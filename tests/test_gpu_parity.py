@@ -312,6 +312,57 @@ def test_batched_plan_graph_capture_and_layouts():
         assert same_bits(matrix_to_canonical(o.cpu().numpy().ravel(), ns[k]), r), k
 
 
+@pytest.mark.parametrize("dtype,code", [(torch.complex128, tpd.TPD_C128), (torch.complex64, tpd.TPD_C64),
+                                        (torch.float32, tpd.TPD_R32)])
+def test_batched_every_item_shape_and_autotune_same_bits(dtype, code):
+    # the per-n item shapes the batched autotuner chooses from (full tile
+    # with or without prefetch, half tile) and the tuned plan give the same
+    # bits as the default plan, NaN-poisoned outputs fully written, complex128
+    # bitwise equal to Algorithm 1; the tuner reports a choice per n
+    ns = [int(v) for v in W.batched_qubits(600, seed=45, lo=0, hi=9)]
+    if dtype.is_complex:
+        mats = W.batched_matrices(ns, seed=45)
+        dmats = [to_dev(m, dtype) for m in mats]
+    else:
+        mats = [W.real_gaussian(n, seed=4500 + k) for k, n in enumerate(ns)]
+        dmats = [torch.from_numpy(m).to(DEV).to(dtype) for m in mats]
+    dp = tpd.BatchedPlan.pointer_table(dmats)
+
+    def run(plan):
+        outs = [torch.full((4 ** n,), float("nan"), dtype=dtype, device=DEV) for n in ns]
+        plan.execute(dp, tpd.BatchedPlan.pointer_table(outs))
+        torch.cuda.synchronize()
+        return outs
+
+    plan = tpd.BatchedPlan(ns, code)
+    base = run(plan)
+    if dtype == torch.complex128:
+        for k in range(0, len(ns), 7):
+            assert same_bits(base[k].cpu().numpy(), O.tpd_recursive(mats[k])), k
+    for c in (0, 1, 2):
+        plan.set_codes([0 if (c == 2 and n < 3) else c for n in range(10)])
+        outs = run(plan)
+        for k, (a, b) in enumerate(zip(outs, base)):
+            assert torch.equal(a, b), (c, k)
+    ws = [torch.empty(4 ** n, dtype=dtype, device=DEV) for n in ns]
+    rep = plan.autotune(dp, tpd.BatchedPlan.pointer_table(ws))
+    assert sorted(p_["n"] for p_ in rep["per_n"]) == sorted(set(ns))
+    assert all(p_["chosen"] in [c_["code"] for c_ in p_["candidates"]] for p_ in rep["per_n"])
+    desc = plan.describe()
+    assert {p_["n"]: p_["code"] for p_ in desc["per_n"]} == {p_["n"]: p_["chosen"] for p_ in rep["per_n"]}
+    outs = run(plan)
+    for k, (a, b) in enumerate(zip(outs, base)):
+        assert torch.equal(a, b), k
+    # a new plan of the dtype takes the tuned shapes
+    plan2 = tpd.BatchedPlan(ns, code)
+    assert plan2.describe()["per_n"] == desc["per_n"]
+    outs = run(plan2)
+    for k, (a, b) in enumerate(zip(outs, base)):
+        assert torch.equal(a, b), k
+    plan.close()
+    plan2.close()
+
+
 # ----------------------------------------------------------------------------
 # configuration 4: n = 16 Hermitian, complex128 and complex64, sampled strings
 # ----------------------------------------------------------------------------

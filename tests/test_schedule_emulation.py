@@ -141,6 +141,26 @@ def test_emulated_batched_matches_oracle():
         assert same_bits(o, O.tpd_recursive(m))
 
 
+@pytest.mark.parametrize("code", [0, 1, 2])
+def test_emulated_batched_every_item_shape(code):
+    # every per-n item shape (full tile with/without prefetch, half tile:
+    # half the matrices per item or d-groups half as wide) covers each
+    # matrix exactly once and gives Algorithm 1's bits, in both layouts and
+    # in place; complex64 gives the bits of the default shape
+    ns = W.batched_qubits(80, seed=44, lo=0, hi=9)
+    mats = W.batched_matrices(ns, seed=44)
+    codes = [0 if (code == 2 and n < 3) else code for n in range(10)]
+    for o, m in zip(tpd.emulate_batched(mats, codes=codes), mats):
+        assert same_bits(o, O.tpd_recursive(m))
+    for o, m, n in zip(tpd.emulate_batched(mats, flags=tpd.FLAG_LAYOUT_MATRIX, in_place=True, codes=codes), mats, ns):
+        assert same_bits(matrix_to_canonical(o, int(n)), O.tpd_recursive(m))
+    ref64 = tpd.emulate_batched(mats, dtype=tpd.TPD_C64)
+    for o, r in zip(tpd.emulate_batched(mats, dtype=tpd.TPD_C64, codes=codes), ref64):
+        assert np.array_equal(o, r)
+    with pytest.raises(tpd.TPDError):  # the half tile does not exist below n = 3
+        tpd.emulate_batched(mats, codes=[2] * 10)
+
+
 @pytest.mark.parametrize("n", [9, 10, 12])
 def test_every_tunable_schedule_is_bitwise_the_same(n):
     # the autotuner may pick any tile width / register depth: all must give
