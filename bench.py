@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBPS = 8000.0
 METRIC = "Pauli coeffs/sec + HBM GB/s (% peak) at n=14/16, FP64 vs FP32; batched mats/s"
 KERNEL_SOURCES = ["paper_2310_13421_amd/csrc/tpd_sweep.h", "paper_2310_13421_amd/csrc/tpd_core.h",
-                  "paper_2310_13421_amd/csrc/tpd_internal.h"]
+                  "paper_2310_13421_amd/csrc/tpd_internal.h", "paper_2310_13421_amd/csrc/tpd_batched.h"]
 
 
 def log(msg):
@@ -44,14 +44,14 @@ def log(msg):
 
 
 def kernel_source_hash():
-    """Hash of the sources of the sweep kernel (its headers and the
-    instantiation units), the kernel whose traffic profiles/traffic.json
-    records."""
+    """Hash of the sources of the sweep and batched kernels (their headers
+    and the instantiation units), the kernels whose traffic
+    profiles/traffic.json records."""
     import glob
 
     h = hashlib.sha256()
-    files = sorted(set(KERNEL_SOURCES) | {os.path.relpath(p, ROOT) for p in glob.glob(
-        os.path.join(ROOT, "paper_2310_13421_amd", "csrc", "tpd_sweep_c*.hip"))})
+    files = sorted(set(KERNEL_SOURCES) | {os.path.relpath(p, ROOT) for pat in ("tpd_sweep_c*.hip", "tpd_batched_*.hip")
+                                          for p in glob.glob(os.path.join(ROOT, "paper_2310_13421_amd", "csrc", pat))})
     for rel in files:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
@@ -61,7 +61,8 @@ def kernel_source_hash():
 def load_traffic(kernel_name, n):
     """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE and
     WRITE_SIZE scaled by a plain-copy calibration) for this kernel at this
-    n, if taken on the current kernel sources."""
+    n (None: the batched kernel on the 4096-matrix set), if taken on the
+    current kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -145,6 +146,9 @@ def ingest_pair(fetch_csv, write_csv):
     wscale = sum(wc[i] for i in sel) / len(sel) / copy_bytes
     kernels = {}
     for name in fetch:
+        if "tpd::k_batched" in name and name in write:
+            kernels[name] = batched_traffic(name, fetch[name], write[name], fscale, wscale)
+            continue
         if "tpd::k_sweep" not in name or name not in write:
             continue
         if "k_sweep<tpd::Real<double>" in name:
@@ -195,6 +199,25 @@ def ingest_pair(fetch_csv, write_csv):
             }
     return kernels, fscale, wscale
 
+
+
+def batched_elements():
+    """Coefficients of the 4096-matrix mixed set (n uniform in 2..9, seed 4)."""
+    import workloads as W
+
+    return int(sum(4 ** int(v) for v in W.batched_qubits(4096, seed=4)))
+
+
+def batched_traffic(name, fetch, write, fscale, wscale):
+    """PMC bytes per dispatch of the batched kernel on the 4096-matrix set
+    (every dispatch of the profiled run decomposes the whole set)."""
+    es = 16 if "k_batched<double" in name else (4 if "Real<float>" in name else 8)
+    alg = batched_elements() * es
+    fb = sum(fetch) / len(fetch) / fscale
+    wb = sum(write) / len(write) / wscale
+    return {"workload": "batched 4096 matrices, n in 2..9", "dispatches": len(fetch), "fetch_bytes": fb,
+            "write_bytes": wb, "total_bytes": fb + wb, "algorithmic_bytes": 2 * alg,
+            "fetch_over_algorithmic": fb / alg, "write_over_algorithmic": wb / alg}
 
 
 def timed_steps(fn, steps, warmup, torch):
@@ -528,24 +551,25 @@ def main():
     n = args.n
     steps_x = max(3, min(args.steps, 10))
     errors = {}
+    if args.copy_calibration:
+        nbytes = 1 << 32
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {nbytes} bytes")
+        del src, dst
+        torch.cuda.empty_cache()
+
     result = {"metric": METRIC, "legs_only": True}
     if not args.legs_only:
         log(f"generating n={n} Hermitian complex128 input on the GPU")
         A = W.gaussian_device(n, seed=5, hermitian=True)
         torch.cuda.synchronize()
 
-        if args.copy_calibration:
-            nbytes = 1 << 32
-            src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
-            dst = torch.empty_like(src)
-            src.fill_(1.0)
-            torch.cuda.synchronize()
-            for _ in range(3):
-                dst.copy_(src)
-            torch.cuda.synchronize()
-            log(f"copy calibration: 3 copies of {nbytes} bytes")
-            del src, dst
-            torch.cuda.empty_cache()
 
         # ---- headline -----------------------------------------------------------
         log(f"main: n={n} complex128 in place (matrix layout), {args.steps} timed steps over {args.allocations} "
@@ -955,6 +979,8 @@ def main():
                 "batched_equals_per_matrix": same,
                 "autotuned": btuned,
                 "plan": plan_g.describe(),
+                "traffic": load_traffic(f"void tpd::k_batched<{'double' if dt == torch.complex128 else 'float'}, 1, "
+                                        f"{12 if dt == torch.complex128 else 13}>(tpd::BatchArgs)", None),
                 "algorithmic_GBps": bytes_ / (ms_graph / 1e3) / 1e9,
             }
             plan.close()

@@ -140,3 +140,19 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_ingest_batched_kernel_against_the_4096_matrix_set(tmp_path):
+    # the batched kernel's bytes are compared with the whole set's
+    # 2 x sum 4^n x s (every dispatch decomposes all 4096 matrices)
+    kb = "void tpd::k_batched<double, 1, 12>(tpd::BatchArgs)"
+    copy = 1 << 32
+    elems = bench.batched_elements()
+    assert elems == sum(4 ** n for n in __import__("workloads").batched_qubits(4096, seed=4))
+    alg = elems * 16
+    write_csv(tmp_path / "f.csv", [(COPY, 0.5 * copy / 1024), (kb, 0.5 * 1.03 * alg / 1024), (kb, 0.5 * 1.01 * alg / 1024)])
+    write_csv(tmp_path / "w.csv", [(COPY, copy / 1024), (kb, alg / 1024), (kb, alg / 1024)])
+    doc = bench.ingest_pmc([(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))], str(tmp_path / "t.json"))
+    k = doc["kernels"][kb]
+    assert k["dispatches"] == 2 and abs(k["fetch_over_algorithmic"] - 1.02) < 1e-9
+    assert abs(k["write_over_algorithmic"] - 1.0) < 1e-9 and abs(k["algorithmic_bytes"] - 2 * alg) < 1
