@@ -25,6 +25,7 @@ partial legs, and the CPU oracle timed on the host.
 import argparse
 import hashlib
 import json
+import math
 import re
 import os
 import sys
@@ -172,6 +173,20 @@ def ingest_pair(fetch_csv, write_csv):
         alg = 4 ** n * es
         fr = [v / fscale / alg for v in fetch[name]]
         wr = [v / wscale / alg for v in write[name]]
+        # chunked order: each dispatch moves 1/2^k of a sweep (2^k chunks);
+        # such a symbol is reported per whole sweep (the 2^k dispatches)
+        if fr and len(fr) == len(wr) and max(fr) < 0.3:
+            ks = [round(math.log2(1.0 / r)) if r > 0 else 0 for r in fr]
+            if all(k >= 2 and abs(r * 2 ** k - 1.0) < 0.05 for r, k in zip(fr, ks)):
+                fo = sum(r * 2 ** k for r, k in zip(fr, ks)) / len(fr)
+                wo = sum(w * 2 ** k for w, k in zip(wr, ks)) / len(wr)
+                kernels[name] = {
+                    "n": n, "sweep": which, "dtype": dt, "dispatches": len(fr), "chunks": sorted({2 ** k for k in ks}),
+                    "fetch_bytes": fo * alg, "write_bytes": wo * alg, "total_bytes": (fo + wo) * alg,
+                    "algorithmic_bytes": 2 * alg, "fetch_over_algorithmic": fo, "write_over_algorithmic": wo,
+                    "per": "whole sweep (the chunked order's dispatches summed over its chunks)",
+                }
+                continue
         # Hermitian / real-symmetric mode shares the kernel symbol and reads
         # about half of what the full mode reads (1.06 against 2.0 for tiles
         # whose runs are shorter than a line): its dispatches are reported
@@ -281,7 +296,7 @@ def single_matrix_run(tpd, torch, A, n, dtype_code, steps, warmup, esize, in_pla
         "kernel_ms": avgs,
         "kernel_launches": cnt,
         "sweeps": len(desc["sweeps"]),
-        "chunk_bits": desc.get("chunk_bits", 0),
+        "chunk_bits": desc.get("chunk_bits", 0), "chunk_window": desc.get("chunk_window", 0),
         "schedule": _sched(desc),
         "autotuned": tuned,
     }
@@ -339,7 +354,7 @@ def inplace_run(tpd, torch, A0, n, dtype_code, steps, warmup, esize, hermitian=F
         "kernel_ms": avgs,
         "kernel_launches": cnt,
         "sweeps": len(desc["sweeps"]),
-        "chunk_bits": desc.get("chunk_bits", 0),
+        "chunk_bits": desc.get("chunk_bits", 0), "chunk_window": desc.get("chunk_window", 0),
         "schedule": _sched(desc),
         "autotuned": tuned,
     }
@@ -356,7 +371,9 @@ def headline_run(tpd, torch, A0, n, steps, warmup, allocations):
     before the next is taken, so the driver may place it elsewhere in
     physical memory); every allocation autotunes on its own buffer and runs
     `warmup` untimed steps first.  Returns (per-allocation results, the last
-    buffer, holding the weights of A0)."""
+    buffer, holding the weights of A0).  At least one step per allocation:
+    fewer steps than allocations use fewer allocations."""
+    allocations = max(1, min(allocations, steps))
     per = [steps // allocations + (1 if k < steps % allocations else 0) for k in range(allocations)]
     runs, B = [], None
     for k in range(allocations):
@@ -367,7 +384,8 @@ def headline_run(tpd, torch, A0, n, steps, warmup, allocations):
         times, avgs, cnt, desc, tuned = inplace_steps(tpd, torch, A0, B, n, tpd.TPD_C128, per[k], warmup)
         runs.append({"steps": per[k], "ms_mean": sum(times) / len(times), "ms_min": min(times),
                      "ms_max": max(times), "kernel_ms": avgs, "kernel_launches": cnt,
-                     "chunk_bits": desc.get("chunk_bits", 0), "schedule": _sched(desc), "autotuned": tuned,
+                     "chunk_bits": desc.get("chunk_bits", 0), "chunk_window": desc.get("chunk_window", 0),
+                     "schedule": _sched(desc), "autotuned": tuned,
                      "buffer_address": int(B.data_ptr())})
         log(f"main: allocation {k}: {runs[-1]['ms_mean']:.3f} ms/step over {per[k]} steps, kernels {avgs}")
     return runs, B

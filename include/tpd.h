@@ -291,8 +291,11 @@ tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len);
  * sweep's rotated tile order (TPD_FLAG_ROTATE_TILES: which tiles run side by
  * side, hence how their rows meet the memory channels, depends on where the
  * buffer sits in physical memory); then, outside the Hermitian mode, the
- * winner in the chunked order (sweep 1 then sweep 2 over 64, 128 or 256 MB
- * of XOR-diagonal strips at a time, see tpd_debug_decompose_tuned).
+ * winner in the chunked order (sweep 1 then sweep 2 over 32 MB to 512 MB
+ * of XOR-diagonal strips at a time, on one stream or pipelined over two,
+ * see tpd_debug_decompose_tuned).  A pipelined choice makes later
+ * calls on a stream create a second stream (default priority) and events,
+ * kept until tpd_release_workspace (plans: until tpd_plan_destroy).
  * The choice never changes results (same operations in the same order).
  * Timed runs include the first sweep's pruning epilogue unless
  * TPD_FLAG_NO_PRUNE is given; in place, where each run transforms the
@@ -344,21 +347,28 @@ tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tpd_dtype_t d
 /* As tpd_debug_emulate with a forced two-sweep tile width 2^db (db = 0:
  * the default schedule); r must be 0 or 4 (elements per thread = 16);
  * chunk_bits > 0 (with db > 0) runs the chunked order of
- * tpd_debug_decompose_tuned.                                              */
+ * tpd_debug_decompose_tuned, and chunk_window >= 2 replays its pipelined
+ * form in one order its streams allow, checking that no element is touched
+ * by two chunks.                                                          */
 tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
-                                     int in_place, int db, int r, int chunk_bits);
+                                     int in_place, int db, int r, int chunk_bits, int chunk_window);
 
 /* One decomposition on the device with a forced two-sweep schedule: tile
  * width 2^db, 2^r elements per thread (r = 4), grid_per_cu workgroups per
  * CU (0 = one per tile), and chunk_bits: 0 runs each sweep over the whole
  * matrix, k > 0 runs sweep 1 then sweep 2 over 2^k first-sweep d-groups
  * (XOR-diagonal strips of 2^db) at a time, 2^(n-db-k) chunks (needs
- * k < n - db, not with TPD_FLAG_HERMITIAN).  For tests that every tunable
- * schedule gives the same bits; arguments and errors otherwise as
+ * k < n - db, not with TPD_FLAG_HERMITIAN).  chunk_window: 0 runs the
+ * chunks one after the other on `stream`; w in 2..8 (with k > 0) runs
+ * sweep 2 of chunk c on a second stream while sweep 1 of the next w - 1
+ * chunks runs on `stream` (sweep 1 of chunk c waits for sweep 2 of chunk
+ * c - w; `stream` waits for the last sweep 2).  For tests that every
+ * tunable schedule gives the same bits; arguments and errors otherwise as
  * tpd_decompose_ex, and TPD_ERROR_INVALID_VALUE for a schedule that does
  * not exist.  n <= 8 ignores the schedule arguments.                      */
 tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
-                                       int db, int r, int grid_per_cu, int chunk_bits, tpd_stream_t stream);
+                                       int db, int r, int grid_per_cu, int chunk_bits, int chunk_window,
+                                       tpd_stream_t stream);
 
 /* Host replays of the partial decomposition (request marking, tile skips,
  * gather) and of the compaction (same chunks, order and clipping); HOST

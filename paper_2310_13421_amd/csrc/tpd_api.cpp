@@ -72,7 +72,13 @@ struct Schedule {
   // intermediate can still sit in the memory-side cache when sweep 2 reads
   // it; 0: each sweep over the whole matrix
   int chunk_bits = 0;
+  // pipelined chunks (with chunk_bits > 0): >= 2 runs sweep 2 of chunk c on
+  // a second stream while sweep 1 of chunks c+1 .. c+window-1 runs on the
+  // caller's, so the GPU never drains between the launches of a chunk; 0:
+  // both sweeps of one chunk, then the next, on the caller's stream
+  int chunk_window = 0;
 };
+constexpr int kMaxWindow = 8;
 
 int single_db(int n) {
   static const int t[9] = {0, 1, 2, 3, 4, 5, 6, 5, 4};
@@ -87,6 +93,7 @@ struct Tuned {
   int db = 0, r = 4, grid = 0;
   int order2 = 0;  // second sweep's tile order (SweepDesc::tile_order)
   int chunk = 0;   // Schedule::chunk_bits
+  int window = 0;  // Schedule::chunk_window
 };
 struct TuneKey {
   int n, dt, matrix, in_place, herm;
@@ -192,6 +199,11 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
     const bool ok = !(flags & TPD_FLAG_HERMITIAN) && t.chunk < n - db1;
     if (!ok && force) return TPD_ERROR_INVALID_VALUE;
     s->chunk_bits = ok ? t.chunk : 0;
+  }
+  if (t.window) {
+    const bool ok = s->chunk_bits > 0 && t.window >= 2 && t.window <= kMaxWindow;
+    if (!ok && force) return TPD_ERROR_INVALID_VALUE;
+    s->chunk_window = ok ? t.window : 0;
   }
   s->prune = (flags & TPD_FLAG_NO_PRUNE) == 0;
   const int cus = g_cus > 0 ? (int)g_cus : 256;
@@ -320,7 +332,7 @@ tpd_status_t make_synth_schedule(int n, Dtype dt, unsigned flags, bool in_place,
 }
 
 // Autotune cache: TPD_AUTOTUNE_CACHE names a text file of lines
-//   tpd-tune-v2 <arch> <cus> <dtype> <n> <matrix> <in_place> <hermitian> <db> <r> <grid> [<order2> [<chunk>]]
+//   tpd-tune-v2 <arch> <cus> <dtype> <n> <matrix> <in_place> <hermitian> <db> <r> <grid> [<order2> [<chunk> [<window>]]]
 // Unreadable or foreign lines are ignored (the built-in defaults apply).
 void load_tune_cache() {
   g_tune_loaded = true;
@@ -331,10 +343,11 @@ void load_tune_cache() {
   while (std::getline(f, line)) {
     std::istringstream is(line);
     std::string tag, arch;
-    int cus, dt, n, mat, inp, herm, db, r, grid, order2 = 0, chunk = 0;
+    int cus, dt, n, mat, inp, herm, db, r, grid, order2 = 0, chunk = 0, window = 0;
     if (!(is >> tag >> arch >> cus >> dt >> n >> mat >> inp >> herm >> db >> r >> grid)) continue;
     if (!(is >> order2)) order2 = 0;  // optional field: the second sweep's tile order
     else if (!(is >> chunk) || chunk < 0 || chunk > 16) chunk = 0;  // optional field: chunked order
+    else if (!(is >> window) || window < 0 || window > kMaxWindow) window = 0;  // optional: pipelined chunks
     if (tag != "tpd-tune-v2" || arch != "gfx950") continue;
     if (g_cus > 0 && cus != g_cus) continue;
     if (dt < 0 || dt > 3 || n < -1 || n > kMaxQubits || r != 4 || grid < 0 || grid > 64) continue;
@@ -344,6 +357,7 @@ void load_tune_cache() {
     t.grid = grid;
     t.order2 = order2 ? 1 : 0;
     t.chunk = chunk;
+    t.window = window;
     g_tuned[TuneKey{n, dt, mat, inp, herm}] = t;
   }
 }
@@ -354,7 +368,7 @@ void save_tune_entry(const TuneKey& k, const Tuned& t) {
   std::ofstream f(path, std::ios::app);
   f << "tpd-tune-v2 gfx950 " << (g_cus > 0 ? (int)g_cus : 0) << " " << k.dt << " " << k.n << " " << k.matrix << " "
     << k.in_place << " " << k.herm << " " << t.db << " " << t.r << " " << t.grid << " " << t.order2 << " "
-    << t.chunk << "\n";
+    << t.chunk << " " << t.window << "\n";
 }
 
 const char* layout_name(int l) { return l == L_MAT ? "MAT" : (l == L_CAN ? "CAN" : "MID"); }
@@ -367,11 +381,12 @@ std::string describe(const Schedule& s) {
   std::snprintf(buf, sizeof buf,
                 "{\"n\":%d,\"dtype\":\"%s\",\"layout\":\"%s\",\"in_place\":%s,\"prune\":%s,"
                 "\"hermitian\":%s,\"elements\":%llu,\"algorithmic_bytes\":%llu,\"bitmap_words\":%llu,"
-                "\"chunk_bits\":%d,\"sweeps\":[",
+                "\"chunk_bits\":%d,\"chunk_window\":%d,\"sweeps\":[",
                 s.n, dtype_name(s.dt), s.matrix_layout ? "matrix" : "canonical",
                 s.in_place ? "true" : "false", s.prune ? "true" : "false",
                 (s.nsweep == 2 && s.sw[0].herm) ? "true" : "false", (unsigned long long)count,
-                (unsigned long long)(2 * count * eb), (unsigned long long)s.bitmap_words, s.chunk_bits);
+                (unsigned long long)(2 * count * eb), (unsigned long long)s.bitmap_words, s.chunk_bits,
+                s.chunk_window);
   j += buf;
   for (int i = 0; i < s.nsweep; ++i) {
     const SweepDesc& w = s.sw[i];
@@ -470,6 +485,40 @@ tpd_status_t dev_alloc(void** p, size_t bytes) {
   return TPD_SUCCESS;
 }
 
+// Second stream and events of the pipelined chunk order (created on first
+// use, kept for the owner's lifetime; the stream has the default priority).
+struct Pipe {
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t s1[kMaxWindow + 1] = {}, s2[kMaxWindow + 1] = {};
+  tpd_status_t ensure() {
+    if (side) return TPD_SUCCESS;
+    if (fail_alloc_hook()) return TPD_ERROR_OUT_OF_MEMORY;
+    bool ok = hipStreamCreateWithFlags(&side, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&join, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i <= kMaxWindow && ok; ++i)
+      ok = hipEventCreateWithFlags(&s1[i], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&s2[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      destroy();
+      return TPD_ERROR_OUT_OF_MEMORY;
+    }
+    return TPD_SUCCESS;
+  }
+  void destroy() {
+    if (side) (void)hipStreamSynchronize(side);
+    for (hipEvent_t* e : {&fork, &join})
+      if (*e) (void)hipEventDestroy(*e), *e = nullptr;
+    for (int i = 0; i <= kMaxWindow; ++i) {
+      if (s1[i]) (void)hipEventDestroy(s1[i]), s1[i] = nullptr;
+      if (s2[i]) (void)hipEventDestroy(s2[i]), s2[i] = nullptr;
+    }
+    if (side) (void)hipStreamDestroy(side), side = nullptr;
+  }
+};
+
 struct Workspace {
   uint32_t* bitmap = nullptr;
   uint64_t bitmap_words = 0;
@@ -485,6 +534,7 @@ struct Workspace {
   void* host_table = nullptr;  // pinned staging copy of the table
   size_t host_bytes = 0;
   hipEvent_t staged = nullptr;  // recorded after the last staging copy
+  Pipe pipe;                    // pipelined chunk order
 };
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 
@@ -640,8 +690,38 @@ tpd_status_t launch_sweep_i(const Schedule& s, int i, const void* A, void* C, ui
   return TPD_SUCCESS;
 }
 
+// Pipelined chunk order: sweep 1 of every chunk on the caller's stream,
+// sweep 2 of chunk c on the pipe's stream after sweep 1 of chunk c, and
+// sweep 1 of chunk c only after sweep 2 of chunk c - window (so at most
+// `window` chunks are between their two sweeps).  Chunks touch disjoint
+// elements (every tile lies in one d-group), so the two streams' launches
+// may overlap in any way these dependencies allow.  The caller's stream
+// waits for the last sweep 2 before anything queued after this call.
+tpd_status_t run_pipelined(const Schedule& s, const void* A, void* C, uint32_t* bitmap, hipStream_t st,
+                           Pipe& p) {
+  const uint64_t nchunks = (uint64_t)1 << (s.n - s.sw[0].db - s.chunk_bits);
+  const uint64_t W = (uint64_t)s.chunk_window, K = W + 1;
+  if (hipEventRecord(p.fork, st) != hipSuccess || hipStreamWaitEvent(p.side, p.fork, 0) != hipSuccess)
+    return TPD_ERROR_LAUNCH;
+  tpd_status_t e = TPD_SUCCESS;
+  for (uint64_t c = 0; c < nchunks && !e; ++c) {
+    if (c >= W && hipStreamWaitEvent(st, p.s2[(c - W) % K], 0) != hipSuccess) e = TPD_ERROR_LAUNCH;
+    if (!e) e = launch_sweep_i(s, 0, A, C, bitmap, nullptr, st, (int64_t)c);
+    if (!e && (hipEventRecord(p.s1[c % K], st) != hipSuccess ||
+               hipStreamWaitEvent(p.side, p.s1[c % K], 0) != hipSuccess))
+      e = TPD_ERROR_LAUNCH;
+    if (!e) e = launch_sweep_i(s, 1, A, C, bitmap, nullptr, p.side, (int64_t)c);
+    if (!e && hipEventRecord(p.s2[c % K], p.side) != hipSuccess) e = TPD_ERROR_LAUNCH;
+  }
+  // join even after a failed launch: nothing queued on the caller's stream
+  // later may overtake what the pipe's stream still runs
+  if (hipEventRecord(p.join, p.side) != hipSuccess || hipStreamWaitEvent(st, p.join, 0) != hipSuccess)
+    return TPD_ERROR_LAUNCH;
+  return e;
+}
+
 tpd_status_t run_schedule(const Schedule& s, const void* A, void* C, uint32_t* bitmap, hipStream_t st,
-                          Timing* tm) {
+                          Timing* tm, Pipe* pipe = nullptr) {
   const size_t eb = elem_bytes(s.dt);
   if (s.n == 0) {
     if (A != C && hipMemcpyAsync(C, A, eb, hipMemcpyDeviceToDevice, st) != hipSuccess) return TPD_ERROR_LAUNCH;
@@ -654,11 +734,17 @@ tpd_status_t run_schedule(const Schedule& s, const void* A, void* C, uint32_t* b
     // sweep 1 then sweep 2 over one chunk of d-groups at a time (the
     // sweeps' tiles never cross a d-group, so each chunk is closed); timing
     // records the whole loop as kernel 0
+    // (a schedule with a chunk window runs pipelined when the caller passes
+    // a pipe; without one, chunk after chunk on one stream)
     const uint64_t nchunks = (uint64_t)1 << (s.n - s.sw[0].db - s.chunk_bits);
     const int slot = tm ? tm->begin(0, st) : -1;
     tpd_status_t e = TPD_SUCCESS;
-    for (uint64_t c = 0; c < nchunks && !e; ++c)
-      for (int i = 0; i < 2 && !e; ++i) e = launch_sweep_i(s, i, A, C, bitmap, nullptr, st, (int64_t)c);
+    if (s.chunk_window >= 2 && pipe) {
+      e = run_pipelined(s, A, C, bitmap, st, *pipe);
+    } else {
+      for (uint64_t c = 0; c < nchunks && !e; ++c)
+        for (int i = 0; i < 2 && !e; ++i) e = launch_sweep_i(s, i, A, C, bitmap, nullptr, st, (int64_t)c);
+    }
     if (tm) tm->end(0, slot, st);
     return e;
   }
@@ -919,6 +1005,7 @@ struct tpd_plan_s {
   int codes[kMaxBatchQubits + 1] = {};  // per-n shape codes of the table
   DevBatch tab;
   Timing timing;
+  Pipe pipe;  // pipelined chunk order (schedules with a chunk window)
 };
 
 extern "C" {
@@ -997,15 +1084,23 @@ tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dt
   // same stream could otherwise grow (free and reallocate) the workspace
   // between this thread taking its pointer and launching on it
   std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
-  if (s.prune && s.nsweep == 2) {
+  Pipe* pipe = nullptr;
+  if ((s.prune && s.nsweep == 2) || s.chunk_window) {
     lk.lock();
     Workspace& w = g_ws[{dev, hs}];
-    st = ensure_bitmap(w, s.bitmap_words);
-    if (st) return st;
-    bm = w.bitmap;
+    if (s.prune && s.nsweep == 2) {
+      st = ensure_bitmap(w, s.bitmap_words);
+      if (st) return st;
+      bm = w.bitmap;
+    }
+    if (s.chunk_window) {
+      st = w.pipe.ensure();
+      if (st) return st;
+      pipe = &w.pipe;
+    }
   }
   logf("decompose n=%d %s", n, describe(s).c_str());
-  return run_schedule(s, A, coeffs, bm, hs, nullptr);
+  return run_schedule(s, A, coeffs, bm, hs, nullptr, pipe);
 }
 
 tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,
@@ -1156,6 +1251,7 @@ tpd_status_t tpd_release_workspace(void) {
     if (w.table) (void)hipFree(w.table);
     if (w.host_table) (void)hipHostFree(w.host_table);
     if (w.staged) (void)hipEventDestroy(w.staged);
+    w.pipe.destroy();
   }
   g_ws.clear();
   return TPD_SUCCESS;
@@ -1187,6 +1283,7 @@ tpd_status_t tpd_plan_create(int n, tpd_dtype_t dtype, unsigned flags, int in_pl
     p->counter = (unsigned long long*)mem;
   }
   if (!st && (flags & TPD_FLAG_TIMING)) st = p->timing.create(kMaxKernels);
+  if (!st && s.chunk_window) st = p->pipe.ensure();
   if (st) {
     tpd_plan_destroy(p);
     return st;
@@ -1237,7 +1334,7 @@ tpd_status_t tpd_plan_execute(tpd_plan_t plan, const void* A, void* coeffs, tpd_
   if (st) return st;
   if ((A == coeffs) != plan->in_place) return TPD_ERROR_INVALID_VALUE;
   return run_schedule(plan->sched, A, coeffs, plan->bitmap, (hipStream_t)stream,
-                      plan->timing.on ? &plan->timing : nullptr);
+                      plan->timing.on ? &plan->timing : nullptr, &plan->pipe);
 }
 
 tpd_status_t tpd_plan_execute_batched(tpd_plan_t plan, const void* const* d_ptrs, void* const* d_out_ptrs,
@@ -1262,6 +1359,7 @@ tpd_status_t tpd_plan_destroy(tpd_plan_t plan) {
   if (plan->counter) (void)hipFree(plan->counter);
   plan->tab.release();
   plan->timing.destroy();
+  plan->pipe.destroy();
   delete plan;
   return TPD_SUCCESS;
 }
@@ -1412,7 +1510,7 @@ tpd_status_t tpd_decompose_batched(const void* const* ptrs, const int* ns, int c
 // ---------------------------------------------------------------------------
 namespace tpd {
 tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, const int* tune, SweepDesc* sw,
-                           int* nsweep, int* n1, uint64_t* bitmap_words, int* chunk_bits) {
+                           int* nsweep, int* n1, uint64_t* bitmap_words, int* chunk_bits, int* chunk_window) {
   tpd_status_t st = check_dtype_flags_complex(dtype, flags);
   if (st) return st;
   Schedule s;
@@ -1422,6 +1520,7 @@ tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, cons
     t.r = tune[1];
     t.grid = tune[2];
     t.chunk = tune[3];
+    t.window = tune[4];
   }
   st = make_schedule_with(n, (Dtype)dtype, flags, in_place, tune && n > 8 ? &t : nullptr, &s);
   if (st) return st;
@@ -1430,6 +1529,7 @@ tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, cons
   *n1 = s.n1;
   *bitmap_words = s.bitmap_words;
   *chunk_bits = s.chunk_bits;
+  *chunk_window = s.chunk_window;
   return TPD_SUCCESS;
 }
 
@@ -1488,11 +1588,11 @@ double median3(std::vector<float>& v) {
 
 extern "C" tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype,
                                                   unsigned flags, int db, int r, int grid_per_cu, int chunk_bits,
-                                                  tpd_stream_t stream) {
+                                                  int chunk_window, tpd_stream_t stream) {
   tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (n < 0 || n > max_qubits((Dtype)dtype)) return TPD_ERROR_UNSUPPORTED;
-  if (grid_per_cu < 0 || grid_per_cu > 64 || chunk_bits < 0) return TPD_ERROR_INVALID_VALUE;
+  if (grid_per_cu < 0 || grid_per_cu > 64 || chunk_bits < 0 || chunk_window < 0) return TPD_ERROR_INVALID_VALUE;
   const Dtype dt = (Dtype)dtype;
   st = check_buffers(A, coeffs, n, dt);
   if (st) return st;
@@ -1504,6 +1604,7 @@ extern "C" tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* co
   t.r = r;
   t.grid = grid_per_cu;
   t.chunk = chunk_bits;
+  t.window = chunk_window;
   Schedule s;
   st = make_schedule_with(n, dt, flags, A == coeffs, n > 8 ? &t : nullptr, &s);
   if (st) return st;
@@ -1513,14 +1614,22 @@ extern "C" tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* co
   // same stream could otherwise grow (free and reallocate) the workspace
   // between this thread taking its pointer and launching on it
   std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
-  if (s.prune && s.nsweep == 2) {
+  Pipe* pipe = nullptr;
+  if ((s.prune && s.nsweep == 2) || s.chunk_window) {
     lk.lock();
     Workspace& w = g_ws[{dev, hs}];
-    st = ensure_bitmap(w, s.bitmap_words);
-    if (st) return st;
-    bm = w.bitmap;
+    if (s.prune && s.nsweep == 2) {
+      st = ensure_bitmap(w, s.bitmap_words);
+      if (st) return st;
+      bm = w.bitmap;
+    }
+    if (s.chunk_window) {
+      st = w.pipe.ensure();
+      if (st) return st;
+      pipe = &w.pipe;
+    }
   }
-  return run_schedule(s, A, coeffs, bm, hs, nullptr);
+  return run_schedule(s, A, coeffs, bm, hs, nullptr, pipe);
 }
 
 extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
@@ -1580,6 +1689,7 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
     (void)hipFree(bm);
     return TPD_ERROR_OUT_OF_MEMORY;
   }
+  Pipe pipe;  // pipelined chunk candidates (created when first timed)
   double best = 1e300;
   Tuned best_t = cands[0];
   rep = "{\"tuned\":true,\"n\":" + std::to_string(n) + ",\"dtype\":\"" + dtype_name(dt) +
@@ -1591,12 +1701,16 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
     Schedule sc;
     if (make_schedule_with(n, dt, tflags, in_place, &t, &sc) != TPD_SUCCESS) return false;
     if (in_place && sc.prune && sc.nsweep == 2) sc.sw[1].bitmap_mode = 0;
-    st = run_schedule(sc, A, coeffs, bm, hs, nullptr);  // warm-up
+    if (sc.chunk_window) {
+      st = pipe.ensure();
+      if (st) return false;
+    }
+    st = run_schedule(sc, A, coeffs, bm, hs, nullptr, &pipe);  // warm-up
     if (st) return false;
     std::vector<float> ms;
     for (int rep_i = 0; rep_i < 3 && !st; ++rep_i) {
       if (hipEventRecord(e0, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
-      if (!st) st = run_schedule(sc, A, coeffs, bm, hs, nullptr);
+      if (!st) st = run_schedule(sc, A, coeffs, bm, hs, nullptr, &pipe);
       if (!st && hipEventRecord(e1, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
       float t_ms = 0;
       if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t_ms, e0, e1) != hipSuccess))
@@ -1607,8 +1721,9 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
     *med = median3(ms);
     char buf[192];
     std::snprintf(buf, sizeof buf,
-                  "%s{\"db\":%d,\"r\":%d,\"grid_per_cu\":%d,\"order2\":%d,\"chunk_bits\":%d,\"ms\":%.4f}",
-                  first ? "" : ",", t.db, t.r, t.grid, t.order2, t.chunk, *med);
+                  "%s{\"db\":%d,\"r\":%d,\"grid_per_cu\":%d,\"order2\":%d,\"chunk_bits\":%d,"
+                  "\"chunk_window\":%d,\"ms\":%.4f}",
+                  first ? "" : ",", t.db, t.r, t.grid, t.order2, t.chunk, t.window, *med);
     rep += buf;
     first = false;
     return true;
@@ -1635,26 +1750,34 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
       best_t = t;
     }
   }
-  // then the winner in the chunked order, sweep 1 and sweep 2 over 64-256 MB
+  // then the winner in the chunked order, sweep 1 and sweep 2 over 32-512 MB
   // of d-groups at a time: the second sweep may then read the chunk from the
   // 256 MB memory-side cache, but each chunk is a strip of columns across
-  // all rows, so the sweeps lose row locality in HBM (measured: a few
-  // percent faster at n = 14, slower at n = 16)
+  // all rows, so the sweeps lose row locality in HBM; on one stream every
+  // chunk's two launches also drain the GPU, which the pipelined form
+  // (sweep 2 on a second stream) avoids
   if (!st && best < 1e300 && !(flags & TPD_FLAG_HERMITIAN)) {
     const Tuned base_t = best_t;
     Schedule sc;
     if (make_schedule_with(n, dt, tflags, in_place, &base_t, &sc) == TPD_SUCCESS && sc.nsweep == 2) {
       const uint64_t group_bytes = ((uint64_t)elem_bytes(dt) << n) << sc.sw[0].db;
-      for (uint64_t mb = 64; mb <= 256 && !st; mb *= 2) {
+      for (uint64_t mb = 32; mb <= 512 && !st; mb *= 2) {
         int cb = 0;
         while ((group_bytes << (cb + 1)) <= (mb << 20)) ++cb;
         if (cb < 1 || cb >= n - sc.sw[0].db || (group_bytes << cb) != (mb << 20)) continue;
-        Tuned t = base_t;
-        t.chunk = cb;
-        double med;
-        if (time_candidate(t, &med) && med < best) {
-          best = med;
-          best_t = t;
+        // one stream (64 MB and up), or pipelined over two streams with 2 or
+        // 4 chunks between their two sweeps
+        for (int w : {0, 2, 4}) {
+          if (w == 0 && mb < 64) continue;
+          Tuned t = base_t;
+          t.chunk = cb;
+          t.window = w;
+          double med;
+          if (time_candidate(t, &med) && med < best) {
+            best = med;
+            best_t = t;
+          }
+          if (st) break;
         }
       }
     }
@@ -1662,6 +1785,7 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(hs);
+  pipe.destroy();
   (void)hipFree(bm);
   if (st) return st;
   const TuneKey key{n, (int)dt, (flags & TPD_FLAG_LAYOUT_MATRIX) ? 1 : 0, in_place ? 1 : 0,
@@ -1675,8 +1799,8 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
   char buf[256];
   std::snprintf(buf, sizeof buf,
                 "],\"chosen\":{\"db\":%d,\"r\":%d,\"grid_per_cu\":%d,\"order2\":%d,\"chunk_bits\":%d,"
-                "\"ms\":%.4f}}",
-                best_t.db, best_t.r, best_t.grid, best_t.order2, best_t.chunk, best);
+                "\"chunk_window\":%d,\"ms\":%.4f}}",
+                best_t.db, best_t.r, best_t.grid, best_t.order2, best_t.chunk, best_t.window, best);
   rep += buf;
   logf("autotune %s", rep.c_str());
   return report ? copy_out(rep, report, len) : TPD_SUCCESS;

@@ -42,15 +42,29 @@ struct Checker {
   const uint32_t* live = nullptr;
   const uint32_t* requested = nullptr;
   bool zero_check = true;
+  // chunked order: the chunk that first touched each element of the
+  // output buffer (and, in place, of the input), -1 = none; a touch by
+  // another chunk fails, so chunks are disjoint and the pipelined streams
+  // may interleave their launches in any order their events allow
+  int32_t* own_rd = nullptr;
+  int32_t* own_wr = nullptr;
+  int32_t tag = 0;
   static bool bit(const uint32_t* m, uint64_t b) { return (m[b >> 5] >> (b & 31)) & 1u; }
   explicit Checker(uint64_t c) : count(c), reads(c, 0), writes(c, 0) {}
+  void own(int32_t* o, uint64_t a) {
+    if (!o) return;
+    if (o[a] < 0) o[a] = tag;
+    else if (o[a] != tag) ok = false;
+  }
   void rd(uint64_t a) {
     if (a >= count) { ok = false; return; }
     if (reads[a]++) ok = false;
+    own(own_rd, a);
   }
   void wr(uint64_t a) {
     if (a >= count) { ok = false; return; }
     if (writes[a]++) ok = false;
+    own(own_wr, a);
   }
   bool complete() const {
     for (uint64_t i = 0; i < count; ++i)
@@ -516,7 +530,7 @@ tpd_status_t emulate_item_n(const void* const* ptrs, void* const* outs, const ui
 namespace tpd {
 // defined in tpd_api.cpp
 tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, const int* tune, SweepDesc* sw,
-                           int* nsweep, int* n1, uint64_t* bitmap_words, int* chunk_bits);
+                           int* nsweep, int* n1, uint64_t* bitmap_words, int* chunk_bits, int* chunk_window);
 tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned flags, int dtype, const int* codes,
                                std::vector<uint32_t>* perm, std::vector<BatchItem>* items);
 tpd_status_t host_synth_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep);
@@ -563,17 +577,18 @@ extern "C" tpd_status_t tpd_debug_emulate_synth(const void* coeffs, int n, void*
 }
 
 extern "C" tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coeffs, tpd_dtype_t dtype,
-                                                unsigned flags, int in_place, int db, int r, int chunk_bits) {
+                                                unsigned flags, int in_place, int db, int r, int chunk_bits,
+                                                int chunk_window) {
   if (!A || !coeffs) return TPD_ERROR_INVALID_VALUE;
   if (n < 0 || n > 12) return TPD_ERROR_UNSUPPORTED;  // host replay is for small n
   if (in_place && A != coeffs) return TPD_ERROR_INVALID_VALUE;
-  if (chunk_bits < 0 || (chunk_bits > 0 && db <= 0)) return TPD_ERROR_INVALID_VALUE;
+  if (chunk_bits < 0 || (chunk_bits > 0 && db <= 0) || chunk_window < 0) return TPD_ERROR_INVALID_VALUE;
   SweepDesc sw[2];
-  int nsweep = 0, n1 = 0, chunk = 0;
+  int nsweep = 0, n1 = 0, chunk = 0, window = 0;
   uint64_t words = 0;
-  const int tune[4] = {db, r, 0, chunk_bits};
-  tpd_status_t st =
-      host_schedule(n, dtype, flags, in_place != 0, db > 0 ? tune : nullptr, sw, &nsweep, &n1, &words, &chunk);
+  const int tune[5] = {db, r, 0, chunk_bits, chunk_window};
+  tpd_status_t st = host_schedule(n, dtype, flags, in_place != 0, db > 0 ? tune : nullptr, sw, &nsweep, &n1, &words,
+                                  &chunk, &window);
   if (st) return st;
   const uint64_t count = (uint64_t)1 << (2 * n);
   const size_t eb = dtype == TPD_C128 ? 16 : 8;
@@ -583,34 +598,53 @@ extern "C" tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coef
   }
   std::vector<uint32_t> bitmap(words ? words : 1, 0u);
   // chunked order: sweep 1 then sweep 2 per chunk of d-groups; each sweep's
-  // checker accumulates over the chunks, so completeness covers the union
+  // checker accumulates over the chunks, so completeness covers the union.
+  // Pipelined (window w): step k runs sweep 1 of chunk k, then sweep 2 of
+  // chunk k - w + 1, the order in which the device streams' dependencies
+  // let sweep 1 run furthest ahead.
   const uint64_t nchunks = (nsweep == 2 && chunk > 0) ? ((uint64_t)1 << (n - sw[0].db - chunk)) : 1;
+  const uint64_t lag = window >= 2 ? (uint64_t)window - 1 : 0;
   Checker ck0(count), ck1(count);
   Checker* cks[2] = {&ck0, &ck1};
-  for (uint64_t c = 0; c < nchunks; ++c) {
-    for (int i = 0; i < nsweep; ++i) {
-      SweepArgs a{};
-      a.in = i == 0 ? A : coeffs;
-      a.out = coeffs;
-      a.n = n;
-      a.xlo = sw[i].xlo;
-      a.db = sw[i].db;
-      a.nfix_d = n - sw[i].db;
-      a.bitmap = bitmap.data();
-      a.bitmap_mode = sw[i].bitmap_mode;
-      a.bm_xbits = n1;
-      a.herm = sw[i].herm;
-      a.ntiles = sw[i].ntiles;
-      if (nchunks > 1) {
-        a.chunk_bits = chunk + sw[0].db - sw[i].db;
-        a.td_base = c << a.chunk_bits;
-        a.ntiles = ((uint64_t)1 << (n - sw[i].xb)) << a.chunk_bits;
-      }
-      if (dtype == TPD_C128)
-        st = emulate_shape<double>(sw[i], (const Cx<double>*)a.in, (Cx<double>*)a.out, a, bitmap.data(), *cks[i]);
-      else
-        st = TPD_IF_C64(
-            emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, bitmap.data(), *cks[i]));
+  std::vector<int32_t> own_out, own_in;
+  if (nchunks > 1) {
+    own_out.assign(count, -1);
+    if (!in_place) own_in.assign(count, -1);
+    ck0.own_rd = in_place ? own_out.data() : own_in.data();
+    ck0.own_wr = own_out.data();
+    ck1.own_rd = ck1.own_wr = own_out.data();
+  }
+  auto run = [&](int i, uint64_t c) -> tpd_status_t {
+    SweepArgs a{};
+    a.in = i == 0 ? A : coeffs;
+    a.out = coeffs;
+    a.n = n;
+    a.xlo = sw[i].xlo;
+    a.db = sw[i].db;
+    a.nfix_d = n - sw[i].db;
+    a.bitmap = bitmap.data();
+    a.bitmap_mode = sw[i].bitmap_mode;
+    a.bm_xbits = n1;
+    a.herm = sw[i].herm;
+    a.ntiles = sw[i].ntiles;
+    if (nchunks > 1) {
+      a.chunk_bits = chunk + sw[0].db - sw[i].db;
+      a.td_base = c << a.chunk_bits;
+      a.ntiles = ((uint64_t)1 << (n - sw[i].xb)) << a.chunk_bits;
+      cks[i]->tag = (int32_t)c;
+    }
+    if (dtype == TPD_C128)
+      return emulate_shape<double>(sw[i], (const Cx<double>*)a.in, (Cx<double>*)a.out, a, bitmap.data(), *cks[i]);
+    return TPD_IF_C64(
+        emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, bitmap.data(), *cks[i]));
+  };
+  for (uint64_t k = 0; k < nchunks + lag; ++k) {
+    if (k < nchunks) {
+      st = run(0, k);
+      if (st) return st;
+    }
+    if (nsweep == 2 && k >= lag) {
+      st = run(1, k - lag);
       if (st) return st;
     }
   }
@@ -621,7 +655,7 @@ extern "C" tpd_status_t tpd_debug_emulate_tuned(const void* A, int n, void* coef
 
 extern "C" tpd_status_t tpd_debug_emulate(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                                           int in_place) {
-  return tpd_debug_emulate_tuned(A, n, coeffs, dtype, flags, in_place, 0, 0, 0);
+  return tpd_debug_emulate_tuned(A, n, coeffs, dtype, flags, in_place, 0, 0, 0, 0);
 }
 
 extern "C" tpd_status_t tpd_debug_emulate_batched(const void* const* ptrs, const int* ns, int count,
@@ -666,7 +700,7 @@ extern "C" tpd_status_t tpd_debug_emulate_partial(const void* A, int n, void* co
   if (n == 0) {
     if (A != coeffs) std::memcpy(coeffs, A, eb);
   } else if (nsweep == 1) {
-    st = tpd_debug_emulate_tuned(A, n, coeffs, dtype, flags, in_place, 0, 0, 0);
+    st = tpd_debug_emulate_tuned(A, n, coeffs, dtype, flags, in_place, 0, 0, 0, 0);
     if (st) return st;
   } else {
     const int db = sw[0].db;

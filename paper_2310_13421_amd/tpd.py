@@ -62,7 +62,7 @@ _SIGS = {
     "tpd_release_workspace": (_I, []),
     "tpd_autotune": (_I, [_P, _I, _P, _I, _U, _P, ctypes.c_char_p, _SZ]),
     "tpd_autotune_batched": (_I, [_P, _P, _P, _P, ctypes.c_char_p, _SZ]),
-    "tpd_debug_emulate_tuned": (_I, [_P, _I, _P, _I, _U, _I, _I, _I, _I]),
+    "tpd_debug_emulate_tuned": (_I, [_P, _I, _P, _I, _U, _I, _I, _I, _I, _I]),
     "tpd_synthesize_ex": (_I, [_P, _I, _P, _I, _U, _P]),
     "tpd_debug_emulate_synth": (_I, [_P, _I, _P, _I, _U, _I]),
     "tpd_status_string": (ctypes.c_char_p, [_I]),
@@ -73,7 +73,7 @@ _SIGS = {
     "tpd_debug_emulate_batched": (_I, [_P, _P, _I, _P, _I, _U, _P]),
     "tpd_debug_plan_batched_codes": (_I, [_P, _P]),
     "tpd_decompose_partial": (_I, [_P, _I, _P, _P, _U64, _P, _I, _U, _P]),
-    "tpd_debug_decompose_tuned": (_I, [_P, _I, _P, _I, _U, _I, _I, _I, _I, _P]),
+    "tpd_debug_decompose_tuned": (_I, [_P, _I, _P, _I, _U, _I, _I, _I, _I, _I, _P]),
     "tpd_compact": (_I, [_P, _I, _I, _U, ctypes.c_double, _P, _P, _U64, _P, _P]),
     "tpd_debug_emulate_partial": (_I, [_P, _I, _P, _P, _U64, _P, _I, _U, _I]),
     "tpd_debug_emulate_compact": (_I, [_P, _I, _I, _U, ctypes.c_double, _P, _P, _U64, _P]),
@@ -154,20 +154,21 @@ def _np_dtype(dtype: int):
 
 
 def emulate(A: np.ndarray, dtype: int = TPD_C128, flags: int = 0, in_place: bool = False, db: int = 0,
-            r: int = 0, chunk_bits: int = 0) -> np.ndarray:
+            r: int = 0, chunk_bits: int = 0, chunk_window: int = 0) -> np.ndarray:
     """Host replay of the device schedule (debugging aid for small n);
     db/r force a two-sweep tile width 2^db and 2^r elements per thread,
-    chunk_bits > 0 the chunked order (2^chunk_bits d-groups per chunk)."""
+    chunk_bits > 0 the chunked order (2^chunk_bits d-groups per chunk),
+    chunk_window >= 2 its pipelined form."""
     A = np.ascontiguousarray(A, dtype=_np_dtype(dtype))
     n = A.shape[0].bit_length() - 1
     if in_place:
         out = A.copy().reshape(-1)
-        _check(lib.tpd_debug_emulate_tuned(out.ctypes.data, n, out.ctypes.data, dtype, flags, 1, db, r, chunk_bits),
-               "tpd_debug_emulate")
+        _check(lib.tpd_debug_emulate_tuned(out.ctypes.data, n, out.ctypes.data, dtype, flags, 1, db, r, chunk_bits,
+                                           chunk_window), "tpd_debug_emulate")
         return out
     out = np.full(A.size, np.nan, _np_dtype(dtype))  # poison: every element must be written
-    _check(lib.tpd_debug_emulate_tuned(A.ctypes.data, n, out.ctypes.data, dtype, flags, 0, db, r, chunk_bits),
-           "tpd_debug_emulate")
+    _check(lib.tpd_debug_emulate_tuned(A.ctypes.data, n, out.ctypes.data, dtype, flags, 0, db, r, chunk_bits,
+                                       chunk_window), "tpd_debug_emulate")
     return out
 
 
@@ -328,10 +329,11 @@ def decompose_noalloc(A, out, *, layout: str = "canonical", prune: bool = True, 
 
 def decompose_tuned(A, out=None, *, db: int, grid_per_cu: int = 0, r: int = 4, layout: str = "canonical",
                     prune: bool = True, hermitian: bool = False, rotate: bool = False, chunk_bits: int = 0,
-                    stream=None):
+                    chunk_window: int = 0, stream=None):
     """decompose() with a forced two-sweep schedule (test aid); rotate=True
     selects the second sweep's rotated tile order, chunk_bits > 0 the
-    chunked order (sweep 1 then sweep 2 over 2^chunk_bits d-groups at a time)."""
+    chunked order (sweep 1 then sweep 2 over 2^chunk_bits d-groups at a
+    time), chunk_window >= 2 its pipelined form over two streams."""
     torch = _torch()
     n = _check_matrix(A)
     if out is None:
@@ -340,7 +342,7 @@ def decompose_tuned(A, out=None, *, db: int, grid_per_cu: int = 0, r: int = 4, l
         raise ValueError("out must be a contiguous CUDA tensor of 4^n elements of A's dtype")
     _check(lib.tpd_debug_decompose_tuned(A.data_ptr(), n, out.data_ptr(), _dtype_code(A),
                                          _flags(layout, prune, False, hermitian) | (FLAG_ROTATE_TILES if rotate else 0),
-                                         db, r, grid_per_cu, chunk_bits, _stream(stream)),
+                                         db, r, grid_per_cu, chunk_bits, chunk_window, _stream(stream)),
            "tpd_debug_decompose_tuned")
     return out
 

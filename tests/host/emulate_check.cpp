@@ -111,13 +111,14 @@ void tuned_and_chunked_checks() {
   const auto A = gaussian(n, 7, false);
   const auto ref = oracle(A, n);
   for (int db = 3; db <= 5; ++db)
-    for (int cb = 0; cb <= 3; cb += 3) {
-      std::vector<cd> out(ref.size(), cd(NAN, NAN));
-      char name[96];
-      std::snprintf(name, sizeof name, "n=10 tile width 2^%d chunk bits %d", db, cb);
-      report(name, tpd_debug_emulate_tuned(A.data(), n, out.data(), TPD_C128, 0, 0, db, 4, cb) == TPD_SUCCESS &&
-                       same_bits(out.data(), ref.data(), ref.size()));
-    }
+    for (int cb = 0; cb <= 3; cb += 3)
+      for (int w = 0; w <= (cb ? 3 : 0); w += (w ? 1 : 2)) {
+        std::vector<cd> out(ref.size(), cd(NAN, NAN));
+        char name[96];
+        std::snprintf(name, sizeof name, "n=10 tile width 2^%d chunk bits %d window %d", db, cb, w);
+        report(name, tpd_debug_emulate_tuned(A.data(), n, out.data(), TPD_C128, 0, 0, db, 4, cb, w) == TPD_SUCCESS &&
+                         same_bits(out.data(), ref.data(), ref.size()));
+      }
 }
 
 // the transverse-field Ising chain, section "Results": weights -1 on Z_i Z_i+1

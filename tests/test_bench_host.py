@@ -156,3 +156,23 @@ def test_ingest_batched_kernel_against_the_4096_matrix_set(tmp_path):
     k = doc["kernels"][kb]
     assert k["dispatches"] == 2 and abs(k["fetch_over_algorithmic"] - 1.02) < 1e-9
     assert abs(k["write_over_algorithmic"] - 1.0) < 1e-9 and abs(k["algorithmic_bytes"] - 2 * alg) < 1
+
+
+def test_ingest_sums_chunked_dispatches_over_their_chunks(tmp_path):
+    # the chunked order launches each sweep once per chunk (here 16 chunks
+    # of the n = 14 matrix-layout kernel): its symbol is reported per whole
+    # sweep, not as a reduced mode
+    k = "void tpd::k_sweep<double, tpd::Geom<7, 3, 0, 4, 0>, 0, 0, false>(tpd::SweepArgs)"
+    alg = 4 ** 14 * 16
+    copy = 1 << 32
+    fetch = [(COPY, 0.5 * copy / 1024)] + [(k, 0.5 * 1.002 * alg / 16 / 1024)] * 32
+    write = [(COPY, copy / 1024)] + [(k, 1.001 * alg / 16 / 1024)] * 32
+    f1, w1 = tmp_path / "f.csv", tmp_path / "w.csv"
+    write_csv(f1, fetch)
+    write_csv(w1, write)
+    doc = bench.ingest_pmc([(str(f1), str(w1))], str(tmp_path / "t.json"))
+    e = doc["kernels"][k]
+    assert e["n"] == 14 and e["chunks"] == [16] and e["dispatches"] == 32
+    assert abs(e["fetch_over_algorithmic"] - 1.002) < 1e-9 and abs(e["write_over_algorithmic"] - 1.001) < 1e-9
+    assert abs(e["total_bytes"] - 2.003 * alg) < 1e-3 * alg
+    assert "only_reduced_mode_dispatches" not in e

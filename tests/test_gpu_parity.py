@@ -236,6 +236,12 @@ def test_config2_n14_heisenberg_round_trip_and_pruning(dyadic):
     # the unpruned schedule gives the same bits
     out2 = tpd.decompose(H, prune=False)
     assert torch.equal(torch.view_as_real(out2), torch.view_as_real(out))
+    # and so do the chunked orders, whose second sweeps skip the tiles the
+    # pruning bits of their own chunk mark (one stream, and pipelined)
+    for cb, w in ((2, 0), (2, 2), (5, 4)):
+        out2.fill_(float("nan"))
+        tpd.decompose_tuned(H, out2, db=4, grid_per_cu=8, chunk_bits=cb, chunk_window=w)
+        assert torch.equal(torch.view_as_real(out2), torch.view_as_real(out)), (cb, w)
     plan.close()
 
 
@@ -493,6 +499,19 @@ def test_n14_dense_every_tuning_candidate(dtype, dbs):
                 B.copy_(A)
                 tpd.decompose_tuned(B, B.view(-1), db=db, grid_per_cu=g, layout="matrix", rotate=rot)
                 assert torch.equal(torch.view_as_real(B), torch.view_as_real(ref_mat)), ("matrix", db, g, rot)
+    # the chunked orders (2^cb d-groups per chunk, from the smallest chunk to
+    # two chunks), on one stream and pipelined over two streams with 2 or 4
+    # chunks between their sweeps
+    for db in dbs:
+        for cb in sorted({1, 4, n - db - 1}):
+            for w in (0, 2, 4):
+                out.fill_(float("nan"))
+                tpd.decompose_tuned(A, out, db=db, grid_per_cu=8, chunk_bits=cb, chunk_window=w)
+                assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref_can)), ("canonical", db, cb, w)
+                B.copy_(A)
+                tpd.decompose_tuned(B, B.view(-1), db=db, grid_per_cu=8, layout="matrix", chunk_bits=cb,
+                                    chunk_window=w)
+                assert torch.equal(torch.view_as_real(B), torch.view_as_real(ref_mat)), ("matrix", db, cb, w)
     del A, B, ref_can, ref_mat, out
     torch.cuda.empty_cache()
 

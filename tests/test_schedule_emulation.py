@@ -238,6 +238,32 @@ def test_chunked_order_is_bitwise_the_same(n):
             tpd.emulate(A, flags=tpd.FLAG_HERMITIAN, db=db, r=4, chunk_bits=1)
 
 
+@pytest.mark.parametrize("n", [9, 10])
+def test_pipelined_chunks_are_disjoint_and_bitwise_the_same(n):
+    # the pipelined chunk order replayed with sweep 1 running window - 1
+    # chunks ahead of sweep 2; the emulator also fails if any element is
+    # touched by two chunks, which is what lets the two device streams
+    # overlap their launches
+    A = W.gaussian(n, seed=1400 + n)
+    ref = O.tpd_recursive(A)
+    H = W.dense_from_terms(W.heisenberg_terms(n, seed=1500 + n, n_local=20, dyadic=True), n)
+    href = O.tpd_recursive(H)
+    db = 4
+    for cb in (1, n - db - 2):
+        for w in (2, 3, 8):
+            assert same_bits(tpd.emulate(A, db=db, r=4, chunk_bits=cb, chunk_window=w), ref), (cb, w)
+            got = tpd.emulate(A, flags=tpd.FLAG_LAYOUT_MATRIX, in_place=True, db=db, r=4, chunk_bits=cb,
+                              chunk_window=w)
+            assert same_bits(matrix_to_canonical(got, n), ref), (cb, w)
+            got = tpd.emulate(H, flags=tpd.FLAG_LAYOUT_MATRIX, in_place=True, db=db, r=4, chunk_bits=cb,
+                              chunk_window=w)
+            assert same_bits(matrix_to_canonical(got, n), href), (cb, w)
+    for bad in ({"chunk_bits": 1, "chunk_window": 1}, {"chunk_bits": 1, "chunk_window": 9},
+                {"chunk_bits": 0, "chunk_window": 2}):
+        with pytest.raises(tpd.TPDError):
+            tpd.emulate(A, db=db, r=4, **bad)
+
+
 def _structured_cases():
     # Hermitian inputs with zero cumulative matrix weights: the transverse-
     # field Ising chain (section "Results") and a dyadic Heisenberg chain
