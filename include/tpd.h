@@ -139,6 +139,26 @@ tpd_status_t tpd_decompose(const void* A, int n, void* coeffs, tpd_stream_t stre
 tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                               tpd_stream_t stream);
 
+/* Hermitian A, real weights (section "Preliminaries": the weights of a
+ * Hermitian matrix are real; TPD_FLAG_HERMITIAN above for the schedule).
+ * The weights go to a separate array of real values in canonical order:
+ * weights[q] = w_q (binary64 for TPD_C128, binary32 for TPD_C64), 4^n x
+ * 8 (4) bytes, half the bytes of a complex output.  A is overwritten: the
+ * first sweep works in place in it (matrix layout, representatives only),
+ * the second reads it and writes only the weights, so the second sweep
+ * stores half the bytes of the complex Hermitian mode.  The values are
+ * bitwise the real parts of tpd_decompose_ex with TPD_FLAG_HERMITIAN.
+ *   A       [in/out] device, 2^n x 2^n TPD_C128 or TPD_C64, row-major,
+ *                    Hermitian (results undefined otherwise); destroyed
+ *   weights [out]    device, 4^n reals; must not overlap A
+ *   flags   [in]     0 or TPD_FLAG_NO_PRUNE
+ * Other dtypes or flags, misaligned or overlapping buffers:
+ * TPD_ERROR_INVALID_VALUE; n out of range: TPD_ERROR_UNSUPPORTED.  n <= 8
+ * runs one sweep from A (not modified) into the weights.  Uses the
+ * per-(device, stream) pruning workspace as tpd_decompose_ex.            */
+tpd_status_t tpd_decompose_hermitian_real(void* A, int n, void* weights, tpd_dtype_t dtype, unsigned flags,
+                                          tpd_stream_t stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * decomposition as tpd_decompose_ex, with the same arguments, errors and
@@ -377,6 +397,10 @@ tpd_status_t tpd_debug_emulate_partial(const void* A, int n, void* coeffs, const
                                        void* values, tpd_dtype_t dtype, unsigned flags, int in_place);
 tpd_status_t tpd_debug_emulate_compact(const void* coeffs, int n, tpd_dtype_t dtype, unsigned flags, double tol,
                                        uint64_t* q_out, void* w_out, uint64_t capacity, uint64_t* count);
+
+/* Host replay of tpd_decompose_hermitian_real (HOST pointers, n <= 12; A
+ * is overwritten as on the device).                                       */
+tpd_status_t tpd_debug_emulate_hermitian_real(void* A, int n, void* weights, tpd_dtype_t dtype, unsigned flags);
 
 /* Host replay of the synthesis schedule (HOST pointers, small n). */
 tpd_status_t tpd_debug_emulate_synth(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,

@@ -77,6 +77,9 @@ struct Schedule {
   // caller's, so the GPU never drains between the launches of a chunk; 0:
   // both sweeps of one chunk, then the next, on the caller's stream
   int chunk_window = 0;
+  // Hermitian input, real weights in a separate array (L_CANR): sweep 1 in
+  // place in the matrix buffer, the last sweep from it into the weights
+  bool real_out = false;
 };
 constexpr int kMaxWindow = 8;
 
@@ -248,6 +251,27 @@ tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Sched
   return make_schedule_with(n, dt, flags, in_place, nullptr, s);
 }
 
+// Hermitian matrix -> real weights: the in-place Hermitian schedule of the
+// matrix layout (its tuned choices), whose last sweep stores into the
+// separate real array in canonical order instead of back into the matrix.
+tpd_status_t make_real_out_schedule(int n, Dtype dt, unsigned flags, Schedule* s) {
+  if (dt != DT_C128 && dt != DT_C64) return TPD_ERROR_INVALID_VALUE;
+  tpd_status_t st =
+      make_schedule_with(n, dt, flags | TPD_FLAG_HERMITIAN | TPD_FLAG_LAYOUT_MATRIX, true, nullptr, s);
+  if (st) return st;
+  s->real_out = true;
+  s->in_place = false;
+  s->matrix_layout = false;
+  s->chunk_bits = 0;
+  s->chunk_window = 0;
+  if (s->nsweep >= 1) {
+    SweepDesc& w = s->sw[s->nsweep - 1];
+    w.out_layout = L_CANR;
+    if (!sweep_supported(dt, w)) return TPD_ERROR_INTERNAL;
+  }
+  return TPD_SUCCESS;
+}
+
 // partial decomposition: the same sweeps, the second one always checking
 // its tile bitmap (requests, ANDed with the live tiles when pruning)
 tpd_status_t make_partial_schedule(int n, Dtype dt, unsigned flags, bool in_place, const Tuned* force,
@@ -371,7 +395,9 @@ void save_tune_entry(const TuneKey& k, const Tuned& t) {
     << t.chunk << " " << t.window << "\n";
 }
 
-const char* layout_name(int l) { return l == L_MAT ? "MAT" : (l == L_CAN ? "CAN" : "MID"); }
+const char* layout_name(int l) {
+  return l == L_MAT ? "MAT" : (l == L_CAN ? "CAN" : (l == L_CANR ? "CANR" : "MID"));
+}
 
 std::string describe(const Schedule& s) {
   char buf[512];
@@ -381,12 +407,12 @@ std::string describe(const Schedule& s) {
   std::snprintf(buf, sizeof buf,
                 "{\"n\":%d,\"dtype\":\"%s\",\"layout\":\"%s\",\"in_place\":%s,\"prune\":%s,"
                 "\"hermitian\":%s,\"elements\":%llu,\"algorithmic_bytes\":%llu,\"bitmap_words\":%llu,"
-                "\"chunk_bits\":%d,\"chunk_window\":%d,\"sweeps\":[",
+                "\"chunk_bits\":%d,\"chunk_window\":%d,\"real_weights\":%s,\"sweeps\":[",
                 s.n, dtype_name(s.dt), s.matrix_layout ? "matrix" : "canonical",
                 s.in_place ? "true" : "false", s.prune ? "true" : "false",
                 (s.nsweep == 2 && s.sw[0].herm) ? "true" : "false", (unsigned long long)count,
                 (unsigned long long)(2 * count * eb), (unsigned long long)s.bitmap_words, s.chunk_bits,
-                s.chunk_window);
+                s.chunk_window, s.real_out ? "true" : "false");
   j += buf;
   for (int i = 0; i < s.nsweep; ++i) {
     const SweepDesc& w = s.sw[i];
@@ -657,12 +683,12 @@ struct Timing {
 // ---------------------------------------------------------------------------
 // single-matrix execution
 // ---------------------------------------------------------------------------
-tpd_status_t launch_sweep_i(const Schedule& s, int i, const void* A, void* C, uint32_t* bitmap,
-                            const uint32_t* req, hipStream_t st, int64_t chunk = -1) {
+tpd_status_t launch_sweep_io(const Schedule& s, int i, const void* in, void* out, uint32_t* bitmap,
+                             const uint32_t* req, hipStream_t st, int64_t chunk = -1) {
   const SweepDesc& w = s.sw[i];
   SweepArgs a{};
-  a.in = (i == 0) ? A : C;
-  a.out = C;
+  a.in = in;
+  a.out = out;
   a.n = s.n;
   a.xlo = w.xlo;
   a.db = w.db;
@@ -686,6 +712,30 @@ tpd_status_t launch_sweep_i(const Schedule& s, int i, const void* A, void* C, ui
   if (e != hipSuccess) {
     logf("sweep %d launch failed: %s", i, hipGetErrorString(e));
     return TPD_ERROR_LAUNCH;
+  }
+  return TPD_SUCCESS;
+}
+
+// sweep i of a schedule that reads A, then works in C
+tpd_status_t launch_sweep_i(const Schedule& s, int i, const void* A, void* C, uint32_t* bitmap,
+                            const uint32_t* req, hipStream_t st, int64_t chunk = -1) {
+  return launch_sweep_io(s, i, i == 0 ? A : C, C, bitmap, req, st, chunk);
+}
+
+// Hermitian matrix -> real weights (make_real_out_schedule): the first sweep
+// in place in A, the last from A into W; n = 0 copies the real part.
+tpd_status_t run_real_out(const Schedule& s, void* A, void* W, uint32_t* bitmap, hipStream_t st, Timing* tm) {
+  const size_t eb = elem_bytes(s.dt);
+  if (s.n == 0)
+    return hipMemcpyAsync(W, A, eb / 2, hipMemcpyDeviceToDevice, st) == hipSuccess ? TPD_SUCCESS : TPD_ERROR_LAUNCH;
+  if (s.prune && s.nsweep == 2 && launch_fill_u32(bitmap, s.bitmap_words, 0u, st) != hipSuccess)
+    return TPD_ERROR_LAUNCH;
+  for (int i = 0; i < s.nsweep; ++i) {
+    const bool last = i == s.nsweep - 1;
+    const int slot = tm ? tm->begin(i, st) : -1;
+    const tpd_status_t e = launch_sweep_io(s, i, A, last ? W : A, bitmap, nullptr, st);
+    if (tm) tm->end(i, slot, st);
+    if (e) return e;
   }
   return TPD_SUCCESS;
 }
@@ -1101,6 +1151,41 @@ tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dt
   }
   logf("decompose n=%d %s", n, describe(s).c_str());
   return run_schedule(s, A, coeffs, bm, hs, nullptr, pipe);
+}
+
+tpd_status_t tpd_decompose_hermitian_real(void* A, int n, void* weights, tpd_dtype_t dtype, unsigned flags,
+                                          tpd_stream_t stream) {
+  if (dtype != TPD_C128 && dtype != TPD_C64) return TPD_ERROR_INVALID_VALUE;
+  if (flags & ~TPD_FLAG_NO_PRUNE) return TPD_ERROR_INVALID_VALUE;
+  if (n < 0 || n > max_qubits((Dtype)dtype)) return TPD_ERROR_UNSUPPORTED;
+  if (!A || !weights) return TPD_ERROR_INVALID_VALUE;
+  const Dtype dt = (Dtype)dtype;
+  const size_t eb = elem_bytes(dt);
+  if (((uintptr_t)A % eb) || ((uintptr_t)weights % (eb / 2))) return TPD_ERROR_INVALID_VALUE;
+  {
+    const uint64_t count = (uint64_t)1 << (2 * n);
+    const uintptr_t a0 = (uintptr_t)A, w0 = (uintptr_t)weights;
+    if (a0 < w0 + count * (eb / 2) && w0 < a0 + count * eb) return TPD_ERROR_INVALID_VALUE;
+  }
+  Schedule s;
+  tpd_status_t st = make_real_out_schedule(n, dt, flags, &s);
+  if (st) return st;
+  int dev;
+  st = current_device(&dev);
+  if (st) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  uint32_t* bm = nullptr;
+  // held until the kernels are enqueued (see tpd_decompose_ex)
+  std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
+  if (s.prune && s.nsweep == 2) {
+    lk.lock();
+    Workspace& w = g_ws[{dev, hs}];
+    st = ensure_bitmap(w, s.bitmap_words);
+    if (st) return st;
+    bm = w.bitmap;
+  }
+  logf("decompose hermitian real n=%d %s", n, describe(s).c_str());
+  return run_real_out(s, A, weights, bm, hs, nullptr);
 }
 
 tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,
@@ -1530,6 +1615,21 @@ tpd_status_t host_schedule(int n, int dtype, unsigned flags, bool in_place, cons
   *bitmap_words = s.bitmap_words;
   *chunk_bits = s.chunk_bits;
   *chunk_window = s.chunk_window;
+  return TPD_SUCCESS;
+}
+
+tpd_status_t host_real_out_schedule(int n, int dtype, unsigned flags, SweepDesc* sw, int* nsweep, int* n1,
+                                    uint64_t* bitmap_words, int* prune) {
+  if (dtype != TPD_C128 && dtype != TPD_C64) return TPD_ERROR_INVALID_VALUE;
+  if (flags & ~TPD_FLAG_NO_PRUNE) return TPD_ERROR_INVALID_VALUE;
+  Schedule s;
+  tpd_status_t st = make_real_out_schedule(n, (Dtype)dtype, flags, &s);
+  if (st) return st;
+  for (int i = 0; i < s.nsweep; ++i) sw[i] = s.sw[i];
+  *nsweep = s.nsweep;
+  *n1 = s.n1;
+  *bitmap_words = s.bitmap_words;
+  *prune = s.prune ? 1 : 0;
   return TPD_SUCCESS;
 }
 

@@ -40,7 +40,9 @@
 
 namespace tpd {
 
-enum Layout : int { L_MAT = 0, L_CAN = 1, L_MID = 2 };
+// L_CANR: the canonical order of L_CAN in an array of real values (the
+// weights of a Hermitian matrix are real; only their real parts are stored)
+enum Layout : int { L_MAT = 0, L_CAN = 1, L_MID = 2, L_CANR = 3 };
 
 // spread the low 16 bits of v to the even bit positions
 TPD_HD uint32_t spread16(uint32_t v) {
@@ -59,7 +61,7 @@ template <int L>
 TPD_HD uint64_t layout_addr(uint64_t x, uint64_t d, int n, int db) {
   if constexpr (L == L_MAT) {
     return (x << n) | (x ^ d);
-  } else if constexpr (L == L_CAN) {
+  } else if constexpr (L == L_CAN || L == L_CANR) {
     return (spread32(x) << 1) | spread32(x ^ d);
   } else {
     const uint64_t m = ((uint64_t)1 << db) - 1;
@@ -69,7 +71,7 @@ TPD_HD uint64_t layout_addr(uint64_t x, uint64_t d, int n, int db) {
 }
 TPD_HD uint64_t layout_addr_rt(int L, uint64_t x, uint64_t d, int n, int db) {
   return L == L_MAT ? layout_addr<L_MAT>(x, d, n, db)
-                    : (L == L_CAN ? layout_addr<L_CAN>(x, d, n, db) : layout_addr<L_MID>(x, d, n, db));
+                    : ((L == L_CAN || L == L_CANR) ? layout_addr<L_CAN>(x, d, n, db) : layout_addr<L_MID>(x, d, n, db));
 }
 
 // ---------------------------------------------------------------------------

@@ -185,8 +185,13 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
               if (z.re != (S)0 || z.im != (S)0) return TPD_ERROR_INTERNAL;  // bit must have been set
             }
             // the kernel stores zeros on the mirrored rows of a Hermitian
-            // zero tile (the first sweep never wrote them)
-            if (mirrored && ao < ck.count) out[ao] = Cx<S>{(S)0, (S)0};
+            // zero tile (the first sweep never wrote them), and on every
+            // element of a separate real output
+            if constexpr (OUTL == L_CANR) {
+              if (ao < ck.count) ((S*)out)[ao] = (S)0;
+            } else if (mirrored && ao < ck.count) {
+              out[ao] = Cx<S>{(S)0, (S)0};
+            }
           }
         }
         continue;
@@ -300,7 +305,7 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
         }
     }
     // canonical-order output: one more pass through LDS into the store mapping
-    constexpr bool REMAP = OUTL == L_CAN && RL.st_ok;
+    constexpr bool REMAP = (OUTL == L_CAN || OUTL == L_CANR) && RL.st_ok;
     if (REMAP) {
       std::vector<uint8_t> seen(lds.size(), 0);
       for (uint32_t tid = 0; tid < (uint32_t)G::NT; ++tid) {
@@ -353,7 +358,8 @@ tpd_status_t emulate_sweep(const Cx<S>* in, Cx<S>* out, const SweepArgs& a, uint
         if (ad >= ck.count) return TPD_ERROR_INTERNAL;
         wset.push_back(ad);
         if (a.herm && !xlo) v[(size_t)tid * G::E + j].im = (S)0;
-        out[ad] = v[(size_t)tid * G::E + j];
+        if constexpr (OUTL == L_CANR) ((S*)out)[ad] = v[(size_t)tid * G::E + j].re;
+        else out[ad] = v[(size_t)tid * G::E + j];
       }
     }
     if (in_place) {
@@ -398,6 +404,7 @@ tpd_status_t emulate_layouts(const SweepDesc& s, const Cx<S>* in, Cx<S>* out, co
   if (s.in_layout == L_MAT && s.out_layout == L_MAT) return emulate_sweep<S, G, L_MAT, L_MAT>(in, out, a, bm, ck);
   if (s.in_layout == L_MAT && s.out_layout == L_MID) return emulate_sweep<S, G, L_MAT, L_MID>(in, out, a, bm, ck);
   if (s.in_layout == L_MID && s.out_layout == L_CAN) return emulate_sweep<S, G, L_MID, L_CAN>(in, out, a, bm, ck);
+  if (s.in_layout == L_MAT && s.out_layout == L_CANR) return emulate_sweep<S, G, L_MAT, L_CANR>(in, out, a, bm, ck);
   return TPD_ERROR_INTERNAL;
 }
 
@@ -536,7 +543,52 @@ tpd_status_t host_batch_tables(const int* ns, int count, bool in_place, unsigned
 tpd_status_t host_synth_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep);
 tpd_status_t host_partial_schedule(int n, int dtype, unsigned flags, bool in_place, SweepDesc* sw, int* nsweep,
                                    int* n1, uint64_t* bitmap_words, int* prune);
+tpd_status_t host_real_out_schedule(int n, int dtype, unsigned flags, SweepDesc* sw, int* nsweep, int* n1,
+                                    uint64_t* bitmap_words, int* prune);
 }  // namespace tpd
+
+// Host replay of tpd_decompose_hermitian_real: the first sweep in place in
+// A, the last from A into the real weights W (HOST pointers, small n).
+extern "C" tpd_status_t tpd_debug_emulate_hermitian_real(void* A, int n, void* W, tpd_dtype_t dtype,
+                                                         unsigned flags) {
+  if (!A || !W) return TPD_ERROR_INVALID_VALUE;
+  if (n < 0 || n > 12) return TPD_ERROR_UNSUPPORTED;
+  SweepDesc sw[2];
+  int nsweep = 0, n1 = 0, prune = 0;
+  uint64_t words = 0;
+  tpd_status_t st = host_real_out_schedule(n, dtype, flags, sw, &nsweep, &n1, &words, &prune);
+  if (st) return st;
+  const uint64_t count = (uint64_t)1 << (2 * n);
+  if (n == 0) {
+    if (dtype == TPD_C128) ((double*)W)[0] = ((const double*)A)[0];
+    else ((float*)W)[0] = ((const float*)A)[0];
+    return TPD_SUCCESS;
+  }
+  std::vector<uint32_t> bitmap(words ? words : 1, 0u);
+  for (int i = 0; i < nsweep; ++i) {
+    const bool last = i == nsweep - 1;
+    SweepArgs a{};
+    a.in = A;
+    a.out = last ? W : A;
+    a.n = n;
+    a.xlo = sw[i].xlo;
+    a.db = sw[i].db;
+    a.nfix_d = n - sw[i].db;
+    a.bitmap = bitmap.data();
+    a.bitmap_mode = sw[i].bitmap_mode;
+    a.bm_xbits = n1;
+    a.herm = sw[i].herm;
+    a.ntiles = sw[i].ntiles;
+    Checker ck(count);
+    if (dtype == TPD_C128)
+      st = emulate_shape<double>(sw[i], (const Cx<double>*)a.in, (Cx<double>*)a.out, a, bitmap.data(), ck);
+    else
+      st = TPD_IF_C64(emulate_shape<float>(sw[i], (const Cx<float>*)a.in, (Cx<float>*)a.out, a, bitmap.data(), ck));
+    if (st) return st;
+    if (!ck.complete()) return TPD_ERROR_INTERNAL;
+  }
+  return TPD_SUCCESS;
+}
 
 extern "C" tpd_status_t tpd_debug_emulate_synth(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,
                                                 int in_place) {

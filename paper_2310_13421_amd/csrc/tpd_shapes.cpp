@@ -19,6 +19,9 @@ bool supported(const SweepDesc& s, bool c128) {
   // 2^4 for the inverse); the 8- and 4-byte elements reach 2^14 (n = 17's
   // 9-level sweeps)
   const int max_xb = c128 ? 8 : 9;
+  // the separate real output (Hermitian weights): complex inputs, the matrix
+  // layout in, the default phase order
+  if (s.out_layout == L_CANR && (Elem<S>::real || s.inv || s.in_layout != L_MAT || s.order != 0)) return false;
   if (s.inv) {
     if (s.out_layout != L_MAT || (s.in_layout != L_CAN && s.in_layout != L_MAT)) return false;
     if (s.is_one) return one_shape(s.xb, s.db);

@@ -42,9 +42,12 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   constexpr bool SPLIT = sizeof(E) <= 4 && INL == L_MAT && OUTL == L_MAT && !INV && G::XB == 8 && G::DB == 6;
   __shared__ uint32_t bits[(SPLIT ? 2 : 1) * NBW];
 
+  static_assert(!(REAL && OUTL == L_CANR), "real-coded elements have no separate real output");
   const uint32_t tid = threadIdx.x;
   const E* __restrict__ in = (const E*)a.in;
   E* __restrict__ out = (E*)a.out;
+  // L_CANR: the output is a separate array of real weights
+  typename Elem<S>::scalar* __restrict__ outr = (typename Elem<S>::scalar*)a.out;
   const int n = a.n, xlo = a.xlo, db = a.db;
   const int tdb = a.chunk_bits > 0 ? a.chunk_bits : a.nfix_d;  // d-group bits of the tile index
   const uint64_t tdmask = ((uint64_t)1 << tdb) - 1;
@@ -52,7 +55,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   // Canonical-order output: the tile is passed once more through LDS so that
   // each store instruction writes 64 consecutive coefficients (whole cache
   // lines) instead of the last phase's 32-byte pieces.
-  constexpr bool REMAP = OUTL == L_CAN && RL.st_ok;
+  constexpr bool REMAP = (OUTL == L_CAN || OUTL == L_CANR) && RL.st_ok;
 
   // register-slot address deltas (layouts are XOR-linear in (x, d))
   uint64_t din[G::R], dout[G::R];
@@ -74,6 +77,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   struct Tile {
     uint64_t td, xf, xfix, hm;
     bool zero;  // Hermitian second sweep, zero tile: only its mirrored rows are stored (zeros)
+    bool zall;  // zero tile of a separate real output: every element is stored (zeros)
   };
   // tiles of this launch: all, or the entries of a work list
   const uint64_t lcount = a.list ? (uint64_t)uniform_word(a.list_count, 0) : 0;
@@ -108,6 +112,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
     // needed ("representatives"); the others follow by conjugation.
     t.hm = 0;  // 1 << m when representatives can be used, else 0
     t.zero = false;
+    t.zall = false;
     if (a.herm) {
       const int n2 = xlo ? xlo : G::XB;
       const uint64_t dlh = t.td & (((uint64_t)1 << (n2 - G::DB)) - 1);
@@ -119,7 +124,13 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
       if (!((uniform_word(a.bitmap, bit >> 5) >> (bit & 31)) & 1u)) {
         // zero subtree: the first sweep already stored its zeros, except, in
         // the Hermitian mode, on the mirrored rows it never visits; those are
-        // written here (stores only, nothing is read)
+        // written here (stores only, nothing is read).  A separate real
+        // output receives zeros on every element.
+        if constexpr (OUTL == L_CANR) {
+          t.zero = true;
+          t.zall = true;
+          return true;
+        }
         if (!(a.herm && !xlo && t.hm)) return false;
         t.zero = true;
       }
@@ -186,12 +197,13 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
 #pragma unroll
       for (int j = 0; j < G::E; ++j) {
         const uint32_t e = REMAP ? (ebo | elem_reg_st<G>(RL, j)) : (ebl | elem_reg<G>(RL, LAST, j));
-        if (!(((uint64_t)((e >> G::DB) & XM)) & hm)) continue;
+        if (!t.zall && !(((uint64_t)((e >> G::DB) & XM)) & hm)) continue;
         uint64_t ad = base;
 #pragma unroll
         for (int s = 0; s < G::R; ++s)
           if ((j >> s) & 1) ad ^= dout[s];
-        out[ad] = E{};
+        if constexpr (OUTL == L_CANR) outr[ad] = (typename Elem<S>::scalar)0;
+        else out[ad] = E{};
       }
       return;
     }
@@ -350,7 +362,8 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
         } else if constexpr (!REAL) {
           if (real_out) v[j].im = (typename Elem<S>::scalar)0;
         }
-        out[ad] = v[j];
+        if constexpr (OUTL == L_CANR) outr[ad] = v[j].re;
+        else out[ad] = v[j];
       }
     }
   };
@@ -427,6 +440,8 @@ hipError_t dispatch_one(const SweepDesc& s, const SweepArgs& a, hipStream_t st) 
   if (s.xb == XB_ && s.db == DB_) {                                                                  \
     if (s.out_layout == L_CAN) return launch_one<S, XB_, DB_, 0, L_MAT, L_CAN, 4>(a, s.grid, st);    \
     if (s.out_layout == L_MAT) return launch_one<S, XB_, DB_, 0, L_MAT, L_MAT, 4>(a, s.grid, st);    \
+    if constexpr (!Elem<S>::real)                                                                    \
+      if (s.out_layout == L_CANR) return launch_one<S, XB_, DB_, 0, L_MAT, L_CANR, 4>(a, s.grid, st); \
   }
   TPD_ONE_SHAPES(TPD_CASE)
 #undef TPD_CASE
@@ -441,6 +456,8 @@ hipError_t dispatch_two_layouts(const SweepDesc& s, const SweepArgs& a, hipStrea
   if (s.in_layout == L_MAT && s.out_layout == L_MID) return launch_one<S, XB, DB, 0, L_MAT, L_MID, RR>(a, s.grid, st);
   if (s.in_layout == L_MID && s.out_layout == L_CAN) return launch_one<S, XB, DB, 0, L_MID, L_CAN, RR>(a, s.grid, st);
   if (s.in_layout == L_MAT && s.out_layout == L_MAT) return launch_one<S, XB, DB, 0, L_MAT, L_MAT, RR>(a, s.grid, st);
+  if constexpr (!Elem<S>::real)  // Hermitian second sweep into a separate real output
+    if (s.in_layout == L_MAT && s.out_layout == L_CANR) return launch_one<S, XB, DB, 0, L_MAT, L_CANR, RR>(a, s.grid, st);
   return hipErrorInvalidValue;
 }
 template <class S, int XB, int DB>

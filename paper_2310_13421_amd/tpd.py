@@ -49,6 +49,7 @@ _SIGS = {
     "tpd_decompose": (_I, [_P, _I, _P, _P]),
     "tpd_decompose_ex": (_I, [_P, _I, _P, _I, _U, _P]),
     "tpd_decompose_noalloc": (_I, [_P, _I, _P, _I, _U, _P]),
+    "tpd_decompose_hermitian_real": (_I, [_P, _I, _P, _I, _U, _P]),
     "tpd_decompose_batched": (_I, [_P, _P, _I, _P, _I, _U, _P]),
     "tpd_plan_create": (_I, [_I, _I, _U, _I, _P]),
     "tpd_plan_create_batched": (_I, [_P, _I, _I, _U, _I, _P]),
@@ -63,6 +64,7 @@ _SIGS = {
     "tpd_autotune": (_I, [_P, _I, _P, _I, _U, _P, ctypes.c_char_p, _SZ]),
     "tpd_autotune_batched": (_I, [_P, _P, _P, _P, ctypes.c_char_p, _SZ]),
     "tpd_debug_emulate_tuned": (_I, [_P, _I, _P, _I, _U, _I, _I, _I, _I, _I]),
+    "tpd_debug_emulate_hermitian_real": (_I, [_P, _I, _P, _I, _U]),
     "tpd_synthesize_ex": (_I, [_P, _I, _P, _I, _U, _P]),
     "tpd_debug_emulate_synth": (_I, [_P, _I, _P, _I, _U, _I]),
     "tpd_status_string": (ctypes.c_char_p, [_I]),
@@ -151,6 +153,17 @@ def _np_dtype(dtype: int):
     if dtype not in (TPD_C128, TPD_C64):
         raise TPDError(2, "the host replays cover the complex dtypes only")
     return np.complex128 if dtype == TPD_C128 else np.complex64
+
+
+def emulate_hermitian_real(A: np.ndarray, dtype: int = TPD_C128, prune: bool = True) -> np.ndarray:
+    """Host replay of decompose_hermitian_real (A is copied, not modified):
+    the real weights in canonical order."""
+    work = np.ascontiguousarray(A, dtype=_np_dtype(dtype)).copy()
+    n = work.shape[0].bit_length() - 1
+    out = np.full(work.size, np.nan, np.float64 if dtype == TPD_C128 else np.float32)  # poison
+    _check(lib.tpd_debug_emulate_hermitian_real(work.ctypes.data, n, out.ctypes.data, dtype,
+                                                0 if prune else FLAG_NO_PRUNE), "tpd_debug_emulate_hermitian_real")
+    return out
 
 
 def emulate(A: np.ndarray, dtype: int = TPD_C128, flags: int = 0, in_place: bool = False, db: int = 0,
@@ -324,6 +337,26 @@ def decompose_noalloc(A, out, *, layout: str = "canonical", prune: bool = True, 
     _check(lib.tpd_decompose_noalloc(A.data_ptr(), n, out.data_ptr(), _dtype_code(A),
                                      _flags(layout, prune, False, hermitian), _stream(stream)),
            "tpd_decompose_noalloc")
+    return out
+
+
+def decompose_hermitian_real(A, out=None, *, prune: bool = True, stream=None):
+    """Real weights of a Hermitian A (complex128 or complex64 CUDA tensor)
+    in a separate real tensor (float64 / float32, 4^n, canonical order)
+    through tpd_decompose_hermitian_real.  A is destroyed (the first sweep
+    works in place in it) for n >= 9."""
+    torch = _torch()
+    n = _check_matrix(A)
+    if A.dtype not in (torch.complex128, torch.complex64):
+        raise ValueError("A must be complex128 or complex64")
+    rdt = torch.float64 if A.dtype == torch.complex128 else torch.float32
+    if out is None:
+        out = torch.empty(4 ** n, dtype=rdt, device=A.device)
+    if out.dtype != rdt or not out.is_cuda or not out.is_contiguous() or out.numel() != 4 ** n:
+        raise ValueError("out must be a contiguous CUDA tensor of 4^n real values of A's precision")
+    _check(lib.tpd_decompose_hermitian_real(A.data_ptr(), n, out.data_ptr(), _dtype_code(A),
+                                            0 if prune else FLAG_NO_PRUNE, _stream(stream)),
+           "tpd_decompose_hermitian_real")
     return out
 
 

@@ -93,6 +93,22 @@ def test_decompose_validation_before_device(args, code):
     assert tpd.lib.tpd_decompose_noalloc(A, n, C, dt, fl, None) == code
 
 
+def test_hermitian_real_validation_before_device():
+    H = tpd.lib.tpd_decompose_hermitian_real
+    assert H(None, 4, FAKE * 4, 0, 0, None) == 1                 # NULL A
+    assert H(FAKE, 4, None, 0, 0, None) == 1                     # NULL weights
+    assert H(FAKE, 4, FAKE * 4, 2, 0, None) == 1                 # real dtypes have no such mode
+    assert H(FAKE, 4, FAKE * 4, 3, 0, None) == 1
+    assert H(FAKE, 4, FAKE * 4, 0, tpd.FLAG_HERMITIAN, None) == 1  # only TPD_FLAG_NO_PRUNE
+    assert H(FAKE, 4, FAKE * 4, 0, tpd.FLAG_LAYOUT_MATRIX, None) == 1
+    assert H(FAKE + 8, 4, FAKE * 4, 0, 0, None) == 1             # misaligned complex128 matrix
+    assert H(FAKE, 4, FAKE * 4 + 4, 0, 0, None) == 1             # misaligned binary64 weights
+    assert H(FAKE, 4, FAKE + 4096 - 8, 0, 0, None) == 1          # weights overlap the matrix's end
+    assert H(FAKE, 4, FAKE - 2048 + 8, 0, 0, None) == 1          # matrix starts inside the weights
+    assert H(FAKE, 17, FAKE * 64, 0, 0, None) == 2               # n too large
+    assert H(FAKE, -1, FAKE * 4, 0, 0, None) == 2
+
+
 def test_noalloc_rejects_timing_flag():
     assert tpd.lib.tpd_decompose_noalloc(FAKE, 4, FAKE * 4, 0, tpd.FLAG_TIMING, None) == 1
 

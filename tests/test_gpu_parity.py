@@ -1185,8 +1185,63 @@ def test_hermitian_mode_structured_input_with_pruning(case):
         T = Hd.clone()
         tpd.decompose(T, T.view(-1), hermitian=True, layout="matrix")
         assert _exactly(_dev_matrix_to_canonical(T.view(-1), n), exp), (case, dtype, "in place")
-        del Hd, gen, exp, T
+        # real weights into a separate NaN-poisoned array: zero tiles store
+        # zeros on every weight
+        T.copy_(Hd)
+        rdt = torch.float64 if dtype == torch.complex128 else torch.float32
+        w = torch.full((4 ** n,), float("nan"), dtype=rdt, device=DEV)
+        tpd.decompose_hermitian_real(T, w)
+        assert _exactly(w, exp.real.contiguous()), (case, dtype, "real weights")
+        del Hd, gen, exp, T, w
     del H
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_hermitian_real_weights_vs_complex_mode(dtype):
+    # tpd_decompose_hermitian_real for n = 0..12: the real weights, written
+    # into a NaN-poisoned array, are bitwise the real parts of the complex
+    # Hermitian mode (complex128: of Algorithm 1 for n <= 10); with and
+    # without pruning; the matrix is destroyed for n >= 9 only
+    rdt = torch.float64 if dtype == torch.complex128 else torch.float32
+    for n in range(0, 13):
+        A = W.gaussian(n, seed=1700 + n, hermitian=True)
+        Ad = to_dev(A, dtype)
+        ref = tpd.decompose(Ad, hermitian=True)
+        for prune in (True, False):
+            B = Ad.clone()
+            w = torch.full((4 ** n,), float("nan"), dtype=rdt, device=DEV)
+            tpd.decompose_hermitian_real(B, w, prune=prune)
+            assert torch.equal(w, ref.real.contiguous()), (n, prune)
+            if n <= 8:
+                assert torch.equal(torch.view_as_real(B), torch.view_as_real(Ad)), n  # one sweep: A unchanged
+        if dtype == torch.complex128 and n <= 10:
+            assert same_bits(w.cpu().numpy(), O.tpd_recursive(A).real), n
+
+
+def test_hermitian_real_weights_n16_full_size():
+    # the n = 16 headline matrix: sampled weights against the definition, and
+    # 10^5 sampled weights bitwise against the complex Hermitian mode in place
+    n = 16
+    torch.cuda.empty_cache()
+    A = W.gaussian_device(n, seed=5, hermitian=True)
+    a_max = float(torch.view_as_real(A).abs().max())
+    qs = W.sampled_strings(n, 2000, seed=161)
+    bf = sampled_oracle(A, n, qs)
+    B = A.clone()
+    w = torch.full((4 ** n,), float("nan"), dtype=torch.float64, device=DEV)
+    tpd.decompose_hermitian_real(B, w)
+    del B
+    torch.cuda.empty_cache()
+    got = w[torch.from_numpy(qs.astype(np.int64)).to(DEV)].cpu().numpy()
+    assert np.max(np.abs(got - bf.real)) <= n * U64 * a_max
+    assert not torch.isnan(w).any()
+    tpd.decompose(A, A.view(-1), hermitian=True, layout="matrix")
+    qs2 = W.sampled_strings(n, 100000, seed=162).astype(np.int64)
+    h, l = deinterleave(qs2)
+    ref = A[torch.from_numpy(h).to(DEV), torch.from_numpy(l).to(DEV)].real
+    assert torch.equal(w[torch.from_numpy(qs2).to(DEV)], ref)
+    del A, w
     torch.cuda.empty_cache()
 
 

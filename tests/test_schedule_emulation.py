@@ -298,6 +298,48 @@ def test_emulated_hermitian_mode_with_pruned_tiles(case):
             assert same_bits(got, expect.astype(got.dtype)), (dt, db)
 
 
+@pytest.mark.parametrize("n", [0, 1, 4, 8, 9, 10])
+def test_emulated_hermitian_real_weights(n):
+    # tpd_decompose_hermitian_real replayed: real weights in a separate,
+    # NaN-poisoned array (every weight must be written), bitwise the real
+    # parts of the complex Hermitian mode and of Algorithm 1 (complex128)
+    A = W.gaussian(n, seed=1600 + n, hermitian=True)
+    ref = O.tpd_recursive(A)
+    for dt in (tpd.TPD_C128, tpd.TPD_C64):
+        Ad = A if dt == tpd.TPD_C128 else A.astype(np.complex64)
+        got = tpd.emulate_hermitian_real(Ad, dt)
+        assert got.dtype == (np.float64 if dt == tpd.TPD_C128 else np.float32)
+        cplx = tpd.emulate(Ad, dt, tpd.FLAG_HERMITIAN)
+        assert same_bits(got, cplx.real), dt
+        if dt == tpd.TPD_C128:
+            assert same_bits(got, ref.real)
+        assert same_bits(tpd.emulate_hermitian_real(Ad, dt, prune=False), got), dt
+
+
+@pytest.mark.parametrize("case", [c[0] for c in _structured_cases()])
+def test_emulated_hermitian_real_weights_with_pruned_tiles(case):
+    # zero second-sweep tiles store zeros on every weight of the separate
+    # output (nothing of it was written before)
+    _, n, terms = next(c for c in _structured_cases() if c[0] == case)
+    H = W.dense_from_terms(terms, n)
+    expect = np.zeros(4 ** n)
+    for s, c in terms:
+        expect[W.string_index(s)] += c.real
+    for dt in (tpd.TPD_C128, tpd.TPD_C64):
+        got = tpd.emulate_hermitian_real(H.astype(np.complex64) if dt == tpd.TPD_C64 else H, dt)
+        assert same_bits(got, expect.astype(got.dtype)), dt
+
+
+def test_emulated_hermitian_real_weights_rejects_other_dtypes_and_flags():
+    A = W.gaussian(9, seed=1, hermitian=True)
+    with pytest.raises(tpd.TPDError):
+        tpd.emulate_hermitian_real(A.real.copy(), tpd.TPD_R64)
+    work = A.copy()
+    out = np.zeros(4 ** 9)
+    for fl in (tpd.FLAG_HERMITIAN, tpd.FLAG_LAYOUT_MATRIX, tpd.FLAG_TIMING):
+        assert tpd.lib.tpd_debug_emulate_hermitian_real(work.ctypes.data, 9, out.ctypes.data, tpd.TPD_C128, fl) == 1
+
+
 def synth_bound(w, n, u):
     # each output component is a sum of 2^n weight components taken with
     # sign +-1: the level tree rounds <= n u 2^n max|w| and the oracle's
