@@ -339,6 +339,39 @@ def inplace_steps(tpd, torch, A0, B, n, dtype_code, steps, warmup, hermitian=Fal
     return times, avgs, cnt, desc, tuned
 
 
+def real_weights_run(tpd, torch, W, A0, B, n, steps, warmup, ms_complex_mode, ms_general):
+    """Real weights of the Hermitian A0 into a separate real array
+    (tpd_decompose_hermitian_real): B, holding the complex Hermitian mode's
+    weights in the matrix layout, gives the reference on 10^5 sampled
+    strings, then serves as the first sweep's workspace (restored from A0
+    before each step, untimed)."""
+    import numpy as np
+
+    qs = torch.from_numpy(W.sampled_strings(n, 100000, seed=163).astype(np.int64))
+    h, l = deinterleave(qs.numpy())
+    ref = B[torch.from_numpy(h).to("cuda"), torch.from_numpy(l).to("cuda")].real.clone()
+    rdt = torch.float64 if A0.dtype == torch.complex128 else torch.float32
+    out = torch.empty(4 ** n, dtype=rdt, device="cuda")
+    ts = []
+    for step in range(warmup + steps):
+        B.copy_(A0)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        tpd.decompose_hermitian_real(B, out)
+        e1.record()
+        torch.cuda.synchronize()
+        if step >= warmup:
+            ts.append(e0.elapsed_time(e1))
+    ms = sum(ts) / len(ts)
+    same = bool(torch.equal(out[qs.to("cuda")], ref))
+    del out, ref
+    return {"ms_per_step": ms, "ms_min": min(ts), "coeffs_per_s": 4 ** n / (ms / 1e3),
+            "speedup_vs_complex_hermitian_mode": ms_complex_mode / ms, "speedup_vs_c128_general": ms_general / ms,
+            "bitwise_equal_to_complex_mode_real_parts_on_samples": same, "samples": int(qs.numel())}
+
+
 def inplace_run(tpd, torch, A0, n, dtype_code, steps, warmup, esize, hermitian=False):
     """In-place decomposition (matrix layout) of a copy of A0 on one buffer;
     returns (result dict, the buffer holding the last step's weights)."""
@@ -711,6 +744,9 @@ def main():
                 r, B32 = inplace_run(tpd, torch, A32, n, tpd.TPD_C64, args.steps, args.warmup, 8, hermitian=True)
                 r["speedup_vs_c128_general"] = ms_step / r["ms_per_step"]
                 result["hermitian_c64"] = r
+                log("extra: Hermitian real weights into a separate float32 array, complex64")
+                result["hermitian_c64_real_weights"] = real_weights_run(tpd, torch, W, A32, B32, n, args.steps,
+                                                                        args.warmup, r["ms_per_step"], ms_step)
                 del B32
                 torch.cuda.empty_cache()
             if "outofplace" in extras:
@@ -768,36 +804,10 @@ def main():
             r, B = inplace_run(tpd, torch, A, n, tpd.TPD_C128, args.steps, args.warmup, 16, hermitian=True)
             r["speedup_vs_general"] = ms_step / r["ms_per_step"]
             result["hermitian_c128"] = r
-            # real weights into a separate float64 array: the matrix buffer is
-            # the first sweep's workspace (restored before each step, untimed),
-            # the second sweep writes 8 instead of 16 bytes per weight
             log("extra: Hermitian real weights into a separate float64 array, complex128")
-            qs_r = torch.from_numpy(W.sampled_strings(n, 100000, seed=163).astype(np.int64))
-            h_r, l_r = deinterleave(qs_r.numpy())
-            ref_r = B[torch.from_numpy(h_r).to("cuda"), torch.from_numpy(l_r).to("cuda")].real.clone()
-            Wt = torch.empty(4 ** n, dtype=torch.float64, device="cuda")
-            ts = []
-            for step in range(args.warmup + args.steps):
-                B.copy_(A)
-                torch.cuda.synchronize()
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-                tpd.decompose_hermitian_real(B, Wt)
-                e1.record()
-                torch.cuda.synchronize()
-                if step >= args.warmup:
-                    ts.append(e0.elapsed_time(e1))
-            ms_r = sum(ts) / len(ts)
-            result["hermitian_c128_real_weights"] = {
-                "ms_per_step": ms_r, "ms_min": min(ts), "coeffs_per_s": 4 ** n / (ms_r / 1e3),
-                "speedup_vs_complex_hermitian_mode": r["ms_per_step"] / ms_r,
-                "speedup_vs_general": ms_step / ms_r,
-                "bitwise_equal_to_complex_mode_real_parts_on_samples":
-                    bool(torch.equal(Wt[qs_r.to("cuda")], ref_r)),
-                "samples": int(qs_r.numel()),
-            }
-            del B, Wt, ref_r
+            result["hermitian_c128_real_weights"] = real_weights_run(tpd, torch, W, A, B, n, args.steps,
+                                                                     args.warmup, r["ms_per_step"], ms_step)
+            del B
             torch.cuda.empty_cache()
         if "outofplace" in extras:
             log("extra: out of place, canonical order, complex128")
