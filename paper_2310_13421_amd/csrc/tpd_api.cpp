@@ -2,6 +2,7 @@
 // workspaces, plans (graph-capturable execution), timing, and a host replay
 // of the device schedule for CPU-side testing of the index algebra.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <atomic>
@@ -20,6 +21,17 @@
 
 #include "../../include/tpd.h"
 #include "tpd_internal.h"
+
+namespace {
+// roctx range over a scope: the library's passes and entry points appear as
+// named host ranges in rocprofv3 --marker-trace (no cost without a tool)
+struct TpdRange {
+  explicit TpdRange(const char* name) { roctxRangePush(name); }
+  ~TpdRange() { roctxRangePop(); }
+  TpdRange(const TpdRange&) = delete;
+  TpdRange& operator=(const TpdRange&) = delete;
+};
+}  // namespace
 
 using namespace tpd;
 
@@ -685,6 +697,7 @@ struct Timing {
 // ---------------------------------------------------------------------------
 tpd_status_t launch_sweep_io(const Schedule& s, int i, const void* in, void* out, uint32_t* bitmap,
                              const uint32_t* req, hipStream_t st, int64_t chunk = -1) {
+  TpdRange range_("tpd sweep");
   const SweepDesc& w = s.sw[i];
   SweepArgs a{};
   a.in = in;
@@ -725,6 +738,7 @@ tpd_status_t launch_sweep_i(const Schedule& s, int i, const void* A, void* C, ui
 // Hermitian matrix -> real weights (make_real_out_schedule): the first sweep
 // in place in A, the last from A into W; n = 0 copies the real part.
 tpd_status_t run_real_out(const Schedule& s, void* A, void* W, uint32_t* bitmap, hipStream_t st, Timing* tm) {
+  TpdRange range_("tpd decompose hermitian real");
   const size_t eb = elem_bytes(s.dt);
   if (s.n == 0)
     return hipMemcpyAsync(W, A, eb / 2, hipMemcpyDeviceToDevice, st) == hipSuccess ? TPD_SUCCESS : TPD_ERROR_LAUNCH;
@@ -749,6 +763,7 @@ tpd_status_t run_real_out(const Schedule& s, void* A, void* W, uint32_t* bitmap,
 // waits for the last sweep 2 before anything queued after this call.
 tpd_status_t run_pipelined(const Schedule& s, const void* A, void* C, uint32_t* bitmap, hipStream_t st,
                            Pipe& p) {
+  TpdRange range_("tpd pipelined chunks");
   const uint64_t nchunks = (uint64_t)1 << (s.n - s.sw[0].db - s.chunk_bits);
   const uint64_t W = (uint64_t)s.chunk_window, K = W + 1;
   if (hipEventRecord(p.fork, st) != hipSuccess || hipStreamWaitEvent(p.side, p.fork, 0) != hipSuccess)
@@ -772,6 +787,7 @@ tpd_status_t run_pipelined(const Schedule& s, const void* A, void* C, uint32_t* 
 
 tpd_status_t run_schedule(const Schedule& s, const void* A, void* C, uint32_t* bitmap, hipStream_t st,
                           Timing* tm, Pipe* pipe = nullptr) {
+  TpdRange range_("tpd decompose");
   const size_t eb = elem_bytes(s.dt);
   if (s.n == 0) {
     if (A != C && hipMemcpyAsync(C, A, eb, hipMemcpyDeviceToDevice, st) != hipSuccess) return TPD_ERROR_LAUNCH;
@@ -824,6 +840,7 @@ struct PartialLists {
 tpd_status_t run_partial(const Schedule& s, const void* A, void* C, const uint64_t* req, uint64_t count,
                          void* values, uint32_t* live, uint32_t* groups, uint64_t group_words, uint32_t* tiles,
                          const PartialLists& pl, hipStream_t st) {
+  TpdRange range_("tpd decompose partial");
   if (s.nsweep == 2) {
     const int cus = g_cus > 0 ? (int)g_cus : 256;
     if (launch_fill_u32(groups, group_words + s.bitmap_words, 0u, st) != hipSuccess) return TPD_ERROR_LAUNCH;
@@ -1259,6 +1276,7 @@ tpd_status_t tpd_decompose_partial(const void* A, int n, void* coeffs, const uin
 
 tpd_status_t tpd_compact(const void* coeffs, int n, tpd_dtype_t dtype, unsigned flags, double tol, uint64_t* q_out,
                          void* w_out, uint64_t capacity, uint64_t* count, tpd_stream_t stream) {
+  TpdRange range_("tpd compact");
   tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (flags & ~TPD_FLAG_LAYOUT_MATRIX) return TPD_ERROR_INVALID_VALUE;
@@ -1424,6 +1442,7 @@ tpd_status_t tpd_plan_execute(tpd_plan_t plan, const void* A, void* coeffs, tpd_
 
 tpd_status_t tpd_plan_execute_batched(tpd_plan_t plan, const void* const* d_ptrs, void* const* d_out_ptrs,
                                       tpd_stream_t stream) {
+  TpdRange range_("tpd batched");
   if (!plan || !plan->batched) return TPD_ERROR_INVALID_VALUE;
   if (plan->count == 0) return TPD_SUCCESS;
   if (!d_ptrs) return TPD_ERROR_INVALID_VALUE;
@@ -1540,6 +1559,7 @@ tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len) {
 
 tpd_status_t tpd_decompose_batched(const void* const* ptrs, const int* ns, int count, void* const* out_ptrs,
                                    tpd_dtype_t dtype, unsigned flags, tpd_stream_t stream) {
+  TpdRange range_("tpd batched");
   tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (count < 0) return TPD_ERROR_INVALID_VALUE;
@@ -1734,6 +1754,7 @@ extern "C" tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* co
 
 extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
                                      tpd_stream_t stream, char* report, size_t len) {
+  TpdRange range_("tpd autotune");
   tpd_status_t st = check_dtype_flags(dtype, flags);
   if (st) return st;
   if (n < 0 || n > max_qubits((Dtype)dtype)) return TPD_ERROR_UNSUPPORTED;
@@ -1908,6 +1929,7 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
 
 extern "C" tpd_status_t tpd_autotune_batched(tpd_plan_t plan, const void* const* d_ptrs, void* const* d_out_ptrs,
                                              tpd_stream_t stream, char* report, size_t len) {
+  TpdRange range_("tpd autotune batched");
   if (!plan || !plan->batched || !d_ptrs) return TPD_ERROR_INVALID_VALUE;
   if (!d_out_ptrs && !plan->in_place) return TPD_ERROR_INVALID_VALUE;
   if (plan->tab.nitems == 0) return TPD_SUCCESS;

@@ -37,7 +37,7 @@ def test_host_replays_and_oracle_under_asan_and_ubsan(tmp_path):
         assert p.returncode == 0, err[-3000:]
     exe = str(tmp_path / "emulate_check")
     r = subprocess.run(["g++", *SAN, "-fopenmp", "-o", exe, *objs, "-L/opt/rocm/lib", "-lamdhip64",
-                        "-Wl,-rpath,/opt/rocm/lib"], capture_output=True, text=True, timeout=300)
+                        "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-3000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1",
                OMP_NUM_THREADS="4")
