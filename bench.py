@@ -160,8 +160,10 @@ def ingest_pair(fetch_csv, write_csv):
             dt, es = "c128", 16
         else:
             dt, es = "c64", 8
-        which = {", 0, 2, false>": 1, ", 2, 1, false>": 2, ", 0, 0, false>": 12}.get(
-            next((k for k in (", 0, 2, false>", ", 2, 1, false>", ", 0, 0, false>") if k in name), ""), 0)
+        # layout template arguments: MAT -> MID (sweep 1), MID -> CAN (sweep 2),
+        # MAT -> MAT in place (both), MAT -> real canonical weights (sweep 2)
+        sweeps = {", 0, 2, false>": 1, ", 2, 1, false>": 2, ", 0, 0, false>": 12, ", 0, 3, false>": 2}
+        which = sweeps.get(next((k for k in sweeps if k in name), ""), 0)
         if not which:
             continue  # 12: matrix layout in place, both sweeps share the symbol
         # the profiled legs split an even n into two sweeps of n/2 levels,
@@ -352,6 +354,10 @@ def real_weights_run(tpd, torch, W, A0, B, n, steps, warmup, ms_complex_mode, ms
     ref = B[torch.from_numpy(h).to("cuda"), torch.from_numpy(l).to("cuda")].real.clone()
     rdt = torch.float64 if A0.dtype == torch.complex128 else torch.float32
     out = torch.empty(4 ** n, dtype=rdt, device="cuda")
+    tuned = None
+    if TUNE:
+        B.copy_(A0)
+        tuned = tpd.autotune_hermitian_real(B, out).get("chosen")
     ts = []
     for step in range(warmup + steps):
         B.copy_(A0)
@@ -369,7 +375,8 @@ def real_weights_run(tpd, torch, W, A0, B, n, steps, warmup, ms_complex_mode, ms
     del out, ref
     return {"ms_per_step": ms, "ms_min": min(ts), "coeffs_per_s": 4 ** n / (ms / 1e3),
             "speedup_vs_complex_hermitian_mode": ms_complex_mode / ms, "speedup_vs_c128_general": ms_general / ms,
-            "bitwise_equal_to_complex_mode_real_parts_on_samples": same, "samples": int(qs.numel())}
+            "bitwise_equal_to_complex_mode_real_parts_on_samples": same, "samples": int(qs.numel()),
+            "autotuned": tuned}
 
 
 def inplace_run(tpd, torch, A0, n, dtype_code, steps, warmup, esize, hermitian=False):

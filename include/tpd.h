@@ -390,6 +390,14 @@ tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* coeffs, tpd_d
                                        int db, int r, int grid_per_cu, int chunk_bits, int chunk_window,
                                        tpd_stream_t stream);
 
+/* tpd_decompose_hermitian_real with a forced two-sweep tile width 2^db
+ * (db = 0: the tuned or default one) and grid_per_cu workgroups per CU (0 =
+ * one per tile), for tests that every schedule gives the same bits;
+ * TPD_ERROR_INVALID_VALUE for a schedule that does not exist.            */
+tpd_status_t tpd_debug_decompose_hermitian_real_tuned(void* A, int n, void* weights, tpd_dtype_t dtype,
+                                                      unsigned flags, int db, int grid_per_cu,
+                                                      tpd_stream_t stream);
+
 /* Host replays of the partial decomposition (request marking, tile skips,
  * gather) and of the compaction (same chunks, order and clipping); HOST
  * pointers, n <= 12, otherwise the arguments of the device calls.         */
@@ -397,6 +405,17 @@ tpd_status_t tpd_debug_emulate_partial(const void* A, int n, void* coeffs, const
                                        void* values, tpd_dtype_t dtype, unsigned flags, int in_place);
 tpd_status_t tpd_debug_emulate_compact(const void* coeffs, int n, tpd_dtype_t dtype, unsigned flags, double tol,
                                        uint64_t* q_out, void* w_out, uint64_t capacity, uint64_t* count);
+
+/* Autotune tpd_decompose_hermitian_real for this (n, dtype): tile widths
+ * and grids as tpd_autotune, each timed on A (transformed repeatedly:
+ * destroyed) and weights; the choice applies to later calls of the dtype
+ * and n (and, with TPD_AUTOTUNE_CACHE, of later processes).  Without a
+ * choice of its own the real-weights schedule takes the in-place Hermitian
+ * mode's.  Arguments and errors as tpd_decompose_hermitian_real; allocates
+ * a bitmap, synchronises `stream`; report/len (optional): JSON of the
+ * candidates' median times and the choice.  n <= 8 has nothing to tune.  */
+tpd_status_t tpd_autotune_hermitian_real(void* A, int n, void* weights, tpd_dtype_t dtype, unsigned flags,
+                                         tpd_stream_t stream, char* report, size_t len);
 
 /* Host replay of tpd_decompose_hermitian_real (HOST pointers, n <= 12; A
  * is overwritten as on the device).                                       */

@@ -266,10 +266,24 @@ tpd_status_t make_schedule(int n, Dtype dt, unsigned flags, bool in_place, Sched
 // Hermitian matrix -> real weights: the in-place Hermitian schedule of the
 // matrix layout (its tuned choices), whose last sweep stores into the
 // separate real array in canonical order instead of back into the matrix.
-tpd_status_t make_real_out_schedule(int n, Dtype dt, unsigned flags, Schedule* s) {
+constexpr int kRealOutKeyMatrix = 3;  // TuneKey.matrix of the real-weights schedule's entries
+
+tpd_status_t make_real_out_schedule(int n, Dtype dt, unsigned flags, Schedule* s, const Tuned* force = nullptr) {
   if (dt != DT_C128 && dt != DT_C64) return TPD_ERROR_INVALID_VALUE;
+  // the real-weights autotuner's choice, else that of the in-place
+  // Hermitian mode (make_schedule_with's own lookup)
+  Tuned tuned;
+  if (!force && n > 8) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) load_tune_cache();
+    auto it = g_tuned.find(TuneKey{n, (int)dt, kRealOutKeyMatrix, 1, 1});
+    if (it != g_tuned.end()) {
+      tuned = it->second;
+      force = &tuned;
+    }
+  }
   tpd_status_t st =
-      make_schedule_with(n, dt, flags | TPD_FLAG_HERMITIAN | TPD_FLAG_LAYOUT_MATRIX, true, nullptr, s);
+      make_schedule_with(n, dt, flags | TPD_FLAG_HERMITIAN | TPD_FLAG_LAYOUT_MATRIX, true, n > 8 ? force : nullptr, s);
   if (st) return st;
   s->real_out = true;
   s->in_place = false;
@@ -1075,6 +1089,47 @@ struct tpd_plan_s {
   Pipe pipe;  // pipelined chunk order (schedules with a chunk window)
 };
 
+// tpd_decompose_hermitian_real, optionally with a forced tile width and grid
+// arguments of tpd_decompose_hermitian_real
+tpd_status_t check_hermitian_real(void* A, int n, void* weights, tpd_dtype_t dtype, unsigned flags) {
+  if (dtype != TPD_C128 && dtype != TPD_C64) return TPD_ERROR_INVALID_VALUE;
+  if (flags & ~TPD_FLAG_NO_PRUNE) return TPD_ERROR_INVALID_VALUE;
+  if (n < 0 || n > max_qubits((Dtype)dtype)) return TPD_ERROR_UNSUPPORTED;
+  if (!A || !weights) return TPD_ERROR_INVALID_VALUE;
+  const size_t eb = elem_bytes((Dtype)dtype);
+  if (((uintptr_t)A % eb) || ((uintptr_t)weights % (eb / 2))) return TPD_ERROR_INVALID_VALUE;
+  const uint64_t count = (uint64_t)1 << (2 * n);
+  const uintptr_t a0 = (uintptr_t)A, w0 = (uintptr_t)weights;
+  if (a0 < w0 + count * (eb / 2) && w0 < a0 + count * eb) return TPD_ERROR_INVALID_VALUE;
+  return TPD_SUCCESS;
+}
+
+tpd_status_t hermitian_real(void* A, int n, void* weights, tpd_dtype_t dtype, unsigned flags, const Tuned* force,
+                            tpd_stream_t stream) {
+  tpd_status_t st0 = check_hermitian_real(A, n, weights, dtype, flags);
+  if (st0) return st0;
+  const Dtype dt = (Dtype)dtype;
+  Schedule s;
+  tpd_status_t st = make_real_out_schedule(n, dt, flags, &s, force);
+  if (st) return st;
+  int dev;
+  st = current_device(&dev);
+  if (st) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  uint32_t* bm = nullptr;
+  // held until the kernels are enqueued (see tpd_decompose_ex)
+  std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
+  if (s.prune && s.nsweep == 2) {
+    lk.lock();
+    Workspace& w = g_ws[{dev, hs}];
+    st = ensure_bitmap(w, s.bitmap_words);
+    if (st) return st;
+    bm = w.bitmap;
+  }
+  logf("decompose hermitian real n=%d %s", n, describe(s).c_str());
+  return run_real_out(s, A, weights, bm, hs, nullptr);
+}
+
 extern "C" {
 
 int tpd_max_qubits(tpd_dtype_t dtype) {
@@ -1172,37 +1227,7 @@ tpd_status_t tpd_decompose_ex(const void* A, int n, void* coeffs, tpd_dtype_t dt
 
 tpd_status_t tpd_decompose_hermitian_real(void* A, int n, void* weights, tpd_dtype_t dtype, unsigned flags,
                                           tpd_stream_t stream) {
-  if (dtype != TPD_C128 && dtype != TPD_C64) return TPD_ERROR_INVALID_VALUE;
-  if (flags & ~TPD_FLAG_NO_PRUNE) return TPD_ERROR_INVALID_VALUE;
-  if (n < 0 || n > max_qubits((Dtype)dtype)) return TPD_ERROR_UNSUPPORTED;
-  if (!A || !weights) return TPD_ERROR_INVALID_VALUE;
-  const Dtype dt = (Dtype)dtype;
-  const size_t eb = elem_bytes(dt);
-  if (((uintptr_t)A % eb) || ((uintptr_t)weights % (eb / 2))) return TPD_ERROR_INVALID_VALUE;
-  {
-    const uint64_t count = (uint64_t)1 << (2 * n);
-    const uintptr_t a0 = (uintptr_t)A, w0 = (uintptr_t)weights;
-    if (a0 < w0 + count * (eb / 2) && w0 < a0 + count * eb) return TPD_ERROR_INVALID_VALUE;
-  }
-  Schedule s;
-  tpd_status_t st = make_real_out_schedule(n, dt, flags, &s);
-  if (st) return st;
-  int dev;
-  st = current_device(&dev);
-  if (st) return st;
-  hipStream_t hs = (hipStream_t)stream;
-  uint32_t* bm = nullptr;
-  // held until the kernels are enqueued (see tpd_decompose_ex)
-  std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
-  if (s.prune && s.nsweep == 2) {
-    lk.lock();
-    Workspace& w = g_ws[{dev, hs}];
-    st = ensure_bitmap(w, s.bitmap_words);
-    if (st) return st;
-    bm = w.bitmap;
-  }
-  logf("decompose hermitian real n=%d %s", n, describe(s).c_str());
-  return run_real_out(s, A, weights, bm, hs, nullptr);
+  return hermitian_real(A, n, weights, dtype, flags, nullptr, stream);
 }
 
 tpd_status_t tpd_synthesize_ex(const void* coeffs, int n, void* A, tpd_dtype_t dtype, unsigned flags,
@@ -1750,6 +1775,116 @@ extern "C" tpd_status_t tpd_debug_decompose_tuned(const void* A, int n, void* co
     }
   }
   return run_schedule(s, A, coeffs, bm, hs, nullptr, pipe);
+}
+
+extern "C" tpd_status_t tpd_debug_decompose_hermitian_real_tuned(void* A, int n, void* weights, tpd_dtype_t dtype,
+                                                                unsigned flags, int db, int grid_per_cu,
+                                                                tpd_stream_t stream) {
+  if (grid_per_cu < 0 || grid_per_cu > 64) return TPD_ERROR_INVALID_VALUE;
+  Tuned t;
+  t.db = db;
+  t.grid = grid_per_cu;
+  return hermitian_real(A, n, weights, dtype, flags, db > 0 ? &t : nullptr, stream);
+}
+
+extern "C" tpd_status_t tpd_autotune_hermitian_real(void* A, int n, void* weights, tpd_dtype_t dtype,
+                                                    unsigned flags, tpd_stream_t stream, char* report, size_t len) {
+  TpdRange range_("tpd autotune hermitian real");
+  tpd_status_t st = check_hermitian_real(A, n, weights, dtype, flags);
+  if (st) return st;
+  const Dtype dt = (Dtype)dtype;
+  Schedule base;
+  st = make_real_out_schedule(n, dt, flags, &base);
+  if (st) return st;
+  int dev;
+  st = current_device(&dev);
+  if (st) return st;
+  std::string rep;
+  if (base.nsweep != 2) {
+    rep = "{\"tuned\":false,\"reason\":\"single-sweep schedule has no tunables\"}";
+    return report ? copy_out(rep, report, len) : TPD_SUCCESS;
+  }
+  hipStream_t hs = (hipStream_t)stream;
+  // each run transforms the previous result in A (in place), whose values
+  // shrink towards zero: while timing, the second sweep skips no tiles
+  const int dbs128[3] = {3, 4, 5}, dbs64[3] = {4, 5, 6};
+  const int* dbs = dt == DT_C128 ? dbs128 : dbs64;
+  const int grids[5] = {0, 1, 2, 4, 8};
+  std::vector<Tuned> cands;
+  uint64_t max_words = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int g : grids) {
+      Tuned t;
+      t.db = dbs[i];
+      t.grid = g;
+      Schedule sc;
+      if (make_real_out_schedule(n, dt, flags, &sc, &t) != TPD_SUCCESS) continue;
+      cands.push_back(t);
+      if (sc.bitmap_words > max_words) max_words = sc.bitmap_words;
+    }
+  if (cands.empty()) return TPD_ERROR_INTERNAL;
+  uint32_t* bm = nullptr;
+  {
+    void* p = nullptr;
+    st = dev_alloc(&p, (size_t)max_words * 4);
+    if (st) return st;
+    bm = (uint32_t*)p;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    (void)hipFree(bm);
+    return TPD_ERROR_OUT_OF_MEMORY;
+  }
+  double best = 1e300;
+  Tuned best_t = cands[0];
+  rep = "{\"tuned\":true,\"n\":" + std::to_string(n) + ",\"dtype\":\"" + dtype_name(dt) + "\",\"candidates\":[";
+  bool first = true;
+  for (const Tuned& t : cands) {
+    Schedule sc;
+    if (make_real_out_schedule(n, dt, flags, &sc, &t) != TPD_SUCCESS) continue;
+    if (sc.prune) sc.sw[1].bitmap_mode = 0;
+    st = run_real_out(sc, A, weights, bm, hs, nullptr);  // warm-up
+    std::vector<float> ms;
+    for (int r = 0; r < 3 && !st; ++r) {
+      if (hipEventRecord(e0, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
+      if (!st) st = run_real_out(sc, A, weights, bm, hs, nullptr);
+      if (!st && hipEventRecord(e1, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
+      float t_ms = 0;
+      if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t_ms, e0, e1) != hipSuccess))
+        st = TPD_ERROR_LAUNCH;
+      ms.push_back(t_ms);
+    }
+    if (st) break;
+    const double med = median3(ms);
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "%s{\"db\":%d,\"grid_per_cu\":%d,\"ms\":%.4f}", first ? "" : ",", t.db, t.grid,
+                  med);
+    rep += buf;
+    first = false;
+    if (med < best) {
+      best = med;
+      best_t = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(hs);
+  (void)hipFree(bm);
+  if (st) return st;
+  const TuneKey key{n, (int)dt, kRealOutKeyMatrix, 1, 1};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) load_tune_cache();
+    g_tuned[key] = best_t;
+    save_tune_entry(key, best_t);
+  }
+  char buf[128];
+  std::snprintf(buf, sizeof buf, "],\"chosen\":{\"db\":%d,\"grid_per_cu\":%d,\"ms\":%.4f}}", best_t.db, best_t.grid,
+                best);
+  rep += buf;
+  logf("autotune hermitian real %s", rep.c_str());
+  return report ? copy_out(rep, report, len) : TPD_SUCCESS;
 }
 
 extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,

@@ -375,12 +375,14 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   // prefetched data then waits for those loads only, never for the stores.
   // Workgroups of 1024 threads have 128 registers per thread: a second copy
   // of the tile fits for 4-byte elements outside the canonical store's extra
-  // LDS pass, and for 8-byte elements in the matrix layout in place (tiles
-  // of 2^8 rows or fewer; no spill); the others load at the top of each
-  // iteration (measured: complex64 n = 16 in place 2.4-3.2 % faster with
-  // the prefetch, real float64 1.5 %).
+  // LDS pass, and for 8-byte elements read in the matrix layout and stored
+  // in place or as real weights (tiles of 2^8 rows or fewer; no spill in
+  // place, 12 bytes per lane for the real weights); the others load at the
+  // top of each iteration (measured: complex64 n = 16 in place 2.4-3.2 %
+  // faster with the prefetch, real float64 1.5 %, complex64 real weights
+  // 6 %).
   constexpr bool PF = G::NT < 1024 || (sizeof(E) <= 4 && OUTL != L_CAN && !INV) ||
-                       (sizeof(E) == 8 && INL == L_MAT && OUTL == L_MAT && !INV && G::XB <= 8);
+                       (sizeof(E) == 8 && INL == L_MAT && (OUTL == L_MAT || OUTL == L_CANR) && !INV && G::XB <= 8);
   if constexpr (PF) {
     Tile cur, nxt;
     const uint64_t first = next_tile(blockIdx.x, cur);

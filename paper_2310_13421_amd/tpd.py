@@ -50,6 +50,8 @@ _SIGS = {
     "tpd_decompose_ex": (_I, [_P, _I, _P, _I, _U, _P]),
     "tpd_decompose_noalloc": (_I, [_P, _I, _P, _I, _U, _P]),
     "tpd_decompose_hermitian_real": (_I, [_P, _I, _P, _I, _U, _P]),
+    "tpd_debug_decompose_hermitian_real_tuned": (_I, [_P, _I, _P, _I, _U, _I, _I, _P]),
+    "tpd_autotune_hermitian_real": (_I, [_P, _I, _P, _I, _U, _P, _P, ctypes.c_size_t]),
     "tpd_decompose_batched": (_I, [_P, _P, _I, _P, _I, _U, _P]),
     "tpd_plan_create": (_I, [_I, _I, _U, _I, _P]),
     "tpd_plan_create_batched": (_I, [_P, _I, _I, _U, _I, _P]),
@@ -340,11 +342,12 @@ def decompose_noalloc(A, out, *, layout: str = "canonical", prune: bool = True, 
     return out
 
 
-def decompose_hermitian_real(A, out=None, *, prune: bool = True, stream=None):
+def decompose_hermitian_real(A, out=None, *, prune: bool = True, db: int = 0, grid_per_cu: int = 0, stream=None):
     """Real weights of a Hermitian A (complex128 or complex64 CUDA tensor)
     in a separate real tensor (float64 / float32, 4^n, canonical order)
     through tpd_decompose_hermitian_real.  A is destroyed (the first sweep
-    works in place in it) for n >= 9."""
+    works in place in it) for n >= 9.  db > 0 forces the tile width 2^db
+    and grid_per_cu the grid (test aid)."""
     torch = _torch()
     n = _check_matrix(A)
     if A.dtype not in (torch.complex128, torch.complex64):
@@ -354,9 +357,14 @@ def decompose_hermitian_real(A, out=None, *, prune: bool = True, stream=None):
         out = torch.empty(4 ** n, dtype=rdt, device=A.device)
     if out.dtype != rdt or not out.is_cuda or not out.is_contiguous() or out.numel() != 4 ** n:
         raise ValueError("out must be a contiguous CUDA tensor of 4^n real values of A's precision")
-    _check(lib.tpd_decompose_hermitian_real(A.data_ptr(), n, out.data_ptr(), _dtype_code(A),
-                                            0 if prune else FLAG_NO_PRUNE, _stream(stream)),
-           "tpd_decompose_hermitian_real")
+    fl = 0 if prune else FLAG_NO_PRUNE
+    if db > 0 or grid_per_cu > 0:
+        _check(lib.tpd_debug_decompose_hermitian_real_tuned(A.data_ptr(), n, out.data_ptr(), _dtype_code(A), fl, db,
+                                                            grid_per_cu, _stream(stream)),
+               "tpd_debug_decompose_hermitian_real_tuned")
+    else:
+        _check(lib.tpd_decompose_hermitian_real(A.data_ptr(), n, out.data_ptr(), _dtype_code(A), fl, _stream(stream)),
+               "tpd_decompose_hermitian_real")
     return out
 
 
@@ -393,6 +401,21 @@ def autotune(A, out=None, *, layout: str = "canonical", prune: bool = True, herm
     buf = ctypes.create_string_buffer(8192)
     _check(lib.tpd_autotune(A.data_ptr(), n, out.data_ptr(), _dtype_code(A), _flags(layout, prune, False, hermitian),
                             _stream(stream), buf, 8192), "tpd_autotune")
+    return json.loads(buf.value.decode())
+
+
+def autotune_hermitian_real(A, out=None, *, prune: bool = True, stream=None) -> dict:
+    """Autotune decompose_hermitian_real for A's (n, dtype) on these buffers
+    (A is destroyed); later calls use the choice."""
+    torch = _torch()
+    n = _check_matrix(A)
+    rdt = torch.float64 if A.dtype == torch.complex128 else torch.float32
+    if out is None:
+        out = torch.empty(4 ** n, dtype=rdt, device=A.device)
+    buf = ctypes.create_string_buffer(8192)
+    _check(lib.tpd_autotune_hermitian_real(A.data_ptr(), n, out.data_ptr(), _dtype_code(A),
+                                           0 if prune else FLAG_NO_PRUNE, _stream(stream), buf, 8192),
+           "tpd_autotune_hermitian_real")
     return json.loads(buf.value.decode())
 
 

@@ -107,6 +107,13 @@ def test_hermitian_real_validation_before_device():
     assert H(FAKE, 4, FAKE - 2048 + 8, 0, 0, None) == 1          # matrix starts inside the weights
     assert H(FAKE, 17, FAKE * 64, 0, 0, None) == 2               # n too large
     assert H(FAKE, -1, FAKE * 4, 0, 0, None) == 2
+    T = tpd.lib.tpd_autotune_hermitian_real  # validates the same way
+    assert T(FAKE, 4, FAKE * 4, 2, 0, None, None, 0) == 1
+    assert T(FAKE, 4, FAKE + 4096 - 8, 0, 0, None, None, 0) == 1
+    assert T(FAKE, 17, FAKE * 64, 0, 0, None, None, 0) == 2
+    D = tpd.lib.tpd_debug_decompose_hermitian_real_tuned
+    assert D(FAKE, 4, FAKE * 4, 0, 0, 4, -1, None) == 1                 # negative grid
+    assert D(FAKE, 4, FAKE * 4, 0, tpd.FLAG_HERMITIAN, 4, 0, None) == 1
 
 
 def test_noalloc_rejects_timing_flag():

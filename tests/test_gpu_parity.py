@@ -1219,6 +1219,36 @@ def test_hermitian_real_weights_vs_complex_mode(dtype):
             assert same_bits(w.cpu().numpy(), O.tpd_recursive(A).real), n
 
 
+@pytest.mark.parametrize("dtype,dbs", [(torch.complex128, (3, 4, 5)), (torch.complex64, (4, 5, 6))])
+def test_hermitian_real_weights_every_tile_width_and_grid(dtype, dbs):
+    # n = 14: every tile width and grid the real-weights path can take gives
+    # the default schedule's bits
+    n = 14
+    torch.cuda.empty_cache()
+    A = W.gaussian_device(n, seed=24, dtype=dtype, hermitian=True)
+    rdt = torch.float64 if dtype == torch.complex128 else torch.float32
+    B = A.clone()
+    ref = tpd.decompose_hermitian_real(B)
+    w = torch.empty_like(ref)
+    for db in dbs:
+        for g in (0, 2, 8):
+            B.copy_(A)
+            w.fill_(float("nan"))
+            tpd.decompose_hermitian_real(B, w, db=db, grid_per_cu=g)
+            assert torch.equal(w, ref), (db, g)
+    assert ref.dtype == rdt
+    # the real-weights autotuner (on B, destroyed) keeps the bits
+    B.copy_(A)
+    rep = tpd.autotune_hermitian_real(B, w)
+    assert rep["tuned"] and rep["chosen"]["db"] in dbs
+    B.copy_(A)
+    w.fill_(float("nan"))
+    tpd.decompose_hermitian_real(B, w)
+    assert torch.equal(w, ref)
+    del A, B, ref, w
+    torch.cuda.empty_cache()
+
+
 def test_hermitian_real_weights_n16_full_size():
     # the n = 16 headline matrix: sampled weights against the definition, and
     # 10^5 sampled weights bitwise against the complex Hermitian mode in place
