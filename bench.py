@@ -450,6 +450,23 @@ def a_max_of(torch, A):
     return m
 
 
+def sum_sq(torch, X):
+    """sum |x|^2 over a large tensor in binary64, by row blocks (no
+    full-size temporaries)"""
+    t = 0.0
+    rows = max(1, (1 << 26) // X.shape[1])
+    for r0 in range(0, X.shape[0], rows):
+        blk = X[r0:r0 + rows]
+        t += float((torch.view_as_real(blk) if blk.is_complex() else blk).double().square().sum())
+    return t
+
+
+def parseval_rel(torch, A, B, n):
+    """|2^n sum |w|^2 - ||A||_F^2| / ||A||_F^2 for the weights B (any layout)"""
+    fro = sum_sq(torch, A)
+    return abs(sum_sq(torch, B) * 2 ** n - fro) / fro
+
+
 def deinterleave(q):
     """canonical q -> (row h, column l) of the matrix layout"""
     import numpy as np
@@ -651,8 +668,10 @@ def main():
         errors["config4_n16_hermitian"] = {
             "samples": int(qs.size), "c128": rel_err(got128, bf, a_max),
             "c128_bound_n_u": n * 2.0 ** -53, "oracle_seconds": oracle_s,
+            "c128_parseval_rel": parseval_rel(torch, A, B, n),
             "what": "max |w_gpu - w_oracle| / max|a_ij| over uniformly sampled strings plus I..I, X..X, Y..Y, Z..Z, "
-                    "4^16-1; in place, matrix layout",
+                    "4^16-1; in place, matrix layout; parseval_rel = |2^n sum|w|^2 - ||A||_F^2| / ||A||_F^2 over "
+                    "all 4^16 weights",
         }
         del B
         torch.cuda.empty_cache()
@@ -743,6 +762,7 @@ def main():
             e64 = rel_err(got64, bf, a_max)
             errors["config4_n16_hermitian"]["c64"] = e64
             errors["config4_n16_hermitian"]["c64_bound_n_plus_1_u"] = (n + 1) * 2.0 ** -24
+            errors["config4_n16_hermitian"]["c64_parseval_rel"] = parseval_rel(torch, A32, B32, n)
             r["max_abs_err_over_max_abs_a"] = e64
             result["fp32"] = r
             del B32

@@ -970,6 +970,70 @@ def test_determinism_and_poison():
     assert torch.equal(torch.view_as_real(o1), torch.view_as_real(o2))
 
 
+def test_pipelined_chunk_schedule_from_the_cache_plan_graph_and_noalloc():
+    # a cached pipelined chunk schedule (n = 12 complex128 out of place: tile
+    # width 2^4, 64 chunks, window 2) reaches tpd_decompose_ex (a second
+    # stream per caller stream), a plan (its own stream), a captured graph of
+    # that plan (the second stream joins the capture through events), and
+    # the no-allocation entry point (chunks on the caller's stream only); all
+    # give the bits of the whole-sweep schedule
+    import subprocess
+    import sys
+    import tempfile
+    import textwrap
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with tempfile.TemporaryDirectory() as td:
+        cache = os.path.join(td, "tune.txt")
+        code = textwrap.dedent("""
+            import json, os, sys
+            sys.path.insert(0, %r)
+            import torch
+            cus = torch.cuda.get_device_properties(0).multi_processor_count
+            with open(os.environ["TPD_AUTOTUNE_CACHE"], "w") as f:
+                f.write("tpd-tune-v2 gfx950 %%d 0 12 0 0 0 4 4 8 0 2 2\\n" %% cus)
+            from paper_2310_13421_amd import tpd
+            import workloads as W
+            A = torch.from_numpy(W.gaussian(12, seed=1201)).to("cuda")
+            ref = tpd.decompose_tuned(A, db=4, grid_per_cu=8)
+            eq = lambda o: bool(torch.equal(torch.view_as_real(o), torch.view_as_real(ref)))
+            ok = []
+            ok.append(eq(tpd.decompose(A)))
+            plan = tpd.Plan(12)
+            d = plan.describe()
+            ok.append(d["chunk_bits"] == 2 and d["chunk_window"] == 2)
+            out = torch.empty_like(ref)
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                plan.execute(A, out)
+            torch.cuda.current_stream().wait_stream(s)
+            torch.cuda.synchronize()
+            ok.append(eq(out))
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                plan.execute(A, out)
+            for _ in range(3):
+                out.fill_(float("nan"))
+                torch.cuda.synchronize()
+                g.replay()
+                torch.cuda.synchronize()
+                ok.append(eq(out))
+            out2 = torch.empty_like(ref)
+            tpd.decompose_noalloc(A, out2)
+            torch.cuda.synchronize()
+            ok.append(eq(out2))
+            plan.close()
+            print("RESULT", json.dumps(ok), flush=True)
+        """ % root)
+        env = dict(os.environ, TPD_AUTOTUNE_CACHE=cache)
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, r.stderr[-2000:]
+    line = [ln for ln in r.stdout.splitlines() if ln.startswith("RESULT")][-1]
+    import json
+    assert all(json.loads(line.split(" ", 1)[1])), line
+
+
 def test_allocation_failure_hook_reports_out_of_memory():
     # TPD_TEST_FAIL_ALLOC=1 makes every library allocation fail: plan
     # creation and the workspace of a pruned decomposition report
