@@ -805,6 +805,32 @@ def test_n17_in_place_sampled_strings(dtype):
     torch.cuda.empty_cache()
 
 
+def test_n17_hermitian_real_weights_complex64():
+    # the largest real-weights case: n = 17 complex64 (128 GiB, destroyed),
+    # 8 + 9 level split (the real-weights store in a 9-level, 2^14-element
+    # tile), sampled weights against the definition, every weight written
+    n = 17
+    torch.cuda.empty_cache()
+    A = W.gaussian_device(n, seed=1717, dtype=torch.complex64, hermitian=True)
+    a_max = 0.0
+    for r0 in range(0, 1 << n, 4096):
+        a_max = max(a_max, float(torch.view_as_real(A[r0:r0 + 4096]).abs().max()))
+    qs = W.sampled_strings(n, 1000, seed=1718)
+    bf = sampled_oracle(A, n, qs)  # read before A is overwritten
+    w = torch.full((4 ** n,), float("nan"), dtype=torch.float32, device=DEV)
+    tpd.decompose_hermitian_real(A, w)
+    del A
+    torch.cuda.empty_cache()
+    got = w[torch.from_numpy(qs.astype(np.int64)).to(DEV)].cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - bf.real)) <= (n + 1) * U32 * a_max
+    nan = False
+    for c0 in range(0, 4 ** n, 1 << 30):  # by blocks: no full-size temporary
+        nan = nan or bool(torch.isnan(w[c0:c0 + (1 << 30)]).any())
+    assert not nan
+    del w
+    torch.cuda.empty_cache()
+
+
 def test_n17_real_tfim_pruning_with_split_tile_widths():
     # the transverse-field Ising chain at n = 17 (real float32, 64 GiB): its
     # X_i terms sit on single diagonals 2^i, so second-sweep d-groups of 2^5
