@@ -17,7 +17,8 @@ Extras in the same line: the other configurations (n = 8 dense and
 integer, n = 12 Hermitian, n = 14 structured with pruning, the 4096-matrix
 batched set against a graph of per-matrix launches, n = 16 complex64), the
 error against the binary64 oracle for every configuration in both
-precisions, out-of-place / Hermitian-mode / real-input / synthesis /
+precisions (with full Parseval sums at n = 16), out-of-place /
+Hermitian-mode (complex and real weights) / real-input / synthesis /
 partial legs, and the CPU oracle timed on the host.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--extras ...]
