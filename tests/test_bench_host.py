@@ -176,3 +176,13 @@ def test_ingest_sums_chunked_dispatches_over_their_chunks(tmp_path):
     assert abs(e["fetch_over_algorithmic"] - 1.002) < 1e-9 and abs(e["write_over_algorithmic"] - 1.001) < 1e-9
     assert abs(e["total_bytes"] - 2.003 * alg) < 1e-3 * alg
     assert "only_reduced_mode_dispatches" not in e
+
+
+def test_sweep_rates_of_whole_and_chunked_legs():
+    alg = 4 ** 16 * 16
+    # whole sweeps: one rate per sweep
+    r = bench.sweep_rates(alg, [27.0, 25.0], 0)
+    assert abs(r[0] - alg / 27e-3 / 1e9) < 1e-6 and abs(r[1] - alg / 25e-3 / 1e9) < 1e-6
+    # chunked: kernel 0 is the whole loop (both sweeps), averaged per sweep
+    r = bench.sweep_rates(alg, [52.0, 0.0], 9)
+    assert abs(r[0] - 2 * alg / 52e-3 / 1e9) < 1e-6 and r[1] is None
