@@ -73,6 +73,10 @@ def load_traffic(kernel_name, n):
     if t.get("kernel_source_sha") != kernel_source_hash():
         return None
     k = t.get("kernels", {}).get(kernel_name)
+    # a symbol seen only in the Hermitian / real-symmetric mode (which reads
+    # about half) says nothing about the general mode's bytes
+    if k and k.get("only_reduced_mode_dispatches"):
+        return None
     return k if k and k.get("n") == n else None
 
 

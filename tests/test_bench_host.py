@@ -186,3 +186,15 @@ def test_sweep_rates_of_whole_and_chunked_legs():
     # chunked: kernel 0 is the whole loop (both sweeps), averaged per sweep
     r = bench.sweep_rates(alg, [52.0, 0.0], 9)
     assert abs(r[0] - 2 * alg / 52e-3 / 1e9) < 1e-6 and r[1] is None
+
+
+def test_traffic_lookup_ignores_reduced_mode_only_symbols(tmp_path, monkeypatch):
+    k = "void tpd::k_sweep<double, tpd::Geom<8, 4, 0, 4, 0>, 0, 0, false>(tpd::SweepArgs)"
+    os.makedirs(tmp_path / "profiles")
+    doc = {"kernel_source_sha": "x", "kernels": {k: {"n": 16, "total_bytes": 7.3e10,
+                                                       "only_reduced_mode_dispatches": True}}}
+    with open(tmp_path / "profiles" / "traffic.json", "w") as f:
+        json.dump(doc, f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "x")
+    assert bench.load_traffic(k, 16) is None
