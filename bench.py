@@ -109,11 +109,21 @@ def ingest_pmc(pairs, out_path):
     WRITE_SIZE, both with --copy-calibration) into profiles/traffic.json.
     Each counter (KiB per dispatch) is scaled by what it reads for the plain
     device copy of 2^32 bytes that --copy-calibration runs.  A kernel seen in
-    several pairs takes the figures of the last one."""
+    several pairs takes the figures of the last one, unless an earlier pair
+    measured whole general-mode sweeps and the later one only chunks or
+    reduced-mode sweeps."""
+
+    def rank(e):
+        if "workload" in e or not (e.get("chunks") or e.get("only_reduced_mode_dispatches")):
+            return 2
+        return 1 if e.get("chunks") else 0
+
     kernels, scales = {}, []
     for fetch_csv, write_csv in pairs:
         ks, fs, ws = ingest_pair(fetch_csv, write_csv)
-        kernels.update(ks)
+        for name, e in ks.items():
+            if name not in kernels or rank(e) >= rank(kernels[name]):
+                kernels[name] = e
         scales.append({"fetch_scale": fs, "write_scale": ws})
     doc = {"kernel_source_sha": kernel_source_hash(), "scales": scales,
            "calibration": "plain device copy of 2^32 bytes (__amd_rocclr_copyBuffer via torch copy_)",
@@ -180,45 +190,54 @@ def ingest_pair(fetch_csv, write_csv):
         alg = 4 ** n * es
         fr = [v / fscale / alg for v in fetch[name]]
         wr = [v / wscale / alg for v in write[name]]
-        # chunked order: each dispatch moves 1/2^k of a sweep (2^k chunks);
-        # such a symbol is reported per whole sweep (the 2^k dispatches)
-        if fr and len(fr) == len(wr) and max(fr) < 0.3:
-            ks = [round(math.log2(1.0 / r)) if r > 0 else 0 for r in fr]
-            if all(k >= 2 and abs(r * 2 ** k - 1.0) < 0.05 for r, k in zip(fr, ks)):
-                fo = sum(r * 2 ** k for r, k in zip(fr, ks)) / len(fr)
-                wo = sum(w * 2 ** k for w, k in zip(wr, ks)) / len(wr)
-                kernels[name] = {
-                    "n": n, "sweep": which, "dtype": dt, "dispatches": len(fr), "chunks": sorted({2 ** k for k in ks}),
-                    "fetch_bytes": fo * alg, "write_bytes": wo * alg, "total_bytes": (fo + wo) * alg,
-                    "algorithmic_bytes": 2 * alg, "fetch_over_algorithmic": fo, "write_over_algorithmic": wo,
-                    "per": "whole sweep (the chunked order's dispatches summed over its chunks)",
-                }
-                continue
-        # Hermitian / real-symmetric mode shares the kernel symbol and reads
-        # about half of what the full mode reads (1.06 against 2.0 for tiles
-        # whose runs are shorter than a line): its dispatches are reported
-        # apart from the full ones
-        top = max(fr) if fr else 0.0
-        full = [i for i, r in enumerate(fr) if r >= 0.75 and r >= 0.75 * top]
-        reduced = [i for i in range(len(fr)) if i not in full] if len(fr) == len(wr) and full else []
-        use = full if reduced else list(range(len(fr)))
-        only_reduced = not full
-        fb = sum(fr[i] for i in use) / len(use) * alg
-        wb = sum(wr[i] for i in (use if len(wr) == len(fr) else range(len(wr)))) / (
-            len(use) if len(wr) == len(fr) else len(wr)) * alg
-        kernels[name] = {
+        # Each dispatch is one of: a whole sweep of the general mode (its
+        # fetch ratio near the symbol's largest); a chunk of the chunked order
+        # (1/2^k of a sweep, k >= 2), counted per whole sweep; or a sweep of
+        # the Hermitian / real-symmetric mode, which shares the symbol and
+        # reads about half (1.06 against 2.0 for tiles whose runs are shorter
+        # than a line).  The entry takes the whole sweeps, else the chunks,
+        # else (flagged) the reduced-mode sweeps.
+        if len(fr) != len(wr) or not fr:
+            continue
+        top = max(fr)
+        cls, kexp = [], []
+        for r in fr:
+            k = round(math.log2(1.0 / r)) if r > 0 else 0
+            if r >= 0.75 and r >= 0.75 * top:
+                cls.append("full")
+            elif k >= 2 and abs(r * 2 ** k - 1.0) < 0.05:
+                cls.append("chunk")
+            else:
+                cls.append("reduced")
+            kexp.append(k)
+        full = [i for i, c in enumerate(cls) if c == "full"]
+        chunk = [i for i, c in enumerate(cls) if c == "chunk"]
+        reduced = [i for i, c in enumerate(cls) if c == "reduced"]
+        use = full or chunk or reduced
+        scale = [2 ** kexp[i] if cls[i] == "chunk" else 1 for i in range(len(fr))]
+        fo = sum(fr[i] * scale[i] for i in use) / len(use)
+        wo = sum(wr[i] * scale[i] for i in use) / len(use)
+        e = {
             "n": n, "sweep": which, "dtype": dt, "dispatches": len(use),
-            "fetch_bytes": fb, "write_bytes": wb, "total_bytes": fb + wb,
-            "algorithmic_bytes": 2 * alg, "fetch_over_algorithmic": fb / alg, "write_over_algorithmic": wb / alg,
+            "fetch_bytes": fo * alg, "write_bytes": wo * alg, "total_bytes": (fo + wo) * alg,
+            "algorithmic_bytes": 2 * alg, "fetch_over_algorithmic": fo, "write_over_algorithmic": wo,
         }
-        if only_reduced:
-            kernels[name]["only_reduced_mode_dispatches"] = True  # Hermitian / real-symmetric mode only
-        if reduced:
-            kernels[name]["reduced_mode_dispatches"] = {
+        if use is chunk:
+            e["chunks"] = sorted({2 ** kexp[i] for i in chunk})
+            e["per"] = "whole sweep (the chunked order's dispatches summed over its chunks)"
+        elif chunk:
+            e["chunked_dispatches"] = {"count": len(chunk), "chunks": sorted({2 ** kexp[i] for i in chunk}),
+                                       "fetch_over_algorithmic": sum(fr[i] * scale[i] for i in chunk) / len(chunk),
+                                       "write_over_algorithmic": sum(wr[i] * scale[i] for i in chunk) / len(chunk)}
+        if use is reduced:
+            e["only_reduced_mode_dispatches"] = True  # Hermitian / real-symmetric mode only
+        elif reduced:
+            e["reduced_mode_dispatches"] = {
                 "count": len(reduced),
                 "fetch_over_algorithmic": sum(fr[i] for i in reduced) / len(reduced),
                 "write_over_algorithmic": sum(wr[i] for i in reduced) / len(reduced),
             }
+        kernels[name] = e
     return kernels, fscale, wscale
 
 

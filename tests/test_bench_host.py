@@ -198,3 +198,31 @@ def test_traffic_lookup_ignores_reduced_mode_only_symbols(tmp_path, monkeypatch)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "x")
     assert bench.load_traffic(k, 16) is None
+
+
+def test_ingest_mixed_dispatch_kinds_and_merge_keeps_whole_sweeps(tmp_path):
+    # one symbol with whole sweeps, chunks of 1/16 and reduced-mode sweeps in
+    # one run: the entry is the whole sweeps, the others are listed apart; a
+    # later run with reduced-mode sweeps only does not replace it
+    k = "void tpd::k_sweep<double, tpd::Geom<8, 4, 0, 4, 0>, 0, 0, false>(tpd::SweepArgs)"
+    alg = 4 ** 16 * 16
+    copy = 1 << 32
+    f1 = [(COPY, 0.5 * copy / 1024)] + [(k, 0.5 * 1.001 * alg / 1024)] * 2 + \
+         [(k, 0.5 * alg / 16 / 1024)] * 32 + [(k, 0.5 * 0.53 * alg / 1024)] * 2
+    w1 = [(COPY, copy / 1024)] + [(k, 1.002 * alg / 1024)] * 2 + [(k, alg / 16 / 1024)] * 32 + \
+         [(k, 0.77 * alg / 1024)] * 2
+    f2 = [(COPY, 0.5 * copy / 1024)] + [(k, 0.5 * 0.53 * alg / 1024)] * 2
+    w2 = [(COPY, copy / 1024)] + [(k, 0.5 * alg / 1024)] * 2
+    paths = []
+    for i, rows in enumerate((f1, w1, f2, w2)):
+        p = tmp_path / f"{i}.csv"
+        write_csv(p, rows)
+        paths.append(str(p))
+    one = bench.ingest_pmc([(paths[0], paths[1])], str(tmp_path / "a.json"))["kernels"][k]
+    assert one["dispatches"] == 2 and abs(one["fetch_over_algorithmic"] - 1.001) < 1e-9
+    assert one["chunked_dispatches"]["count"] == 32 and one["chunked_dispatches"]["chunks"] == [16]
+    assert one["reduced_mode_dispatches"]["count"] == 2
+    both = bench.ingest_pmc([(paths[0], paths[1]), (paths[2], paths[3])], str(tmp_path / "b.json"))["kernels"][k]
+    assert both == one
+    later = bench.ingest_pmc([(paths[2], paths[3])], str(tmp_path / "c.json"))["kernels"][k]
+    assert later["only_reduced_mode_dispatches"]
