@@ -11,8 +11,8 @@
 // grid, and with prefetch it issues the next item's loads before it
 // transforms and stores the current one.  Every run is inlined into the
 // kernel (no device-function calls: the item's descriptor and the kernel
-// arguments stay in scalar registers), and the kernel asks for two waves per
-// SIMD, the residency its 64 KiB LDS tile allows anyway.  The shape tables
+// arguments stay in scalar registers), and the kernel is compiled for the
+// residency its 64 KiB LDS tile allows, two workgroups per CU (batch_waves).  The shape tables
 // are function-local constants so that every register index folds at
 // compile time (as a class member the table was read from memory and the
 // tile went to scratch).
@@ -30,9 +30,8 @@ struct BatchedOps {
   static constexpr uint32_t DM = (1u << G::DB) - 1;
   static constexpr uint32_t XM = (1u << G::XB) - 1;
 
-  __device__ __forceinline__ static void load(const BatchArgs& a, const BatchItem& it, E* v) {
+  __device__ __forceinline__ static void load(const BatchArgs& a, const BatchItem& it, E* v, uint32_t tid) {
     static constexpr Roles RL = make_roles<G>();
-    const uint32_t tid = threadIdx.x;
     const uint64_t td = it.tile;
     const uint32_t e = elem_base<G>(RL, 0, tid);
     const uint32_t ml = e >> (G::DB + G::XB);
@@ -51,9 +50,8 @@ struct BatchedOps {
   }
 
   // transform the loaded item through its register phases and store it
-  __device__ __forceinline__ static void process(const BatchArgs& a, const BatchItem& it, E* v, E* lds) {
+  __device__ __forceinline__ static void process(const BatchArgs& a, const BatchItem& it, E* v, E* lds, uint32_t tid) {
     static constexpr Roles RL = make_roles<G>();
-    const uint32_t tid = threadIdx.x;
     const uint64_t td = it.tile;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -101,16 +99,21 @@ __device__ __forceinline__ void batched_run(const BatchArgs& a, uint32_t first, 
   const uint32_t grid = gridDim.x;
   uint32_t i = first + (blockIdx.x + grid - first % grid) % grid;  // first item of this workgroup in the run
   if (i >= end) return;
+  // the thread index as an opaque value defined here: otherwise the
+  // compiler hoists every shape's per-thread offsets out of the loop over
+  // runs and keeps them all live across the kernel (193-254 VGPRs, spills)
+  uint32_t tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   if constexpr (PF) {
     E v[G::E], pf[G::E];
     BatchItem cur = a.items[i], nxt;
-    Ops::load(a, cur, v);
+    Ops::load(a, cur, v, tid);
     uint32_t next = i + grid;
     if (next < end) {
       nxt = a.items[next];
-      Ops::load(a, nxt, pf);
+      Ops::load(a, nxt, pf, tid);
     }
-    Ops::process(a, cur, v, lds);
+    Ops::process(a, cur, v, lds, tid);
     while (next < end) {
 #pragma unroll
       for (int j = 0; j < G::E; ++j) v[j] = pf[j];
@@ -118,16 +121,16 @@ __device__ __forceinline__ void batched_run(const BatchArgs& a, uint32_t first, 
       next += grid;
       if (next < end) {
         nxt = a.items[next];
-        Ops::load(a, nxt, pf);
+        Ops::load(a, nxt, pf, tid);
       }
-      Ops::process(a, cur, v, lds);
+      Ops::process(a, cur, v, lds, tid);
     }
   } else {
     for (; i < end; i += grid) {
       E v[G::E];
       const BatchItem it = a.items[i];
-      Ops::load(a, it, v);
-      Ops::process(a, it, v, lds);
+      Ops::load(a, it, v, tid);
+      Ops::process(a, it, v, lds, tid);
     }
   }
 }
@@ -140,8 +143,17 @@ __device__ __forceinline__ void batched_shape(const BatchArgs& a, const BatchSeg
   else if constexpr (N >= 3) batched_run<S, typename BatchShape<N, BT, 1>::G, OUTL, true>(a, sg.first, sg.end, lds);
 }
 
+// waves per SIMD the kernel is compiled for: two 64 KiB tiles per CU, i.e.
+// 2 waves per SIMD with 256-thread complex128 workgroups and 4 with the
+// 512-thread workgroups of the 8- and 4-byte dtypes, except real float64,
+// which would spill at 128 VGPRs and keeps one workgroup per CU
+template <class S>
+constexpr int batch_waves() {
+  return (std::is_same_v<S, double> || std::is_same_v<S, Real<double>>) ? 2 : 4;
+}
+
 template <class S, int OUTL, int BT>
-__global__ void __launch_bounds__(1 << (BT - 4)) __attribute__((amdgpu_waves_per_eu(2, 2))) k_batched(BatchArgs a) {
+__global__ void __launch_bounds__(1 << (BT - 4)) __attribute__((amdgpu_waves_per_eu(batch_waves<S>(), batch_waves<S>()))) k_batched(BatchArgs a) {
   __shared__ typename Elem<S>::type lds[1 << BT];
   for (uint32_t s = 0; s < a.nseg; ++s) {
     const BatchSeg sg = a.segs[s];
