@@ -66,9 +66,18 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
     const uint32_t eo = 1u << (REMAP ? RL.st_reg[s] : RL.reg[LAST][s]);
     dout[s] = layout_addr<OUTL>((uint64_t)((eo >> G::DB) & XM) << xlo, eo & DM, n, db);
   }
-  const uint32_t eb0 = elem_base<G>(RL, 0, tid);
-  const uint32_t ebl = elem_base<G>(RL, LAST, tid);
-  const uint32_t ebo = REMAP ? elem_base_st<G>(RL, tid) : ebl;  // element base of the stores
+  // The thread's element bases are recomputed for every tile from an
+  // opaque copy of the thread index: hoisted out of the tile loop, every
+  // phase's LDS offsets and every register slot's address stayed live
+  // across the whole kernel (up to 256 VGPRs and spills; with the copy 90-195
+  // VGPRs, no spills, and twice the resident workgroups for 512-thread
+  // tiles of 8-byte elements).  The recomputation is a few integer
+  // operations per tile.
+  auto thread_index = [&]() -> uint32_t {
+    uint32_t t = tid;
+    asm volatile("" : "+v"(t));
+    return t;
+  };
 
   // Tile decode.  A tile is skipped (nothing read or written) when no
   // requested string lies in its d-group, when the pruning bitmap marks its
@@ -143,6 +152,7 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   };
   auto load = [&](const Tile& t, E* v) {
     if (t.zero) return;
+    const uint32_t eb0 = elem_base<G>(RL, 0, thread_index());
     const uint64_t x = t.xfix | ((uint64_t)((eb0 >> G::DB) & XM) << xlo);
     const uint64_t d = (t.td << G::DB) | (eb0 & DM);
     const uint64_t base = layout_addr<INL>(x, d, n, db);
@@ -186,6 +196,10 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   // Transform one loaded tile and store it.
   auto process = [&](const Tile& t, E* v) {
     const uint64_t td = t.td, hm = t.hm, xfix = t.xfix;
+    const uint32_t tid = thread_index();
+    const uint32_t eb0 = elem_base<G>(RL, 0, tid);
+    const uint32_t ebl = elem_base<G>(RL, LAST, tid);
+    const uint32_t ebo = REMAP ? elem_base_st<G>(RL, tid) : ebl;  // element base of the stores
     if (t.zero) {
       // Hermitian zero tile: zeros on the rows with x bit m set (the
       // representatives already hold the first sweep's zeros).  Row bit m
