@@ -387,14 +387,16 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   // so that the loop is entered with the same operations in flight as on
   // its back edge (next loads, then current stores): the copy of the
   // prefetched data then waits for those loads only, never for the stores.
-  // Workgroups of 1024 threads have 128 registers per thread: a second copy
-  // of the tile fits for 4-byte elements outside the canonical store's extra
-  // LDS pass, and for 8-byte elements read in the matrix layout and stored
-  // in place or as real weights (tiles of 2^8 rows or fewer; no spill in
-  // place, 12 bytes per lane for the real weights); the others load at the
-  // top of each iteration (measured: complex64 n = 16 in place 2.4-3.2 %
-  // faster with the prefetch, real float64 1.5 %, complex64 real weights
-  // 6 %).
+  // Workgroups of 1024 threads have 128 registers per thread.  They prefetch
+  // for 4-byte elements outside the canonical store's extra LDS pass, and
+  // for 8-byte elements read in the matrix layout and stored in place or as
+  // real weights (tiles of 2^8 rows or fewer); the others load at the top of
+  // each iteration (measured: complex64 n = 16 in place 2.4-3.2 % faster
+  // with the prefetch, real float64 1.5 %, complex64 real weights 6 %).
+  // Since the element bases are recomputed per tile, a second copy fits
+  // without spills in every 1024-thread kernel, but prefetching in the
+  // remaining ones measured no gain (complex64, real float64 and real
+  // float32 n = 16 out of place, complex64 synthesis: within 1 %).
   constexpr bool PF = G::NT < 1024 || (sizeof(E) <= 4 && OUTL != L_CAN && !INV) ||
                        (sizeof(E) == 8 && INL == L_MAT && (OUTL == L_MAT || OUTL == L_CANR) && !INV && G::XB <= 8);
   if constexpr (PF) {
