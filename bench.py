@@ -111,19 +111,34 @@ def ingest_pmc(pairs, out_path):
     device copy of 2^32 bytes that --copy-calibration runs.  A kernel seen in
     several pairs takes the figures of the last one, unless an earlier pair
     measured whole general-mode sweeps and the later one only chunks or
-    reduced-mode sweeps."""
+    reduced-mode sweeps; the chunk and reduced-mode figures of the entry not
+    kept are carried over as its sub-records where the kept one has none."""
 
     def rank(e):
         if "workload" in e or not (e.get("chunks") or e.get("only_reduced_mode_dispatches")):
             return 2
         return 1 if e.get("chunks") else 0
 
+    def subrecords(e):
+        out = {k: e[k] for k in ("reduced_mode_dispatches", "chunked_dispatches") if k in e}
+        ratios = {"fetch_over_algorithmic": e.get("fetch_over_algorithmic"),
+                  "write_over_algorithmic": e.get("write_over_algorithmic")}
+        if e.get("only_reduced_mode_dispatches"):
+            out["reduced_mode_dispatches"] = {"count": e["dispatches"], **ratios}
+        elif e.get("chunks"):
+            out["chunked_dispatches"] = {"count": e["dispatches"], "chunks": e["chunks"], **ratios}
+        return out
+
     kernels, scales = {}, []
     for fetch_csv, write_csv in pairs:
         ks, fs, ws = ingest_pair(fetch_csv, write_csv)
         for name, e in ks.items():
-            if name not in kernels or rank(e) >= rank(kernels[name]):
-                kernels[name] = e
+            old = kernels.get(name)
+            keep, other = (e, old) if old is None or rank(e) >= rank(old) else (old, e)
+            if other is not None and "workload" not in keep and rank(keep) > rank(other):
+                for k, v in subrecords(other).items():
+                    keep.setdefault(k, v)
+            kernels[name] = keep
         scales.append({"fetch_scale": fs, "write_scale": ws})
     doc = {"kernel_source_sha": kernel_source_hash(), "scales": scales,
            "calibration": "plain device copy of 2^32 bytes (__amd_rocclr_copyBuffer via torch copy_)",

@@ -317,11 +317,11 @@ tpd_status_t tpd_plan_describe(tpd_plan_t plan, char* buf, size_t len);
  * calls on a stream create a second stream (default priority) and events,
  * kept until tpd_release_workspace (plans: until tpd_plan_destroy).
  * The choice never changes results (same operations in the same order).
- * Timed runs include the first sweep's pruning epilogue unless
- * TPD_FLAG_NO_PRUNE is given; in place, where each run transforms the
- * previous result, the second sweep skips no tiles while timing.
- * Arguments as tpd_decompose_ex; `coeffs` is overwritten; with
- * A == coeffs the matrix is transformed repeatedly (destroyed).  Allocates
+ * Timed runs are the schedule as it will run, pruning included unless
+ * TPD_FLAG_NO_PRUNE is given.  Arguments as tpd_decompose_ex; `coeffs` is
+ * overwritten; with A == coeffs the matrix is destroyed: before every
+ * timed run (untimed) it is refilled with seeded uniform noise in [-1, 1),
+ * so that the values do not decay to zero over repeated transforms.  Allocates
  * a bitmap, synchronises `stream`.  report/len (optional): JSON of the
  * candidates' median times and the choice.  n <= 8 has nothing to tune.   */
 tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dtype_t dtype, unsigned flags,
@@ -407,8 +407,9 @@ tpd_status_t tpd_debug_emulate_compact(const void* coeffs, int n, tpd_dtype_t dt
                                        uint64_t* q_out, void* w_out, uint64_t capacity, uint64_t* count);
 
 /* Autotune tpd_decompose_hermitian_real for this (n, dtype): tile widths
- * and grids as tpd_autotune, each timed on A (transformed repeatedly:
- * destroyed) and weights; the choice applies to later calls of the dtype
+ * and grids as tpd_autotune, each timed on A and weights (A destroyed:
+ * refilled with seeded noise before every run, as tpd_autotune does in
+ * place); the choice applies to later calls of the dtype
  * and n (and, with TPD_AUTOTUNE_CACHE, of later processes).  Without a
  * choice of its own the real-weights schedule takes the in-place Hermitian
  * mode's.  Arguments and errors as tpd_decompose_hermitian_real; allocates

@@ -33,6 +33,12 @@ struct TpdRange {
 };
 }  // namespace
 
+namespace tpd {
+// seeded uniform noise in [-1, 1) over `scalars` doubles (f64) or floats
+// (tpd_kernels.hip): the in-place autotuners' refill between timed runs
+hipError_t launch_fill_noise(void* p, uint64_t scalars, bool f64, uint64_t seed, hipStream_t st);
+}  // namespace tpd
+
 using namespace tpd;
 
 namespace {
@@ -1805,8 +1811,6 @@ extern "C" tpd_status_t tpd_autotune_hermitian_real(void* A, int n, void* weight
     return report ? copy_out(rep, report, len) : TPD_SUCCESS;
   }
   hipStream_t hs = (hipStream_t)stream;
-  // each run transforms the previous result in A (in place), whose values
-  // shrink towards zero: while timing, the second sweep skips no tiles
   const int dbs128[3] = {3, 4, 5}, dbs64[3] = {4, 5, 6};
   const int* dbs = dt == DT_C128 ? dbs128 : dbs64;
   const int grids[5] = {0, 1, 2, 4, 8};
@@ -1840,14 +1844,23 @@ extern "C" tpd_status_t tpd_autotune_hermitian_real(void* A, int n, void* weight
   Tuned best_t = cands[0];
   rep = "{\"tuned\":true,\"n\":" + std::to_string(n) + ",\"dtype\":\"" + dtype_name(dt) + "\",\"candidates\":[";
   bool first = true;
+  // the first sweep transforms A in place: A is refilled with seeded noise
+  // before every run (untimed), as the values of repeated transforms would
+  // decay towards zero and time differently
+  const uint64_t scalars = (uint64_t)2 << (2 * n);
+  uint64_t seed = 0x7470645f74756e65ull;
+  auto refill = [&]() {
+    if (launch_fill_noise(A, scalars, dt == DT_C128, seed++, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
+  };
   for (const Tuned& t : cands) {
     Schedule sc;
     if (make_real_out_schedule(n, dt, flags, &sc, &t) != TPD_SUCCESS) continue;
-    if (sc.prune) sc.sw[1].bitmap_mode = 0;
-    st = run_real_out(sc, A, weights, bm, hs, nullptr);  // warm-up
+    refill();
+    if (!st) st = run_real_out(sc, A, weights, bm, hs, nullptr);  // warm-up
     std::vector<float> ms;
     for (int r = 0; r < 3 && !st; ++r) {
-      if (hipEventRecord(e0, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
+      refill();
+      if (!st && hipEventRecord(e0, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
       if (!st) st = run_real_out(sc, A, weights, bm, hs, nullptr);
       if (!st && hipEventRecord(e1, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
       float t_ms = 0;
@@ -1909,9 +1922,12 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
     return report ? copy_out(rep, report, len) : TPD_SUCCESS;
   }
   hipStream_t hs = (hipStream_t)stream;
-  // in place every run transforms the previous result, whose values shrink
-  // towards zero: while timing, the second sweep skips no tiles, and the
-  // first still sets the pruning bitmap (its epilogue is part of the cost)
+  // in place the buffer is refilled with seeded noise before every run
+  // (untimed): the values of repeated transforms decay towards zero, and on
+  // all-zero data the first sweep's pruning epilogue sets no bits and the
+  // second sweep skips every tile, which times the candidates differently
+  // (real float32 n = 16: a chunked schedule at 12.5 ms on decayed data that
+  // takes 18.0 ms on data that stays live)
   const unsigned tflags = flags & ~TPD_FLAG_ORDER_BOTTOM;
   const int dbs128[3] = {3, 4, 5}, dbs64[3] = {4, 5, 6};
   const int* dbs = dt == DT_C128 ? dbs128 : dbs64;
@@ -1951,21 +1967,28 @@ extern "C" tpd_status_t tpd_autotune(const void* A, int n, void* coeffs, tpd_dty
   rep = "{\"tuned\":true,\"n\":" + std::to_string(n) + ",\"dtype\":\"" + dtype_name(dt) +
         "\",\"candidates\":[";
   bool first = true;
+  const uint64_t scalars = (uint64_t)(dt == DT_C128 || dt == DT_C64 ? 2 : 1) << (2 * n);
+  uint64_t seed = 0x7470645f74756e65ull;
+  auto refill = [&]() {
+    if (in_place && launch_fill_noise(coeffs, scalars, dt == DT_C128 || dt == DT_R64, seed++, hs) != hipSuccess)
+      st = TPD_ERROR_LAUNCH;
+  };
   // median of three timed runs after a warm-up; false if the schedule does
   // not exist or a call failed (st set)
   auto time_candidate = [&](const Tuned& t, double* med) -> bool {
     Schedule sc;
     if (make_schedule_with(n, dt, tflags, in_place, &t, &sc) != TPD_SUCCESS) return false;
-    if (in_place && sc.prune && sc.nsweep == 2) sc.sw[1].bitmap_mode = 0;
     if (sc.chunk_window) {
       st = pipe.ensure();
       if (st) return false;
     }
-    st = run_schedule(sc, A, coeffs, bm, hs, nullptr, &pipe);  // warm-up
+    refill();
+    if (!st) st = run_schedule(sc, A, coeffs, bm, hs, nullptr, &pipe);  // warm-up
     if (st) return false;
     std::vector<float> ms;
     for (int rep_i = 0; rep_i < 3 && !st; ++rep_i) {
-      if (hipEventRecord(e0, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
+      refill();
+      if (!st && hipEventRecord(e0, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
       if (!st) st = run_schedule(sc, A, coeffs, bm, hs, nullptr, &pipe);
       if (!st && hipEventRecord(e1, hs) != hipSuccess) st = TPD_ERROR_LAUNCH;
       float t_ms = 0;

@@ -52,6 +52,36 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t words, uint32_t value, hipStrea
   return hipGetLastError();
 }
 
+// Seeded noise, uniform in [-1, 1): scalar i is the top bits of
+// splitmix64(seed + i) (the published SplitMix64 finaliser).  The in-place
+// autotuners refill their buffer with it before every timed run, so that the
+// values do not decay towards zero over repeated transforms (all-zero data
+// skips the pruning epilogue's atomics and lets the second sweep skip tiles,
+// and timed that way the candidates rank differently).
+template <class T>
+__global__ void k_fill_noise(T* p, uint64_t count, uint64_t seed) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + i * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    if constexpr (sizeof(T) == 8) p[i] = (T)(int64_t)(z >> 11) * (T)0x1p-52 - (T)1;
+    else p[i] = (T)(int32_t)(uint32_t)(z >> 40) * (T)0x1p-23 - (T)1;
+  }
+}
+
+hipError_t launch_fill_noise(void* p, uint64_t scalars, bool f64, uint64_t seed, hipStream_t st) {
+  if (scalars == 0) return hipSuccess;
+  uint64_t g = (scalars + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (f64)
+    hipLaunchKernelGGL(k_fill_noise<double>, dim3((unsigned)g), dim3(256), 0, st, (double*)p, scalars, seed);
+  else
+    hipLaunchKernelGGL(k_fill_noise<float>, dim3((unsigned)g), dim3(256), 0, st, (float*)p, scalars, seed);
+  return hipGetLastError();
+}
+
 hipError_t launch_popcount(const uint32_t* p, uint64_t words, unsigned long long* out, hipStream_t st) {
   uint64_t g = (words + 255) / 256;
   if (g > 2048) g = 2048;

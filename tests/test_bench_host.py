@@ -226,3 +226,19 @@ def test_ingest_mixed_dispatch_kinds_and_merge_keeps_whole_sweeps(tmp_path):
     assert both == one
     later = bench.ingest_pmc([(paths[2], paths[3])], str(tmp_path / "c.json"))["kernels"][k]
     assert later["only_reduced_mode_dispatches"]
+    # whole sweeps only, then reduced-mode sweeps only: the whole sweeps are
+    # kept and the later pair's reduced-mode figures become their sub-record
+    # (in either order of the pairs)
+    f3 = [(COPY, 0.5 * copy / 1024)] + [(k, 0.5 * 1.001 * alg / 1024)] * 2
+    w3 = [(COPY, copy / 1024)] + [(k, 1.002 * alg / 1024)] * 2
+    for i, rows in enumerate((f3, w3)):
+        p = tmp_path / f"w{i}.csv"
+        write_csv(p, rows)
+        paths.append(str(p))
+    for order in (((paths[4], paths[5]), (paths[2], paths[3])), ((paths[2], paths[3]), (paths[4], paths[5]))):
+        m = bench.ingest_pmc(list(order), str(tmp_path / "d.json"))["kernels"][k]
+        assert m["dispatches"] == 2 and abs(m["fetch_over_algorithmic"] - 1.001) < 1e-9
+        assert "only_reduced_mode_dispatches" not in m
+        red = m["reduced_mode_dispatches"]
+        assert red["count"] == 2 and abs(red["fetch_over_algorithmic"] - 0.53) < 1e-9
+        assert abs(red["write_over_algorithmic"] - 0.5) < 1e-9

@@ -1176,6 +1176,24 @@ def test_autotune_keeps_results_bitwise():
             assert same_bits(after.cpu().numpy(), O.tpd_recursive(W.gaussian(n, seed=90 + n)))
     rep = tpd.autotune(to_dev(W.gaussian(6, 1)))
     assert rep["tuned"] is False
+    # in place the tuner refills its buffer with seeded noise before every
+    # timed run: the buffer ends holding a transform of noise (live values),
+    # not the decayed result of dozens of repeated transforms, which in
+    # float32 is all zeros; the choice keeps the bits
+    for n, dtype in ((12, torch.float32), (12, torch.complex128)):
+        A = to_dev(W.gaussian(n, seed=95).real.copy() if dtype == torch.float32 else W.gaussian(n, seed=95), dtype)
+        ref = A.clone()
+        tpd.decompose(ref, ref.view(-1), layout="matrix")
+        B = A.clone()
+        rep = tpd.autotune(B, B.view(-1), layout="matrix")
+        assert rep["tuned"] and len(rep["candidates"]) >= 4
+        live = torch.view_as_real(B) if B.is_complex() else B
+        assert float((live != 0).double().mean()) > 0.9, dtype
+        assert bool(torch.isfinite(live).all())
+        B.copy_(A)
+        tpd.decompose(B, B.view(-1), layout="matrix")
+        assert torch.equal(torch.view_as_real(B) if B.is_complex() else B,
+                           torch.view_as_real(ref) if ref.is_complex() else ref), dtype
     # batched plan autotune
     ns = [int(v) for v in W.batched_qubits(200, seed=13)]
     mats = W.batched_matrices(ns, seed=13)
