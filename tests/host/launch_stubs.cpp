@@ -6,6 +6,7 @@
 namespace tpd {
 hipError_t launch_sweep(Dtype, const SweepDesc&, const SweepArgs&, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_fill_u32(uint32_t*, uint64_t, uint32_t, hipStream_t) { return hipErrorNoDevice; }
+hipError_t launch_fill_noise(void*, uint64_t, bool, uint64_t, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_batched_perm(Dtype, const void* const*, void* const*, const uint32_t*, const BatchItem*, uint32_t,
                                const BatchSeg*, uint32_t, int, int, hipStream_t) {
   return hipErrorNoDevice;
