@@ -198,7 +198,7 @@ tpd_status_t make_schedule_with(int n, Dtype dt, unsigned flags, bool in_place, 
   // requested width up to its own cap (n = 17: 2^6 in the 8-level sweep, 2^5
   // in the 9-level one; the pruning bits follow the second sweep's
   // d-groups); otherwise both sweeps share one width (MID order, Hermitian
-  // representatives, and no register room for the split in 8-byte kernels).
+  // representatives, and a split that did not pay in the 8-byte kernels).
   const int max_tile_bits = dt == DT_C128 ? 13 : 14;
   const int cap1 = max_tile_bits - s->n1, cap2 = max_tile_bits - s->n2;
   const bool split_db = dt == DT_R32 && s->matrix_layout && !(flags & TPD_FLAG_HERMITIAN) && s->n1 >= 5;
