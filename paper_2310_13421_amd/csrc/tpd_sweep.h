@@ -69,10 +69,9 @@ __global__ void __launch_bounds__(G::NT) k_sweep(SweepArgs a) {
   // The thread's element bases are recomputed for every tile from an
   // opaque copy of the thread index: hoisted out of the tile loop, every
   // phase's LDS offsets and every register slot's address stayed live
-  // across the whole kernel (up to 256 VGPRs and spills; with the copy 90-195
-  // VGPRs, no spills, and twice the resident workgroups for 512-thread
-  // tiles of 8-byte elements).  The recomputation is a few integer
-  // operations per tile.
+  // across the whole kernel (up to 256 VGPRs, and spills); recomputed, the
+  // two-sweep kernels take 58-198 VGPRs and none spills.  The
+  // recomputation is a few integer operations per tile.
   auto thread_index = [&]() -> uint32_t {
     uint32_t t = tid;
     asm volatile("" : "+v"(t));
